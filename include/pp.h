@@ -1,0 +1,175 @@
+/*
+ * pp.h -- C ABI of the MI355X (gfx950) pressure-projection library.
+ *
+ * The library performs the projection step of a one-fluid incompressible
+ * Navier-Stokes method on a staggered (MAC) grid (paper Sec. 3.2):
+ *
+ *   u = u* - dt * beta * G p                                 (eq. fotm)
+ *   D (beta G p) = D u* / dt,   so that D u = 0               (eqs. cont-eq1, poisson)
+ *
+ * with beta = 1/rho on the cell faces (Sec. 3.7.1: the coefficients of the
+ * pressure system are interpolations of 1/rho), D the MAC divergence
+ * (eq. cont2) and G the face gradient.  Written as the paper's seven-point
+ * system (Sec. 3.7.1) the operator has link coefficients A1..A6 = beta_f / h^2
+ * and A7 = A1 + ... + A6.  Walls are Neumann boundaries for p: the link
+ * coefficient of a wall face is zero (Sec. 3.8) and its normal velocity is 0.
+ *
+ * ------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ * ------------------------------------------------------------------------
+ *  - Every array argument is a DEVICE pointer (hipMalloc'd or torch CUDA
+ *    tensor storage) to contiguous FP64 data owned by the caller.  The
+ *    library never frees or retains caller pointers after a call returns.
+ *  - Cell arrays have shape (nz, ny, nx) in C order (x fastest).
+ *  - A face array for direction m has the same shape; entry c is the LOW
+ *    face of cell c in direction m (between c - e_m and c).
+ *  - Direction m is periodic (PP_PERIODIC: c - e_m wraps) or walled
+ *    (PP_WALL: the entry with c_m == 0 is the wall face; its value is
+ *    ignored on input and treated as zero; the upper wall face is implicit).
+ *  - Work is enqueued on the HIP stream given to pp_setup.  Calls that report
+ *    a convergence result (pp_solve, pp_solve_adjoint) block the host until
+ *    the solve ends; the others only enqueue work.
+ *  - The operator is singular (constants span its null space): solves remove
+ *    the mean of the right-hand side and return the mean-zero solution.
+ *  - A context is used by one host thread at a time.
+ *
+ * Errors: every int-returning function returns PP_OK (0) or a negative
+ * pp_status.  Argument validation happens before any GPU work, so PP_EINVAL
+ * leaves all outputs untouched.  pp_strerror() names a code; pp_last_error()
+ * gives the detail text of the most recent failure on the calling thread.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pp_ctx pp_ctx;
+
+typedef enum {
+    PP_OK = 0,
+    PP_EINVAL = -1,      /* bad argument (null pointer, bad size, bad option) */
+    PP_ENOMEM = -2,      /* device or host allocation failed */
+    PP_EHIP = -3,        /* a HIP runtime call failed */
+    PP_ENOCONV = -4,     /* not converged within max_outer: p holds the best iterate */
+    PP_EDIVERGED = -5    /* NaN/Inf or residual blow-up: p is undefined */
+} pp_status;
+
+enum { PP_PERIODIC = 0, PP_WALL = 1 };
+
+/* arithmetic of the multigrid preconditioner; the outer loop, its residual,
+ * the coarsest-grid solve and the projection are always FP64 */
+enum { PP_FP64 = 0, PP_MIXED_FP32 = 1, PP_MIXED_FP16 = 2 };
+
+/* outer iteration around the V-cycle */
+enum { PP_OUTER_PCG = 0, PP_OUTER_DC = 1 };
+
+typedef struct {
+    int32_t n[3];        /* cells per direction {nx, ny, nz}; see pp_setup */
+    double h;            /* cell edge (cubic cells) */
+    int32_t bc[3];       /* PP_PERIODIC or PP_WALL per direction {x, y, z} */
+} pp_grid;
+
+typedef struct {
+    int32_t precision;   /* PP_FP64 / PP_MIXED_FP32 / PP_MIXED_FP16 */
+    int32_t outer;       /* PP_OUTER_PCG (flexible CG) or PP_OUTER_DC (defect correction) */
+    int32_t nu_pre;      /* red-black Gauss-Seidel sweeps before coarsening (>= 1) */
+    int32_t nu_post;     /* sweeps after the coarse correction (>= 1) */
+    int32_t max_outer;   /* outer iterations before PP_ENOCONV (1..4096) */
+    int32_t warm_start;  /* 1: pp_solve starts from the p passed in; 0: from p = 0 */
+    int32_t fallback;    /* 1: on stagnation of a mixed solve, continue with FP64 V-cycles */
+    int32_t reserved;
+} pp_opts;
+
+#define PP_HIST 128
+
+typedef struct {
+    int32_t outer_iters; /* outer iterations done */
+    int32_t vcycles;     /* V-cycles applied */
+    int32_t fell_back;   /* 1 if a mixed solve switched to FP64 V-cycles */
+    int32_t status;      /* the pp_status the call returned */
+    double rel_res;      /* final ||b - A p||_2 / ||b||_2 (b mean-removed) */
+    double res_hist[PP_HIST]; /* relative residual after each outer iteration */
+    double ms;           /* host wall time of the call, milliseconds */
+} pp_stats;
+
+/* Fill *o with the defaults: mixed FP32, PCG, nu_pre = nu_post = 2,
+ * max_outer = 500, warm_start = 0, fallback = 1. */
+void pp_opts_default(pp_opts *o);
+
+/* Face coefficients from cell densities, beta_m[c] = 2 / (rho[c - e_m] + rho[c])
+ * (arithmetic averaging of rho on the two cells of a face; Sec. 3.7.1 builds
+ * the coefficients from 1/rho interpolated to the faces).  Wall faces get 0.
+ * rho: n cells, all > 0.  beta_x/y/z: n cells each, written.  Needs no
+ * context; work goes on `hip_stream` (NULL = default stream). */
+int pp_face_coeffs(const pp_grid *grid, const double *rho, double *beta_x, double *beta_y,
+                   double *beta_z, void *hip_stream);
+
+/* Build a solver context for one set of face coefficients beta = 1/rho_f.
+ * Grid: every n[m] >= 4; the grid is halved in all directions while all
+ * n[m] are even and >= 8; the coarsest level reached must have at most 1024
+ * cells (every power-of-two grid qualifies).  h > 0.  beta_x/y/z: n cells
+ * each, finite; every non-wall face must have beta > 0 (a connected domain).
+ * The context copies beta (caller may free it afterwards), builds the
+ * multigrid hierarchy and the FP64 pseudo-inverse of the coarsest operator,
+ * and owns all device scratch; later calls allocate nothing.  opts may be
+ * NULL (defaults).  hip_stream: the hipStream_t to use (NULL = default).
+ * On success *out receives the context; release it with pp_destroy. */
+int pp_setup(const pp_grid *grid, const double *beta_x, const double *beta_y,
+             const double *beta_z, const pp_opts *opts, void *hip_stream, pp_ctx **out);
+
+/* Replace the face coefficients of an existing context (same grid), rebuilding
+ * the hierarchy in place without reallocating.  Same rules as pp_setup. */
+int pp_update_coeffs(pp_ctx *ctx, const double *beta_x, const double *beta_y,
+                     const double *beta_z);
+
+/* out = scale * D u with D the MAC divergence (eq. cont2); wall faces count
+ * as zero flux whatever their stored value.  u_x/u_y/u_z, out: n cells.
+ * The pressure right-hand side of eq. poisson is scale = 1/dt. */
+int pp_divergence(pp_ctx *ctx, const double *u_x, const double *u_y, const double *u_z,
+                  double scale, double *out);
+
+/* out = A x, the FP64 pressure operator (x, out: n cells; must not alias). */
+int pp_apply(pp_ctx *ctx, const double *x, double *out);
+
+/* Solve A p = rhs - mean(rhs) to ||b - A p||_2 <= tol ||b||_2 (b = rhs -
+ * mean(rhs)) and return the mean-zero p.  rhs, p: n cells; p is read as the
+ * initial guess when opts.warm_start is set, and written.  tol in (0, 1).
+ * stats may be NULL.  Returns PP_OK, PP_ENOCONV (p = best iterate, stats
+ * filled) or PP_EDIVERGED (p undefined). */
+int pp_solve(pp_ctx *ctx, const double *rhs, double *p, double tol, pp_stats *stats);
+
+/* Projection (eq. fotm): u_m = us_m - dt * beta_m * (p[c] - p[c - e_m]) / h on
+ * every non-wall face, u_m = 0 on wall faces.  us_x/y/z, p, u_x/y/z: n cells.
+ * u may alias us (in-place update); p must not alias u. */
+int pp_project(pp_ctx *ctx, const double *us_x, const double *us_y, const double *us_z,
+               const double *p, double dt, double *u_x, double *u_y, double *u_z);
+
+/* Adjoint of p = pp_solve(rhs) for a loss L with dL/dp = g_p: solves
+ * A lambda = g_p - mean(g_p) with the same hierarchy (A is symmetric) and
+ * writes g_rhs = lambda (mean zero) and, on every non-wall face,
+ * g_beta_m[c] = (lambda[c] - lambda[c - e_m]) (p[c] - p[c - e_m]) / h^2
+ * (wall faces 0).  p is the forward solution.  All arrays n cells; tol as in
+ * pp_solve; stats may be NULL. */
+int pp_solve_adjoint(pp_ctx *ctx, const double *p, const double *g_p, double tol,
+                     double *g_rhs, double *g_beta_x, double *g_beta_y, double *g_beta_z,
+                     pp_stats *stats);
+
+/* Number of multigrid levels and the dimensions of level `level` (0 = fine). */
+int pp_levels(const pp_ctx *ctx, int32_t *nlevels);
+int pp_level_dims(const pp_ctx *ctx, int32_t level, int32_t dims[3]);
+
+/* Device bytes held by the context. */
+int pp_memory(const pp_ctx *ctx, int64_t *bytes);
+
+void pp_destroy(pp_ctx *ctx);
+const char *pp_strerror(int status);
+const char *pp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_H */

@@ -1,0 +1,82 @@
+/*
+ * pp_kernels.h -- single-kernel entry points of the pressure-projection
+ * library, for component tests and kernel timing.
+ *
+ * These expose the building blocks of the multigrid V-cycle one launch at a
+ * time, on caller-provided FP64 device arrays, with the same layout rules as
+ * pp.h (cell arrays (nz, ny, nx), low-face beta arrays, walls encoded by the
+ * grid's bc).  The V-cycle itself is the in-code geometric multigrid of the
+ * paper (Sec. 3.7.3, grids of 2^n cells per direction, user-set numbers of
+ * relaxations on the way down and up); its smoother is the red-black
+ * Gauss-Seidel of Sec. 3.7.1 (eq. beta_pressure) with over-relaxation 1.
+ * Transfer operators are not given in the paper; the readings used:
+ *   restriction   r_H = mean of the 8 fine residuals of a coarse cell,
+ *   prolongation  trilinear in cell centres (weights 3/4, 1/4 per axis; at a
+ *                 wall the missing coarse neighbour is the cell itself),
+ *   coarse beta   mean of the 4 fine faces that make up a coarse face.
+ * Each call validates its arguments, enqueues on `hip_stream` (NULL = default
+ * stream) and returns a pp_status.
+ */
+#ifndef PP_KERNELS_H
+#define PP_KERNELS_H
+
+#include <stdint.h>
+
+#include "pp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* `sweeps` red-black Gauss-Seidel sweeps on A e = r (one sweep = all red
+ * cells (i+j+k even), then all black cells), each cell update
+ *   e_c <- (sum_nb beta_f e_nb - h^2 r_c) / sum_nb beta_f.
+ * zero_init = 1 treats e as zero on entry (e need not be initialised).
+ * beta_*: fine beta with wall faces already 0 or not (wall entries ignored).
+ * Periodic directions need an even cell count (consistent colouring). */
+int pp_k_smooth(const pp_grid *grid, const double *beta_x, const double *beta_y,
+                const double *beta_z, const double *r, double *e, int32_t sweeps,
+                int32_t zero_init, void *hip_stream);
+
+/* rH[C] = (1/8) sum over the 8 fine cells c of C of (r - A e)[c].
+ * grid: the fine grid (all n even); rH has n/2 cells per direction. */
+int pp_k_resid_restrict(const pp_grid *grid, const double *beta_x, const double *beta_y,
+                        const double *beta_z, const double *e, const double *r, double *rH,
+                        void *hip_stream);
+
+/* e += P eH, trilinear cell-centred prolongation.  grid: the fine grid. */
+int pp_k_prolong_add(const pp_grid *grid, const double *eH, double *e, void *hip_stream);
+
+/* Coarse face coefficients: mean of the 4 fine faces of each coarse face
+ * (wall faces stay 0).  grid: the fine grid; outputs have n/2 cells each. */
+int pp_k_coarsen_beta(const pp_grid *grid, const double *beta_x, const double *beta_y,
+                      const double *beta_z, double *bH_x, double *bH_y, double *bH_z,
+                      void *hip_stream);
+
+/* One V-cycle of the context's hierarchy, in its configured precision, for
+ * A e = r (r mean-zero FP64, n cells; e written, FP64). */
+int pp_vcycle(pp_ctx *ctx, const double *r, double *e);
+
+/* Plain device copy kernel dst[i] = src[i], i < count (bandwidth reference). */
+int pp_k_copy(const double *src, double *dst, int64_t count, void *hip_stream);
+
+/* Kernel timing on the context's stream: while enabled, every launch of the
+ * fine-level kernels below is bracketed by HIP events and its duration is
+ * accumulated per kind.  pp_timing_get reports launches and total ms since
+ * the last reset (events are resolved when a solve ends or when queried). */
+enum {
+    PP_KT_SMOOTH = 0,          /* fine-level red-black half sweep */
+    PP_KT_RESTRICT = 1,        /* fine-level residual + restriction */
+    PP_KT_PROLONG = 2,         /* fine-level prolongation + correction */
+    PP_KT_OUTER_APPLY = 3,     /* FP64 operator apply (+ dot) of the outer loop */
+    PP_KT_OUTER_UPDATE = 4,    /* FP64 vector update (+ norms) of the outer loop */
+    PP_KT_COUNT = 5
+};
+int pp_timing_enable(pp_ctx *ctx, int32_t on);
+int pp_timing_reset(pp_ctx *ctx);
+int pp_timing_get(pp_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_KERNELS_H */

@@ -1,0 +1,1090 @@
+// pp_api.hip -- host driver and C ABI of the pressure-projection library.
+//
+// pp_solve runs an FP64 outer iteration (flexible preconditioned conjugate
+// gradients by default, or defect correction) around one geometric-multigrid
+// V-cycle per iteration (the paper's in-code multigrid, Sec. 3.7.3; red-black
+// Gauss-Seidel smoothing, Sec. 3.7.1).  The V-cycle runs in FP64, or in FP32
+// (FP16 storage as a variant) on a right-hand side normalised by the RMS of
+// the current residual; the outer residual, the coarsest-grid solve and the
+// projection stay FP64.  Convergence is checked on the relative L2 norm of
+// the residual (the paper lets the user pick L1, L2 or Linf, Sec. 3.7.2),
+// read back once per outer iteration.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pp.h"
+#include "pp_internal.h"
+#include "pp_kernels.h"
+
+using namespace pp;
+
+namespace {
+
+constexpr int MAXLEV = 24;
+constexpr int COARSEST_MAX = 1024;
+constexpr int STAGNATED = 1;   // internal code: outer loop stopped improving
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define PP_HIP(call)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(PP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+#define PP_TRY(call)                                                                            \
+    do {                                                                                        \
+        int rc_ = (call);                                                                       \
+        if (rc_ != PP_OK)                                                                       \
+            return rc_;                                                                         \
+    } while (0)
+
+int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(PP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return PP_OK;
+}
+
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
+
+size_t storage_bytes(int st) { return st == ST_F64 ? 8 : (st == ST_F32 ? 4 : 2); }
+
+struct LevelBuf {
+    Dims d;
+    double h;
+    void *b[3];
+    void *e;
+    void *r;
+};
+
+struct Hier {
+    int st = ST_F64;
+    int nlev = 0;
+    bool present = false;
+    LevelBuf lev[MAXLEV];
+};
+
+struct EventPair {
+    hipEvent_t a, b;
+    int kind;
+};
+
+}  // namespace
+
+struct pp_ctx {
+    pp_grid grid;
+    pp_opts opts;
+    hipStream_t stream;
+    Dims d;
+    Bc bc;
+    size_t N;
+    int nlev;
+    Dims ld[MAXLEV];
+    double lh[MAXLEV];
+    double *chain[MAXLEV][3];   // FP64 face coefficients per level; chain[0] = the fine copy
+    Hier hmix;                   // FP32 / FP16 hierarchy (mixed precision)
+    Hier h64;                    // FP64 hierarchy (FP64 mode, and the mixed-mode fallback)
+    double *pinv;
+    int ncoarse;
+    double *r64, *d64, *q64;
+    double *part;
+    size_t pstride;
+    double *scal;
+    double *hscal;
+    std::vector<void *> allocs;
+    int64_t bytes;
+    // kernel timing
+    bool timing;
+    std::vector<EventPair> ev;
+    size_t ev_used;
+    int64_t kt_count[PP_KT_COUNT];
+    double kt_ms[PP_KT_COUNT];
+};
+
+namespace {
+
+int dev_alloc(pp_ctx *c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0)
+        bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(PP_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                   hipGetErrorString(e));
+    }
+    c->allocs.push_back(*p);
+    c->bytes += (int64_t)bytes;
+    return PP_OK;
+}
+
+template <typename P>
+int dev_alloc_t(pp_ctx *c, P **p, size_t bytes)
+{
+    void *v = nullptr;
+    int rc = dev_alloc(c, &v, bytes);
+    *p = static_cast<P *>(v);
+    return rc;
+}
+
+Dims to_dims(const pp_grid *g) { return Dims{g->n[0], g->n[1], g->n[2]}; }
+Bc to_bc(const pp_grid *g) { return Bc{g->bc[0] == PP_WALL, g->bc[1] == PP_WALL, g->bc[2] == PP_WALL}; }
+
+int validate_grid(const pp_grid *g, int *nlev_out, Dims *ld, double *lh)
+{
+    if (!g)
+        return fail(PP_EINVAL, "grid is NULL");
+    for (int m = 0; m < 3; ++m) {
+        if (g->n[m] < 4)
+            return fail(PP_EINVAL, "grid: every n[m] must be >= 4 (got " + std::to_string(g->n[m]) + ")");
+        if (g->n[m] > (1 << 16))
+            return fail(PP_EINVAL, "grid: n[m] must be <= 65536");
+        if (g->bc[m] != PP_PERIODIC && g->bc[m] != PP_WALL)
+            return fail(PP_EINVAL, "grid: bc[m] must be PP_PERIODIC or PP_WALL");
+    }
+    if (!(g->h > 0.0) || !std::isfinite(g->h))
+        return fail(PP_EINVAL, "grid: h must be a finite positive number");
+    const double ncell = (double)g->n[0] * g->n[1] * g->n[2];
+    if (ncell > 4.0e9)
+        return fail(PP_EINVAL, "grid: more than 4e9 cells");
+    if (nlev_out) {
+        Dims d = to_dims(g);
+        double h = g->h;
+        int l = 0;
+        ld[0] = d;
+        lh[0] = h;
+        while (d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.nx >= 8 && d.ny >= 8 &&
+               d.nz >= 8 && l + 1 < MAXLEV) {
+            d = Dims{d.nx / 2, d.ny / 2, d.nz / 2};
+            h *= 2.0;
+            ++l;
+            ld[l] = d;
+            lh[l] = h;
+        }
+        if (cells(d) > (size_t)COARSEST_MAX)
+            return fail(PP_EINVAL, "grid: halving all directions while every n is even and >= 8 stops at " +
+                                       std::to_string(d.nx) + "x" + std::to_string(d.ny) + "x" +
+                                       std::to_string(d.nz) + " cells (> 1024)");
+        *nlev_out = l + 1;
+    }
+    return PP_OK;
+}
+
+int validate_opts(const pp_opts *o)
+{
+    if (o->precision < PP_FP64 || o->precision > PP_MIXED_FP16)
+        return fail(PP_EINVAL, "opts.precision must be PP_FP64, PP_MIXED_FP32 or PP_MIXED_FP16");
+    if (o->outer != PP_OUTER_PCG && o->outer != PP_OUTER_DC)
+        return fail(PP_EINVAL, "opts.outer must be PP_OUTER_PCG or PP_OUTER_DC");
+    if (o->nu_pre < 1 || o->nu_pre > 16 || o->nu_post < 1 || o->nu_post > 16)
+        return fail(PP_EINVAL, "opts.nu_pre / nu_post must be in 1..16");
+    if (o->max_outer < 1 || o->max_outer > 4096)
+        return fail(PP_EINVAL, "opts.max_outer must be in 1..4096");
+    if (o->warm_start != 0 && o->warm_start != 1)
+        return fail(PP_EINVAL, "opts.warm_start must be 0 or 1");
+    if (o->fallback != 0 && o->fallback != 1)
+        return fail(PP_EINVAL, "opts.fallback must be 0 or 1");
+    return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+
+struct KT {
+    pp_ctx *c;
+    int kind;
+    size_t slot;
+    KT(pp_ctx *ctx, int k, bool fine) : c(ctx), kind(k), slot((size_t)-1)
+    {
+        if (!c->timing || !fine)
+            return;
+        if (c->ev_used >= c->ev.size())
+            return;
+        slot = c->ev_used++;
+        c->ev[slot].kind = k;
+        (void)hipEventRecord(c->ev[slot].a, c->stream);
+    }
+    ~KT()
+    {
+        if (slot != (size_t)-1)
+            (void)hipEventRecord(c->ev[slot].b, c->stream);
+    }
+};
+
+void resolve_timing(pp_ctx *c)
+{
+    if (c->ev_used == 0)
+        return;
+    (void)hipStreamSynchronize(c->stream);
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[i].a, c->ev[i].b) == hipSuccess) {
+            c->kt_ms[c->ev[i].kind] += ms;
+            c->kt_count[c->ev[i].kind] += 1;
+        }
+    }
+    c->ev_used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy
+// ---------------------------------------------------------------------------
+
+int alloc_hier(pp_ctx *c, Hier &H, int st)
+{
+    H.st = st;
+    H.nlev = c->nlev;
+    H.present = true;
+    const size_t sb = storage_bytes(st);
+    for (int l = 0; l < c->nlev; ++l) {
+        LevelBuf &v = H.lev[l];
+        v.d = c->ld[l];
+        v.h = c->lh[l];
+        const size_t n = cells(v.d);
+        for (int m = 0; m < 3; ++m) {
+            if (st == ST_F64)
+                v.b[m] = c->chain[l][m];
+            else
+                PP_TRY(dev_alloc(c, &v.b[m], n * sb));
+        }
+        PP_TRY(dev_alloc(c, &v.e, n * sb));
+        PP_TRY(dev_alloc(c, &v.r, n * sb));
+    }
+    return PP_OK;
+}
+
+int fill_hier(pp_ctx *c, Hier &H)
+{
+    if (!H.present || H.st == ST_F64)
+        return PP_OK;
+    for (int l = 0; l < c->nlev; ++l) {
+        const size_t n = cells(c->ld[l]);
+        for (int m = 0; m < 3; ++m) {
+            if (H.st == ST_F32)
+                launch_convert<float>(n, c->chain[l][m], (float *)H.lev[l].b[m], c->stream);
+            else
+                launch_convert<_Float16>(n, c->chain[l][m], (_Float16 *)H.lev[l].b[m], c->stream);
+        }
+    }
+    return check_launch("convert coefficients");
+}
+
+int cholesky(std::vector<double> &a, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        double dgl = a[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k)
+            dgl -= a[(size_t)j * n + k] * a[(size_t)j * n + k];
+        if (!(dgl > 0.0))
+            return -1;
+        dgl = std::sqrt(dgl);
+        a[(size_t)j * n + j] = dgl;
+        for (int i = j + 1; i < n; ++i) {
+            double s = a[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k)
+                s -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
+            a[(size_t)i * n + j] = s / dgl;
+        }
+    }
+    return 0;
+}
+
+// FP64 pseudo-inverse of the coarsest operator A (singular, constants in the
+// null space): with K = -A + (s/n) 1 1^T positive definite,
+// A^+ = (1/(s n)) 1 1^T - K^-1.
+int build_pinv(pp_ctx *c)
+{
+    const int L = c->nlev - 1;
+    const Dims d = c->ld[L];
+    const int n = (int)cells(d);
+    const double h = c->lh[L];
+    std::vector<double> b[3];
+    for (int m = 0; m < 3; ++m) {
+        b[m].resize(n);
+        PP_HIP(hipMemcpyAsync(b[m].data(), c->chain[L][m], sizeof(double) * n, hipMemcpyDeviceToHost,
+                              c->stream));
+    }
+    PP_HIP(hipStreamSynchronize(c->stream));
+    std::vector<double> A((size_t)n * n, 0.0);
+    const int nn[3] = {d.nx, d.ny, d.nz};
+    const int wall[3] = {c->bc.x, c->bc.y, c->bc.z};
+    for (int k = 0; k < d.nz; ++k)
+        for (int j = 0; j < d.ny; ++j)
+            for (int i = 0; i < d.nx; ++i) {
+                const int R = (k * d.ny + j) * d.nx + i;
+                int q[3] = {i, j, k};
+                for (int m = 0; m < 3; ++m) {
+                    int lo[3] = {q[0], q[1], q[2]};
+                    lo[m] -= 1;
+                    if (lo[m] < 0) {
+                        if (wall[m])
+                            continue;
+                        lo[m] += nn[m];
+                    }
+                    const int Lc = (lo[2] * d.ny + lo[1]) * d.nx + lo[0];
+                    const double w = b[m][R] / (h * h);
+                    A[(size_t)R * n + R] -= w;
+                    A[(size_t)R * n + Lc] += w;
+                    A[(size_t)Lc * n + Lc] -= w;
+                    A[(size_t)Lc * n + R] += w;
+                }
+            }
+    double s = 0.0;
+    for (int i = 0; i < n; ++i)
+        s = std::max(s, -A[(size_t)i * n + i]);
+    if (!(s > 0.0))
+        return fail(PP_EINVAL, "coarsest operator is zero");
+    std::vector<double> K((size_t)n * n);
+    for (size_t i = 0; i < (size_t)n * n; ++i)
+        K[i] = -A[i] + s / n;
+    if (cholesky(K, n) != 0)
+        return fail(PP_EINVAL, "coarsest operator is not definite on mean-zero fields "
+                               "(disconnected domain?)");
+    std::vector<double> P((size_t)n * n);
+    std::vector<double> y(n);
+    for (int col = 0; col < n; ++col) {
+        for (int i = 0; i < n; ++i) {
+            double t = (i == col) ? 1.0 : 0.0;
+            for (int kk = 0; kk < i; ++kk)
+                t -= K[(size_t)i * n + kk] * y[kk];
+            y[i] = t / K[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int kk = i + 1; kk < n; ++kk)
+                t -= K[(size_t)kk * n + i] * y[kk];
+            y[i] = t / K[(size_t)i * n + i];
+        }
+        for (int i = 0; i < n; ++i)
+            P[(size_t)i * n + col] = 1.0 / (s * n) - y[i];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double v = 0.5 * (P[(size_t)i * n + j] + P[(size_t)j * n + i]);
+            P[(size_t)i * n + j] = v;
+            P[(size_t)j * n + i] = v;
+        }
+    PP_HIP(hipMemcpyAsync(c->pinv, P.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, c->stream));
+    PP_HIP(hipStreamSynchronize(c->stream));
+    return PP_OK;
+}
+
+int read_scal(pp_ctx *c)
+{
+    PP_HIP(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
+                          c->stream));
+    PP_HIP(hipStreamSynchronize(c->stream));
+    return PP_OK;
+}
+
+int nparts(pp_ctx *c) { return (int)grid_blocks(cell_grid(c->d)); }
+
+int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
+{
+    const double *src[3] = {bx, by, bz};
+    for (int m = 0; m < 3; ++m)
+        PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N, hipMemcpyDeviceToDevice,
+                              c->stream));
+    launch_zero_walls(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->stream);
+    launch_check_beta(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->part, c->stream);
+    launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_COUNT, (double)c->N, 0, c->scal,
+                    c->stream);
+    PP_TRY(check_launch("coefficient check"));
+    PP_TRY(read_scal(c));
+    if (c->hscal[S_COUNT] != 0.0)
+        return fail(PP_EINVAL, "beta: " + std::to_string((long long)c->hscal[S_COUNT]) +
+                                   " non-wall faces are not finite positive numbers");
+    for (int l = 0; l + 1 < c->nlev; ++l)
+        launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
+                            c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2], c->stream);
+    PP_TRY(check_launch("coarsen coefficients"));
+    PP_TRY(fill_hier(c, c->hmix));
+    PP_TRY(build_pinv(c));
+    return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void vcycle_run(pp_ctx *c, Hier &H)
+{
+    hipStream_t s = c->stream;
+    const int L = H.nlev;
+    for (int l = 0; l + 1 < L; ++l) {
+        LevelBuf &v = H.lev[l];
+        const double h2 = v.h * v.h;
+        const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
+        for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
+            {
+                KT t(c, PP_KT_SMOOTH, l == 0);
+                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 0, sw == 0, s);
+            }
+            {
+                KT t(c, PP_KT_SMOOTH, l == 0);
+                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 1, false, s);
+            }
+        }
+        KT t(c, PP_KT_RESTRICT, l == 0);
+        launch_resid_restrict<T>(v.d, c->bc, b0, b1, b2, (const T *)v.e, (const T *)v.r,
+                                 (T *)H.lev[l + 1].r, 1.0 / h2, s);
+    }
+    launch_coarsest<T>(c->ncoarse, c->pinv, (const T *)H.lev[L - 1].r, (T *)H.lev[L - 1].e, s);
+    for (int l = L - 2; l >= 0; --l) {
+        LevelBuf &v = H.lev[l];
+        const double h2 = v.h * v.h;
+        const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
+        {
+            KT t(c, PP_KT_PROLONG, l == 0);
+            launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].e, (T *)v.e, s);
+        }
+        for (int sw = 0; sw < c->opts.nu_post; ++sw) {
+            {
+                KT t(c, PP_KT_SMOOTH, l == 0);
+                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 1, false, s);
+            }
+            {
+                KT t(c, PP_KT_SMOOTH, l == 0);
+                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 0, false, s);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// outer iterations
+// ---------------------------------------------------------------------------
+
+struct SolveState {
+    double nb;
+    double rel;
+    double best;
+    int it;
+    pp_stats *st;
+};
+
+void record(SolveState &S)
+{
+    if (S.st && S.it >= 1 && S.it <= PP_HIST)
+        S.st->res_hist[S.it - 1] = S.rel;
+}
+
+int check_progress(SolveState &S, int since_best_limit, int &since, double &best_window)
+{
+    if (!std::isfinite(S.rel))
+        return fail(PP_EDIVERGED, "residual is not finite");
+    if (S.rel > 1e3 * S.best)
+        return fail(PP_EDIVERGED, "residual grew a thousandfold above its best value");
+    S.best = std::min(S.best, S.rel);
+    if (S.rel < 0.9 * best_window) {
+        best_window = S.rel;
+        since = 0;
+    } else if (++since >= since_best_limit) {
+        return STAGNATED;
+    }
+    return PP_OK;
+}
+
+// residual of the current iterate into r64 (+ RR, BB, scales); returns rel
+int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveState &S)
+{
+    const double ih2 = 1.0 / (c->grid.h * c->grid.h);
+    {
+        KT t(c, PP_KT_OUTER_APPLY, true);
+        launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs, c->scal, x,
+                        zero_x, c->r64, ih2, c->part, c->pstride, c->stream);
+    }
+    launch_finalize(c->part, c->pstride, nparts(c), OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
+    PP_TRY(check_launch("residual"));
+    PP_TRY(read_scal(c));
+    S.nb = std::sqrt(c->hscal[S_BB]);
+    S.rel = (S.nb > 0.0) ? std::sqrt(c->hscal[S_RR]) / S.nb : 0.0;
+    return PP_OK;
+}
+
+template <typename T>
+int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
+{
+    hipStream_t s = c->stream;
+    const double ih2 = 1.0 / (c->grid.h * c->grid.h);
+    const int np = nparts(c);
+    LevelBuf &v0 = H.lev[0];
+    launch_scale_T<T>(c->N, c->r64, (T *)v0.r, c->scal, s);
+    bool first = true;
+    int since = 0;
+    double window = S.rel;
+    for (;;) {
+        if (S.it >= c->opts.max_outer)
+            return fail(PP_ENOCONV, "no convergence within max_outer iterations");
+        vcycle_run<T>(c, H);
+        if (S.st)
+            S.st->vcycles++;
+        launch_dot_rz<T>(c->d, c->r64, (const T *)v0.e, c->part, s);
+        launch_finalize(c->part, c->pstride, np, OP_RZ, 0, (double)c->N, first ? 1 : 0, c->scal, s);
+        launch_pcg_dir<T>(c->N, (const T *)v0.e, c->d64, c->scal, first, s);
+        first = false;
+        {
+            KT t(c, PP_KT_OUTER_APPLY, true);
+            launch_apply_dot(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->d64,
+                             c->q64, ih2, c->part, s);
+        }
+        launch_finalize(c->part, c->pstride, np, OP_ALPHA, 0, (double)c->N, 0, c->scal, s);
+        {
+            KT t(c, PP_KT_OUTER_UPDATE, true);
+            launch_pcg_update<T>(c->d, c->d64, c->q64, x, c->r64, (T *)v0.r, (const T *)v0.e, c->scal,
+                                 c->part, c->pstride, s);
+        }
+        launch_finalize(c->part, c->pstride, np, OP_UPDATE, 0, (double)c->N, 0, c->scal, s);
+        PP_TRY(check_launch("pcg iteration"));
+        PP_TRY(read_scal(c));
+        S.it++;
+        S.rel = std::sqrt(c->hscal[S_RR]) / S.nb;
+        record(S);
+        if (S.rel <= tol)
+            return PP_OK;
+        int rc = check_progress(S, 8, since, window);
+        if (rc != PP_OK)
+            return rc;
+    }
+}
+
+template <typename T>
+int dc_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, SolveState &S)
+{
+    hipStream_t s = c->stream;
+    const double ih2 = 1.0 / (c->grid.h * c->grid.h);
+    const int np = nparts(c);
+    LevelBuf &v0 = H.lev[0];
+    launch_scale_T<T>(c->N, c->r64, (T *)v0.r, c->scal, s);
+    int since = 0;
+    double window = S.rel;
+    for (;;) {
+        if (S.it >= c->opts.max_outer)
+            return fail(PP_ENOCONV, "no convergence within max_outer iterations");
+        vcycle_run<T>(c, H);
+        if (S.st)
+            S.st->vcycles++;
+        launch_axpy_T<T>(c->N, (const T *)v0.e, x, c->scal, s);
+        {
+            KT t(c, PP_KT_OUTER_APPLY, true);
+            launch_residual_T<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs,
+                                 c->scal, x, (T *)v0.r, ih2, c->part, s);
+        }
+        launch_finalize(c->part, c->pstride, np, OP_DC, 0, (double)c->N, 0, c->scal, s);
+        PP_TRY(check_launch("defect-correction iteration"));
+        PP_TRY(read_scal(c));
+        S.it++;
+        S.rel = std::sqrt(c->hscal[S_RR]) / S.nb;
+        record(S);
+        if (S.rel <= tol)
+            return PP_OK;
+        int rc = check_progress(S, 6, since, window);
+        if (rc != PP_OK)
+            return rc;
+    }
+}
+
+int run_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, SolveState &S)
+{
+    if (c->opts.outer == PP_OUTER_PCG) {
+        switch (H.st) {
+        case ST_F64: return pcg_loop<double>(c, H, x, tol, S);
+        case ST_F32: return pcg_loop<float>(c, H, x, tol, S);
+        default: return pcg_loop<_Float16>(c, H, x, tol, S);
+        }
+    }
+    switch (H.st) {
+    case ST_F64: return dc_loop<double>(c, H, rhs, x, tol, S);
+    case ST_F32: return dc_loop<float>(c, H, rhs, x, tol, S);
+    default: return dc_loop<_Float16>(c, H, rhs, x, tol, S);
+    }
+}
+
+int gauge(pp_ctx *c, double *x)
+{
+    launch_sum(c->d, x, c->part, c->stream);
+    launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_XMEAN, (double)c->N, 0, c->scal,
+                    c->stream);
+    launch_sub_mean(c->N, x, c->scal, S_XMEAN, c->stream);
+    return check_launch("gauge");
+}
+
+int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st, bool warm)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+    }
+    SolveState S{0.0, 0.0, INFINITY, 0, st};
+    launch_sum(c->d, rhs, c->part, c->stream);
+    launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_MEAN, (double)c->N, 0, c->scal,
+                    c->stream);
+    PP_TRY(true_residual(c, rhs, x, !warm, S));
+    int rc = PP_OK;
+    if (!(S.nb > 0.0)) {
+        // b = 0 after mean removal: the mean-zero solution is 0
+        launch_fill(x, c->N, 0.0, c->stream);
+        PP_TRY(check_launch("fill"));
+        S.rel = 0.0;
+    } else if (S.rel > tol) {
+        Hier *H = (c->opts.precision == PP_FP64) ? &c->h64 : &c->hmix;
+        S.best = S.rel;
+        for (int restart = 0;; ++restart) {
+            rc = run_loop(c, *H, rhs, x, tol, S);
+            if (rc == PP_OK) {
+                if (c->opts.outer == PP_OUTER_DC)
+                    break;   // DC residuals are true residuals already
+                // recurrences drift from the true residual: confirm it
+                PP_TRY(true_residual(c, rhs, x, false, S));
+                if (S.rel <= tol)
+                    break;
+                if (restart >= 4) {
+                    rc = fail(PP_ENOCONV, "true residual stays above tol after restarts");
+                    break;
+                }
+                continue;
+            }
+            if (rc == STAGNATED) {
+                if (H != &c->h64 && c->opts.fallback && c->h64.present) {
+                    H = &c->h64;
+                    if (st)
+                        st->fell_back = 1;
+                    PP_TRY(true_residual(c, rhs, x, false, S));
+                    if (S.rel <= tol) {
+                        rc = PP_OK;
+                        break;
+                    }
+                    continue;
+                }
+                rc = fail(PP_ENOCONV, "outer iteration stagnated");
+            }
+            break;
+        }
+    }
+    if (rc == PP_OK || rc == PP_ENOCONV)
+        PP_TRY(gauge(c, x));
+    if (c->timing)
+        resolve_timing(c);
+    else
+        PP_HIP(hipStreamSynchronize(c->stream));
+    if (st) {
+        st->outer_iters = S.it;
+        st->rel_res = S.rel;
+        st->status = rc;
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rc;
+}
+
+int check_ctx(const pp_ctx *c)
+{
+    if (!c)
+        return fail(PP_EINVAL, "context is NULL");
+    return PP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void pp_opts_default(pp_opts *o)
+{
+    if (!o)
+        return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = PP_MIXED_FP32;
+    o->outer = PP_OUTER_PCG;
+    o->nu_pre = 2;
+    o->nu_post = 2;
+    o->max_outer = 500;
+    o->warm_start = 0;
+    o->fallback = 1;
+}
+
+const char *pp_strerror(int status)
+{
+    switch (status) {
+    case PP_OK: return "ok";
+    case PP_EINVAL: return "invalid argument";
+    case PP_ENOMEM: return "out of memory";
+    case PP_EHIP: return "HIP runtime error";
+    case PP_ENOCONV: return "not converged";
+    case PP_EDIVERGED: return "diverged";
+    default: return "unknown status";
+    }
+}
+
+const char *pp_last_error(void) { return g_err.c_str(); }
+
+int pp_face_coeffs(const pp_grid *grid, const double *rho, double *bx, double *by, double *bz,
+                   void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!rho || !bx || !by || !bz)
+        return fail(PP_EINVAL, "pp_face_coeffs: NULL array");
+    launch_face_coeffs(to_dims(grid), to_bc(grid), rho, bx, by, bz, (hipStream_t)hip_stream);
+    return check_launch("pp_face_coeffs");
+}
+
+void pp_destroy(pp_ctx *c)
+{
+    if (!c)
+        return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &e : c->ev) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (void *p : c->allocs)
+        (void)hipFree(p);
+    if (c->hscal)
+        (void)hipHostFree(c->hscal);
+    delete c;
+}
+
+int pp_setup(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+             const pp_opts *opts, void *hip_stream, pp_ctx **out)
+{
+    if (!out)
+        return fail(PP_EINVAL, "pp_setup: out is NULL");
+    *out = nullptr;
+    int nlev = 0;
+    Dims ld[MAXLEV];
+    double lh[MAXLEV];
+    PP_TRY(validate_grid(grid, &nlev, ld, lh));
+    if (!bx || !by || !bz)
+        return fail(PP_EINVAL, "pp_setup: NULL beta array");
+    pp_opts o;
+    if (opts)
+        o = *opts;
+    else
+        pp_opts_default(&o);
+    PP_TRY(validate_opts(&o));
+
+    pp_ctx *c = new pp_ctx();
+    c->grid = *grid;
+    c->opts = o;
+    c->stream = (hipStream_t)hip_stream;
+    c->d = to_dims(grid);
+    c->bc = to_bc(grid);
+    c->N = cells(c->d);
+    c->nlev = nlev;
+    for (int l = 0; l < nlev; ++l) {
+        c->ld[l] = ld[l];
+        c->lh[l] = lh[l];
+    }
+    c->ncoarse = (int)cells(ld[nlev - 1]);
+    c->timing = false;
+    c->ev_used = 0;
+    int rc = PP_OK;
+    auto bail = [&](int code) {
+        pp_destroy(c);
+        return code;
+    };
+    for (int l = 0; l < nlev && rc == PP_OK; ++l)
+        for (int m = 0; m < 3 && rc == PP_OK; ++m)
+            rc = dev_alloc_t(c, &c->chain[l][m], sizeof(double) * cells(ld[l]));
+    if (rc == PP_OK && (o.precision == PP_FP64 || o.fallback))
+        rc = alloc_hier(c, c->h64, ST_F64);
+    if (rc == PP_OK && o.precision != PP_FP64)
+        rc = alloc_hier(c, c->hmix, o.precision == PP_MIXED_FP32 ? ST_F32 : ST_F16);
+    if (rc == PP_OK)
+        rc = dev_alloc_t(c, &c->pinv, sizeof(double) * (size_t)c->ncoarse * c->ncoarse);
+    if (rc == PP_OK)
+        rc = dev_alloc_t(c, &c->r64, sizeof(double) * c->N);
+    if (rc == PP_OK)
+        rc = dev_alloc_t(c, &c->d64, sizeof(double) * c->N);
+    if (rc == PP_OK)
+        rc = dev_alloc_t(c, &c->q64, sizeof(double) * c->N);
+    c->pstride = grid_blocks(cell_grid(c->d));
+    if (rc == PP_OK)
+        rc = dev_alloc_t(c, &c->part, sizeof(double) * 2 * c->pstride);
+    if (rc == PP_OK)
+        rc = dev_alloc_t(c, &c->scal, sizeof(double) * S_NSLOTS);
+    if (rc != PP_OK)
+        return bail(rc);
+    if (hipHostMalloc((void **)&c->hscal, sizeof(double) * S_NSLOTS, hipHostMallocDefault) !=
+        hipSuccess) {
+        c->hscal = nullptr;
+        return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
+    }
+    if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
+        return bail(fail(PP_EHIP, "hipMemsetAsync failed"));
+    rc = load_coeffs(c, bx, by, bz);
+    if (rc != PP_OK)
+        return bail(rc);
+    *out = c;
+    return PP_OK;
+}
+
+int pp_update_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
+{
+    PP_TRY(check_ctx(c));
+    if (!bx || !by || !bz)
+        return fail(PP_EINVAL, "pp_update_coeffs: NULL beta array");
+    return load_coeffs(c, bx, by, bz);
+}
+
+int pp_divergence(pp_ctx *c, const double *ux, const double *uy, const double *uz, double scale,
+                  double *out)
+{
+    PP_TRY(check_ctx(c));
+    if (!ux || !uy || !uz || !out)
+        return fail(PP_EINVAL, "pp_divergence: NULL array");
+    if (!std::isfinite(scale))
+        return fail(PP_EINVAL, "pp_divergence: scale must be finite");
+    launch_divergence(c->d, c->bc, ux, uy, uz, scale / c->grid.h, out, c->stream);
+    return check_launch("pp_divergence");
+}
+
+int pp_apply(pp_ctx *c, const double *x, double *y)
+{
+    PP_TRY(check_ctx(c));
+    if (!x || !y)
+        return fail(PP_EINVAL, "pp_apply: NULL array");
+    if (x == y)
+        return fail(PP_EINVAL, "pp_apply: x and out must not alias");
+    launch_apply(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], x, y,
+                 1.0 / (c->grid.h * c->grid.h), c->stream);
+    return check_launch("pp_apply");
+}
+
+int pp_solve(pp_ctx *c, const double *rhs, double *p, double tol, pp_stats *st)
+{
+    PP_TRY(check_ctx(c));
+    if (!rhs || !p)
+        return fail(PP_EINVAL, "pp_solve: NULL array");
+    if (rhs == p)
+        return fail(PP_EINVAL, "pp_solve: rhs and p must not alias");
+    if (!(tol > 0.0 && tol < 1.0))
+        return fail(PP_EINVAL, "pp_solve: tol must be in (0, 1)");
+    return solve_impl(c, rhs, p, tol, st, c->opts.warm_start != 0);
+}
+
+int pp_project(pp_ctx *c, const double *usx, const double *usy, const double *usz, const double *p,
+               double dt, double *ux, double *uy, double *uz)
+{
+    PP_TRY(check_ctx(c));
+    if (!usx || !usy || !usz || !p || !ux || !uy || !uz)
+        return fail(PP_EINVAL, "pp_project: NULL array");
+    if (p == ux || p == uy || p == uz)
+        return fail(PP_EINVAL, "pp_project: p must not alias the output");
+    if (!std::isfinite(dt))
+        return fail(PP_EINVAL, "pp_project: dt must be finite");
+    launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], usx, usy, usz, p,
+                   dt / c->grid.h, ux, uy, uz, c->stream);
+    return check_launch("pp_project");
+}
+
+int pp_solve_adjoint(pp_ctx *c, const double *p, const double *gp, double tol, double *grhs,
+                     double *gbx, double *gby, double *gbz, pp_stats *st)
+{
+    PP_TRY(check_ctx(c));
+    if (!p || !gp || !grhs || !gbx || !gby || !gbz)
+        return fail(PP_EINVAL, "pp_solve_adjoint: NULL array");
+    if (grhs == gp || grhs == p)
+        return fail(PP_EINVAL, "pp_solve_adjoint: g_rhs must not alias p or g_p");
+    if (!(tol > 0.0 && tol < 1.0))
+        return fail(PP_EINVAL, "pp_solve_adjoint: tol must be in (0, 1)");
+    int rc = solve_impl(c, gp, grhs, tol, st, false);
+    if (rc != PP_OK && rc != PP_ENOCONV)
+        return rc;
+    launch_adjoint_faces(c->d, c->bc, grhs, p, 1.0 / (c->grid.h * c->grid.h), gbx, gby, gbz,
+                         c->stream);
+    PP_TRY(check_launch("adjoint faces"));
+    return rc;
+}
+
+int pp_levels(const pp_ctx *c, int32_t *nlevels)
+{
+    PP_TRY(check_ctx(c));
+    if (!nlevels)
+        return fail(PP_EINVAL, "pp_levels: NULL output");
+    *nlevels = c->nlev;
+    return PP_OK;
+}
+
+int pp_level_dims(const pp_ctx *c, int32_t level, int32_t dims[3])
+{
+    PP_TRY(check_ctx(c));
+    if (!dims || level < 0 || level >= c->nlev)
+        return fail(PP_EINVAL, "pp_level_dims: bad level or NULL output");
+    dims[0] = c->ld[level].nx;
+    dims[1] = c->ld[level].ny;
+    dims[2] = c->ld[level].nz;
+    return PP_OK;
+}
+
+int pp_memory(const pp_ctx *c, int64_t *bytes)
+{
+    PP_TRY(check_ctx(c));
+    if (!bytes)
+        return fail(PP_EINVAL, "pp_memory: NULL output");
+    *bytes = c->bytes;
+    return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single-kernel entry points (pp_kernels.h)
+// ---------------------------------------------------------------------------
+
+int pp_k_smooth(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+                const double *r, double *e, int32_t sweeps, int32_t zero_init, void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!bx || !by || !bz || !r || !e)
+        return fail(PP_EINVAL, "pp_k_smooth: NULL array");
+    if (sweeps < 1)
+        return fail(PP_EINVAL, "pp_k_smooth: sweeps must be >= 1");
+    for (int m = 0; m < 3; ++m)
+        if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
+            return fail(PP_EINVAL, "pp_k_smooth: periodic directions need an even cell count");
+    const Dims d = to_dims(grid);
+    const Bc bc = to_bc(grid);
+    const double h2 = grid->h * grid->h;
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        launch_rbgs<double>(d, bc, bx, by, bz, r, e, h2, 0, zero_init && sw == 0, s);
+        launch_rbgs<double>(d, bc, bx, by, bz, r, e, h2, 1, false, s);
+    }
+    return check_launch("pp_k_smooth");
+}
+
+int pp_k_resid_restrict(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+                        const double *e, const double *r, double *rH, void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!bx || !by || !bz || !e || !r || !rH)
+        return fail(PP_EINVAL, "pp_k_resid_restrict: NULL array");
+    for (int m = 0; m < 3; ++m)
+        if (grid->n[m] % 2)
+            return fail(PP_EINVAL, "pp_k_resid_restrict: the fine grid needs even cell counts");
+    launch_resid_restrict<double>(to_dims(grid), to_bc(grid), bx, by, bz, e, r, rH,
+                                  1.0 / (grid->h * grid->h), (hipStream_t)hip_stream);
+    return check_launch("pp_k_resid_restrict");
+}
+
+int pp_k_prolong_add(const pp_grid *grid, const double *eH, double *e, void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!eH || !e)
+        return fail(PP_EINVAL, "pp_k_prolong_add: NULL array");
+    for (int m = 0; m < 3; ++m)
+        if (grid->n[m] % 2)
+            return fail(PP_EINVAL, "pp_k_prolong_add: the fine grid needs even cell counts");
+    launch_prolong<double>(to_dims(grid), to_bc(grid), eH, e, (hipStream_t)hip_stream);
+    return check_launch("pp_k_prolong_add");
+}
+
+int pp_k_coarsen_beta(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+                      double *hx, double *hy, double *hz, void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!bx || !by || !bz || !hx || !hy || !hz)
+        return fail(PP_EINVAL, "pp_k_coarsen_beta: NULL array");
+    for (int m = 0; m < 3; ++m)
+        if (grid->n[m] % 2)
+            return fail(PP_EINVAL, "pp_k_coarsen_beta: the fine grid needs even cell counts");
+    launch_coarsen_beta(to_dims(grid), to_bc(grid), bx, by, bz, hx, hy, hz, (hipStream_t)hip_stream);
+    return check_launch("pp_k_coarsen_beta");
+}
+
+int pp_vcycle(pp_ctx *c, const double *r, double *e)
+{
+    PP_TRY(check_ctx(c));
+    if (!r || !e)
+        return fail(PP_EINVAL, "pp_vcycle: NULL array");
+    Hier &H = (c->opts.precision == PP_FP64) ? c->h64 : c->hmix;
+    LevelBuf &v0 = H.lev[0];
+    switch (H.st) {
+    case ST_F64:
+        launch_copy(r, (double *)v0.r, c->N, c->stream);
+        vcycle_run<double>(c, H);
+        launch_copy((const double *)v0.e, e, c->N, c->stream);
+        break;
+    case ST_F32:
+        launch_convert<float>(c->N, r, (float *)v0.r, c->stream);
+        vcycle_run<float>(c, H);
+        launch_to_double<float>(c->N, (const float *)v0.e, e, c->stream);
+        break;
+    default:
+        launch_convert<_Float16>(c->N, r, (_Float16 *)v0.r, c->stream);
+        vcycle_run<_Float16>(c, H);
+        launch_to_double<_Float16>(c->N, (const _Float16 *)v0.e, e, c->stream);
+        break;
+    }
+    return check_launch("pp_vcycle");
+}
+
+int pp_k_copy(const double *src, double *dst, int64_t count, void *hip_stream)
+{
+    if (!src || !dst || count < 0)
+        return fail(PP_EINVAL, "pp_k_copy: bad arguments");
+    if (count == 0)
+        return PP_OK;
+    launch_copy(src, dst, (size_t)count, (hipStream_t)hip_stream);
+    return check_launch("pp_k_copy");
+}
+
+int pp_timing_enable(pp_ctx *c, int32_t on)
+{
+    PP_TRY(check_ctx(c));
+    if (on && c->ev.empty()) {
+        c->ev.resize(8192);
+        for (auto &e : c->ev) {
+            PP_HIP(hipEventCreate(&e.a));
+            PP_HIP(hipEventCreate(&e.b));
+        }
+    }
+    if (!on)
+        resolve_timing(c);
+    c->timing = on != 0;
+    return PP_OK;
+}
+
+int pp_timing_reset(pp_ctx *c)
+{
+    PP_TRY(check_ctx(c));
+    resolve_timing(c);
+    for (int k = 0; k < PP_KT_COUNT; ++k) {
+        c->kt_count[k] = 0;
+        c->kt_ms[k] = 0.0;
+    }
+    return PP_OK;
+}
+
+int pp_timing_get(pp_ctx *c, int32_t kind, int64_t *launches, double *total_ms)
+{
+    PP_TRY(check_ctx(c));
+    if (kind < 0 || kind >= PP_KT_COUNT || !launches || !total_ms)
+        return fail(PP_EINVAL, "pp_timing_get: bad kind or NULL output");
+    resolve_timing(c);
+    *launches = c->kt_count[kind];
+    *total_ms = c->kt_ms[kind];
+    return PP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// pp_internal.h -- internal declarations shared by the HIP sources of the
+// pressure-projection library (kernels + host driver).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pp {
+
+// Cell kernels run 64 x 4 thread blocks (four 64-wide waves, one x-row
+// segment per wave), with the z index taken from blockIdx.z.
+constexpr int BX = 64;
+constexpr int BY = 4;
+constexpr int BLOCK = BX * BY;
+
+struct Dims {
+    int nx, ny, nz;
+};
+
+// 1 = wall in that direction, 0 = periodic.
+struct Bc {
+    int x, y, z;
+};
+
+inline size_t cells(Dims d) { return (size_t)d.nx * d.ny * d.nz; }
+
+inline dim3 cell_grid(Dims d)
+{
+    return dim3((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);
+}
+
+// grid for kernels that give each thread one cell of one colour
+inline dim3 colour_grid(Dims d)
+{
+    int half = (d.nx + 1) / 2;
+    return dim3((half + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);
+}
+
+inline size_t grid_blocks(dim3 g) { return (size_t)g.x * g.y * g.z; }
+
+// ---------------------------------------------------------------------------
+// scalar slots of the device scalar array used by the outer iterations
+// ---------------------------------------------------------------------------
+enum Slot {
+    S_MEAN = 0,     // mean of the right-hand side
+    S_RR = 1,       // ||r||^2
+    S_BB = 2,       // ||b||^2 (b mean-removed)
+    S_RZ = 3,       // r . z (current)
+    S_RZOLD = 4,    // r_new . z_old (flexible CG)
+    S_ALPHA = 5,
+    S_BETA = 6,
+    S_USED = 7,     // scale of the right-hand side the V-cycle currently holds
+    S_NEXT = 8,     // RMS of the latest residual (scale for the next V-cycle)
+    S_XMEAN = 9,    // mean of the iterate (gauge)
+    S_COUNT = 10,   // generic count (validation)
+    S_DQ = 11,
+    S_NSLOTS = 16
+};
+
+enum FinalizeOp {
+    OP_STORE = 0,   // scal[slot] = sum0
+    OP_MEAN = 1,    // scal[slot] = sum0 / N
+    OP_INIT = 2,    // RR, BB, S_USED = S_NEXT = rms(r)
+    OP_RZ = 3,      // RZ, BETA (flexible Polak-Ribiere)
+    OP_ALPHA = 4,   // ALPHA = RZ / DQ
+    OP_UPDATE = 5,  // RR, RZOLD, rotate scales
+    OP_DC = 6       // RR, rotate scales
+};
+
+// ---------------------------------------------------------------------------
+// launchers (pp_kernels.hip); T is the storage type of V-cycle data
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e, double h2,
+                 int colour, bool zero, hipStream_t s);
+template <typename T>
+void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
+                           const T *r, T *rH, double ih2, hipStream_t s);
+template <typename T>
+void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s);
+template <typename T>
+void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s);
+template <typename T>
+void launch_convert(size_t n, const double *src, T *dst, hipStream_t s);
+template <typename T>
+void launch_to_double(size_t n, const T *src, double *dst, hipStream_t s);
+
+void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, const double *bz,
+                         double *hx, double *hy, double *hz, hipStream_t s);
+void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s);
+void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                       double *part, hipStream_t s);
+void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by, double *bz,
+                        hipStream_t s);
+void launch_divergence(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
+                       double scale_over_h, double *out, hipStream_t s);
+void launch_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                  const double *x, double *y, double ih2, hipStream_t s);
+void launch_project(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                    const double *usx, const double *usy, const double *usz, const double *p,
+                    double dt_over_h, double *ux, double *uy, double *uz, hipStream_t s);
+void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, double ih2,
+                          double *gx, double *gy, double *gz, hipStream_t s);
+void launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+void launch_fill(double *x, size_t n, double v, hipStream_t s);
+
+// reductions and outer-loop kernels (FP64); `part` holds one partial sum per
+// block and quantity, quantity q at part[q * pstride + block]
+void launch_sum(Dims d, const double *x, double *part, hipStream_t s);
+void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
+                     double ncells, int first, double *scal, hipStream_t s);
+void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                     const double *b, const double *scal, double *x, bool zero_x, double *r64,
+                     double ih2, double *part, size_t pstride, hipStream_t s);
+template <typename T>
+void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                       const double *b, const double *scal, const double *x, T *rT, double ih2,
+                       double *part, hipStream_t s);
+template <typename T>
+void launch_scale_T(size_t n, const double *r, T *rT, const double *scal, hipStream_t s);
+template <typename T>
+void launch_axpy_T(size_t n, const T *e, double *x, const double *scal, hipStream_t s);
+template <typename T>
+void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_t s);
+template <typename T>
+void launch_pcg_dir(size_t n, const T *z, double *dvec, const double *scal, bool first,
+                    hipStream_t s);
+void launch_apply_dot(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                      const double *dvec, double *q, double ih2, double *part, hipStream_t s);
+template <typename T>
+void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, double *r, T *rT,
+                       const T *zold, const double *scal, double *part, size_t pstride,
+                       hipStream_t s);
+void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStream_t s);
+
+}  // namespace pp

@@ -1,0 +1,923 @@
+// pp_kernels.hip -- HIP kernels (gfx950) of the pressure-projection library.
+//
+// Discretisation (paper Sec. 3.1, Sec. 3.7.1): cell-centred p on a MAC grid
+// with cubic cells of edge h; face coefficient beta = 1/rho; the operator
+//   (A x)_c = sum_m [ beta_m(c+e_m) (x_{c+e_m} - x_c) - beta_m(c) (x_c - x_{c-e_m}) ] / h^2
+// is the seven-point system of Sec. 3.7.1 (A1..A6 = beta/h^2, A7 = their sum).
+// Walls (Sec. 3.8) zero the link coefficient of the wall face.  Every kernel
+// masks wall links explicitly from the grid's bc, so stored wall entries are
+// never used; periodic neighbours wrap.
+//
+// The kernels are memory-bound stencils: one thread per cell (or per cell of
+// one colour), 64-wide rows in x so each wave reads contiguous x segments,
+// neighbours in y and z served by L2.  Reductions are two-stage and fixed
+// order (wave shuffle -> LDS -> one partial per block -> one finalising
+// block), so every result is bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "pp_internal.h"
+
+namespace pp {
+
+template <typename T>
+struct Acc {
+    using type = float;   // FP32 arithmetic for FP32 and FP16 storage
+};
+template <>
+struct Acc<double> {
+    using type = double;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Acc<T>::type ld(const T *p, size_t i)
+{
+    return static_cast<typename Acc<T>::type>(p[i]);
+}
+
+struct Nb {
+    size_t c, xm, xp, ym, yp, zm, zp;
+    bool wxl, wxh, wyl, wyh, wzl, wzh;   // link crosses a wall
+};
+
+__device__ __forceinline__ Nb neighbours(Dims d, Bc bc, int i, int j, int k)
+{
+    const size_t sy = (size_t)d.nx;
+    const size_t sz = (size_t)d.nx * d.ny;
+    Nb n;
+    n.c = (size_t)k * sz + (size_t)j * sy + (size_t)i;
+    const size_t row = n.c - (size_t)i;
+    n.xm = row + (size_t)(i == 0 ? d.nx - 1 : i - 1);
+    n.xp = row + (size_t)(i == d.nx - 1 ? 0 : i + 1);
+    const size_t col = n.c - (size_t)j * sy;
+    n.ym = col + (size_t)(j == 0 ? d.ny - 1 : j - 1) * sy;
+    n.yp = col + (size_t)(j == d.ny - 1 ? 0 : j + 1) * sy;
+    const size_t pil = n.c - (size_t)k * sz;
+    n.zm = pil + (size_t)(k == 0 ? d.nz - 1 : k - 1) * sz;
+    n.zp = pil + (size_t)(k == d.nz - 1 ? 0 : k + 1) * sz;
+    n.wxl = bc.x && i == 0;
+    n.wxh = bc.x && i == d.nx - 1;
+    n.wyl = bc.y && j == 0;
+    n.wyh = bc.y && j == d.ny - 1;
+    n.wzl = bc.z && k == 0;
+    n.wzh = bc.z && k == d.nz - 1;
+    return n;
+}
+
+// the six link coefficients of a cell (0 across walls)
+template <typename T>
+struct Links {
+    typename Acc<T>::type xl, xh, yl, yh, zl, zh;
+};
+
+template <typename T>
+__device__ __forceinline__ Links<T> links(const Nb &n, const T *bx, const T *by, const T *bz)
+{
+    using C = typename Acc<T>::type;
+    Links<T> L;
+    L.xl = n.wxl ? C(0) : ld(bx, n.c);
+    L.xh = n.wxh ? C(0) : ld(bx, n.xp);
+    L.yl = n.wyl ? C(0) : ld(by, n.c);
+    L.yh = n.wyh ? C(0) : ld(by, n.yp);
+    L.zl = n.wzl ? C(0) : ld(bz, n.c);
+    L.zh = n.wzh ? C(0) : ld(bz, n.zp);
+    return L;
+}
+
+// h^2 (A x)_c
+template <typename T, typename X>
+__device__ __forceinline__ typename Acc<T>::type flux_sum(const Nb &n, const Links<T> &L, const X *x)
+{
+    using C = typename Acc<T>::type;
+    const C xc = static_cast<C>(x[n.c]);
+    return L.xh * (static_cast<C>(x[n.xp]) - xc) - L.xl * (xc - static_cast<C>(x[n.xm])) +
+           L.yh * (static_cast<C>(x[n.yp]) - xc) - L.yl * (xc - static_cast<C>(x[n.ym])) +
+           L.zh * (static_cast<C>(x[n.zp]) - xc) - L.zl * (xc - static_cast<C>(x[n.zm]));
+}
+
+// one partial sum per block and quantity, in a fixed order
+template <int NQ>
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double (*sm)[BLOCK / 64],
+                                               double *part, size_t pstride)
+{
+    const int lane = threadIdx.x + BX * threadIdx.y;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            x += __shfl_xor(x, o, 64);
+        if ((lane & 63) == 0)
+            sm[q][lane >> 6] = x;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const size_t blin =
+            blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            part[(size_t)q * pstride + blin] = (sm[q][0] + sm[q][1]) + (sm[q][2] + sm[q][3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle kernels (templated on the storage type)
+// ---------------------------------------------------------------------------
+
+// One colour of red-black Gauss-Seidel (eq. beta_pressure with relaxation 1):
+// e_c <- (sum beta e_nb - h^2 r_c) / sum beta.  ZERO: e is zero on entry.
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restrict__ bx,
+                                                const T *__restrict__ by,
+                                                const T *__restrict__ bz,
+                                                const T *__restrict__ r, T *e,
+                                                typename Acc<T>::type h2, int colour)
+{
+    using C = typename Acc<T>::type;
+    const int t = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (j >= d.ny)
+        return;
+    const int i = 2 * t + ((j + k + colour) & 1);
+    if (i >= d.nx)
+        return;
+    const Nb n = neighbours(d, bc, i, j, k);
+    const Links<T> L = links(n, bx, by, bz);
+    const C diag = (L.xl + L.xh) + (L.yl + L.yh) + (L.zl + L.zh);
+    C s = C(0);
+    if (!ZERO) {
+        s = L.xl * ld(e, n.xm) + L.xh * ld(e, n.xp) + L.yl * ld(e, n.ym) + L.yh * ld(e, n.yp) +
+            L.zl * ld(e, n.zm) + L.zh * ld(e, n.zp);
+    }
+    e[n.c] = static_cast<T>((s - h2 * ld(r, n.c)) / diag);
+}
+
+// rH = mean over the 8 children of (r - A e); one thread per coarse cell.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const T *__restrict__ bx,
+                                                          const T *__restrict__ by,
+                                                          const T *__restrict__ bz,
+                                                          const T *__restrict__ e,
+                                                          const T *__restrict__ r,
+                                                          T *__restrict__ rH,
+                                                          typename Acc<T>::type ih2)
+{
+    using C = typename Acc<T>::type;
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int I = blockIdx.x * BX + threadIdx.x;
+    const int J = blockIdx.y * BY + threadIdx.y;
+    const int K = blockIdx.z;
+    if (I >= cd.nx || J >= cd.ny)
+        return;
+    C acc = C(0);
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+                const Nb n = neighbours(fd, bc, 2 * I + di, 2 * J + dj, 2 * K + dk);
+                const Links<T> L = links(n, bx, by, bz);
+                acc += ld(r, n.c) - ih2 * flux_sum(n, L, e);
+            }
+    rH[((size_t)K * cd.ny + J) * cd.nx + I] = static_cast<T>(acc * C(0.125));
+}
+
+__device__ __forceinline__ int other_parent(int i, int nH, int wall)
+{
+    const int I = i >> 1;
+    int o = (i & 1) ? I + 1 : I - 1;
+    if (o < 0 || o >= nH)
+        o = wall ? I : (o + nH) % nH;
+    return o;
+}
+
+// e += P eH: cell-centred trilinear interpolation (3/4 parent, 1/4 the next
+// coarse cell on the fine cell's side, per axis).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_prolong(Dims fd, Bc bc, const T *__restrict__ eH,
+                                                   T *__restrict__ e)
+{
+    using C = typename Acc<T>::type;
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= fd.nx || j >= fd.ny)
+        return;
+    const int I0 = i >> 1, I1 = other_parent(i, cd.nx, bc.x);
+    const int J0 = j >> 1, J1 = other_parent(j, cd.ny, bc.y);
+    const int K0 = k >> 1, K1 = other_parent(k, cd.nz, bc.z);
+    const size_t sy = cd.nx, sz = (size_t)cd.nx * cd.ny;
+    const size_t k0 = K0 * sz, k1 = K1 * sz, j0 = J0 * sy, j1 = J1 * sy;
+    const C a = C(0.75), b = C(0.25);
+    const C x00 = a * ld(eH, k0 + j0 + I0) + b * ld(eH, k0 + j0 + I1);
+    const C x01 = a * ld(eH, k0 + j1 + I0) + b * ld(eH, k0 + j1 + I1);
+    const C x10 = a * ld(eH, k1 + j0 + I0) + b * ld(eH, k1 + j0 + I1);
+    const C x11 = a * ld(eH, k1 + j1 + I0) + b * ld(eH, k1 + j1 + I1);
+    const C v = a * (a * x00 + b * x01) + b * (a * x10 + b * x11);
+    const size_t c = ((size_t)k * fd.ny + j) * fd.nx + i;
+    e[c] = static_cast<T>(ld(e, c) + v);
+}
+
+// Coarsest level: e = A^+ r with the FP64 pseudo-inverse (symmetric, n <= 1024).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarsest(int n, const double *__restrict__ pinv,
+                                                   const T *__restrict__ r, T *__restrict__ e)
+{
+    __shared__ double rs[1024];
+    for (int t = threadIdx.x; t < n; t += blockDim.x)
+        rs[t] = static_cast<double>(r[t]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double s = 0.0;
+        for (int jj = 0; jj < n; ++jj)
+            s += pinv[(size_t)jj * n + i] * rs[jj];
+        e[i] = static_cast<T>(s);
+    }
+}
+
+template <typename T>
+__global__ void k_convert(size_t n, const double *__restrict__ src, T *__restrict__ dst)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = static_cast<T>(src[i]);
+}
+
+template <typename T>
+__global__ void k_to_double(size_t n, const T *__restrict__ src, double *__restrict__ dst)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = static_cast<double>(src[i]);
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels (FP64)
+// ---------------------------------------------------------------------------
+
+// coarse beta = mean of the 4 fine faces of a coarse face; wall faces stay 0
+__global__ __launch_bounds__(BLOCK) void k_coarsen_beta(Dims fd, Bc bc, const double *__restrict__ bx,
+                                                        const double *__restrict__ by,
+                                                        const double *__restrict__ bz,
+                                                        double *__restrict__ hx,
+                                                        double *__restrict__ hy,
+                                                        double *__restrict__ hz)
+{
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int I = blockIdx.x * BX + threadIdx.x;
+    const int J = blockIdx.y * BY + threadIdx.y;
+    const int K = blockIdx.z;
+    if (I >= cd.nx || J >= cd.ny)
+        return;
+    const size_t sy = fd.nx, sz = (size_t)fd.nx * fd.ny;
+    const size_t f = (size_t)(2 * K) * sz + (size_t)(2 * J) * sy + (size_t)(2 * I);
+    const size_t C = ((size_t)K * cd.ny + J) * cd.nx + I;
+    // x faces: fine i = 2I, (j, k) in {2J, 2J+1} x {2K, 2K+1}
+    hx[C] = (bc.x && I == 0) ? 0.0 : 0.25 * ((bx[f] + bx[f + sy]) + (bx[f + sz] + bx[f + sz + sy]));
+    hy[C] = (bc.y && J == 0) ? 0.0 : 0.25 * ((by[f] + by[f + 1]) + (by[f + sz] + by[f + sz + 1]));
+    hz[C] = (bc.z && K == 0) ? 0.0 : 0.25 * ((bz[f] + bz[f + 1]) + (bz[f + sy] + bz[f + sy + 1]));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny)
+        return;
+    const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+    if (bc.x && i == 0)
+        bx[c] = 0.0;
+    if (bc.y && j == 0)
+        by[c] = 0.0;
+    if (bc.z && k == 0)
+        bz[c] = 0.0;
+}
+
+// counts non-wall faces whose beta is not a finite positive number
+__global__ __launch_bounds__(BLOCK) void k_check_beta(Dims d, Bc bc, const double *__restrict__ bx,
+                                                      const double *__restrict__ by,
+                                                      const double *__restrict__ bz, double *part)
+{
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny) {
+        const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+        const double b[3] = {bx[c], by[c], bz[c]};
+        const bool wall[3] = {bc.x && i == 0, bc.y && j == 0, bc.z && k == 0};
+        for (int m = 0; m < 3; ++m)
+            if (!wall[m] && !(b[m] > 0.0 && b[m] < INFINITY))
+                v[0] += 1.0;
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
+// beta_m[c] = 2 / (rho[c - e_m] + rho[c]); 0 on wall faces
+__global__ __launch_bounds__(BLOCK) void k_face_coeffs(Dims d, Bc bc, const double *__restrict__ rho,
+                                                       double *__restrict__ bx,
+                                                       double *__restrict__ by,
+                                                       double *__restrict__ bz)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny)
+        return;
+    const Nb n = neighbours(d, bc, i, j, k);
+    const double rc = rho[n.c];
+    bx[n.c] = (bc.x && i == 0) ? 0.0 : 2.0 / (rho[n.xm] + rc);
+    by[n.c] = (bc.y && j == 0) ? 0.0 : 2.0 / (rho[n.ym] + rc);
+    bz[n.c] = (bc.z && k == 0) ? 0.0 : 2.0 / (rho[n.zm] + rc);
+}
+
+// out = scale/h * sum_m (u_m(high face) - u_m(low face)), wall faces 0
+__global__ __launch_bounds__(BLOCK) void k_divergence(Dims d, Bc bc, const double *__restrict__ ux,
+                                                      const double *__restrict__ uy,
+                                                      const double *__restrict__ uz, double s_h,
+                                                      double *__restrict__ out)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny)
+        return;
+    const Nb n = neighbours(d, bc, i, j, k);
+    const double xl = n.wxl ? 0.0 : ux[n.c], xh = n.wxh ? 0.0 : ux[n.xp];
+    const double yl = n.wyl ? 0.0 : uy[n.c], yh = n.wyh ? 0.0 : uy[n.yp];
+    const double zl = n.wzl ? 0.0 : uz[n.c], zh = n.wzh ? 0.0 : uz[n.zp];
+    out[n.c] = s_h * ((xh - xl) + (yh - yl) + (zh - zl));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_apply(Dims d, Bc bc, const double *__restrict__ bx,
+                                                 const double *__restrict__ by,
+                                                 const double *__restrict__ bz,
+                                                 const double *__restrict__ x,
+                                                 double *__restrict__ y, double ih2)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny)
+        return;
+    const Nb n = neighbours(d, bc, i, j, k);
+    const Links<double> L = links(n, bx, by, bz);
+    y[n.c] = ih2 * flux_sum(n, L, x);
+}
+
+// u_m = us_m - dt beta_m G_m p on non-wall faces, 0 on wall faces (eq. fotm).
+// u may alias us: each thread reads and writes only its own entries.
+__global__ __launch_bounds__(BLOCK) void k_project(Dims d, Bc bc, const double *__restrict__ bx,
+                                                   const double *__restrict__ by,
+                                                   const double *__restrict__ bz,
+                                                   const double *usx, const double *usy,
+                                                   const double *usz, const double *__restrict__ p,
+                                                   double dt_h, double *ux, double *uy, double *uz)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny)
+        return;
+    const Nb n = neighbours(d, bc, i, j, k);
+    const double pc = p[n.c];
+    const double vx = n.wxl ? 0.0 : usx[n.c] - dt_h * bx[n.c] * (pc - p[n.xm]);
+    const double vy = n.wyl ? 0.0 : usy[n.c] - dt_h * by[n.c] * (pc - p[n.ym]);
+    const double vz = n.wzl ? 0.0 : usz[n.c] - dt_h * bz[n.c] * (pc - p[n.zm]);
+    ux[n.c] = vx;
+    uy[n.c] = vy;
+    uz[n.c] = vz;
+}
+
+// g_beta_m = G_m lambda * G_m p on non-wall faces, 0 on walls
+__global__ __launch_bounds__(BLOCK) void k_adjoint_faces(Dims d, Bc bc, const double *__restrict__ lam,
+                                                         const double *__restrict__ p, double ih2,
+                                                         double *__restrict__ gx,
+                                                         double *__restrict__ gy,
+                                                         double *__restrict__ gz)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny)
+        return;
+    const Nb n = neighbours(d, bc, i, j, k);
+    const double lc = lam[n.c], pc = p[n.c];
+    gx[n.c] = n.wxl ? 0.0 : ih2 * (lc - lam[n.xm]) * (pc - p[n.xm]);
+    gy[n.c] = n.wyl ? 0.0 : ih2 * (lc - lam[n.ym]) * (pc - p[n.ym]);
+    gz[n.c] = n.wzl ? 0.0 : ih2 * (lc - lam[n.zm]) * (pc - p[n.zm]);
+}
+
+__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_fill(double *__restrict__ x, size_t n, double v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// outer-loop kernels (FP64) and reductions
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(BLOCK) void k_sum(Dims d, const double *__restrict__ x, double *part)
+{
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny)
+        v[0] = x[((size_t)k * d.ny + j) * d.nx + i];
+    block_partials<1>(v, sm, part, 0);
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ part, size_t pstride,
+                                                   int nparts, int op, int slot, double ncells,
+                                                   int first, double *scal)
+{
+    __shared__ double sm[2][1024];
+    const int nq = (op == OP_INIT || op == OP_UPDATE) ? 2 : 1;
+    const int t = threadIdx.x;
+    for (int q = 0; q < 2; ++q) {
+        double acc = 0.0;
+        if (q < nq)
+            for (int i = t; i < nparts; i += 1024)
+                acc += part[(size_t)q * pstride + i];
+        sm[q][t] = acc;
+    }
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) {
+            sm[0][t] += sm[0][t + w];
+            sm[1][t] += sm[1][t + w];
+        }
+        __syncthreads();
+    }
+    if (t != 0)
+        return;
+    const double s0 = sm[0][0], s1 = sm[1][0];
+    double rms;
+    switch (op) {
+    case OP_STORE:
+        scal[slot] = s0;
+        break;
+    case OP_MEAN:
+        scal[slot] = s0 / ncells;
+        break;
+    case OP_INIT:
+        scal[S_RR] = s0;
+        scal[S_BB] = s1;
+        rms = sqrt(s0 / ncells);
+        if (!(rms > 0.0) || !(rms < INFINITY))
+            rms = 1.0;
+        scal[S_USED] = rms;
+        scal[S_NEXT] = rms;
+        break;
+    case OP_RZ: {
+        const double rz = scal[S_USED] * s0;
+        scal[S_BETA] = first ? 0.0 : (rz - scal[S_RZOLD]) / scal[S_RZ];
+        scal[S_RZ] = rz;
+        break;
+    }
+    case OP_ALPHA:
+        scal[S_DQ] = s0;
+        scal[S_ALPHA] = scal[S_RZ] / s0;
+        break;
+    case OP_UPDATE:
+        scal[S_RR] = s0;
+        scal[S_RZOLD] = scal[S_USED] * s1;
+        scal[S_USED] = scal[S_NEXT];
+        rms = sqrt(s0 / ncells);
+        scal[S_NEXT] = (rms > 0.0 && rms < INFINITY) ? rms : 1.0;
+        break;
+    case OP_DC:
+        scal[S_RR] = s0;
+        scal[S_USED] = scal[S_NEXT];
+        rms = sqrt(s0 / ncells);
+        scal[S_NEXT] = (rms > 0.0 && rms < INFINITY) ? rms : 1.0;
+        break;
+    default:
+        break;
+    }
+}
+
+// r = (b - mean b) - A x; partials ||r||^2 and ||b - mean b||^2.
+// ZEROX: x is set to zero (cold start) and A x is skipped.
+template <bool ZEROX>
+__global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double *__restrict__ bx,
+                                                    const double *__restrict__ by,
+                                                    const double *__restrict__ bz,
+                                                    const double *__restrict__ b,
+                                                    const double *__restrict__ scal, double *x,
+                                                    double *__restrict__ r64, double ih2,
+                                                    double *part, size_t pstride)
+{
+    __shared__ double sm[2][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    double v[2] = {0.0, 0.0};
+    if (i < d.nx && j < d.ny) {
+        const Nb n = neighbours(d, bc, i, j, k);
+        const double bm = b[n.c] - scal[S_MEAN];
+        double ax = 0.0;
+        if (ZEROX) {
+            x[n.c] = 0.0;
+        } else {
+            const Links<double> L = links(n, bx, by, bz);
+            ax = ih2 * flux_sum(n, L, x);
+        }
+        const double r = bm - ax;
+        r64[n.c] = r;
+        v[0] = r * r;
+        v[1] = bm * bm;
+    }
+    block_partials<2>(v, sm, part, pstride);
+}
+
+// defect-correction residual: rT = ((b - mean b) - A x) / scal[S_NEXT]; partial ||r||^2
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_residual_T(Dims d, Bc bc, const double *__restrict__ bx,
+                                                      const double *__restrict__ by,
+                                                      const double *__restrict__ bz,
+                                                      const double *__restrict__ b,
+                                                      const double *__restrict__ scal,
+                                                      const double *__restrict__ x,
+                                                      T *__restrict__ rT, double ih2, double *part)
+{
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny) {
+        const Nb n = neighbours(d, bc, i, j, k);
+        const Links<double> L = links(n, bx, by, bz);
+        const double r = (b[n.c] - scal[S_MEAN]) - ih2 * flux_sum(n, L, x);
+        rT[n.c] = static_cast<T>(r / scal[S_NEXT]);
+        v[0] = r * r;
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
+template <typename T>
+__global__ void k_scale_T(size_t n, const double *__restrict__ r, T *__restrict__ rT,
+                          const double *__restrict__ scal)
+{
+    const double inv = 1.0 / scal[S_USED];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        rT[i] = static_cast<T>(r[i] * inv);
+}
+
+// x += scal[S_USED] * e
+template <typename T>
+__global__ void k_axpy_T(size_t n, const T *__restrict__ e, double *__restrict__ x,
+                         const double *__restrict__ scal)
+{
+    const double s = scal[S_USED];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] += s * static_cast<double>(e[i]);
+}
+
+// partial r . z (z in storage precision; the scale is applied when finalising)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_dot_rz(Dims d, const double *__restrict__ r,
+                                                  const T *__restrict__ z, double *part)
+{
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny) {
+        const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+        v[0] = r[c] * static_cast<double>(z[c]);
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
+// d = s z + beta d  (first iteration: d = s z)
+template <typename T, bool FIRST>
+__global__ void k_pcg_dir(size_t n, const T *__restrict__ z, double *__restrict__ dv,
+                          const double *__restrict__ scal)
+{
+    const double s = scal[S_USED];
+    const double beta = scal[S_BETA];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double zz = s * static_cast<double>(z[i]);
+        dv[i] = FIRST ? zz : zz + beta * dv[i];
+    }
+}
+
+// q = A d; partial d . q
+__global__ __launch_bounds__(BLOCK) void k_apply_dot(Dims d, Bc bc, const double *__restrict__ bx,
+                                                     const double *__restrict__ by,
+                                                     const double *__restrict__ bz,
+                                                     const double *__restrict__ dv,
+                                                     double *__restrict__ q, double ih2,
+                                                     double *part)
+{
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny) {
+        const Nb n = neighbours(d, bc, i, j, k);
+        const Links<double> L = links(n, bx, by, bz);
+        const double qq = ih2 * flux_sum(n, L, dv);
+        q[n.c] = qq;
+        v[0] = dv[n.c] * qq;
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
+// x += alpha d; r -= alpha q; rT = r / scal[S_NEXT];
+// partials ||r||^2 and r . z_old (z_old unscaled, storage precision)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__restrict__ dv,
+                                                      const double *__restrict__ q,
+                                                      double *__restrict__ x,
+                                                      double *__restrict__ r, T *__restrict__ rT,
+                                                      const T *__restrict__ zold,
+                                                      const double *__restrict__ scal,
+                                                      double *part, size_t pstride)
+{
+    __shared__ double sm[2][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    double v[2] = {0.0, 0.0};
+    if (i < d.nx && j < d.ny) {
+        const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+        const double alpha = scal[S_ALPHA];
+        x[c] += alpha * dv[c];
+        const double rn = r[c] - alpha * q[c];
+        r[c] = rn;
+        rT[c] = static_cast<T>(rn / scal[S_NEXT]);
+        v[0] = rn * rn;
+        v[1] = rn * static_cast<double>(zold[c]);
+    }
+    block_partials<2>(v, sm, part, pstride);
+}
+
+__global__ void k_sub_mean(size_t n, double *__restrict__ x, const double *__restrict__ scal, int slot)
+{
+    const double m = scal[slot];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] -= m;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline dim3 flat_grid(size_t n)
+{
+    size_t b = (n + 255) / 256;
+    if (b > 16384)
+        b = 16384;
+    if (b == 0)
+        b = 1;
+    return dim3((unsigned)b);
+}
+
+static const dim3 kBlock(BX, BY, 1);
+
+template <typename T>
+void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e, double h2,
+                 int colour, bool zero, hipStream_t s)
+{
+    using C = typename Acc<T>::type;
+    if (zero)
+        hipLaunchKernelGGL((k_rbgs<T, true>), colour_grid(d), kBlock, 0, s, d, bc, bx, by, bz, r, e,
+                           (C)h2, colour);
+    else
+        hipLaunchKernelGGL((k_rbgs<T, false>), colour_grid(d), kBlock, 0, s, d, bc, bx, by, bz, r,
+                           e, (C)h2, colour);
+}
+
+template <typename T>
+void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
+                           const T *r, T *rH, double ih2, hipStream_t s)
+{
+    using C = typename Acc<T>::type;
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    hipLaunchKernelGGL((k_resid_restrict<T>), cell_grid(cd), kBlock, 0, s, fd, bc, bx, by, bz, e, r,
+                       rH, (C)ih2);
+}
+
+template <typename T>
+void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_prolong<T>), cell_grid(fd), kBlock, 0, s, fd, bc, eH, e);
+}
+
+template <typename T>
+void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s)
+{
+    int threads = ((n + 63) / 64) * 64;
+    if (threads > 1024)
+        threads = 1024;
+    hipLaunchKernelGGL((k_coarsest<T>), dim3(1), dim3(threads), 0, s, n, pinv, r, e);
+}
+
+template <typename T>
+void launch_convert(size_t n, const double *src, T *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_convert<T>), flat_grid(n), dim3(256), 0, s, n, src, dst);
+}
+
+template <typename T>
+void launch_to_double(size_t n, const T *src, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_to_double<T>), flat_grid(n), dim3(256), 0, s, n, src, dst);
+}
+
+void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, const double *bz,
+                         double *hx, double *hy, double *hz, hipStream_t s)
+{
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    hipLaunchKernelGGL(k_coarsen_beta, cell_grid(cd), kBlock, 0, s, fd, bc, bx, by, bz, hx, hy, hz);
+}
+
+void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_walls, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz);
+}
+
+void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                       double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_beta, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, part);
+}
+
+void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by, double *bz,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_face_coeffs, cell_grid(d), kBlock, 0, s, d, bc, rho, bx, by, bz);
+}
+
+void launch_divergence(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
+                       double scale_over_h, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_divergence, cell_grid(d), kBlock, 0, s, d, bc, ux, uy, uz, scale_over_h,
+                       out);
+}
+
+void launch_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                  const double *x, double *y, double ih2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_apply, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, x, y, ih2);
+}
+
+void launch_project(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                    const double *usx, const double *usy, const double *usz, const double *p,
+                    double dt_over_h, double *ux, double *uy, double *uz, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_project, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, usx, usy, usz, p,
+                       dt_over_h, ux, uy, uz);
+}
+
+void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, double ih2,
+                          double *gx, double *gy, double *gz, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adjoint_faces, cell_grid(d), kBlock, 0, s, d, bc, lam, p, ih2, gx, gy, gz);
+}
+
+void launch_copy(const double *src, double *dst, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, flat_grid(n), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_fill(double *x, size_t n, double v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, flat_grid(n), dim3(256), 0, s, x, n, v);
+}
+
+void launch_sum(Dims d, const double *x, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum, cell_grid(d), kBlock, 0, s, d, x, part);
+}
+
+void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
+                     double ncells, int first, double *scal, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, part, pstride, nparts, op, slot,
+                       ncells, first, scal);
+}
+
+void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                     const double *b, const double *scal, double *x, bool zero_x, double *r64,
+                     double ih2, double *part, size_t pstride, hipStream_t s)
+{
+    if (zero_x)
+        hipLaunchKernelGGL(k_residual<true>, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal,
+                           x, r64, ih2, part, pstride);
+    else
+        hipLaunchKernelGGL(k_residual<false>, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b,
+                           scal, x, r64, ih2, part, pstride);
+}
+
+template <typename T>
+void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                       const double *b, const double *scal, const double *x, T *rT, double ih2,
+                       double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_residual_T<T>), cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal, x,
+                       rT, ih2, part);
+}
+
+template <typename T>
+void launch_scale_T(size_t n, const double *r, T *rT, const double *scal, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_scale_T<T>), flat_grid(n), dim3(256), 0, s, n, r, rT, scal);
+}
+
+template <typename T>
+void launch_axpy_T(size_t n, const T *e, double *x, const double *scal, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_axpy_T<T>), flat_grid(n), dim3(256), 0, s, n, e, x, scal);
+}
+
+template <typename T>
+void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_dot_rz<T>), cell_grid(d), kBlock, 0, s, d, r, z, part);
+}
+
+template <typename T>
+void launch_pcg_dir(size_t n, const T *z, double *dvec, const double *scal, bool first,
+                    hipStream_t s)
+{
+    if (first)
+        hipLaunchKernelGGL((k_pcg_dir<T, true>), flat_grid(n), dim3(256), 0, s, n, z, dvec, scal);
+    else
+        hipLaunchKernelGGL((k_pcg_dir<T, false>), flat_grid(n), dim3(256), 0, s, n, z, dvec, scal);
+}
+
+void launch_apply_dot(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                      const double *dvec, double *q, double ih2, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_apply_dot, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, dvec, q, ih2,
+                       part);
+}
+
+template <typename T>
+void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, double *r, T *rT,
+                       const T *zold, const double *scal, double *part, size_t pstride,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pcg_update<T>), cell_grid(d), kBlock, 0, s, d, dvec, q, x, r, rT, zold,
+                       scal, part, pstride);
+}
+
+void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_mean, flat_grid(n), dim3(256), 0, s, n, x, scal, slot);
+}
+
+// explicit instantiations for the three storage types
+#define PP_INSTANTIATE(T)                                                                        \
+    template void launch_rbgs<T>(Dims, Bc, const T *, const T *, const T *, const T *, T *,     \
+                                 double, int, bool, hipStream_t);                               \
+    template void launch_resid_restrict<T>(Dims, Bc, const T *, const T *, const T *, const T *, \
+                                           const T *, T *, double, hipStream_t);                \
+    template void launch_prolong<T>(Dims, Bc, const T *, T *, hipStream_t);                     \
+    template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
+    template void launch_convert<T>(size_t, const double *, T *, hipStream_t);                  \
+    template void launch_to_double<T>(size_t, const T *, double *, hipStream_t);                \
+    template void launch_residual_T<T>(Dims, Bc, const double *, const double *, const double *, \
+                                       const double *, const double *, const double *, T *,     \
+                                       double, double *, hipStream_t);                          \
+    template void launch_scale_T<T>(size_t, const double *, T *, const double *, hipStream_t);  \
+    template void launch_axpy_T<T>(size_t, const T *, double *, const double *, hipStream_t);   \
+    template void launch_dot_rz<T>(Dims, const double *, const T *, double *, hipStream_t);     \
+    template void launch_pcg_dir<T>(size_t, const T *, double *, const double *, bool,          \
+                                    hipStream_t);                                               \
+    template void launch_pcg_update<T>(Dims, const double *, const double *, double *, double *, \
+                                       T *, const T *, const double *, double *, size_t,        \
+                                       hipStream_t);
+
+PP_INSTANTIATE(double)
+PP_INSTANTIATE(float)
+PP_INSTANTIATE(_Float16)
+
+}  // namespace pp

@@ -1,0 +1,283 @@
+"""Python binding of the pressure-projection library.
+
+Argument marshalling only: every computation runs in the HIP kernels of
+libpp.so.  PyTorch provides device memory (CUDA/HIP tensors) and the stream.
+All arrays are float64 CUDA tensors of shape (nz, ny, nx), contiguous; face
+arrays use the low-face convention of include/pp.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.PP_FP64, "fp32": L.PP_MIXED_FP32, "fp16": L.PP_MIXED_FP16}
+OUTERS = {"pcg": L.PP_OUTER_PCG, "dc": L.PP_OUTER_DC}
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_field(t: torch.Tensor, shape, name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64 (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_grid(shape: Sequence[int], h: float, bc: Sequence[int]) -> L.Grid:
+    """shape is (nz, ny, nx); bc is (bc_x, bc_y, bc_z) with 0 periodic, 1 wall."""
+    nz, ny, nx = (int(v) for v in shape)
+    g = L.Grid()
+    g.n[0], g.n[1], g.n[2] = nx, ny, nz
+    g.h = float(h)
+    for m in range(3):
+        g.bc[m] = int(bc[m])
+    return g
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def face_coeffs(rho: torch.Tensor, h: float, bc: Sequence[int],
+                out: Optional[Tuple[torch.Tensor, ...]] = None):
+    """beta_m = 2 / (rho_L + rho_R) on every face, 0 on wall faces."""
+    lib = L.load()
+    g = make_grid(rho.shape, h, bc)
+    _check_field(rho, rho.shape, "rho")
+    if out is None:
+        out = tuple(torch.empty_like(rho) for _ in range(3))
+    for m, t in enumerate(out):
+        _check_field(t, rho.shape, f"beta[{m}]")
+    L.check(lib.pp_face_coeffs(ctypes.byref(g), _ptr(rho), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
+                               _stream_handle(None)), "pp_face_coeffs")
+    return out
+
+
+class Solver:
+    """A solver context for one set of face coefficients beta = 1/rho_f."""
+
+    def __init__(self, beta: Sequence[torch.Tensor], h: float, bc: Sequence[int],
+                 precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
+                 max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
+                 stream: Optional[torch.cuda.Stream] = None):
+        lib = L.load()
+        self._lib = lib
+        self.shape = tuple(beta[0].shape)
+        for m, t in enumerate(beta):
+            _check_field(t, self.shape, f"beta[{m}]")
+        self.h = float(h)
+        self.bc = tuple(int(v) for v in bc)
+        self.grid = make_grid(self.shape, h, bc)
+        o = L.Opts()
+        lib.pp_opts_default(ctypes.byref(o))
+        o.precision = PRECISIONS[precision]
+        o.outer = OUTERS[outer]
+        o.nu_pre = nu_pre
+        o.nu_post = nu_post
+        o.max_outer = max_outer
+        o.warm_start = int(bool(warm_start))
+        o.fallback = int(bool(fallback))
+        self.opts = o
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ctx = ctypes.c_void_p()
+        L.check(lib.pp_setup(ctypes.byref(self.grid), _ptr(beta[0]), _ptr(beta[1]), _ptr(beta[2]),
+                             ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
+                             ctypes.byref(self._ctx)), "pp_setup")
+        self.last_stats = None
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self) -> None:
+        if self._ctx:
+            self._lib.pp_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries ----------------------------------------------------------
+    @property
+    def levels(self) -> int:
+        n = ctypes.c_int32()
+        L.check(self._lib.pp_levels(self._ctx, ctypes.byref(n)), "pp_levels")
+        return n.value
+
+    def level_dims(self, level: int) -> Tuple[int, int, int]:
+        d = (ctypes.c_int32 * 3)()
+        L.check(self._lib.pp_level_dims(self._ctx, level, d), "pp_level_dims")
+        return (d[0], d[1], d[2])
+
+    @property
+    def memory_bytes(self) -> int:
+        b = ctypes.c_int64()
+        L.check(self._lib.pp_memory(self._ctx, ctypes.byref(b)), "pp_memory")
+        return b.value
+
+    # -- operations -------------------------------------------------------
+    def _field(self, t, name):
+        _check_field(t, self.shape, name)
+        return _ptr(t)
+
+    def update_coeffs(self, beta: Sequence[torch.Tensor]) -> None:
+        L.check(self._lib.pp_update_coeffs(self._ctx, *(self._field(b, "beta") for b in beta)),
+                "pp_update_coeffs")
+
+    def divergence(self, u: Sequence[torch.Tensor], scale: float = 1.0,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=u[0].device)
+        L.check(self._lib.pp_divergence(self._ctx, *(self._field(v, "u") for v in u), float(scale),
+                                        self._field(out, "out")), "pp_divergence")
+        return out
+
+    def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty_like(x)
+        L.check(self._lib.pp_apply(self._ctx, self._field(x, "x"), self._field(out, "out")), "pp_apply")
+        return out
+
+    def solve(self, rhs: torch.Tensor, tol: float = 1e-8, p: Optional[torch.Tensor] = None,
+              check: bool = True) -> torch.Tensor:
+        """Mean-zero p with A p = rhs - mean(rhs); stats in self.last_stats."""
+        if p is None:
+            p = torch.empty_like(rhs)
+        st = L.Stats()
+        rc = self._lib.pp_solve(self._ctx, self._field(rhs, "rhs"), self._field(p, "p"), float(tol),
+                                ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        if check or rc not in (L.PP_OK, L.PP_ENOCONV):
+            L.check(rc, "pp_solve")
+        return p
+
+    def project(self, us: Sequence[torch.Tensor], p: torch.Tensor, dt: float,
+                out: Optional[Sequence[torch.Tensor]] = None):
+        if out is None:
+            out = tuple(torch.empty_like(p) for _ in range(3))
+        L.check(self._lib.pp_project(self._ctx, *(self._field(v, "us") for v in us),
+                                     self._field(p, "p"), float(dt),
+                                     *(self._field(v, "u") for v in out)), "pp_project")
+        return out
+
+    def adjoint(self, p: torch.Tensor, g_p: torch.Tensor, tol: float = 1e-8,
+                check: bool = True):
+        """Returns (g_rhs, (g_beta_x, g_beta_y, g_beta_z)) for L with dL/dp = g_p."""
+        g_rhs = torch.empty_like(p)
+        g_b = tuple(torch.empty_like(p) for _ in range(3))
+        st = L.Stats()
+        rc = self._lib.pp_solve_adjoint(self._ctx, self._field(p, "p"), self._field(g_p, "g_p"),
+                                        float(tol), _ptr(g_rhs), _ptr(g_b[0]), _ptr(g_b[1]),
+                                        _ptr(g_b[2]), ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        if check or rc not in (L.PP_OK, L.PP_ENOCONV):
+            L.check(rc, "pp_solve_adjoint")
+        return g_rhs, g_b
+
+    def vcycle(self, r: torch.Tensor) -> torch.Tensor:
+        e = torch.empty_like(r)
+        L.check(self._lib.pp_vcycle(self._ctx, self._field(r, "r"), self._field(e, "e")), "pp_vcycle")
+        return e
+
+    # -- kernel timing ----------------------------------------------------
+    def timing(self, on: bool) -> None:
+        L.check(self._lib.pp_timing_enable(self._ctx, int(on)), "pp_timing_enable")
+
+    def timing_reset(self) -> None:
+        L.check(self._lib.pp_timing_reset(self._ctx), "pp_timing_reset")
+
+    def timing_get(self, kind: int) -> Tuple[int, float]:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        L.check(self._lib.pp_timing_get(self._ctx, kind, ctypes.byref(n), ctypes.byref(ms)),
+                "pp_timing_get")
+        return n.value, ms.value
+
+
+class PressureSolve(torch.autograd.Function):
+    """p = S(rhs; beta): the mean-zero solution of D(beta G p) = rhs - mean(rhs).
+
+    backward returns dL/d rhs (one transposed solve; the operator is symmetric)
+    and dL/d beta on every face (the face product G lambda * G p).
+    """
+
+    @staticmethod
+    def forward(ctx, rhs, beta_x, beta_y, beta_z, solver: Solver, tol: float, adj_tol: float):
+        p = solver.solve(rhs, tol=tol)
+        ctx.solver = solver
+        ctx.adj_tol = adj_tol
+        ctx.save_for_backward(p)
+        return p
+
+    @staticmethod
+    def backward(ctx, g_p):
+        (p,) = ctx.saved_tensors
+        g_rhs, g_b = ctx.solver.adjoint(p, g_p.contiguous(), tol=ctx.adj_tol)
+        return g_rhs, g_b[0], g_b[1], g_b[2], None, None, None
+
+
+def pressure_solve(rhs: torch.Tensor, beta: Sequence[torch.Tensor], solver: Solver,
+                   tol: float = 1e-8, adj_tol: Optional[float] = None) -> torch.Tensor:
+    """Differentiable solve; `solver` must have been built from these beta."""
+    return PressureSolve.apply(rhs, beta[0], beta[1], beta[2], solver, tol,
+                               tol if adj_tol is None else adj_tol)
+
+
+# -- single-kernel entry points -----------------------------------------------
+
+def k_smooth(shape, h, bc, beta, r, e, sweeps=1, zero_init=False):
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    L.check(lib.pp_k_smooth(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r), _ptr(e), sweeps,
+                            int(zero_init), _stream_handle(None)), "pp_k_smooth")
+    return e
+
+
+def k_resid_restrict(shape, h, bc, beta, e, r, rH):
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    L.check(lib.pp_k_resid_restrict(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(e), _ptr(r),
+                                    _ptr(rH), _stream_handle(None)), "pp_k_resid_restrict")
+    return rH
+
+
+def k_prolong_add(shape, h, bc, eH, e):
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    L.check(lib.pp_k_prolong_add(ctypes.byref(g), _ptr(eH), _ptr(e), _stream_handle(None)),
+            "pp_k_prolong_add")
+    return e
+
+
+def k_coarsen_beta(shape, h, bc, beta, out):
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    L.check(lib.pp_k_coarsen_beta(ctypes.byref(g), *(_ptr(b) for b in beta), *(_ptr(o) for o in out),
+                                  _stream_handle(None)), "pp_k_coarsen_beta")
+    return out
+
+
+def k_copy(src: torch.Tensor, dst: torch.Tensor):
+    lib = L.load()
+    L.check(lib.pp_k_copy(_ptr(src), _ptr(dst), src.numel(), _stream_handle(None)), "pp_k_copy")
+    return dst

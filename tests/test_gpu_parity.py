@@ -1,0 +1,393 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Tolerances:
+  * single passes (face coefficients, divergence, operator, projection, one
+    Gauss-Seidel sweep, transfers) are the same FP64 arithmetic in another
+    order: relative 1e-14..1e-13 of the field's scale;
+  * solves: both sides converge to a relative residual; the p error is then
+    bounded by the conditioning, so parity is asserted at a tight tolerance
+    (GPU 1e-11, oracle 1e-13) with max|p - p_o| / max|p_o| <= 1e-8, and at
+    the timing tolerance 1e-8 through the oracle's own FP64 residual of the
+    GPU answer (<= 1.05e-8) plus a looser p bound.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_11744_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_2012_11744_amd import solver
+    return solver
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+RAGGED = [((8, 8, 8), (0, 0, 0)), ((40, 20, 56), (1, 0, 1)), ((144, 80, 32), (0, 1, 1)),
+          ((48, 36, 24), (1, 1, 1))]
+
+
+# ---------------------------------------------------------------------------
+# single passes
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,bc", RAGGED)
+def test_face_coeffs(S, n, bc):
+    _say(f"face_coeffs n={n} bc={bc}")
+    w = W.random_case(n, bc, seed=101)
+    ref = oracle.face_coeffs(w.rho, bc)
+    got = S.face_coeffs(dev(w.rho), w.h, bc)
+    for m in range(3):
+        assert relmax(host(got[m]), ref[m]) <= 2e-16
+
+
+@pytest.mark.parametrize("n,bc", RAGGED)
+def test_divergence_apply_project(S, n, bc):
+    _say(f"divergence/apply/project n={n} bc={bc}")
+    w = W.random_case(n, bc, seed=102)
+    beta = oracle.face_coeffs(w.rho, bc)
+    with S.Solver([dev(b) for b in beta], w.h, bc, precision="fp64") as sol:
+        us = [dev(u) for u in w.us]
+        d = sol.divergence(us, 1.0 / w.dt)
+        assert relmax(host(d), oracle.divergence(w.us, bc, w.h, 1.0 / w.dt)) <= 1e-14
+        x = np.random.default_rng(1).standard_normal(w.shape)
+        y = sol.apply(dev(x))
+        assert relmax(host(y), oracle.apply(beta, bc, w.h, x)) <= 1e-13
+        u = sol.project(us, dev(x), w.dt)
+        ref = oracle.project(beta, bc, w.h, w.dt, w.us, x)
+        for m in range(3):
+            assert relmax(host(u[m]), ref[m]) <= 1e-14
+        # in place (u aliases u*)
+        sol.project(us, dev(x), w.dt, out=us)
+        for m in range(3):
+            assert relmax(host(us[m]), ref[m]) <= 1e-14
+
+
+@pytest.mark.parametrize("n,bc", RAGGED)
+def test_one_gauss_seidel_sweep_matches_paper_sor(S, n, bc):
+    """One red-black sweep (relaxation 1) equals the oracle's sweep of eq.
+    beta_pressure: same-colour updates are independent, so order-free."""
+    _say(f"rbgs sweep n={n} bc={bc}")
+    w = W.random_case(n, bc, seed=103)
+    beta = oracle.face_coeffs(w.rho, bc)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(w.shape)
+    e0 = rng.standard_normal(w.shape)
+    ref, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=e0, omega=1.0, sweeps=1)
+    e = dev(e0)
+    S.k_smooth(w.shape, w.h, bc, [dev(b) for b in beta], dev(r), e, sweeps=1)
+    assert relmax(host(e), ref) <= 1e-14
+    # two sweeps from zero (zero_init skips reading e)
+    ref2, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=np.zeros(w.shape), omega=1.0, sweeps=2)
+    e = dev(np.full(w.shape, np.nan))
+    S.k_smooth(w.shape, w.h, bc, [dev(b) for b in beta], dev(r), e, sweeps=2, zero_init=True)
+    assert relmax(host(e), ref2) <= 1e-14
+
+
+def _restrict_ref(x):
+    nz, ny, nx = x.shape
+    return x.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(1, 3, 5))
+
+
+def _prolong_ref(eH, bc):
+    """Cell-centred trilinear: 3/4 parent + 1/4 next coarse cell per axis."""
+    out = eH
+    for ax, m in ((2, 0), (1, 1), (0, 2)):
+        nH = out.shape[ax]
+        i = np.arange(2 * nH)
+        par = i // 2
+        oth = np.where(i % 2 == 0, par - 1, par + 1)
+        if bc[m] == 1:
+            oth = np.clip(oth, 0, nH - 1)
+        else:
+            oth = oth % nH
+        out = 0.75 * np.take(out, par, axis=ax) + 0.25 * np.take(out, oth, axis=ax)
+    return out
+
+
+@pytest.mark.parametrize("n,bc", RAGGED)
+def test_transfers(S, n, bc):
+    _say(f"transfers n={n} bc={bc}")
+    w = W.random_case(n, bc, seed=104)
+    beta = oracle.face_coeffs(w.rho, bc)
+    rng = np.random.default_rng(3)
+    e = rng.standard_normal(w.shape)
+    r = rng.standard_normal(w.shape)
+    nz, ny, nx = w.shape
+    cshape = (nz // 2, ny // 2, nx // 2)
+    rH = dev(np.zeros(cshape))
+    S.k_resid_restrict(w.shape, w.h, bc, [dev(b) for b in beta], dev(e), dev(r), rH)
+    ref = _restrict_ref(r - oracle.apply(beta, bc, w.h, e))
+    assert relmax(host(rH), ref) <= 1e-13
+    eH = rng.standard_normal(cshape)
+    ef = dev(e)
+    S.k_prolong_add(w.shape, w.h, bc, dev(eH), ef)
+    assert relmax(host(ef), e + _prolong_ref(eH, bc)) <= 1e-14
+    out = [dev(np.zeros(cshape)) for _ in range(3)]
+    S.k_coarsen_beta(w.shape, w.h, bc, [dev(b) for b in beta], out)
+    for m in range(3):
+        ax = 2 - m
+        sl = [slice(None)] * 3
+        sl[ax] = slice(0, None, 2)
+        f = beta[m][tuple(sl)].copy()
+        if bc[m] == 1:
+            s0 = [slice(None)] * 3
+            s0[ax] = 0
+            f[tuple(s0)] = 0.0
+        for a in range(3):
+            if a == ax:
+                continue
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[a] = slice(0, None, 2)
+            hi[a] = slice(1, None, 2)
+            f = 0.5 * (f[tuple(lo)] + f[tuple(hi)])
+        assert relmax(host(out[m]), f) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# solves
+# ---------------------------------------------------------------------------
+
+_ORACLE_P = {}
+
+
+def _oracle_p(w, beta, rhs, tol):
+    key = (w.name, w.n, w.bc, tol)
+    if key not in _ORACLE_P:
+        _ORACLE_P[key] = oracle.solve(beta, w.bc, w.h, rhs, tol=tol)[0]
+    return _ORACLE_P[key]
+
+
+def _parity_solve(S, w, precision, outer="pcg", tol=1e-11, tol_oracle=1e-13, ptol=1e-8):
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    p_o = _oracle_p(w, beta, rhs, tol_oracle)
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision=precision, outer=outer) as sol:
+        us = [dev(u) for u in w.us]
+        b = sol.divergence(us, 1.0 / w.dt)
+        p = sol.solve(b, tol=tol)
+        st = sol.last_stats
+        u = sol.project(us, p, w.dt)
+        p_h = host(p)
+        err_p = relmax(p_h, p_o)
+        u_o = oracle.project(beta, w.bc, w.h, w.dt, w.us, p_o)
+        du = oracle.divergence([host(c) for c in u], w.bc, w.h)
+        du_o = oracle.divergence(u_o, w.bc, w.h)
+        ds = oracle.divergence(w.us, w.bc, w.h)
+        err_div = np.abs(du - du_o).max() / np.abs(ds).max()
+        res = oracle.apply(beta, w.bc, w.h, p_h)
+        bm = rhs - rhs.mean()
+        rel_true = np.linalg.norm(bm - res) / np.linalg.norm(bm)
+    _say(f"  {w.name} {precision}/{outer} tol={tol:g}: iters={st['outer_iters']} "
+         f"rel={st['rel_res']:.2e} true={rel_true:.2e} err_p={err_p:.2e} err_div={err_div:.2e} "
+         f"fell_back={st['fell_back']}")
+    assert rel_true <= 1.05 * tol
+    assert err_p <= ptol
+    assert abs(p_h.mean()) <= 1e-12 * np.abs(p_h).max()
+    return st, err_p, err_div
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config1_sphere_periodic(S, precision):
+    _say(f"config1 32^3 {precision}")
+    w = W.config1(32)
+    _parity_solve(S, w, precision, tol=1e-10, ptol=1e-8)
+
+
+@pytest.mark.parametrize("n,bc", RAGGED)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_random_ratio1000_ragged(S, n, bc, precision):
+    _say(f"random ratio1000 n={n} bc={bc} {precision}")
+    w = W.random_case(n, bc, seed=105, ratio=1000.0)
+    _parity_solve(S, w, precision, tol=1e-11, ptol=1e-8)
+
+
+@pytest.mark.parametrize("outer", ["pcg", "dc"])
+def test_config3_layer_droplets_64(S, outer):
+    _say(f"config3 geometry at 64^3, fp32, {outer}")
+    w = W.config3(64)
+    _parity_solve(S, w, "fp32", outer=outer, tol=1e-11, ptol=1e-8)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config2_bubbles_128(S, precision):
+    _say(f"config2 128^3 {precision}")
+    w = W.config2(128)
+    _parity_solve(S, w, precision, tol=1e-10, ptol=1e-8)
+    _parity_solve(S, w, precision, tol=1e-8, ptol=1e-5)
+
+
+def test_manufactured_cosine_gpu(S):
+    """The GPU solve reproduces the closed-form discrete solution
+    p (pi h)^2 / sin^2(pi h) of the cosine mode (walls)."""
+    n = 64
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    c = np.cos(2 * np.pi * x)
+    p = c[None, None, :] * c[None, :, None] * c[:, None, None]
+    bc = (1, 1, 1)
+    beta = oracle.face_coeffs(np.full((n, n, n), 2.0), bc)
+    with S.Solver([dev(b) for b in beta], h, bc, precision="fp32") as sol:
+        ph = host(sol.solve(dev(-12 * np.pi ** 2 * p / 2.0), tol=1e-12))
+    assert np.abs(ph - p * (np.pi * h) ** 2 / np.sin(np.pi * h) ** 2).max() <= 1e-10
+
+
+def test_deterministic_bitwise(S):
+    w = W.config3(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = dev(oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt))
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision="fp32") as sol:
+        p1 = host(sol.solve(rhs, tol=1e-9)).copy()
+        p2 = host(sol.solve(rhs, tol=1e-9)).copy()
+    assert np.array_equal(p1, p2)
+
+
+def test_smallest_grid_single_level(S):
+    """4^3: the whole problem is the coarsest level (direct FP64 solve)."""
+    w = W.random_case((4, 4, 4), (1, 0, 1), seed=106)
+    st, err, _ = _parity_solve(S, w, "fp32", tol=1e-11, ptol=1e-10)
+    assert st["outer_iters"] <= 2
+
+
+def test_zero_rhs_and_constant_rhs(S):
+    w = W.random_case((16, 16, 16), (0, 0, 0), seed=107)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    with S.Solver([dev(b) for b in beta], w.h, w.bc) as sol:
+        p = sol.solve(dev(np.zeros(w.shape)), tol=1e-8)
+        assert np.all(host(p) == 0.0) and sol.last_stats["outer_iters"] == 0
+        p = sol.solve(dev(np.full(w.shape, 3.0)), tol=1e-8)   # mean removed -> zero
+        assert np.all(host(p) == 0.0)
+
+
+def test_warm_start_and_update_coeffs(S):
+    w = W.config4(32)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    p_o, _, _ = oracle.solve(beta, w.bc, w.h, rhs)
+    with S.Solver([dev(np.ones(w.shape)) for _ in range(3)], w.h, w.bc, warm_start=True) as sol:
+        sol.update_coeffs([dev(b) for b in beta])
+        p = dev(np.zeros(w.shape))
+        sol.solve(dev(rhs), tol=1e-11, p=p)
+        cold = sol.last_stats["outer_iters"]
+        sol.solve(dev(rhs), tol=1e-11, p=p)          # warm: already converged
+        assert sol.last_stats["outer_iters"] <= 1 < cold
+        assert relmax(host(p), p_o) <= 1e-8
+
+
+def test_invalid_coefficients_rejected(S):
+    from paper_2012_11744_amd import _lib as L
+    n = 8
+    b = np.ones((n, n, n))
+    bad = b.copy()
+    bad[3, 4, 5] = 0.0                      # an interior face with zero coefficient
+    with pytest.raises(L.PPError) as ei:
+        S.Solver([dev(b), dev(bad), dev(b)], 1.0 / n, (0, 0, 0))
+    assert ei.value.code == L.PP_EINVAL and "non-wall faces" in ei.value.detail
+    nanb = b.copy()
+    nanb[0, 0, 1] = np.nan
+    with pytest.raises(L.PPError):
+        S.Solver([dev(nanb), dev(b), dev(b)], 1.0 / n, (0, 0, 0))
+    # a zero on a wall face is fine (wall entries are ignored)
+    wallb = b.copy()
+    wallb[:, :, 0] = 0.0
+    S.Solver([dev(wallb), dev(b), dev(b)], 1.0 / n, (1, 0, 0)).close()
+
+
+def test_max_outer_reports_noconv(S):
+    from paper_2012_11744_amd import _lib as L
+    w = W.config3(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = dev(oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt))
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, max_outer=2) as sol:
+        p = sol.solve(rhs, tol=1e-12, check=False)
+        st = sol.last_stats
+        assert st["status"] == L.PP_ENOCONV and st["outer_iters"] == 2
+        assert np.isfinite(host(p)).all()
+        with pytest.raises(L.PPError):
+            sol.solve(rhs, tol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adjoint_matches_oracle(S, precision):
+    _say(f"adjoint config4 64^3 {precision}")
+    w = W.config4(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    p_o, _, _ = oracle.solve(beta, w.bc, w.h, rhs)
+    g_o, gb_o, _, _ = oracle.adjoint(beta, w.bc, w.h, p_o, w.w)
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision=precision) as sol:
+        p = sol.solve(dev(rhs), tol=1e-11)
+        g, gb = sol.adjoint(p, dev(w.w), tol=1e-11)
+        assert relmax(host(g), g_o) <= 1e-8
+        for m in range(3):
+            assert relmax(host(gb[m]), gb_o[m]) <= 1e-8
+
+
+def test_autograd_finite_differences(S):
+    """Backward of the autograd Function against central differences of
+    L = sum(w p) in 50 rhs entries and 50 face coefficients (FP64 solves)."""
+    _say("autograd FD config4 geometry at 32^3")
+    w = W.config4(32)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    bt = [dev(b).requires_grad_(True) for b in beta]
+    rt = dev(rhs).requires_grad_(True)
+    wt = dev(w.w)
+    with S.Solver([b.detach() for b in bt], w.h, w.bc, precision="fp32") as sol:
+        p = S.pressure_solve(rt, bt, sol, tol=1e-12)
+        loss = (wt * p).sum()
+        loss.backward()
+    g_rhs = host(rt.grad)
+    g_b = [host(b.grad) for b in bt]
+    rng = np.random.default_rng(3)
+
+    def L_of(rhs_, beta_):
+        with S.Solver([dev(b) for b in beta_], w.h, w.bc, precision="fp64") as s2:
+            return float((wt * s2.solve(dev(rhs_), tol=1e-13)).sum())
+
+    d = 1e-6 * np.sqrt(np.mean(rhs ** 2))
+    for _ in range(50):
+        c = tuple(int(v) for v in rng.integers(0, 32, 3))
+        rp = rhs.copy(); rp[c] += d
+        rm = rhs.copy(); rm[c] -= d
+        fd = (L_of(rp, beta) - L_of(rm, beta)) / (2 * d)
+        assert abs(fd - g_rhs[c]) <= 1e-5 * np.abs(g_rhs).max()
+    for _ in range(50):
+        m = int(rng.integers(0, 3))
+        c = tuple(int(v) for v in rng.integers(0, 32, 3))
+        bp = [b.copy() for b in beta]; bp[m][c] += 1e-6
+        bm = [b.copy() for b in beta]; bm[m][c] -= 1e-6
+        fd = (L_of(rhs, bp) - L_of(rhs, bm)) / 2e-6
+        assert abs(fd - g_b[m][c]) <= 1e-4 * np.abs(g_b[m]).max()
