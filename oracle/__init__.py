@@ -74,8 +74,15 @@ def _load():
         lib.ppo_adjoint.argtypes = [I64P, IP, D, P, P, P, P, P, D, ctypes.c_int, P, P, P, P,
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D)]
         lib.ppo_adjoint.restype = ctypes.c_int
+        lib.ppo_threads.argtypes = []
+        lib.ppo_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().ppo_threads())
 
 
 def _grid(shape, bc):

@@ -47,6 +47,10 @@
 
 #define EXPORT __attribute__((visibility("default")))
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 typedef struct {
     int64_t n[3];   /* nx, ny, nz */
     int bc[3];      /* 0 periodic, 1 wall */
@@ -108,6 +112,16 @@ static grid_t make_grid(const int64_t *n, const int *bc, double h)
     }
     g.h = h;
     return g;
+}
+
+/* number of threads the parallel loops use */
+EXPORT int ppo_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
