@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=12,
                     help="oracle PCG iterations in the CPU-baseline sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="time the plain copy kernel on 2 x 1 GiB buffers and exit (reference "
+                         "for achievable HBM bandwidth and for scaling FETCH/WRITE counters)")
     ap.add_argument("--summarize-db", metavar="RESULTS_DB",
                     help="print a per-kernel, per-grid summary of a rocprofv3 kernel trace "
                          "(the *_results.db it writes) and exit")
@@ -75,10 +78,37 @@ def summarize_db(path):
               f"{mn / 1e3:.2f} | {mx / 1e3:.2f} | {100 * tot / total:.1f} |")
 
 
+def copy_bandwidth(reps=10, nbytes=1 << 30):
+    """Plain device copy through the library's copy kernel: GB/s counting the
+    bytes read plus the bytes written."""
+    import torch
+    from paper_2012_11744_amd import solver as S
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    S.k_copy(src, dst)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        S.k_copy(src, dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del src, dst
+    return {"bytes_per_launch": 2 * n * 8, "avg_ms": ms, "GBps": 2 * n * 8 / (ms * 1e-3) / 1e9}
+
+
 def main():
     args = parse()
     if args.summarize_db:
         summarize_db(args.summarize_db)
+        return
+    if args.calibrate_copy:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"copy_kernel": copy_bandwidth()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -159,10 +189,11 @@ def main():
             "fell_back": st["fell_back"],
             "memory_bytes": sol.memory_bytes,
         }
-        # fine-level smoother: algorithmic bytes per half sweep = r and e of
-        # the updated colour (N/2 each), e of the other colour (N/2), all 3N
-        # face coefficients, and the N/2 writes: 9 words per 2 cells... i.e.
-        # (0.5 + 0.5 + 3 + 0.5) = 4.5 words per cell
+        # fine-level smoother, one fused red-black sweep per launch: reads e_in,
+        # r and the three face coefficients once and writes e_out: 6 words per
+        # cell; the first sweep of each cycle starts from zero and skips e_in
+        # (5 words).  With nu_pre = nu_post = 2 one launch in four is such a
+        # zero-start sweep.
         word = {"fp64": 8, "fp32": 4, "fp16": 2}[mode]
         n_sm, ms_sm = kt[L.PP_KT_SMOOTH]
         n_rr, ms_rr = kt[L.PP_KT_RESTRICT]
@@ -171,9 +202,9 @@ def main():
         kern = {}
         if n_sm:
             avg = ms_sm / n_sm
-            byt = 4.5 * word * w.cells
-            kern["smoother_half_sweep"] = {"launches": n_sm, "avg_ms": avg, "alg_bytes": byt,
-                                           "GBps": byt / (avg * 1e-3) / 1e9}
+            byt = (6.0 - 0.25) * word * w.cells
+            kern["smoother_sweep"] = {"launches": n_sm, "avg_ms": avg, "alg_bytes": byt,
+                                      "GBps": byt / (avg * 1e-3) / 1e9}
         if n_rr:
             avg = ms_rr / n_rr
             byt = (5 * word + word / 8) * w.cells   # e, r, 3 beta in; r_H out
@@ -181,7 +212,9 @@ def main():
                                       "GBps": byt / (avg * 1e-3) / 1e9}
         if n_oa:
             avg = ms_oa / n_oa
-            byt = 40 * w.cells                      # d, 3 beta in; q out (FP64)
+            # new direction + operator: z (V-cycle word), d_old, 3 beta in; d_new, q out
+            # (FP64); the first iteration of each solve does not read d_old
+            byt = (48 + word - 8.0 / max(1, r["outer_iters"])) * w.cells
             kern["outer_apply"] = {"launches": n_oa, "avg_ms": avg, "alg_bytes": byt,
                                    "GBps": byt / (avg * 1e-3) / 1e9}
         if n_ou:
@@ -190,9 +223,9 @@ def main():
             kern["outer_update"] = {"launches": n_ou, "avg_ms": avg, "alg_bytes": byt,
                                     "GBps": byt / (avg * 1e-3) / 1e9}
         r["kernels"] = kern
-        if mi == 0 and "smoother_half_sweep" in kern:
-            k = kern["smoother_half_sweep"]
-            roof = {"kernel": "red-black Gauss-Seidel half sweep (fine level, %s)" % mode,
+        if mi == 0 and "smoother_sweep" in kern:
+            k = kern["smoother_sweep"]
+            roof = {"kernel": "fused red-black Gauss-Seidel sweep (fine level, %s)" % mode,
                     "bound": "hbm", "achieved": round(k["GBps"], 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(k["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
                     "alg_bytes_per_launch": k["alg_bytes"], "avg_launch_ms": k["avg_ms"]}
@@ -214,6 +247,12 @@ def main():
             f"(no timers {ms_plain:.3f}), iters={r['outer_iters']}, kernels="
             + ", ".join(f"{k}={v['GBps']:.0f}GB/s" for k, v in kern.items()))
         sol.close()
+
+    copy = copy_bandwidth()
+    log(f"[bench] copy kernel: {copy['GBps']:.0f} GB/s")
+    if roof is not None:
+        roof["copy_kernel_GBps"] = round(copy["GBps"], 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy["GBps"], 4)
 
     cpu = None
     if not args.no_cpu_baseline:

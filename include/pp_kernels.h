@@ -38,6 +38,16 @@ int pp_k_smooth(const pp_grid *grid, const double *beta_x, const double *beta_y,
                 const double *beta_z, const double *r, double *e, int32_t sweeps,
                 int32_t zero_init, void *hip_stream);
 
+/* One fused red-black sweep, out of place: e_out = sweep(e_in), the first
+ * colour updated first (first_colour 0: red, (i+j+k) even; 1: black) and the
+ * second colour from the new first-colour values.  Equal, value for value, to
+ * two colour passes of pp_k_smooth.  e_in and e_out must not alias;
+ * zero_init = 1 treats e_in as zero (it is not read).  nx must be even, and
+ * so must the cell count of every periodic direction. */
+int pp_k_smooth_fused(const pp_grid *grid, const double *beta_x, const double *beta_y,
+                      const double *beta_z, const double *r, const double *e_in, double *e_out,
+                      int32_t first_colour, int32_t zero_init, void *hip_stream);
+
 /* rH[C] = (1/8) sum over the 8 fine cells c of C of (r - A e)[c].
  * grid: the fine grid (all n even); rH has n/2 cells per direction. */
 int pp_k_resid_restrict(const pp_grid *grid, const double *beta_x, const double *beta_y,
@@ -68,7 +78,7 @@ enum {
     PP_KT_SMOOTH = 0,          /* fine-level red-black half sweep */
     PP_KT_RESTRICT = 1,        /* fine-level residual + restriction */
     PP_KT_PROLONG = 2,         /* fine-level prolongation + correction */
-    PP_KT_OUTER_APPLY = 3,     /* FP64 operator apply (+ dot) of the outer loop */
+    PP_KT_OUTER_APPLY = 3,     /* FP64 search direction + operator apply (+ dot), outer loop */
     PP_KT_OUTER_UPDATE = 4,    /* FP64 vector update (+ norms) of the outer loop */
     PP_KT_COUNT = 5
 };

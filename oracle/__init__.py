@@ -65,7 +65,7 @@ def _load():
         lib.ppo_apply.restype = None
         lib.ppo_project.argtypes = [I64P, IP, D, D, P, P, P, P, P, P, P, P, P, P]
         lib.ppo_project.restype = None
-        lib.ppo_rbsor.argtypes = [I64P, IP, D, P, P, P, P, P, D, ctypes.c_int, D,
+        lib.ppo_rbsor.argtypes = [I64P, IP, D, P, P, P, P, P, D, ctypes.c_int, D, ctypes.c_int,
                                   ctypes.POINTER(D)]
         lib.ppo_rbsor.restype = ctypes.c_int
         lib.ppo_solve.argtypes = [I64P, IP, D, P, P, P, P, P, D, ctypes.c_int,
@@ -138,10 +138,11 @@ def project(beta, bc, h: float, dt: float, us, p: np.ndarray):
 
 
 def rbsor(beta, bc, h: float, rhs: np.ndarray, p0: np.ndarray = None, omega: float = 1.3,
-          sweeps: int = 100000, tol: float = 0.0):
+          sweeps: int = 100000, tol: float = 0.0, first_colour: int = 0):
     """The paper's red-black SOR; returns (p, sweeps_done, rel_residual).
 
     rhs is used as given; remove its mean first for a consistent system.
+    first_colour 0 updates red ((i+j+k) even) first, as the paper does.
     """
     bx, by, bz = (_c(v) for v in beta)
     rhs = _c(rhs)
@@ -149,7 +150,7 @@ def rbsor(beta, bc, h: float, rhs: np.ndarray, p0: np.ndarray = None, omega: flo
     n, b = _grid(rhs.shape, bc)
     rel = ctypes.c_double(0.0)
     s = _load().ppo_rbsor(n, b, h, _p(bx), _p(by), _p(bz), _p(rhs), _p(p), omega, sweeps, tol,
-                          ctypes.byref(rel))
+                          int(first_colour), ctypes.byref(rel))
     return p, s, rel.value
 
 

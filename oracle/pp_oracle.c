@@ -273,13 +273,14 @@ static double norm2(const double *x, int64_t N)
     return sqrt(s);
 }
 
-/* Red (i+j+k even) first, then black, `sweeps` times or until the relative
- * L2 residual ||rhs - A p|| / ||rhs|| <= tol (checked after each sweep when
- * tol > 0).  rhs is used as given (no mean removal); p is updated in place.
- * Returns the number of sweeps done; *relres receives the last residual. */
+/* Red (i+j+k even) first, then black (first = 0; the paper's order), or
+ * black first (first = 1), `sweeps` times or until the relative L2 residual
+ * ||rhs - A p|| / ||rhs|| <= tol (checked after each sweep when tol > 0).
+ * rhs is used as given (no mean removal); p is updated in place.  Returns
+ * the number of sweeps done; *relres receives the last residual. */
 EXPORT int ppo_rbsor(const int64_t *n, const int *bc, double h, const double *bx,
                      const double *by, const double *bz, const double *rhs, double *p,
-                     double omega, int sweeps, double tol, double *relres)
+                     double omega, int sweeps, double tol, int first, double *relres)
 {
     grid_t g = make_grid(n, bc, h);
     const double *beta[3] = {bx, by, bz};
@@ -289,8 +290,8 @@ EXPORT int ppo_rbsor(const int64_t *n, const int *bc, double h, const double *bx
     int s = 0;
     double rel = 0.0;
     for (s = 0; s < sweeps;) {
-        sor_colour(&g, beta, rhs, p, omega, 0);
-        sor_colour(&g, beta, rhs, p, omega, 1);
+        sor_colour(&g, beta, rhs, p, omega, first);
+        sor_colour(&g, beta, rhs, p, omega, 1 - first);
         ++s;
         if (tol > 0.0) {
             apply_A(&g, beta, p, r);

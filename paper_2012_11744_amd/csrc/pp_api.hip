@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pp.h"
@@ -68,8 +69,10 @@ struct LevelBuf {
     Dims d;
     double h;
     void *b[3];
-    void *e;
+    void *e;      // correction, ping-pong pair with e2 (sweeps are out of place)
+    void *e2;
     void *r;
+    void *cur;    // whichever of e / e2 holds the current correction
 };
 
 struct Hier {
@@ -101,7 +104,7 @@ struct pp_ctx {
     Hier h64;                    // FP64 hierarchy (FP64 mode, and the mixed-mode fallback)
     double *pinv;
     int ncoarse;
-    double *r64, *d64, *q64;
+    double *r64, *d64, *d64b, *q64;
     double *part;
     size_t pstride;
     double *scal;
@@ -266,7 +269,9 @@ int alloc_hier(pp_ctx *c, Hier &H, int st)
                 PP_TRY(dev_alloc(c, &v.b[m], n * sb));
         }
         PP_TRY(dev_alloc(c, &v.e, n * sb));
+        PP_TRY(dev_alloc(c, &v.e2, n * sb));
         PP_TRY(dev_alloc(c, &v.r, n * sb));
+        v.cur = v.e;
     }
     return PP_OK;
 }
@@ -395,7 +400,7 @@ int read_scal(pp_ctx *c)
     return PP_OK;
 }
 
-int nparts(pp_ctx *c) { return (int)grid_blocks(cell_grid(c->d)); }
+int nparts(pp_ctx *c) { return (int)grid_blocks(red_grid(c->d)); }
 
 int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 {
@@ -430,43 +435,46 @@ void vcycle_run(pp_ctx *c, Hier &H)
 {
     hipStream_t s = c->stream;
     const int L = H.nlev;
+    // down: nu_pre fused sweeps (red first) from e = 0, then residual + restriction
     for (int l = 0; l + 1 < L; ++l) {
         LevelBuf &v = H.lev[l];
         const double h2 = v.h * v.h;
         const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
+        void *cur = v.e2;
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
-            {
-                KT t(c, PP_KT_SMOOTH, l == 0);
-                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 0, sw == 0, s);
-            }
-            {
-                KT t(c, PP_KT_SMOOTH, l == 0);
-                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 1, false, s);
-            }
+            void *out = (cur == v.e) ? v.e2 : v.e;
+            KT t(c, PP_KT_SMOOTH, l == 0);
+            launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
+                                 h2, 0, sw == 0, s);
+            cur = out;
         }
+        v.cur = cur;
         KT t(c, PP_KT_RESTRICT, l == 0);
-        launch_resid_restrict<T>(v.d, c->bc, b0, b1, b2, (const T *)v.e, (const T *)v.r,
+        launch_resid_restrict<T>(v.d, c->bc, b0, b1, b2, (const T *)v.cur, (const T *)v.r,
                                  (T *)H.lev[l + 1].r, 1.0 / h2, s);
     }
-    launch_coarsest<T>(c->ncoarse, c->pinv, (const T *)H.lev[L - 1].r, (T *)H.lev[L - 1].e, s);
+    LevelBuf &vc = H.lev[L - 1];
+    launch_coarsest<T>(c->ncoarse, c->pinv, (const T *)vc.r, (T *)vc.e, s);
+    vc.cur = vc.e;
+    // up: prolongation + correction, then nu_post fused sweeps (black first),
+    // the mirror image of the way down so the cycle is a symmetric operator
     for (int l = L - 2; l >= 0; --l) {
         LevelBuf &v = H.lev[l];
         const double h2 = v.h * v.h;
         const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
         {
             KT t(c, PP_KT_PROLONG, l == 0);
-            launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].e, (T *)v.e, s);
+            launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
         }
+        void *cur = v.cur;
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
-            {
-                KT t(c, PP_KT_SMOOTH, l == 0);
-                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 1, false, s);
-            }
-            {
-                KT t(c, PP_KT_SMOOTH, l == 0);
-                launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 0, false, s);
-            }
+            void *out = (cur == v.e) ? v.e2 : v.e;
+            KT t(c, PP_KT_SMOOTH, l == 0);
+            launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
+                                 h2, 1, false, s);
+            cur = out;
         }
+        v.cur = cur;
     }
 }
 
@@ -508,11 +516,8 @@ int check_progress(SolveState &S, int since_best_limit, int &since, double &best
 int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveState &S)
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
-    {
-        KT t(c, PP_KT_OUTER_APPLY, true);
-        launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs, c->scal, x,
-                        zero_x, c->r64, ih2, c->part, c->pstride, c->stream);
-    }
+    launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs, c->scal, x,
+                    zero_x, c->r64, ih2, c->part, c->pstride, c->stream);
     launch_finalize(c->part, c->pstride, nparts(c), OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
     PP_TRY(check_launch("residual"));
     PP_TRY(read_scal(c));
@@ -530,6 +535,7 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
     LevelBuf &v0 = H.lev[0];
     launch_scale_T<T>(c->N, c->r64, (T *)v0.r, c->scal, s);
     bool first = true;
+    double *dold = c->d64, *dnew = c->d64b;
     int since = 0;
     double window = S.rel;
     for (;;) {
@@ -538,21 +544,22 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         vcycle_run<T>(c, H);
         if (S.st)
             S.st->vcycles++;
-        launch_dot_rz<T>(c->d, c->r64, (const T *)v0.e, c->part, s);
+        launch_dot_rz<T>(c->d, c->r64, (const T *)v0.cur, c->part, s);
         launch_finalize(c->part, c->pstride, np, OP_RZ, 0, (double)c->N, first ? 1 : 0, c->scal, s);
-        launch_pcg_dir<T>(c->N, (const T *)v0.e, c->d64, c->scal, first, s);
-        first = false;
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
-            launch_apply_dot(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->d64,
-                             c->q64, ih2, c->part, s);
+            launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                                (const T *)v0.cur, dold, dnew, c->q64, c->scal, first, ih2,
+                                c->part, s);
         }
+        first = false;
         launch_finalize(c->part, c->pstride, np, OP_ALPHA, 0, (double)c->N, 0, c->scal, s);
         {
             KT t(c, PP_KT_OUTER_UPDATE, true);
-            launch_pcg_update<T>(c->d, c->d64, c->q64, x, c->r64, (T *)v0.r, (const T *)v0.e, c->scal,
+            launch_pcg_update<T>(c->d, dnew, c->q64, x, c->r64, (T *)v0.r, (const T *)v0.cur, c->scal,
                                  c->part, c->pstride, s);
         }
+        std::swap(dold, dnew);
         launch_finalize(c->part, c->pstride, np, OP_UPDATE, 0, (double)c->N, 0, c->scal, s);
         PP_TRY(check_launch("pcg iteration"));
         PP_TRY(read_scal(c));
@@ -583,7 +590,7 @@ int dc_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, SolveS
         vcycle_run<T>(c, H);
         if (S.st)
             S.st->vcycles++;
-        launch_axpy_T<T>(c->N, (const T *)v0.e, x, c->scal, s);
+        launch_axpy_T<T>(c->N, (const T *)v0.cur, x, c->scal, s);
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
             launch_residual_T<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs,
@@ -818,8 +825,10 @@ int pp_setup(const pp_grid *grid, const double *bx, const double *by, const doub
     if (rc == PP_OK)
         rc = dev_alloc_t(c, &c->d64, sizeof(double) * c->N);
     if (rc == PP_OK)
+        rc = dev_alloc_t(c, &c->d64b, sizeof(double) * c->N);
+    if (rc == PP_OK)
         rc = dev_alloc_t(c, &c->q64, sizeof(double) * c->N);
-    c->pstride = grid_blocks(cell_grid(c->d));
+    c->pstride = grid_blocks(red_grid(c->d));
     if (rc == PP_OK)
         rc = dev_alloc_t(c, &c->part, sizeof(double) * 2 * c->pstride);
     if (rc == PP_OK)
@@ -973,6 +982,28 @@ int pp_k_smooth(const pp_grid *grid, const double *bx, const double *by, const d
     return check_launch("pp_k_smooth");
 }
 
+int pp_k_smooth_fused(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+                      const double *r, const double *e_in, double *e_out, int32_t first_colour,
+                      int32_t zero_init, void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!bx || !by || !bz || !r || !e_in || !e_out)
+        return fail(PP_EINVAL, "pp_k_smooth_fused: NULL array");
+    if (e_in == e_out)
+        return fail(PP_EINVAL, "pp_k_smooth_fused: e_in and e_out must not alias");
+    if (first_colour != 0 && first_colour != 1)
+        return fail(PP_EINVAL, "pp_k_smooth_fused: first_colour must be 0 or 1");
+    if (grid->n[0] % 2)
+        return fail(PP_EINVAL, "pp_k_smooth_fused: nx must be even (threads own x-pairs)");
+    for (int m = 0; m < 3; ++m)
+        if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
+            return fail(PP_EINVAL, "pp_k_smooth_fused: periodic directions need an even cell count");
+    launch_rbgs_fused<double>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in, e_out,
+                              grid->h * grid->h, first_colour, zero_init != 0,
+                              (hipStream_t)hip_stream);
+    return check_launch("pp_k_smooth_fused");
+}
+
 int pp_k_resid_restrict(const pp_grid *grid, const double *bx, const double *by, const double *bz,
                         const double *e, const double *r, double *rH, void *hip_stream)
 {
@@ -1023,17 +1054,17 @@ int pp_vcycle(pp_ctx *c, const double *r, double *e)
     case ST_F64:
         launch_copy(r, (double *)v0.r, c->N, c->stream);
         vcycle_run<double>(c, H);
-        launch_copy((const double *)v0.e, e, c->N, c->stream);
+        launch_copy((const double *)v0.cur, e, c->N, c->stream);
         break;
     case ST_F32:
         launch_convert<float>(c->N, r, (float *)v0.r, c->stream);
         vcycle_run<float>(c, H);
-        launch_to_double<float>(c->N, (const float *)v0.e, e, c->stream);
+        launch_to_double<float>(c->N, (const float *)v0.cur, e, c->stream);
         break;
     default:
         launch_convert<_Float16>(c->N, r, (_Float16 *)v0.r, c->stream);
         vcycle_run<_Float16>(c, H);
-        launch_to_double<_Float16>(c->N, (const _Float16 *)v0.e, e, c->stream);
+        launch_to_double<_Float16>(c->N, (const _Float16 *)v0.cur, e, c->stream);
         break;
     }
     return check_launch("pp_vcycle");

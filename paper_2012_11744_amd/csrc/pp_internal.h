@@ -40,6 +40,13 @@ inline dim3 colour_grid(Dims d)
 
 inline size_t grid_blocks(dim3 g) { return (size_t)g.x * g.y * g.z; }
 
+// kernels that also reduce walk RZ planes per block: fewer partial sums
+constexpr int RZ = 8;
+inline dim3 red_grid(Dims d)
+{
+    return dim3((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + RZ - 1) / RZ);
+}
+
 // ---------------------------------------------------------------------------
 // scalar slots of the device scalar array used by the outer iterations
 // ---------------------------------------------------------------------------
@@ -75,6 +82,12 @@ enum FinalizeOp {
 template <typename T>
 void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e, double h2,
                  int colour, bool zero, hipStream_t s);
+// one fused red-black sweep, e_in -> e_out (must not alias); first_colour 0
+// updates red ((i+j+k) even) first, 1 black first; zero: e_in treated as 0
+template <typename T>
+void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
+                       const T *ein, T *eout, double h2, int first_colour, bool zero,
+                       hipStream_t s);
 template <typename T>
 void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
                            const T *r, T *rH, double ih2, hipStream_t s);
@@ -125,10 +138,9 @@ void launch_axpy_T(size_t n, const T *e, double *x, const double *scal, hipStrea
 template <typename T>
 void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_t s);
 template <typename T>
-void launch_pcg_dir(size_t n, const T *z, double *dvec, const double *scal, bool first,
-                    hipStream_t s);
-void launch_apply_dot(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                      const double *dvec, double *q, double ih2, double *part, hipStream_t s);
+void launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                      const T *z, const double *dold, double *dnew, double *q, const double *scal,
+                      bool first, double ih2, double *part, hipStream_t s);
 template <typename T>
 void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, double *r, T *rT,
                        const T *zold, const double *scal, double *part, size_t pstride,

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 
 #include "pp_internal.h"
 
@@ -28,6 +29,21 @@ struct Acc {
 template <>
 struct Acc<double> {
     using type = double;
+};
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    using type = double __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<float> {
+    using type = float __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<_Float16> {
+    using type = _Float16 __attribute__((ext_vector_type(2)));
 };
 
 template <typename T>
@@ -154,7 +170,296 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restri
     e[n.c] = static_cast<T>((s - h2 * ld(r, n.c)) / diag);
 }
 
-// rH = mean over the 8 children of (r - A e); one thread per coarse cell.
+// ---------------------------------------------------------------------------
+// Fused red-black Gauss-Seidel sweep (both colours in one pass, out of place).
+//
+// A block owns an FTX x FTY tile of an x-y plane and marches along z through a
+// chunk of planes [k0, k1).  Each thread owns one x-pair of cells (2p, 2p+1)
+// of one row: at every plane exactly one cell of a pair has each colour.  At
+// step k a thread updates the first-colour cell of its pair in plane k and
+// publishes it in an LDS plane slot; after one barrier the tile threads
+// update the second-colour cell of plane k-1 from the slots (in-plane
+// neighbours) and from their own registers (the z neighbours, which are the
+// first-colour cells of the same pair in planes k-2 and k), and store the
+// finished pair of plane k-1.
+//
+// The threads of a one-pair / one-row ring around the tile, and the planes
+// k0-1 and k1, recompute first-colour values that belong to neighbouring
+// tiles and chunks from the same inputs, so blocks never read each other's
+// output (e_in is read only, e_out written only) and the result equals a
+// red-black sweep value for value.  Coefficients and e_in of plane k+1 are
+// loaded one step ahead; every input cell is fetched from memory once per
+// sweep apart from the ring.
+// ---------------------------------------------------------------------------
+constexpr int FTX = 64;                 // tile width in cells (32 pairs)
+constexpr int FTY = 8;                  // tile height in rows
+constexpr int FPX = FTX / 2 + 2;        // pairs per row including the ring pairs
+constexpr int FRY = FTY + 2;            // rows including the ring rows
+constexpr int FTHREADS = 384;           // >= FPX * FRY, whole waves
+constexpr int FLW = FTX + 4;            // LDS row: cells i0-2 .. i0+FTX+1
+
+// Inputs of one thread's pair at one plane, as loaded (storage precision).
+// Ring rows also carry the e_in pair of the row beyond them (eo) and, for the
+// upper ring row, the y faces above (byo), which no thread of the tile loads.
+template <typename T>
+struct PairIn {
+    using T2 = typename Vec2<T>::type;
+    T2 e, r, bx, by, bz, eo, byo;
+};
+
+__device__ __forceinline__ int slot3(int k) { return ((k % 3) + 3) % 3; }
+
+// Block id -> (tile x, tile y, chunk), spreading contiguous ranges of tiles over
+// the 8 XCDs: consecutive workgroups are dispatched round-robin to the XCDs,
+// so workgroup b is given logical tile (b % 8) * (n / 8) + b / 8, which keeps
+// neighbouring tiles (which share halo lines) in one XCD's L2.
+__device__ __forceinline__ void xcd_tile(unsigned nb, unsigned tx_tiles, unsigned ty_tiles,
+                                         int &bxi, int &byi, int &bzi)
+{
+    unsigned b = blockIdx.x;
+    const unsigned full = nb & ~7u;
+    if (b < full)
+        b = (b & 7u) * (full >> 3) + (b >> 3);
+    bxi = (int)(b % tx_tiles);
+    byi = (int)((b / tx_tiles) % ty_tiles);
+    bzi = (int)(b / (tx_tiles * ty_tiles));
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T *__restrict__ bx,
+                                                         const T *__restrict__ by,
+                                                         const T *__restrict__ bz,
+                                                         const T *__restrict__ r,
+                                                         const T *__restrict__ ein,
+                                                         T *__restrict__ eout,
+                                                         typename Acc<T>::type h2, int c0, int kz,
+                                                         unsigned tx_tiles, unsigned ty_tiles)
+{
+    using C = typename Acc<T>::type;
+    using T2 = typename Vec2<T>::type;
+    // LDS: e_in, beta_x and beta_y of planes k and k+1 (two slots) for the
+    // in-plane neighbours, and the first-colour values of planes k-2..k
+    __shared__ C SE[2][FRY][FLW];
+    __shared__ C SX[2][FRY][FLW];
+    __shared__ C SY[2][FRY][FLW];
+    __shared__ C RED[3][FRY][FLW];
+    int bxi, byi, bzi;
+    xcd_tile(gridDim.x, tx_tiles, ty_tiles, bxi, byi, bzi);
+    const int i0 = bxi * FTX, j0 = byi * FTY;
+    const int k0 = bzi * kz;
+    const int k1 = min(k0 + kz, d.nz);
+
+    const int tid = threadIdx.x;
+    const bool in_layout = tid < FPX * FRY;
+    const int pl = tid % FPX - 1;     // pair within the tile; -1 and FTX/2 are ring pairs
+    const int rl = tid / FPX - 1;     // row within the tile; -1 and FTY are ring rows
+    int x = i0 + 2 * pl;
+    int j = j0 + rl;
+    // the pair / row just past the grid's end is the periodic wrap: ring only
+    const bool ringx = pl < 0 || pl >= FTX / 2 || x == d.nx;
+    const bool ringy = rl < 0 || rl >= FTY || j == d.ny;
+    bool act = in_layout;             // loads its pair into LDS
+    if (x < 0) {
+        if (bc.x) act = false; else x += d.nx;
+    } else if (x >= d.nx) {
+        if (bc.x || x > d.nx) act = false; else x = 0;
+    }
+    if (j < 0) {
+        if (bc.y) act = false; else j += d.ny;
+    } else if (j >= d.ny) {
+        if (bc.y || j > d.ny) act = false; else j = 0;
+    }
+    if (!act) {
+        x = 0;
+        j = 0;
+    }
+    const bool owned = act && !ringx && !ringy;
+    // which first-colour cell of the pair the tile needs from this thread:
+    // 3 = both, 2 = only the second cell, 1 = only the first, 0 = none
+    int need = 0;
+    if (act && !(ringx && ringy))
+        need = !ringx ? 3 : (pl < 0 ? 2 : 1);
+    const bool dn_row = act && rl < 0 && !ringx;                        // loads the row below
+    const bool up_row = act && ringy && rl >= 0 && !ringx;              // loads the row above
+    const size_t sy = (size_t)d.nx;
+    const size_t sz = (size_t)d.nx * d.ny;
+    const int jm = (j == 0) ? d.ny - 1 : j - 1;
+    const int jp = (j == d.ny - 1) ? 0 : j + 1;
+    const bool wyl = bc.y && j == 0, wyh = bc.y && j == d.ny - 1;
+    const bool wxl = bc.x && x == 0, wxh = bc.x && x + 2 == d.nx;
+    const size_t rowc = (size_t)j * sy + x;
+    const size_t rowo = (size_t)(dn_row ? jm : jp) * sy + x;
+    const int lx = 2 * pl + 2;        // LDS column of the pair's first cell
+    const int ly = rl + 1;
+
+    auto plane = [&](int q, int &qw) -> bool {
+        qw = q;
+        if (q < 0) {
+            if (bc.z) return false;
+            qw = q + d.nz;
+        } else if (q >= d.nz) {
+            if (bc.z) return false;
+            qw = q - d.nz;
+        }
+        return true;
+    };
+    auto ld2 = [&](const T *p, size_t i) -> T2 { return *reinterpret_cast<const T2 *>(p + i); };
+    auto load_in = [&](int q) -> PairIn<T> {
+        PairIn<T> v;
+        const T2 z2 = {T(0), T(0)};
+        v.e = z2; v.r = z2; v.bx = z2; v.by = z2; v.bz = z2; v.eo = z2; v.byo = z2;
+        int qw;
+        if (!act || !plane(q, qw))
+            return v;
+        const size_t base = (size_t)qw * sz;
+        if (!ZERO)
+            v.e = ld2(ein, base + rowc);
+        v.r = ld2(r, base + rowc);
+        v.bx = ld2(bx, base + rowc);
+        v.by = ld2(by, base + rowc);
+        v.bz = ld2(bz, base + rowc);
+        if (!ZERO && (dn_row || up_row))
+            v.eo = ld2(ein, base + rowo);
+        if (up_row)
+            v.byo = ld2(by, base + rowo);
+        if (bc.z && qw == 0)
+            v.bz = z2;                // the wall below plane 0
+        return v;
+    };
+    auto publish = [&](int slot, const PairIn<T> &v) {
+        if (!in_layout)
+            return;
+        SE[slot][ly][lx] = C(v.e.x);
+        SE[slot][ly][lx + 1] = C(v.e.y);
+        SX[slot][ly][lx] = C(v.bx.x);
+        SX[slot][ly][lx + 1] = C(v.bx.y);
+        SY[slot][ly][lx] = C(v.by.x);
+        SY[slot][ly][lx + 1] = C(v.by.y);
+    };
+
+    // pipeline: inputs of planes k-1, k, k+1 resident, k+2 in flight
+    PairIn<T> pm = load_in(k0 - 2), pc = load_in(k0 - 1), pn = load_in(k0), pf;
+    publish((k0 - 1) & 1, pc);
+    __syncthreads();
+    C red_km2 = C(0), red_km1 = C(0);
+    C bxh_prev = C(0), byh_prev = C(0);   // high x / y faces of the second-colour cell, plane k-1
+
+    for (int k = k0 - 1; k <= k1; ++k) {
+        pf = load_in(k + 2);
+        const int si = k & 1;
+        int kw;
+        const bool kin = act && plane(k, kw);
+        const int o = (c0 + j + (kin ? kw : k)) & 1;     // first-colour cell of the pair in plane k
+        // phase A: first colour of plane k
+        C red = C(0);
+        if (kin && (need & (1 << o))) {
+            const int cx = lx + o;
+            C xl, xh, yl, yh, zl, zh, rr, exm, exp, eym, eyp, ezm, ezp;
+            if (o == 0) {
+                xl = wxl ? C(0) : C(pc.bx.x);
+                xh = C(pc.bx.y);
+                yl = wyl ? C(0) : C(pc.by.x);
+                zl = C(pc.bz.x);
+                zh = C(pn.bz.x);
+                rr = C(pc.r.x);
+                exp = C(pc.e.y);
+                ezm = C(pm.e.x);
+                ezp = C(pn.e.x);
+            } else {
+                xl = C(pc.bx.y);
+                xh = wxh ? C(0) : SX[si][ly][lx + 2];
+                yl = wyl ? C(0) : C(pc.by.y);
+                zl = C(pc.bz.y);
+                zh = C(pn.bz.y);
+                rr = C(pc.r.y);
+                exm = C(pc.e.x);
+                ezm = C(pm.e.y);
+                ezp = C(pn.e.y);
+            }
+            if (o == 0)
+                exm = SE[si][ly][cx - 1];
+            else
+                exp = SE[si][ly][cx + 1];
+            if (up_row) {
+                yh = wyh ? C(0) : C(o == 0 ? pc.byo.x : pc.byo.y);
+                eyp = C(o == 0 ? pc.eo.x : pc.eo.y);
+            } else {
+                yh = wyh ? C(0) : SY[si][ly + 1][cx];
+                eyp = SE[si][ly + 1][cx];
+            }
+            eym = dn_row ? C(o == 0 ? pc.eo.x : pc.eo.y) : SE[si][ly - 1][cx];
+            const C diag = (xl + xh) + (yl + yh) + (zl + zh);
+            C s = C(0);
+            if (!ZERO)
+                s = xl * exm + xh * exp + yl * eym + yh * eyp + zl * ezm + zh * ezp;
+            red = (s - h2 * rr) / diag;
+        }
+        // the second-colour cell of this plane (used in phase B at the next
+        // step) needs its high x / y faces from the neighbours' LDS entries
+        C bxh_cur = C(0), byh_cur = C(0);
+        if (owned) {
+            const int ob = 1 - o;
+            bxh_cur = ob == 0 ? C(pc.bx.y) : (wxh ? C(0) : SX[si][ly][lx + 2]);
+            byh_cur = wyh ? C(0) : SY[si][ly + 1][lx + ob];
+        }
+        const int sa = slot3(k);
+        if (in_layout) {
+            RED[sa][ly][lx + o] = red;
+            RED[sa][ly][lx + 1 - o] = C(0);
+        }
+        publish(si ^ 1, pn);          // plane k+1 for the next step's phase A
+        __syncthreads();
+        // phase B: second colour of plane k-1, then store the finished pair
+        const int kb = k - 1;
+        if (owned && kb >= k0) {
+            const int sb = slot3(kb);
+            const int ob = o;                            // second-colour cell in plane k-1
+            const int cx = lx + ob;
+            C xl, xh, yl, zl, zh, rr;
+            if (ob == 0) {
+                xl = wxl ? C(0) : C(pm.bx.x);
+                yl = wyl ? C(0) : C(pm.by.x);
+                zl = C(pm.bz.x);
+                zh = C(pc.bz.x);
+                rr = C(pm.r.x);
+            } else {
+                xl = C(pm.bx.y);
+                yl = wyl ? C(0) : C(pm.by.y);
+                zl = C(pm.bz.y);
+                zh = C(pc.bz.y);
+                rr = C(pm.r.y);
+            }
+            xh = bxh_prev;
+            const C yh = byh_prev;
+            const C s = xl * RED[sb][ly][cx - 1] + xh * RED[sb][ly][cx + 1] +
+                        yl * RED[sb][ly - 1][cx] + yh * RED[sb][ly + 1][cx] + zl * red_km2 +
+                        zh * red;
+            const C diag = (xl + xh) + (yl + yh) + (zl + zh);
+            const C blk = (s - h2 * rr) / diag;
+            T2 outv;
+            if (ob == 0) {
+                outv.x = static_cast<T>(blk);
+                outv.y = static_cast<T>(red_km1);
+            } else {
+                outv.x = static_cast<T>(red_km1);
+                outv.y = static_cast<T>(blk);
+            }
+            *reinterpret_cast<T2 *>(eout + (size_t)kb * sz + rowc) = outv;
+        }
+        // rotate the pipeline
+        red_km2 = red_km1;
+        red_km1 = red;
+        bxh_prev = bxh_cur;
+        byh_prev = byh_cur;
+        pm = pc;
+        pc = pn;
+        pn = pf;
+    }
+}
+
+// rH = mean over the 8 children of (r - A e).  One thread per coarse cell;
+// the two x-children of each of its four (y, z) child rows are handled as a
+// pair with two-element vector loads.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const T *__restrict__ bx,
                                                           const T *__restrict__ by,
@@ -165,23 +470,55 @@ __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const 
                                                           typename Acc<T>::type ih2)
 {
     using C = typename Acc<T>::type;
+    using T2 = typename Vec2<T>::type;
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     const int I = blockIdx.x * BX + threadIdx.x;
     const int J = blockIdx.y * BY + threadIdx.y;
     const int K = blockIdx.z;
     if (I >= cd.nx || J >= cd.ny)
         return;
+    const size_t sy = (size_t)fd.nx, sz = (size_t)fd.nx * fd.ny;
+    const int x = 2 * I;
+    const int xm1 = (x == 0) ? fd.nx - 1 : x - 1;
+    const int xp2 = (x + 2 == fd.nx) ? 0 : x + 2;
+    const bool wxl = bc.x && x == 0, wxh = bc.x && x + 2 == fd.nx;
+    auto ld2 = [](const T *p, size_t i) -> T2 { return *reinterpret_cast<const T2 *>(p + i); };
     C acc = C(0);
+#pragma unroll 1
+    for (int dk = 0; dk < 2; ++dk) {
+        const int k = 2 * K + dk;
+        const int km = (k == 0) ? fd.nz - 1 : k - 1, kp = (k == fd.nz - 1) ? 0 : k + 1;
+        const bool wzl = bc.z && k == 0, wzh = bc.z && k == fd.nz - 1;
 #pragma unroll
-    for (int dk = 0; dk < 2; ++dk)
-#pragma unroll
-        for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-            for (int di = 0; di < 2; ++di) {
-                const Nb n = neighbours(fd, bc, 2 * I + di, 2 * J + dj, 2 * K + dk);
-                const Links<T> L = links(n, bx, by, bz);
-                acc += ld(r, n.c) - ih2 * flux_sum(n, L, e);
-            }
+        for (int dj = 0; dj < 2; ++dj) {
+            const int j = 2 * J + dj;
+            const int jm = (j == 0) ? fd.ny - 1 : j - 1, jp = (j == fd.ny - 1) ? 0 : j + 1;
+            const bool wyl = bc.y && j == 0, wyh = bc.y && j == fd.ny - 1;
+            const size_t plane = (size_t)k * sz, rowj = (size_t)j * sy;
+            const size_t c = plane + rowj + x;
+            const T2 ec = ld2(e, c), rr = ld2(r, c), xx = ld2(bx, c), ylo = ld2(by, c), zlo = ld2(bz, c);
+            const T2 yhi = ld2(by, plane + (size_t)jp * sy + x);
+            const T2 zhi = ld2(bz, (size_t)kp * sz + rowj + x);
+            const T2 eym = ld2(e, plane + (size_t)jm * sy + x), eyp = ld2(e, plane + (size_t)jp * sy + x);
+            const T2 ezm = ld2(e, (size_t)km * sz + rowj + x), ezp = ld2(e, (size_t)kp * sz + rowj + x);
+            const C exm = ld(e, plane + rowj + xm1), exp = ld(e, plane + rowj + xp2);
+            const C bxn = ld(bx, plane + rowj + xp2);
+            const C e0 = C(ec.x), e1 = C(ec.y);
+            // cell x
+            const C f0 = C(xx.y) * (e1 - e0) - (wxl ? C(0) : C(xx.x)) * (e0 - exm) +
+                         (wyh ? C(0) : C(yhi.x)) * (C(eyp.x) - e0) -
+                         (wyl ? C(0) : C(ylo.x)) * (e0 - C(eym.x)) +
+                         (wzh ? C(0) : C(zhi.x)) * (C(ezp.x) - e0) -
+                         (wzl ? C(0) : C(zlo.x)) * (e0 - C(ezm.x));
+            // cell x + 1
+            const C f1 = (wxh ? C(0) : bxn) * (exp - e1) - C(xx.y) * (e1 - e0) +
+                         (wyh ? C(0) : C(yhi.y)) * (C(eyp.y) - e1) -
+                         (wyl ? C(0) : C(ylo.y)) * (e1 - C(eym.y)) +
+                         (wzh ? C(0) : C(zhi.y)) * (C(ezp.y) - e1) -
+                         (wzl ? C(0) : C(zlo.y)) * (e1 - C(ezm.y));
+            acc += (C(rr.x) - ih2 * f0) + (C(rr.y) - ih2 * f1);
+        }
+    }
     rH[((size_t)K * cd.ny + J) * cd.nx + I] = static_cast<T>(acc * C(0.125));
 }
 
@@ -306,15 +643,17 @@ __global__ __launch_bounds__(BLOCK) void k_check_beta(Dims d, Bc bc, const doubl
     __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
     double v[1] = {0.0};
     if (i < d.nx && j < d.ny) {
-        const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
-        const double b[3] = {bx[c], by[c], bz[c]};
-        const bool wall[3] = {bc.x && i == 0, bc.y && j == 0, bc.z && k == 0};
-        for (int m = 0; m < 3; ++m)
-            if (!wall[m] && !(b[m] > 0.0 && b[m] < INFINITY))
-                v[0] += 1.0;
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+            const double b[3] = {bx[c], by[c], bz[c]};
+            const bool wall[3] = {bc.x && i == 0, bc.y && j == 0, bc.z && k == 0};
+            for (int m = 0; m < 3; ++m)
+                if (!wall[m] && !(b[m] > 0.0 && b[m] < INFINITY))
+                    v[0] += 1.0;
+        }
     }
     block_partials<1>(v, sm, part, 0);
 }
@@ -414,7 +753,31 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(Dims d, Bc bc, const do
     gz[n.c] = n.wzl ? 0.0 : ih2 * (lc - lam[n.zm]) * (pc - p[n.zm]);
 }
 
-__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, size_t n)
+// Streaming copy: 16-byte accesses, four independent loads per thread in
+// flight, a grid that fills every CU several times over.
+__global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src,
+                                              double *__restrict__ dst, size_t n)
+{
+    using D2 = double __attribute__((ext_vector_type(2)));
+    const size_t n2 = n / 2;
+    const D2 *s2 = reinterpret_cast<const D2 *>(src);
+    D2 *d2 = reinterpret_cast<D2 *>(dst);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n2; i += 4 * stride) {
+        const D2 a = s2[i], b = s2[i + stride], c = s2[i + 2 * stride], e = s2[i + 3 * stride];
+        d2[i] = a;
+        d2[i + stride] = b;
+        d2[i + 2 * stride] = c;
+        d2[i + 3 * stride] = e;
+    }
+    for (; i < n2; i += stride)
+        d2[i] = s2[i];
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+        dst[n - 1] = src[n - 1];
+}
+
+__global__ void k_copy_unaligned(const double *__restrict__ src, double *__restrict__ dst, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
@@ -437,10 +800,12 @@ __global__ __launch_bounds__(BLOCK) void k_sum(Dims d, const double *__restrict_
     __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
     double v[1] = {0.0};
-    if (i < d.nx && j < d.ny)
-        v[0] = x[((size_t)k * d.ny + j) * d.nx + i];
+    if (i < d.nx && j < d.ny) {
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k)
+            v[0] += x[((size_t)k * d.ny + j) * d.nx + i];
+    }
     block_partials<1>(v, sm, part, 0);
 }
 
@@ -528,22 +893,25 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
     __shared__ double sm[2][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
     double v[2] = {0.0, 0.0};
     if (i < d.nx && j < d.ny) {
-        const Nb n = neighbours(d, bc, i, j, k);
-        const double bm = b[n.c] - scal[S_MEAN];
-        double ax = 0.0;
-        if (ZEROX) {
-            x[n.c] = 0.0;
-        } else {
-            const Links<double> L = links(n, bx, by, bz);
-            ax = ih2 * flux_sum(n, L, x);
+        const double mean = scal[S_MEAN];
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const Nb n = neighbours(d, bc, i, j, k);
+            const double bm = b[n.c] - mean;
+            double ax = 0.0;
+            if (ZEROX) {
+                x[n.c] = 0.0;
+            } else {
+                const Links<double> L = links(n, bx, by, bz);
+                ax = ih2 * flux_sum(n, L, x);
+            }
+            const double r = bm - ax;
+            r64[n.c] = r;
+            v[0] += r * r;
+            v[1] += bm * bm;
         }
-        const double r = bm - ax;
-        r64[n.c] = r;
-        v[0] = r * r;
-        v[1] = bm * bm;
     }
     block_partials<2>(v, sm, part, pstride);
 }
@@ -561,14 +929,18 @@ __global__ __launch_bounds__(BLOCK) void k_residual_T(Dims d, Bc bc, const doubl
     __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
     double v[1] = {0.0};
     if (i < d.nx && j < d.ny) {
-        const Nb n = neighbours(d, bc, i, j, k);
-        const Links<double> L = links(n, bx, by, bz);
-        const double r = (b[n.c] - scal[S_MEAN]) - ih2 * flux_sum(n, L, x);
-        rT[n.c] = static_cast<T>(r / scal[S_NEXT]);
-        v[0] = r * r;
+        const double mean = scal[S_MEAN];
+        const double inv = 1.0 / scal[S_NEXT];
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const Nb n = neighbours(d, bc, i, j, k);
+            const Links<double> L = links(n, bx, by, bz);
+            const double r = (b[n.c] - mean) - ih2 * flux_sum(n, L, x);
+            rT[n.c] = static_cast<T>(r * inv);
+            v[0] += r * r;
+        }
     }
     block_partials<1>(v, sm, part, 0);
 }
@@ -602,48 +974,59 @@ __global__ __launch_bounds__(BLOCK) void k_dot_rz(Dims d, const double *__restri
     __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
     double v[1] = {0.0};
     if (i < d.nx && j < d.ny) {
-        const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
-        v[0] = r[c] * static_cast<double>(z[c]);
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+            v[0] += r[c] * static_cast<double>(z[c]);
+        }
     }
     block_partials<1>(v, sm, part, 0);
 }
 
-// d = s z + beta d  (first iteration: d = s z)
+// New search direction and its image in one pass:
+//   d_new = s z + beta d_old   (s = scal[S_USED]; beta = scal[S_BETA], or 0 on
+//                               the first iteration, when d_old is not read)
+//   q = A d_new,  partial d_new . q
+// d_new is recomputed at the six neighbours from z and d_old (the same
+// expression, so the same bits), which is why d_new and d_old are different
+// buffers.
 template <typename T, bool FIRST>
-__global__ void k_pcg_dir(size_t n, const T *__restrict__ z, double *__restrict__ dv,
-                          const double *__restrict__ scal)
-{
-    const double s = scal[S_USED];
-    const double beta = scal[S_BETA];
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double zz = s * static_cast<double>(z[i]);
-        dv[i] = FIRST ? zz : zz + beta * dv[i];
-    }
-}
-
-// q = A d; partial d . q
-__global__ __launch_bounds__(BLOCK) void k_apply_dot(Dims d, Bc bc, const double *__restrict__ bx,
+__global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double *__restrict__ bx,
                                                      const double *__restrict__ by,
                                                      const double *__restrict__ bz,
-                                                     const double *__restrict__ dv,
-                                                     double *__restrict__ q, double ih2,
+                                                     const T *__restrict__ z,
+                                                     const double *__restrict__ dold,
+                                                     double *__restrict__ dnew,
+                                                     double *__restrict__ q,
+                                                     const double *__restrict__ scal, double ih2,
                                                      double *part)
 {
     __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
     double v[1] = {0.0};
     if (i < d.nx && j < d.ny) {
-        const Nb n = neighbours(d, bc, i, j, k);
-        const Links<double> L = links(n, bx, by, bz);
-        const double qq = ih2 * flux_sum(n, L, dv);
-        q[n.c] = qq;
-        v[0] = dv[n.c] * qq;
+        const double s = scal[S_USED];
+        const double beta = FIRST ? 0.0 : scal[S_BETA];
+        auto dv = [&](size_t c) -> double {
+            const double t = s * static_cast<double>(z[c]);
+            return FIRST ? t : t + beta * dold[c];
+        };
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const Nb n = neighbours(d, bc, i, j, k);
+            const Links<double> L = links(n, bx, by, bz);
+            const double dc = dv(n.c);
+            const double f = L.xh * (dv(n.xp) - dc) - L.xl * (dc - dv(n.xm)) +
+                             L.yh * (dv(n.yp) - dc) - L.yl * (dc - dv(n.ym)) +
+                             L.zh * (dv(n.zp) - dc) - L.zl * (dc - dv(n.zm));
+            const double qq = ih2 * f;
+            dnew[n.c] = dc;
+            q[n.c] = qq;
+            v[0] += dc * qq;
+        }
     }
     block_partials<1>(v, sm, part, 0);
 }
@@ -662,17 +1045,20 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__re
     __shared__ double sm[2][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
     double v[2] = {0.0, 0.0};
     if (i < d.nx && j < d.ny) {
-        const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
         const double alpha = scal[S_ALPHA];
-        x[c] += alpha * dv[c];
-        const double rn = r[c] - alpha * q[c];
-        r[c] = rn;
-        rT[c] = static_cast<T>(rn / scal[S_NEXT]);
-        v[0] = rn * rn;
-        v[1] = rn * static_cast<double>(zold[c]);
+        const double inv = 1.0 / scal[S_NEXT];
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+            x[c] += alpha * dv[c];
+            const double rn = r[c] - alpha * q[c];
+            r[c] = rn;
+            rT[c] = static_cast<T>(rn * inv);
+            v[0] += rn * rn;
+            v[1] += rn * static_cast<double>(zold[c]);
+        }
     }
     block_partials<2>(v, sm, part, pstride);
 }
@@ -712,6 +1098,62 @@ void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *
     else
         hipLaunchKernelGGL((k_rbgs<T, false>), colour_grid(d), kBlock, 0, s, d, bc, bx, by, bz, r,
                            e, (C)h2, colour);
+}
+
+// Workgroups of a kernel that the whole GPU holds at once (occupancy x CUs),
+// queried once per kernel and device.
+template <typename K>
+static long long resident_slots(K kernel, int block)
+{
+    static long long cached[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64)
+        dev = 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 256;
+        cached[dev] = (long long)per_cu * cus;
+    }
+    return cached[dev];
+}
+
+// Chunk length along z: the smallest chunk (fewest redundant halo planes)
+// whose workgroups all fit on the GPU at once, so a sweep runs as a single
+// round of resident workgroups with no tail.
+static int fused_kz(Dims d, unsigned tiles, long long slots)
+{
+    long long kz = ((long long)d.nz * tiles + slots - 1) / slots;
+    if (kz < 4)
+        kz = 4;
+    if (kz > d.nz)
+        kz = d.nz;
+    return (int)kz;
+}
+
+template <typename T>
+void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
+                       const T *ein, T *eout, double h2, int first_colour, bool zero,
+                       hipStream_t s)
+{
+    using C = typename Acc<T>::type;
+    const unsigned tx = (d.nx + FTX - 1) / FTX, ty = (d.ny + FTY - 1) / FTY;
+    const long long slots = zero ? resident_slots(k_rbgs_fused<T, true>, FTHREADS)
+                                 : resident_slots(k_rbgs_fused<T, false>, FTHREADS);
+    const int kz = fused_kz(d, tx * ty, slots);
+    const unsigned tz = (d.nz + kz - 1) / kz;
+    const dim3 grid(tx * ty * tz);
+    if (zero)
+        hipLaunchKernelGGL((k_rbgs_fused<T, true>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz,
+                           r, ein, eout, (C)h2, first_colour, kz, tx, ty);
+    else
+        hipLaunchKernelGGL((k_rbgs_fused<T, false>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz,
+                           r, ein, eout, (C)h2, first_colour, kz, tx, ty);
 }
 
 template <typename T>
@@ -766,7 +1208,7 @@ void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStr
 void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                        double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check_beta, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, part);
+    hipLaunchKernelGGL(k_check_beta, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, part);
 }
 
 void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by, double *bz,
@@ -804,7 +1246,12 @@ void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, dou
 
 void launch_copy(const double *src, double *dst, size_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy, flat_grid(n), dim3(256), 0, s, src, dst, n);
+    // 2048 x 256 threads: 8 workgroups per CU; 16-byte accesses need
+    // 16-byte aligned pointers, otherwise fall back to the plain loop
+    if (((uintptr_t)src | (uintptr_t)dst) & 15)
+        hipLaunchKernelGGL(k_copy_unaligned, flat_grid(n), dim3(256), 0, s, src, dst, n);
+    else
+        hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, src, dst, n);
 }
 
 void launch_fill(double *x, size_t n, double v, hipStream_t s)
@@ -814,7 +1261,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t s)
 
 void launch_sum(Dims d, const double *x, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum, cell_grid(d), kBlock, 0, s, d, x, part);
+    hipLaunchKernelGGL(k_sum, red_grid(d), kBlock, 0, s, d, x, part);
 }
 
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
@@ -829,10 +1276,10 @@ void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const do
                      double ih2, double *part, size_t pstride, hipStream_t s)
 {
     if (zero_x)
-        hipLaunchKernelGGL(k_residual<true>, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal,
+        hipLaunchKernelGGL(k_residual<true>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal,
                            x, r64, ih2, part, pstride);
     else
-        hipLaunchKernelGGL(k_residual<false>, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b,
+        hipLaunchKernelGGL(k_residual<false>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b,
                            scal, x, r64, ih2, part, pstride);
 }
 
@@ -841,7 +1288,7 @@ void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const 
                        const double *b, const double *scal, const double *x, T *rT, double ih2,
                        double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_residual_T<T>), cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal, x,
+    hipLaunchKernelGGL((k_residual_T<T>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal, x,
                        rT, ih2, part);
 }
 
@@ -860,24 +1307,21 @@ void launch_axpy_T(size_t n, const T *e, double *x, const double *scal, hipStrea
 template <typename T>
 void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_dot_rz<T>), cell_grid(d), kBlock, 0, s, d, r, z, part);
+    hipLaunchKernelGGL((k_dot_rz<T>), red_grid(d), kBlock, 0, s, d, r, z, part);
 }
+
 
 template <typename T>
-void launch_pcg_dir(size_t n, const T *z, double *dvec, const double *scal, bool first,
-                    hipStream_t s)
+void launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                      const T *z, const double *dold, double *dnew, double *q, const double *scal,
+                      bool first, double ih2, double *part, hipStream_t s)
 {
     if (first)
-        hipLaunchKernelGGL((k_pcg_dir<T, true>), flat_grid(n), dim3(256), 0, s, n, z, dvec, scal);
+        hipLaunchKernelGGL((k_dir_apply<T, true>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
+                           dold, dnew, q, scal, ih2, part);
     else
-        hipLaunchKernelGGL((k_pcg_dir<T, false>), flat_grid(n), dim3(256), 0, s, n, z, dvec, scal);
-}
-
-void launch_apply_dot(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                      const double *dvec, double *q, double ih2, double *part, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_apply_dot, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, dvec, q, ih2,
-                       part);
+        hipLaunchKernelGGL((k_dir_apply<T, false>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
+                           dold, dnew, q, scal, ih2, part);
 }
 
 template <typename T>
@@ -885,7 +1329,7 @@ void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, d
                        const T *zold, const double *scal, double *part, size_t pstride,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pcg_update<T>), cell_grid(d), kBlock, 0, s, d, dvec, q, x, r, rT, zold,
+    hipLaunchKernelGGL((k_pcg_update<T>), red_grid(d), kBlock, 0, s, d, dvec, q, x, r, rT, zold,
                        scal, part, pstride);
 }
 
@@ -901,6 +1345,8 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStrea
     template void launch_resid_restrict<T>(Dims, Bc, const T *, const T *, const T *, const T *, \
                                            const T *, T *, double, hipStream_t);                \
     template void launch_prolong<T>(Dims, Bc, const T *, T *, hipStream_t);                     \
+    template void launch_rbgs_fused<T>(Dims, Bc, const T *, const T *, const T *, const T *,    \
+                                       const T *, T *, double, int, bool, hipStream_t);         \
     template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
     template void launch_convert<T>(size_t, const double *, T *, hipStream_t);                  \
     template void launch_to_double<T>(size_t, const T *, double *, hipStream_t);                \
@@ -910,8 +1356,9 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStrea
     template void launch_scale_T<T>(size_t, const double *, T *, const double *, hipStream_t);  \
     template void launch_axpy_T<T>(size_t, const T *, double *, const double *, hipStream_t);   \
     template void launch_dot_rz<T>(Dims, const double *, const T *, double *, hipStream_t);     \
-    template void launch_pcg_dir<T>(size_t, const T *, double *, const double *, bool,          \
-                                    hipStream_t);                                               \
+    template void launch_dir_apply<T>(Dims, Bc, const double *, const double *, const double *, \
+                                      const T *, const double *, double *, double *,            \
+                                      const double *, bool, double, double *, hipStream_t);     \
     template void launch_pcg_update<T>(Dims, const double *, const double *, double *, double *, \
                                        T *, const T *, const double *, double *, size_t,        \
                                        hipStream_t);

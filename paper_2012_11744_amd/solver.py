@@ -253,6 +253,15 @@ def k_smooth(shape, h, bc, beta, r, e, sweeps=1, zero_init=False):
     return e
 
 
+def k_smooth_fused(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero_init=False):
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    L.check(lib.pp_k_smooth_fused(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r), _ptr(e_in),
+                                  _ptr(e_out), int(first_colour), int(zero_init),
+                                  _stream_handle(None)), "pp_k_smooth_fused")
+    return e_out
+
+
 def k_resid_restrict(shape, h, bc, beta, e, r, rH):
     lib = L.load()
     g = make_grid(shape, h, bc)

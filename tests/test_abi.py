@@ -121,6 +121,14 @@ def test_kernel_entries_validate(lib):
     g2 = _grid((9, 8, 8), 0.1, (0, 0, 0))   # an odd periodic count is not
     assert lib.pp_k_smooth(ctypes.byref(g2), fake, fake, fake, fake, fake, 1, 0, None) == L.PP_EINVAL
     assert lib.pp_k_smooth(ctypes.byref(g), fake, fake, fake, fake, fake, 0, 0, None) == L.PP_EINVAL
+    g3 = _grid((9, 8, 8), 0.1, (1, 0, 0))   # the fused sweep needs even nx even with walls
+    other = ctypes.c_void_p(0x2000)
+    assert lib.pp_k_smooth_fused(ctypes.byref(g3), fake, fake, fake, fake, fake, other, 0, 0,
+                                 None) == L.PP_EINVAL
+    assert lib.pp_k_smooth_fused(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0, 0,
+                                 None) == L.PP_EINVAL      # e_in aliases e_out
+    assert lib.pp_k_smooth_fused(ctypes.byref(g), fake, fake, fake, fake, fake, other, 2, 0,
+                                 None) == L.PP_EINVAL      # bad colour
     assert lib.pp_k_resid_restrict(ctypes.byref(g2), fake, fake, fake, fake, fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g2), fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_copy(None, fake, 10, None) == L.PP_EINVAL

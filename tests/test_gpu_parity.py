@@ -111,6 +111,31 @@ def test_one_gauss_seidel_sweep_matches_paper_sor(S, n, bc):
     assert relmax(host(e), ref2) <= 1e-14
 
 
+@pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0))])
+@pytest.mark.parametrize("first", [0, 1])
+def test_fused_sweep_matches_paper_sor(S, n, bc, first):
+    """One fused out-of-place sweep (tiles of 64 x 8 cells, z chunks, ring
+    recomputation) equals the oracle's sweep of eq. beta_pressure with the
+    same colour order; also from a zero start (e_in not read)."""
+    _say(f"fused rbgs sweep n={n} bc={bc} first={first}")
+    w = W.random_case(n, bc, seed=113)
+    beta = oracle.face_coeffs(w.rho, bc)
+    bt = [dev(b) for b in beta]
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal(w.shape)
+    e0 = rng.standard_normal(w.shape)
+    ref, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=e0, omega=1.0, sweeps=1, first_colour=first)
+    out = dev(np.full(w.shape, np.nan))
+    S.k_smooth_fused(w.shape, w.h, bc, bt, dev(r), dev(e0), out, first_colour=first)
+    assert relmax(host(out), ref) <= 1e-14
+    ref0, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=np.zeros(w.shape), omega=1.0, sweeps=1,
+                              first_colour=first)
+    out = dev(np.full(w.shape, np.nan))
+    S.k_smooth_fused(w.shape, w.h, bc, bt, dev(r), dev(np.full(w.shape, np.nan)), out,
+                     first_colour=first, zero_init=True)
+    assert relmax(host(out), ref0) <= 1e-14
+
+
 def _restrict_ref(x):
     nz, ny, nx = x.shape
     return x.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(1, 3, 5))

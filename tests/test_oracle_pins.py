@@ -277,8 +277,9 @@ def test_paper_rb_sor_matches_dense(bc):
     assert np.abs(p - pd).max() <= 1e-10 * np.abs(pd).max()
 
 
+@pytest.mark.parametrize("first", [0, 1])
 @pytest.mark.parametrize("omega", [1.0, 1.3])
-def test_rb_sor_single_sweep_by_hand(omega):
+def test_rb_sor_single_sweep_by_hand(omega, first):
     """One sweep of eq. beta_pressure, red first, checked against a direct loop
     over cells of the face-assembled matrix."""
     n = (4, 4, 4)
@@ -287,11 +288,11 @@ def test_rb_sor_single_sweep_by_hand(omega):
     rng = np.random.default_rng(5)
     rhs = rng.standard_normal(w.shape)
     p0 = rng.standard_normal(w.shape)
-    p1, _, _ = oracle.rbsor(beta, bc, w.h, rhs, p0=p0, omega=omega, sweeps=1)
+    p1, _, _ = oracle.rbsor(beta, bc, w.h, rhs, p0=p0, omega=omega, sweeps=1, first_colour=first)
     A = dense.matrix(beta, bc, w.h)
     ref = p0.ravel().copy()
     nz, ny, nx = w.shape
-    for colour in (0, 1):
+    for colour in (first, 1 - first):
         for c in range(nz * ny * nx):
             i, j, k = c % nx, (c // nx) % ny, c // (nx * ny)
             if (i + j + k) % 2 != colour:
