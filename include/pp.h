@@ -81,7 +81,8 @@ typedef struct {
     int32_t max_outer;   /* outer iterations before PP_ENOCONV (1..4096) */
     int32_t warm_start;  /* 1: pp_solve starts from the p passed in; 0: from p = 0 */
     int32_t fallback;    /* 1: on stagnation of a mixed solve, continue with FP64 V-cycles */
-    int32_t reserved;
+    int32_t coarse_graph; /* 1: replay the coarse levels of each V-cycle from a HIP graph
+                            captured in pp_setup (same kernels, same order, same results) */
 } pp_opts;
 
 #define PP_HIST 128
@@ -97,7 +98,7 @@ typedef struct {
 } pp_stats;
 
 /* Fill *o with the defaults: mixed FP32, PCG, nu_pre = nu_post = 2,
- * max_outer = 500, warm_start = 0, fallback = 1. */
+ * max_outer = 500, warm_start = 0, fallback = 1, coarse_graph = 1. */
 void pp_opts_default(pp_opts *o);
 
 /* Face coefficients from cell densities, beta_m[c] = 2 / (rho[c - e_m] + rho[c])
@@ -122,7 +123,10 @@ int pp_setup(const pp_grid *grid, const double *beta_x, const double *beta_y,
              const double *beta_z, const pp_opts *opts, void *hip_stream, pp_ctx **out);
 
 /* Replace the face coefficients of an existing context (same grid), rebuilding
- * the hierarchy in place without reallocating.  Same rules as pp_setup. */
+ * the hierarchy in place without reallocating.  Same rules as pp_setup.  If
+ * the coefficients are rejected (PP_EINVAL: a non-wall face that is not a
+ * finite positive number), the context's coefficients are undefined until a
+ * later successful update. */
 int pp_update_coeffs(pp_ctx *ctx, const double *beta_x, const double *beta_y,
                      const double *beta_z);
 

@@ -43,13 +43,15 @@ int pp_k_smooth(const pp_grid *grid, const double *beta_x, const double *beta_y,
  * second colour from the new first-colour values.  Equal, value for value, to
  * two colour passes of pp_k_smooth.  e_in and e_out must not alias;
  * zero_init = 1 treats e_in as zero (it is not read).  nx must be even, and
- * so must the cell count of every periodic direction. */
+ * so must the cell count of every periodic direction; all arrays 16-byte
+ * aligned (the kernel reads x-pairs of cells as vectors). */
 int pp_k_smooth_fused(const pp_grid *grid, const double *beta_x, const double *beta_y,
                       const double *beta_z, const double *r, const double *e_in, double *e_out,
                       int32_t first_colour, int32_t zero_init, void *hip_stream);
 
 /* rH[C] = (1/8) sum over the 8 fine cells c of C of (r - A e)[c].
- * grid: the fine grid (all n even); rH has n/2 cells per direction. */
+ * grid: the fine grid (all n even); rH has n/2 cells per direction; beta,
+ * e and r 16-byte aligned. */
 int pp_k_resid_restrict(const pp_grid *grid, const double *beta_x, const double *beta_y,
                         const double *beta_z, const double *e, const double *r, double *rH,
                         void *hip_stream);
@@ -70,10 +72,11 @@ int pp_vcycle(pp_ctx *ctx, const double *r, double *e);
 /* Plain device copy kernel dst[i] = src[i], i < count (bandwidth reference). */
 int pp_k_copy(const double *src, double *dst, int64_t count, void *hip_stream);
 
-/* Kernel timing on the context's stream: while enabled, every launch of the
- * fine-level kernels below is bracketed by HIP events and its duration is
- * accumulated per kind.  pp_timing_get reports launches and total ms since
- * the last reset (events are resolved when a solve ends or when queried). */
+/* Kernel timing on the context's stream: every launch of a fine-level kernel
+ * whose kind bit is set in `mask` (bit k = 1 << PP_KT_*) is bracketed by HIP
+ * events and its duration accumulated per kind; mask 0 turns timing off.
+ * pp_timing_get reports launches and total ms since the last reset (events
+ * are resolved when a solve ends or when queried). */
 enum {
     PP_KT_SMOOTH = 0,          /* fine-level red-black half sweep */
     PP_KT_RESTRICT = 1,        /* fine-level residual + restriction */
@@ -82,7 +85,7 @@ enum {
     PP_KT_OUTER_UPDATE = 4,    /* FP64 vector update (+ norms) of the outer loop */
     PP_KT_COUNT = 5
 };
-int pp_timing_enable(pp_ctx *ctx, int32_t on);
+int pp_timing_enable(pp_ctx *ctx, int32_t mask);
 int pp_timing_reset(pp_ctx *ctx);
 int pp_timing_get(pp_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);
 

@@ -11,8 +11,10 @@
 // read back once per outer iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -80,6 +82,8 @@ struct Hier {
     int nlev = 0;
     bool present = false;
     LevelBuf lev[MAXLEV];
+    int tail = 0;                            // first level of the single-workgroup tail
+    hipGraphExec_t coarse_exec = nullptr;   // levels 1 .. L-1 of the cycle
 };
 
 struct EventPair {
@@ -113,6 +117,7 @@ struct pp_ctx {
     int64_t bytes;
     // kernel timing
     bool timing;
+    uint32_t timing_mask;     // bit k: time launches of kind k
     std::vector<EventPair> ev;
     size_t ev_used;
     int64_t kt_count[PP_KT_COUNT];
@@ -204,6 +209,8 @@ int validate_opts(const pp_opts *o)
         return fail(PP_EINVAL, "opts.warm_start must be 0 or 1");
     if (o->fallback != 0 && o->fallback != 1)
         return fail(PP_EINVAL, "opts.fallback must be 0 or 1");
+    if (o->coarse_graph != 0 && o->coarse_graph != 1)
+        return fail(PP_EINVAL, "opts.coarse_graph must be 0 or 1");
     return PP_OK;
 }
 
@@ -217,7 +224,7 @@ struct KT {
     size_t slot;
     KT(pp_ctx *ctx, int k, bool fine) : c(ctx), kind(k), slot((size_t)-1)
     {
-        if (!c->timing || !fine)
+        if (!c->timing || !fine || !((c->timing_mask >> k) & 1u))
             return;
         if (c->ev_used >= c->ev.size())
             return;
@@ -256,6 +263,9 @@ int alloc_hier(pp_ctx *c, Hier &H, int st)
     H.st = st;
     H.nlev = c->nlev;
     H.present = true;
+    H.tail = c->nlev - 1;
+    while (H.tail > 0 && cells(c->ld[H.tail - 1]) <= TAIL_CELLS && c->nlev - (H.tail - 1) <= TAIL_MAX)
+        --H.tail;
     const size_t sb = storage_bytes(st);
     for (int l = 0; l < c->nlev; ++l) {
         LevelBuf &v = H.lev[l];
@@ -276,11 +286,11 @@ int alloc_hier(pp_ctx *c, Hier &H, int st)
     return PP_OK;
 }
 
-int fill_hier(pp_ctx *c, Hier &H)
+int fill_hier(pp_ctx *c, Hier &H, int from)
 {
     if (!H.present || H.st == ST_F64)
         return PP_OK;
-    for (int l = 0; l < c->nlev; ++l) {
+    for (int l = from; l < c->nlev; ++l) {
         const size_t n = cells(c->ld[l]);
         for (int m = 0; m < 3; ++m) {
             if (H.st == ST_F32)
@@ -405,23 +415,51 @@ int nparts(pp_ctx *c) { return (int)grid_blocks(red_grid(c->d)); }
 int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 {
     const double *src[3] = {bx, by, bz};
-    for (int m = 0; m < 3; ++m)
-        PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N, hipMemcpyDeviceToDevice,
-                              c->stream));
-    launch_zero_walls(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->stream);
-    launch_check_beta(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->part, c->stream);
-    launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_COUNT, (double)c->N, 0, c->scal,
-                    c->stream);
+    int first_coarse = 0;   // first level whose coefficients are still to be coarsened from
+    bool level0_converted = false;
+    const bool aligned = !(((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz) & 15);
+    if (c->nlev > 1 && aligned) {
+        // one pass: copy, walls, validity, storage copy of level 0, level 1
+        double *dst[3] = {c->chain[0][0], c->chain[0][1], c->chain[0][2]};
+        double *crs[3] = {c->chain[1][0], c->chain[1][1], c->chain[1][2]};
+        int np = 0;
+        const Hier &H = c->hmix;
+        if (H.present && H.st == ST_F32) {
+            float *t[3] = {(float *)H.lev[0].b[0], (float *)H.lev[0].b[1], (float *)H.lev[0].b[2]};
+            np = launch_load_coeffs<float>(c->d, c->bc, src, dst, t, crs, c->part, c->stream);
+            level0_converted = true;
+        } else if (H.present && H.st == ST_F16) {
+            _Float16 *t[3] = {(_Float16 *)H.lev[0].b[0], (_Float16 *)H.lev[0].b[1],
+                              (_Float16 *)H.lev[0].b[2]};
+            np = launch_load_coeffs<_Float16>(c->d, c->bc, src, dst, t, crs, c->part, c->stream);
+            level0_converted = true;
+        } else {
+            float *t[3] = {nullptr, nullptr, nullptr};
+            np = launch_load_coeffs<float>(c->d, c->bc, src, dst, t, crs, c->part, c->stream);
+        }
+        launch_finalize(c->part, c->pstride, np, OP_STORE, S_COUNT, (double)c->N, 0, c->scal,
+                        c->stream);
+        first_coarse = 1;
+    } else {
+        for (int m = 0; m < 3; ++m)
+            PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        launch_zero_walls(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->stream);
+        launch_check_beta(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->part,
+                          c->stream);
+        launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_COUNT, (double)c->N, 0,
+                        c->scal, c->stream);
+    }
     PP_TRY(check_launch("coefficient check"));
+    for (int l = first_coarse; l + 1 < c->nlev; ++l)
+        launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
+                            c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2], c->stream);
+    PP_TRY(check_launch("coarsen coefficients"));
+    PP_TRY(fill_hier(c, c->hmix, level0_converted ? 1 : 0));
     PP_TRY(read_scal(c));
     if (c->hscal[S_COUNT] != 0.0)
         return fail(PP_EINVAL, "beta: " + std::to_string((long long)c->hscal[S_COUNT]) +
                                    " non-wall faces are not finite positive numbers");
-    for (int l = 0; l + 1 < c->nlev; ++l)
-        launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
-                            c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2], c->stream);
-    PP_TRY(check_launch("coarsen coefficients"));
-    PP_TRY(fill_hier(c, c->hmix));
     PP_TRY(build_pinv(c));
     return PP_OK;
 }
@@ -430,16 +468,18 @@ int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 // V-cycle
 // ---------------------------------------------------------------------------
 
+// nu_pre red-black sweeps (red first) from e = 0 on level l, then residual +
+// restriction into the right-hand side of level l + 1.  Large levels use the
+// fused out-of-place sweep (ping-pong between e and e2); smaller ones, where
+// the fused kernel's march along z is latency-bound, use one launch per
+// colour in place.
 template <typename T>
-void vcycle_run(pp_ctx *c, Hier &H)
+void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s)
 {
-    hipStream_t s = c->stream;
-    const int L = H.nlev;
-    // down: nu_pre fused sweeps (red first) from e = 0, then residual + restriction
-    for (int l = 0; l + 1 < L; ++l) {
-        LevelBuf &v = H.lev[l];
-        const double h2 = v.h * v.h;
-        const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
+    LevelBuf &v = H.lev[l];
+    const double h2 = v.h * v.h;
+    const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
+    if (cells(v.d) > FUSED_MIN_CELLS) {
         void *cur = v.e2;
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
             void *out = (cur == v.e) ? v.e2 : v.e;
@@ -449,23 +489,31 @@ void vcycle_run(pp_ctx *c, Hier &H)
             cur = out;
         }
         v.cur = cur;
-        KT t(c, PP_KT_RESTRICT, l == 0);
-        launch_resid_restrict<T>(v.d, c->bc, b0, b1, b2, (const T *)v.cur, (const T *)v.r,
-                                 (T *)H.lev[l + 1].r, 1.0 / h2, s);
-    }
-    LevelBuf &vc = H.lev[L - 1];
-    launch_coarsest<T>(c->ncoarse, c->pinv, (const T *)vc.r, (T *)vc.e, s);
-    vc.cur = vc.e;
-    // up: prolongation + correction, then nu_post fused sweeps (black first),
-    // the mirror image of the way down so the cycle is a symmetric operator
-    for (int l = L - 2; l >= 0; --l) {
-        LevelBuf &v = H.lev[l];
-        const double h2 = v.h * v.h;
-        const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
-        {
-            KT t(c, PP_KT_PROLONG, l == 0);
-            launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
+    } else {
+        for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 0, sw == 0, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 1, false, s);
         }
+        v.cur = v.e;
+    }
+    KT t(c, PP_KT_RESTRICT, l == 0);
+    launch_resid_restrict<T>(v.d, c->bc, b0, b1, b2, (const T *)v.cur, (const T *)v.r,
+                             (T *)H.lev[l + 1].r, 1.0 / h2, s);
+}
+
+// prolongation + correction from level l + 1, then nu_post sweeps (black
+// first): the mirror image of level_down, so the cycle is symmetric
+template <typename T>
+void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
+{
+    LevelBuf &v = H.lev[l];
+    const double h2 = v.h * v.h;
+    const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
+    {
+        KT t(c, PP_KT_PROLONG, l == 0);
+        launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
+    }
+    if (cells(v.d) > FUSED_MIN_CELLS) {
         void *cur = v.cur;
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
             void *out = (cur == v.e) ? v.e2 : v.e;
@@ -475,7 +523,113 @@ void vcycle_run(pp_ctx *c, Hier &H)
             cur = out;
         }
         v.cur = cur;
+    } else {
+        for (int sw = 0; sw < c->opts.nu_post; ++sw) {
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, h2, 1, false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, h2, 0, false, s);
+        }
     }
+}
+
+// levels t .. L-1 (the tail) in one single-workgroup kernel, in place on e
+template <typename T>
+void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
+{
+    const int n = H.nlev - t;
+    Dims d[TAIL_MAX];
+    double h2[TAIL_MAX];
+    const void *b[TAIL_MAX][3];
+    void *e[TAIL_MAX];
+    void *r[TAIL_MAX];
+    for (int q = 0; q < n; ++q) {
+        LevelBuf &v = H.lev[t + q];
+        d[q] = v.d;
+        h2[q] = v.h * v.h;
+        for (int m = 0; m < 3; ++m)
+            b[q][m] = v.b[m];
+        e[q] = v.e;
+        r[q] = v.r;
+        v.cur = v.e;
+    }
+    launch_tail<T>(n, d, h2, b, e, r, c->bc, c->opts.nu_pre, c->opts.nu_post, c->pinv, c->ncoarse,
+                   s);
+}
+
+// the V-cycle restricted to levels from .. L-1 (input: lev[from].r)
+template <typename T>
+void cycle_from(pp_ctx *c, Hier &H, int from, hipStream_t s)
+{
+    const int t = std::max(H.tail, from);
+    for (int l = from; l < t; ++l)
+        level_down<T>(c, H, l, s);
+    run_tail<T>(c, H, t, s);
+    for (int l = t - 1; l >= from; --l)
+        level_up<T>(c, H, l, s);
+}
+
+// One V-cycle for A e = r on level 0 (input lev[0].r, output lev[0].cur).
+// Levels 1 .. L-1 are short kernels whose cost is launch latency; they are
+// replayed from a HIP graph captured at setup when one is available.
+template <typename T>
+void vcycle_run(pp_ctx *c, Hier &H)
+{
+    hipStream_t s = c->stream;
+    if (H.tail == 0) {
+        cycle_from<T>(c, H, 0, s);
+        return;
+    }
+    level_down<T>(c, H, 0, s);
+    if (!H.coarse_exec || hipGraphLaunch(H.coarse_exec, s) != hipSuccess)
+        cycle_from<T>(c, H, 1, s);    // no graph, or it could not be launched: run eagerly
+    level_up<T>(c, H, 0, s);
+}
+
+// Record levels 1 .. L-1 of the cycle into a graph on a private stream.  The
+// host-side bookkeeping of which correction buffer is current is the same at
+// every replay, because the captured sequence is fixed.
+template <typename T>
+int capture_coarse(pp_ctx *c, Hier &H)
+{
+    if (!H.present || H.tail < 2)
+        return PP_OK;             // levels 1 .. L-1 are one kernel or none
+    prepare_fused<T>();
+    hipStream_t cap = nullptr;
+    PP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        cycle_from<T>(c, H, 1, cap);
+        e = hipStreamEndCapture(cap, &g);
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&H.coarse_exec, g, nullptr, nullptr, 0);
+    if (g)
+        (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        H.coarse_exec = nullptr;
+        return fail(PP_EHIP, std::string("capturing the coarse-level graph: ") + hipGetErrorString(e));
+    }
+    return PP_OK;
+}
+
+int capture_graphs(pp_ctx *c)
+{
+    if (!c->opts.coarse_graph)
+        return PP_OK;
+    for (Hier *H : {&c->hmix, &c->h64}) {
+        if (!H->present)
+            continue;
+        int rc = PP_OK;
+        switch (H->st) {
+        case ST_F64: rc = capture_coarse<double>(c, *H); break;
+        case ST_F32: rc = capture_coarse<float>(c, *H); break;
+        default: rc = capture_coarse<_Float16>(c, *H); break;
+        }
+        if (rc != PP_OK)
+            return rc;
+    }
+    return PP_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -729,6 +883,7 @@ void pp_opts_default(pp_opts *o)
     o->max_outer = 500;
     o->warm_start = 0;
     o->fallback = 1;
+    o->coarse_graph = 1;
 }
 
 const char *pp_strerror(int status)
@@ -761,6 +916,9 @@ void pp_destroy(pp_ctx *c)
     if (!c)
         return;
     (void)hipStreamSynchronize(c->stream);
+    for (Hier *H : {&c->hmix, &c->h64})
+        if (H->coarse_exec)
+            (void)hipGraphExecDestroy(H->coarse_exec);
     for (auto &e : c->ev) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -843,6 +1001,8 @@ int pp_setup(const pp_grid *grid, const double *bx, const double *by, const doub
     if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
         return bail(fail(PP_EHIP, "hipMemsetAsync failed"));
     rc = load_coeffs(c, bx, by, bz);
+    if (rc == PP_OK)
+        rc = capture_graphs(c);
     if (rc != PP_OK)
         return bail(rc);
     *out = c;
@@ -989,6 +1149,9 @@ int pp_k_smooth_fused(const pp_grid *grid, const double *bx, const double *by, c
     PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
     if (!bx || !by || !bz || !r || !e_in || !e_out)
         return fail(PP_EINVAL, "pp_k_smooth_fused: NULL array");
+    if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)r | (uintptr_t)e_in |
+         (uintptr_t)e_out) & 15)
+        return fail(PP_EINVAL, "pp_k_smooth_fused: arrays must be 16-byte aligned");
     if (e_in == e_out)
         return fail(PP_EINVAL, "pp_k_smooth_fused: e_in and e_out must not alias");
     if (first_colour != 0 && first_colour != 1)
@@ -1010,6 +1173,8 @@ int pp_k_resid_restrict(const pp_grid *grid, const double *bx, const double *by,
     PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
     if (!bx || !by || !bz || !e || !r || !rH)
         return fail(PP_EINVAL, "pp_k_resid_restrict: NULL array");
+    if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)e | (uintptr_t)r) & 15)
+        return fail(PP_EINVAL, "pp_k_resid_restrict: arrays must be 16-byte aligned");
     for (int m = 0; m < 3; ++m)
         if (grid->n[m] % 2)
             return fail(PP_EINVAL, "pp_k_resid_restrict: the fine grid needs even cell counts");
@@ -1080,19 +1245,22 @@ int pp_k_copy(const double *src, double *dst, int64_t count, void *hip_stream)
     return check_launch("pp_k_copy");
 }
 
-int pp_timing_enable(pp_ctx *c, int32_t on)
+int pp_timing_enable(pp_ctx *c, int32_t mask)
 {
     PP_TRY(check_ctx(c));
-    if (on && c->ev.empty()) {
+    if (mask < 0 || mask >= (1 << PP_KT_COUNT))
+        return fail(PP_EINVAL, "pp_timing_enable: mask has bits beyond the kernel kinds");
+    if (mask && c->ev.empty()) {
         c->ev.resize(8192);
         for (auto &e : c->ev) {
             PP_HIP(hipEventCreate(&e.a));
             PP_HIP(hipEventCreate(&e.b));
         }
     }
-    if (!on)
+    if (!mask)
         resolve_timing(c);
-    c->timing = on != 0;
+    c->timing = mask != 0;
+    c->timing_mask = (uint32_t)mask;
     return PP_OK;
 }
 

@@ -24,7 +24,12 @@ struct Bc {
     int x, y, z;
 };
 
-inline size_t cells(Dims d) { return (size_t)d.nx * d.ny * d.nz; }
+__host__ __device__ inline size_t cells(Dims d) { return (size_t)d.nx * d.ny * d.nz; }
+
+// levels handled by the single-workgroup tail of the V-cycle
+constexpr int TAIL_MAX = 8;
+constexpr size_t TAIL_CELLS = 4096;       // a level joins the tail at or below this size
+constexpr size_t FUSED_MIN_CELLS = (size_t)1 << 21;   // fused sweeps above 128^3 cells
 
 inline dim3 cell_grid(Dims d)
 {
@@ -82,6 +87,10 @@ enum FinalizeOp {
 template <typename T>
 void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e, double h2,
                  int colour, bool zero, hipStream_t s);
+// query (once) the occupancy figures the fused sweep's launch geometry uses;
+// called before stream capture so that capture records kernel launches only
+template <typename T>
+void prepare_fused();
 // one fused red-black sweep, e_in -> e_out (must not alias); first_colour 0
 // updates red ((i+j+k) even) first, 1 black first; zero: e_in treated as 0
 template <typename T>
@@ -95,6 +104,12 @@ template <typename T>
 void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s);
 template <typename T>
 void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s);
+// the V-cycle on nlev levels (the last one the coarsest) in one workgroup;
+// input r[0], output e[0] (in place; every level's e is overwritten)
+template <typename T>
+void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
+                 void *const *r, Bc bc, int nu_pre, int nu_post, const double *pinv, int ncoarse,
+                 hipStream_t s);
 template <typename T>
 void launch_convert(size_t n, const double *src, T *dst, hipStream_t s);
 template <typename T>
@@ -102,6 +117,12 @@ void launch_to_double(size_t n, const T *src, double *dst, hipStream_t s);
 
 void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, const double *bz,
                          double *hx, double *hy, double *hz, hipStream_t s);
+// one pass: copy + wall zeroing + validity count (partials) + storage copy
+// (dstT[0] may be null) + first coarse level; the fine grid's n must all be
+// even; returns the number of partial sums written
+template <typename T>
+int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
+                       T *const dstT[3], double *const coarse[3], double *part, hipStream_t s);
 void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s);
 void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                        double *part, hipStream_t s);

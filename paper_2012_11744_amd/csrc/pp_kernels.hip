@@ -576,6 +576,136 @@ __global__ __launch_bounds__(1024) void k_coarsest(int n, const double *__restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// The bottom of the V-cycle in one workgroup.  Levels of at most a few
+// thousand cells cost a kernel launch per step and little else, so all of
+// them (smoothing, transfers and the coarsest solve) run in a single
+// 1024-thread workgroup that walks the levels with barriers between steps.
+// The arithmetic is the same as in the per-level kernels.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TailArgs {
+    int n;                     // levels in the tail (the last is the coarsest)
+    Dims d[TAIL_MAX];
+    double h2[TAIL_MAX];
+    const T *b[TAIL_MAX][3];
+    T *e[TAIL_MAX];
+    T *r[TAIL_MAX];
+    Bc bc;
+    int nu_pre, nu_post;
+    const double *pinv;        // pseudo-inverse of the coarsest operator
+    int ncoarse;
+};
+
+template <typename T>
+__device__ void tail_gs(const TailArgs<T> &a, int l, int colour, bool zero)
+{
+    using C = typename Acc<T>::type;
+    const Dims d = a.d[l];
+    const size_t n = cells(d);
+    const C h2 = (C)a.h2[l];
+    for (size_t c = threadIdx.x; c < n; c += blockDim.x) {
+        const int i = (int)(c % d.nx), j = (int)((c / d.nx) % d.ny), k = (int)(c / ((size_t)d.nx * d.ny));
+        if (((i + j + k) & 1) != colour)
+            continue;
+        const Nb nb = neighbours(d, a.bc, i, j, k);
+        const Links<T> L = links(nb, a.b[l][0], a.b[l][1], a.b[l][2]);
+        const C diag = (L.xl + L.xh) + (L.yl + L.yh) + (L.zl + L.zh);
+        const T *e = a.e[l];
+        C s = C(0);
+        if (!zero)
+            s = L.xl * ld(e, nb.xm) + L.xh * ld(e, nb.xp) + L.yl * ld(e, nb.ym) +
+                L.yh * ld(e, nb.yp) + L.zl * ld(e, nb.zm) + L.zh * ld(e, nb.zp);
+        a.e[l][c] = static_cast<T>((s - h2 * ld(a.r[l], c)) / diag);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void tail_restrict(const TailArgs<T> &a, int l)
+{
+    using C = typename Acc<T>::type;
+    const Dims fd = a.d[l];
+    const Dims cd = a.d[l + 1];
+    const size_t nc = cells(cd);
+    const C ih2 = (C)(1.0 / a.h2[l]);
+    for (size_t cc = threadIdx.x; cc < nc; cc += blockDim.x) {
+        const int I = (int)(cc % cd.nx), J = (int)((cc / cd.nx) % cd.ny),
+                  K = (int)(cc / ((size_t)cd.nx * cd.ny));
+        C acc = C(0);
+        for (int q = 0; q < 8; ++q) {
+            const Nb nb = neighbours(fd, a.bc, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1),
+                                     2 * K + (q >> 2));
+            const Links<T> L = links(nb, a.b[l][0], a.b[l][1], a.b[l][2]);
+            acc += ld(a.r[l], nb.c) - ih2 * flux_sum(nb, L, a.e[l]);
+        }
+        a.r[l + 1][cc] = static_cast<T>(acc * C(0.125));
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void tail_prolong(const TailArgs<T> &a, int l)
+{
+    using C = typename Acc<T>::type;
+    const Dims fd = a.d[l];
+    const Dims cd = a.d[l + 1];
+    const size_t n = cells(fd);
+    const T *eH = a.e[l + 1];
+    for (size_t c = threadIdx.x; c < n; c += blockDim.x) {
+        const int i = (int)(c % fd.nx), j = (int)((c / fd.nx) % fd.ny), k = (int)(c / ((size_t)fd.nx * fd.ny));
+        const int I0 = i >> 1, I1 = other_parent(i, cd.nx, a.bc.x);
+        const int J0 = j >> 1, J1 = other_parent(j, cd.ny, a.bc.y);
+        const int K0 = k >> 1, K1 = other_parent(k, cd.nz, a.bc.z);
+        const size_t sy = cd.nx, sz = (size_t)cd.nx * cd.ny;
+        const size_t k0 = K0 * sz, k1 = K1 * sz, j0 = J0 * sy, j1 = J1 * sy;
+        const C w0 = C(0.75), w1 = C(0.25);
+        const C x00 = w0 * ld(eH, k0 + j0 + I0) + w1 * ld(eH, k0 + j0 + I1);
+        const C x01 = w0 * ld(eH, k0 + j1 + I0) + w1 * ld(eH, k0 + j1 + I1);
+        const C x10 = w0 * ld(eH, k1 + j0 + I0) + w1 * ld(eH, k1 + j0 + I1);
+        const C x11 = w0 * ld(eH, k1 + j1 + I0) + w1 * ld(eH, k1 + j1 + I1);
+        const C v = w0 * (w0 * x00 + w1 * x01) + w1 * (w0 * x10 + w1 * x11);
+        a.e[l][c] = static_cast<T>(ld(a.e[l], c) + v);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail_cycle(TailArgs<T> a)
+{
+    __shared__ double rs[1024];
+    const int L = a.n;
+    for (int l = 0; l + 1 < L; ++l) {
+        for (int sw = 0; sw < a.nu_pre; ++sw) {
+            tail_gs(a, l, 0, sw == 0);
+            tail_gs(a, l, 1, false);
+        }
+        tail_restrict(a, l);
+    }
+    // coarsest level: e = A^+ r (FP64)
+    {
+        const int n = a.ncoarse;
+        const T *r = a.r[L - 1];
+        for (int t = threadIdx.x; t < n; t += blockDim.x)
+            rs[t] = static_cast<double>(r[t]);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double s = 0.0;
+            for (int jj = 0; jj < n; ++jj)
+                s += a.pinv[(size_t)jj * n + i] * rs[jj];
+            a.e[L - 1][i] = static_cast<T>(s);
+        }
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        tail_prolong(a, l);
+        for (int sw = 0; sw < a.nu_post; ++sw) {
+            tail_gs(a, l, 1, false);
+            tail_gs(a, l, 0, false);
+        }
+    }
+}
+
 template <typename T>
 __global__ void k_convert(size_t n, const double *__restrict__ src, T *__restrict__ dst)
 {
@@ -633,6 +763,78 @@ __global__ __launch_bounds__(BLOCK) void k_zero_walls(Dims d, Bc bc, double *bx,
         by[c] = 0.0;
     if (bc.z && k == 0)
         bz[c] = 0.0;
+}
+
+// Coefficient load in one pass over the fine level (all n even): copies the
+// caller's beta (FP64) with wall faces set to 0, counts non-wall faces that
+// are not finite positive numbers, writes the storage-precision copy used by
+// the V-cycle (WT), and the first coarse level (mean of the 4 fine faces of
+// each coarse face).  One thread per coarse cell, i.e. per 2x2x2 fine block;
+// each block of threads covers RZ/2 coarse planes.
+template <typename T, bool WT>
+__global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const double *__restrict__ sx,
+                                                       const double *__restrict__ sy_,
+                                                       const double *__restrict__ sz_,
+                                                       double *__restrict__ dx, double *__restrict__ dy,
+                                                       double *__restrict__ dz, T *__restrict__ tx,
+                                                       T *__restrict__ ty, T *__restrict__ tz,
+                                                       double *__restrict__ hx, double *__restrict__ hy,
+                                                       double *__restrict__ hz, double *part)
+{
+    using D2 = double __attribute__((ext_vector_type(2)));
+    using T2 = typename Vec2<T>::type;
+    __shared__ double sm[1][BLOCK / 64];
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int I = blockIdx.x * BX + threadIdx.x;
+    const int J = blockIdx.y * BY + threadIdx.y;
+    double v[1] = {0.0};
+    if (I < cd.nx && J < cd.ny) {
+        const size_t fy = (size_t)fd.nx, fz = (size_t)fd.nx * fd.ny;
+        const int Ke = min(cd.nz, ((int)blockIdx.z + 1) * (RZ / 2));
+        for (int K = blockIdx.z * (RZ / 2); K < Ke; ++K) {
+            double ax[2][2], ay[2][2], az[2][2];   // [dk][dj] / [dk][di] / [dj][di] terms
+            for (int dk = 0; dk < 2; ++dk)
+                for (int dj = 0; dj < 2; ++dj) {
+                    const int j = 2 * J + dj, k = 2 * K + dk;
+                    const size_t c = (size_t)k * fz + (size_t)j * fy + 2 * I;
+                    D2 bxv = *reinterpret_cast<const D2 *>(sx + c);
+                    D2 byv = *reinterpret_cast<const D2 *>(sy_ + c);
+                    D2 bzv = *reinterpret_cast<const D2 *>(sz_ + c);
+                    const bool wx = bc.x && I == 0, wy = bc.y && j == 0, wz = bc.z && k == 0;
+                    if (wx) bxv.x = 0.0;
+                    if (wy) byv = D2{0.0, 0.0};
+                    if (wz) bzv = D2{0.0, 0.0};
+                    const double f[6] = {bxv.x, bxv.y, byv.x, byv.y, bzv.x, bzv.y};
+                    const bool w[6] = {wx, false, wy, wy, wz, wz};
+                    for (int q = 0; q < 6; ++q)
+                        if (!w[q] && !(f[q] > 0.0 && f[q] < INFINITY))
+                            v[0] += 1.0;
+                    *reinterpret_cast<D2 *>(dx + c) = bxv;
+                    *reinterpret_cast<D2 *>(dy + c) = byv;
+                    *reinterpret_cast<D2 *>(dz + c) = bzv;
+                    if (WT) {
+                        *reinterpret_cast<T2 *>(tx + c) = T2{static_cast<T>(bxv.x), static_cast<T>(bxv.y)};
+                        *reinterpret_cast<T2 *>(ty + c) = T2{static_cast<T>(byv.x), static_cast<T>(byv.y)};
+                        *reinterpret_cast<T2 *>(tz + c) = T2{static_cast<T>(bzv.x), static_cast<T>(bzv.y)};
+                    }
+                    ax[dk][dj] = bxv.x;
+                    if (dj == 0) {
+                        ay[dk][0] = byv.x;
+                        ay[dk][1] = byv.y;
+                    }
+                    if (dk == 0) {
+                        az[dj][0] = bzv.x;
+                        az[dj][1] = bzv.y;
+                    }
+                }
+            const size_t C = ((size_t)K * cd.ny + J) * cd.nx + I;
+            // same grouping as k_coarsen_beta
+            hx[C] = (bc.x && I == 0) ? 0.0 : 0.25 * ((ax[0][0] + ax[0][1]) + (ax[1][0] + ax[1][1]));
+            hy[C] = (bc.y && J == 0) ? 0.0 : 0.25 * ((ay[0][0] + ay[0][1]) + (ay[1][0] + ay[1][1]));
+            hz[C] = (bc.z && K == 0) ? 0.0 : 0.25 * ((az[0][0] + az[0][1]) + (az[1][0] + az[1][1]));
+        }
+    }
+    block_partials<1>(v, sm, part, 0);
 }
 
 // counts non-wall faces whose beta is not a finite positive number
@@ -1137,6 +1339,13 @@ static int fused_kz(Dims d, unsigned tiles, long long slots)
 }
 
 template <typename T>
+void prepare_fused()
+{
+    (void)resident_slots(k_rbgs_fused<T, true>, FTHREADS);
+    (void)resident_slots(k_rbgs_fused<T, false>, FTHREADS);
+}
+
+template <typename T>
 void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
                        const T *ein, T *eout, double h2, int first_colour, bool zero,
                        hipStream_t s)
@@ -1173,6 +1382,29 @@ void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s)
 }
 
 template <typename T>
+void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
+                 void *const *r, Bc bc, int nu_pre, int nu_post, const double *pinv, int ncoarse,
+                 hipStream_t s)
+{
+    TailArgs<T> a;
+    a.n = nlev;
+    for (int l = 0; l < nlev; ++l) {
+        a.d[l] = d[l];
+        a.h2[l] = h2[l];
+        for (int m = 0; m < 3; ++m)
+            a.b[l][m] = (const T *)b[l][m];
+        a.e[l] = (T *)e[l];
+        a.r[l] = (T *)r[l];
+    }
+    a.bc = bc;
+    a.nu_pre = nu_pre;
+    a.nu_post = nu_post;
+    a.pinv = pinv;
+    a.ncoarse = ncoarse;
+    hipLaunchKernelGGL((k_tail_cycle<T>), dim3(1), dim3(1024), 0, s, a);
+}
+
+template <typename T>
 void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s)
 {
     int threads = ((n + 63) / 64) * 64;
@@ -1203,6 +1435,23 @@ void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, con
 void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_walls, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz);
+}
+
+template <typename T>
+int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
+                       T *const dstT[3], double *const coarse[3], double *part, hipStream_t s)
+{
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const dim3 g((cd.nx + BX - 1) / BX, (cd.ny + BY - 1) / BY, (cd.nz + RZ / 2 - 1) / (RZ / 2));
+    if (dstT[0])
+        hipLaunchKernelGGL((k_load_coeffs<T, true>), g, kBlock, 0, s, fd, bc, src[0], src[1], src[2],
+                           dst[0], dst[1], dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1],
+                           coarse[2], part);
+    else
+        hipLaunchKernelGGL((k_load_coeffs<T, false>), g, kBlock, 0, s, fd, bc, src[0], src[1],
+                           src[2], dst[0], dst[1], dst[2], dstT[0], dstT[1], dstT[2], coarse[0],
+                           coarse[1], coarse[2], part);
+    return (int)grid_blocks(g);
 }
 
 void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
@@ -1345,9 +1594,15 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStrea
     template void launch_resid_restrict<T>(Dims, Bc, const T *, const T *, const T *, const T *, \
                                            const T *, T *, double, hipStream_t);                \
     template void launch_prolong<T>(Dims, Bc, const T *, T *, hipStream_t);                     \
+    template void prepare_fused<T>();                                                           \
+    template int launch_load_coeffs<T>(Dims, Bc, const double *const[3], double *const[3],      \
+                                       T *const[3], double *const[3], double *, hipStream_t);   \
     template void launch_rbgs_fused<T>(Dims, Bc, const T *, const T *, const T *, const T *,    \
                                        const T *, T *, double, int, bool, hipStream_t);         \
     template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
+    template void launch_tail<T>(int, const Dims *, const double *, const void *const (*)[3],   \
+                                 void *const *, void *const *, Bc, int, int, const double *,     \
+                                 int, hipStream_t);                                             \
     template void launch_convert<T>(size_t, const double *, T *, hipStream_t);                  \
     template void launch_to_double<T>(size_t, const T *, double *, hipStream_t);                \
     template void launch_residual_T<T>(Dims, Bc, const double *, const double *, const double *, \

@@ -72,7 +72,7 @@ class Solver:
     def __init__(self, beta: Sequence[torch.Tensor], h: float, bc: Sequence[int],
                  precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
                  max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 coarse_graph: bool = True, stream: Optional[torch.cuda.Stream] = None):
         lib = L.load()
         self._lib = lib
         self.shape = tuple(beta[0].shape)
@@ -90,6 +90,7 @@ class Solver:
         o.max_outer = max_outer
         o.warm_start = int(bool(warm_start))
         o.fallback = int(bool(fallback))
+        o.coarse_graph = int(bool(coarse_graph))
         self.opts = o
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -200,8 +201,17 @@ class Solver:
         return e
 
     # -- kernel timing ----------------------------------------------------
-    def timing(self, on: bool) -> None:
-        L.check(self._lib.pp_timing_enable(self._ctx, int(on)), "pp_timing_enable")
+    def timing(self, on, kinds=None) -> None:
+        """Time fine-level launches of the given kinds (all kinds by default)."""
+        if not on:
+            mask = 0
+        elif kinds is None:
+            mask = (1 << L.PP_KT_COUNT) - 1
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << int(k)
+        L.check(self._lib.pp_timing_enable(self._ctx, mask), "pp_timing_enable")
 
     def timing_reset(self) -> None:
         L.check(self._lib.pp_timing_reset(self._ctx), "pp_timing_reset")

@@ -52,8 +52,8 @@ def test_opts_default(lib):
     from paper_2012_11744_amd import _lib as L
     o = L.Opts()
     lib.pp_opts_default(ctypes.byref(o))
-    assert (o.precision, o.outer, o.nu_pre, o.nu_post, o.max_outer, o.warm_start, o.fallback) == \
-        (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1)
+    assert (o.precision, o.outer, o.nu_pre, o.nu_post, o.max_outer, o.warm_start, o.fallback,
+            o.coarse_graph) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1, 1)
 
 
 def _grid(n=(8, 8, 8), h=0.125, bc=(0, 0, 0)):
@@ -95,7 +95,7 @@ def test_setup_rejects_null_and_bad_options(lib):
     assert lib.pp_setup(None, fake, fake, fake, None, None, ctypes.byref(ctx)) == L.PP_EINVAL
     assert lib.pp_setup(ctypes.byref(g), fake, fake, fake, None, None, None) == L.PP_EINVAL
     for field, bad in (("precision", 7), ("outer", 3), ("nu_pre", 0), ("nu_post", 17),
-                       ("max_outer", 0), ("warm_start", 2)):
+                       ("max_outer", 0), ("warm_start", 2), ("coarse_graph", 5)):
         o = L.Opts()
         lib.pp_opts_default(ctypes.byref(o))
         setattr(o, field, bad)
