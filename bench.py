@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time the plain copy kernel on 2 x 1 GiB buffers and exit (reference "
                          "for achievable HBM bandwidth and for scaling FETCH/WRITE counters)")
+    ap.add_argument("--workload", default="layer256", choices=["layer256", "jet512"],
+                    help="layer256: the headline metric; jet512: forward + backward projection "
+                         "at 512^3 (time and memory per solve), printed as its own JSON line")
     ap.add_argument("--summarize-db", metavar="RESULTS_DB",
                     help="print a per-kernel, per-grid summary of a rocprofv3 kernel trace "
                          "(the *_results.db it writes) and exit")
@@ -125,6 +128,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "jet512":
+        jet512(args)
+        return
     N = args.n
     t0 = time.time()
     w = W.config3(N)
@@ -294,6 +300,75 @@ def main():
     }
     if "fp64" in results and modes[0] != "fp64":
         line["mixed_over_fp64"] = round(head["solves_per_s"] / results["fp64"]["solves_per_s"], 3)
+    print(json.dumps(line), flush=True)
+
+
+def jet512(args):
+    """Forward (setup + divergence + mixed solve to 1e-8 + projection) and
+    backward (adjoint solve re-running the V-cycles + face products) at 512^3
+    with walls on all sides: ms and device memory per solve."""
+    import numpy as np
+    import torch
+
+    from paper_2012_11744_amd import solver as S
+    from paper_2012_11744_amd import workloads as W
+    t0 = time.time()
+    w = W.config5(512)
+    log(f"[bench] jet 512^3 generated in {time.time() - t0:.1f}s")
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    rho = dev(w.rho)
+    us = [dev(u) for u in w.us]
+    wt = dev(w.w)
+    beta = tuple(torch.empty_like(rho) for _ in range(3))
+    b = torch.empty_like(rho)
+    p = torch.empty_like(rho)
+    u = tuple(torch.empty_like(rho) for _ in range(3))
+    S.face_coeffs(rho, w.h, w.bc, out=beta)
+    torch.cuda.synchronize()
+    fields = torch.cuda.memory_allocated()
+    sol = S.Solver(beta, w.h, w.bc, precision="fp32")
+
+    def forward():
+        S.face_coeffs(rho, w.h, w.bc, out=beta)
+        sol.update_coeffs(beta)
+        sol.divergence(us, 1.0 / w.dt, out=b)
+        sol.solve(b, tol=args.tol, p=p)
+        sol.project(us, p, w.dt, out=u)
+
+    reps = max(2, args.steps // 4)
+    forward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        forward()
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t1) * 1e3 / reps
+    fwd_it = sol.last_stats["outer_iters"]
+    sol.adjoint(p, wt, tol=args.tol)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(reps):
+        g = sol.adjoint(p, wt, tol=args.tol)
+        del g
+    torch.cuda.synchronize()
+    bwd_ms = (time.perf_counter() - t2) * 1e3 / reps
+    bwd_it = sol.last_stats["outer_iters"]
+    peak = torch.cuda.max_memory_allocated()
+    line = {
+        "metric": "pressure projection forward + backward at 512^3, ms and device memory per solve",
+        "workload": "jet along x, rho 800 / 1, 512^3, walls, mixed FP32 V-cycle in FP64 PCG, tol %g"
+                    % args.tol,
+        "forward_ms": round(fwd_ms, 3), "forward_iters": fwd_it,
+        "backward_ms": round(bwd_ms, 3), "backward_iters": bwd_it,
+        "solver_context_bytes": sol.memory_bytes,
+        "torch_fields_bytes": int(fields),
+        "torch_peak_bytes_with_backward_outputs": int(peak),
+        "cells": w.cells, "reps": reps,
+    }
+    sol.close()
     print(json.dumps(line), flush=True)
 
 
