@@ -81,6 +81,30 @@ def summarize_db(path):
               f"{mn / 1e3:.2f} | {mx / 1e3:.2f} | {100 * tot / total:.1f} |")
 
 
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "fused_rbgs_layer256.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2012_11744_amd", "csrc", "pp_kernels.hip")
+
+
+def counter_traffic():
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled by the copy-kernel
+    calibration), or None when the kernel source changed since then."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTER_SUMMARY).read()
+        src = open(KERNEL_SOURCE, "rb").read()
+    except OSError:
+        return None, "no counter summary"
+    m = re.search(r"kernel_source_sha256_16: (\w+)", text)
+    t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m or not t:
+        return None, "no counter summary"
+    if m.group(1) != hashlib.sha256(src).hexdigest()[:16]:
+        return None, "kernel source changed since the counters were taken"
+    return int(t.group(1)), os.path.relpath(COUNTER_SUMMARY, ROOT)
+
+
 def copy_bandwidth(reps=10, nbytes=1 << 30):
     """Plain device copy through the library's copy kernel: GB/s counting the
     bytes read plus the bytes written."""
@@ -242,9 +266,11 @@ def main():
         r["kernels"] = kern
         if mi == 0 and "smoother_sweep" in kern:
             k = kern["smoother_sweep"]
+            traffic, source = counter_traffic() if mode == "fp32" and N == 256 else (None, "other shape")
             roof = {"kernel": "fused red-black Gauss-Seidel sweep (fine level, %s)" % mode,
                     "bound": "hbm", "achieved": round(k["GBps"], 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(k["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(k["GBps"] / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "traffic_source": source,
                     "alg_bytes_per_launch": k["alg_bytes"], "avg_launch_ms": k["avg_ms"]}
         if not args.no_adjoint and mi == 0:
             g_p = dev(w.us[0])
