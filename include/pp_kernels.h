@@ -40,11 +40,13 @@ int pp_k_smooth(const pp_grid *grid, const double *beta_x, const double *beta_y,
 
 /* One fused red-black sweep, out of place: e_out = sweep(e_in), the first
  * colour updated first (first_colour 0: red, (i+j+k) even; 1: black) and the
- * second colour from the new first-colour values.  Equal, value for value, to
- * two colour passes of pp_k_smooth.  e_in and e_out must not alias;
- * zero_init = 1 treats e_in as zero (it is not read).  nx must be even, and
- * so must the cell count of every periodic direction; all arrays 16-byte
- * aligned (the kernel reads x-pairs of cells as vectors). */
+ * second colour from the new first-colour values.  The same cell update as
+ * two colour passes of pp_k_smooth (results agree to rounding: the compiler
+ * may contract the products into fused multiply-adds differently).  e_in and
+ * e_out must not alias; zero_init = 1 treats e_in as zero (it is not read).
+ * nx must be even, and so must the cell count of every periodic direction;
+ * an x-y plane must stay below 2^31 bytes; all arrays 16-byte aligned (the
+ * kernel reads x-pairs of cells as vectors). */
 int pp_k_smooth_fused(const pp_grid *grid, const double *beta_x, const double *beta_y,
                       const double *beta_z, const double *r, const double *e_in, double *e_out,
                       int32_t first_colour, int32_t zero_init, void *hip_stream);

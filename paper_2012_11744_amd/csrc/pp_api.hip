@@ -479,7 +479,7 @@ void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s)
     LevelBuf &v = H.lev[l];
     const double h2 = v.h * v.h;
     const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
-    if (cells(v.d) > FUSED_MIN_CELLS) {
+    if (cells(v.d) > FUSED_MIN_CELLS && fused_plane_fits(v.d, sizeof(T))) {
         void *cur = v.e2;
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
             void *out = (cur == v.e) ? v.e2 : v.e;
@@ -513,7 +513,7 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
         KT t(c, PP_KT_PROLONG, l == 0);
         launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
     }
-    if (cells(v.d) > FUSED_MIN_CELLS) {
+    if (cells(v.d) > FUSED_MIN_CELLS && fused_plane_fits(v.d, sizeof(T))) {
         void *cur = v.cur;
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
             void *out = (cur == v.e) ? v.e2 : v.e;
@@ -1161,6 +1161,8 @@ int pp_k_smooth_fused(const pp_grid *grid, const double *bx, const double *by, c
     for (int m = 0; m < 3; ++m)
         if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
             return fail(PP_EINVAL, "pp_k_smooth_fused: periodic directions need an even cell count");
+    if (!fused_plane_fits(to_dims(grid), sizeof(double)))
+        return fail(PP_EINVAL, "pp_k_smooth_fused: an x-y plane must stay below 2^31 bytes");
     launch_rbgs_fused<double>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in, e_out,
                               grid->h * grid->h, first_colour, zero_init != 0,
                               (hipStream_t)hip_stream);

@@ -31,6 +31,13 @@ constexpr int TAIL_MAX = 8;
 constexpr size_t TAIL_CELLS = 4096;       // a level joins the tail at or below this size
 constexpr size_t FUSED_MIN_CELLS = (size_t)1 << 21;   // fused sweeps above 128^3 cells
 
+// The fused sweep addresses a plane through 32-bit byte offsets with one
+// reserved out-of-range value: planes must stay below 2^31 bytes.
+inline bool fused_plane_fits(Dims d, size_t word)
+{
+    return (size_t)d.nx * d.ny * word < ((size_t)1 << 31);
+}
+
 inline dim3 cell_grid(Dims d)
 {
     return dim3((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);

@@ -187,25 +187,83 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restri
 // k0-1 and k1, recompute first-colour values that belong to neighbouring
 // tiles and chunks from the same inputs, so blocks never read each other's
 // output (e_in is read only, e_out written only) and the result equals a
-// red-black sweep value for value.  Coefficients and e_in of plane k+1 are
-// loaded one step ahead; every input cell is fetched from memory once per
-// sweep apart from the ring.
+// red-black sweep value for value.  Every input cell is fetched from memory
+// once per sweep apart from the ring.
+//
+// The step has no data-dependent branches: every thread of the layout
+// computes the first-colour cell of its pair, reading in-plane neighbours
+// from LDS at a column chosen by the pair's colour parity; ring rows also
+// publish the row beyond them (two extra LDS rows), padding columns hold
+// zeros, and wall faces are zeroed as they are published.  Loads address a
+// plane through a block-uniform base plus a fixed per-thread 32-bit offset,
+// are issued unconditionally (inactive threads read their own valid dummy
+// address) and are masked where used, so the loads of plane k+1+FPD stay in
+// flight across FPD steps; the loop is unrolled by the buffer rotation period
+// so no buffer with loads in flight is copied.
 // ---------------------------------------------------------------------------
 constexpr int FTX = 64;                 // tile width in cells (32 pairs)
-constexpr int FTY = 8;                  // tile height in rows
+constexpr int FTY = 16;                 // tile height in rows
 constexpr int FPX = FTX / 2 + 2;        // pairs per row including the ring pairs
-constexpr int FRY = FTY + 2;            // rows including the ring rows
-constexpr int FTHREADS = 384;           // >= FPX * FRY, whole waves
-constexpr int FLW = FTX + 4;            // LDS row: cells i0-2 .. i0+FTX+1
+constexpr int FRY = FTY + 2;            // thread rows including the ring rows
+constexpr int FTHREADS = (FPX * FRY + 63) / 64 * 64;   // whole waves
+constexpr int FLW = FTX + 8;            // LDS row: cells i0-4 .. i0+FTX+3
+constexpr int FLR = FTY + 4;            // LDS rows: j0-2 .. j0+FTY+1
+
+// Planes of loads in flight beyond plane k+1, per storage type: two for FP32
+// (its loads are small, so it needs more of them in flight); one for FP64,
+// whose registers would otherwise spill, and for FP16 (measured best at one).
+template <typename T>
+struct FusedDepth {
+    static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+};
 
 // Inputs of one thread's pair at one plane, as loaded (storage precision).
-// Ring rows also carry the e_in pair of the row beyond them (eo) and, for the
-// upper ring row, the y faces above (byo), which no thread of the tile loads.
+// eo / byo: e_in and beta_y of the row beyond a ring row (a copy of the own
+// row for the other threads).  Values a thread must treat as zero (inactive
+// thread, missing plane, wall faces of y and z) arrive as zero from the
+// buffer range check.
 template <typename T>
 struct PairIn {
     using T2 = typename Vec2<T>::type;
     T2 e, r, bx, by, bz, eo, byo;
 };
+
+// Buffer resource over one plane: loads at byte offsets >= `bytes` return
+// zero and stores there are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type ld_pair(__amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    using T2 = typename Vec2<T>::type;
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    else
+        return __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void st_pair(__amdgpu_buffer_rsrc_t rs, unsigned off,
+                                        typename Vec2<T>::type v)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b128(
+            __builtin_bit_cast(unsigned __attribute__((ext_vector_type(4))), v), rs, off, 0, 0);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(unsigned __attribute__((ext_vector_type(2))), v), rs, off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+}
+
+// an offset past every plane (planes of a fused sweep stay below 2^31 bytes)
+constexpr unsigned OFF_NONE = 0x80000000u;
 
 __device__ __forceinline__ int slot3(int k) { return ((k % 3) + 3) % 3; }
 
@@ -237,12 +295,14 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
 {
     using C = typename Acc<T>::type;
     using T2 = typename Vec2<T>::type;
+    constexpr int FPD = FusedDepth<T>::value;   // planes of loads in flight beyond k+1
+    constexpr int FNB = FPD + 3;                // input buffers: k-1, k, k+1 and those in flight
     // LDS: e_in, beta_x and beta_y of planes k and k+1 (two slots) for the
     // in-plane neighbours, and the first-colour values of planes k-2..k
-    __shared__ C SE[2][FRY][FLW];
-    __shared__ C SX[2][FRY][FLW];
-    __shared__ C SY[2][FRY][FLW];
-    __shared__ C RED[3][FRY][FLW];
+    __shared__ C SE[2][FLR][FLW];
+    __shared__ C SX[2][FLR][FLW];
+    __shared__ C SY[2][FLR][FLW];
+    __shared__ C RED[3][FLR][FLW];
     int bxi, byi, bzi;
     xcd_tile(gridDim.x, tx_tiles, ty_tiles, bxi, byi, bzi);
     const int i0 = bxi * FTX, j0 = byi * FTY;
@@ -251,14 +311,17 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
 
     const int tid = threadIdx.x;
     const bool in_layout = tid < FPX * FRY;
-    const int pl = tid % FPX - 1;     // pair within the tile; -1 and FTX/2 are ring pairs
-    const int rl = tid / FPX - 1;     // row within the tile; -1 and FTY are ring rows
+    // threads past the layout shadow thread 0 (inactive: they publish and
+    // store nothing, and their LDS reads stay inside the arrays)
+    const int tl = in_layout ? tid : 0;
+    const int pl = tl % FPX - 1;      // pair within the tile; -1 and FTX/2 are ring pairs
+    const int rl = tl / FPX - 1;      // row within the tile; -1 and FTY are ring rows
     int x = i0 + 2 * pl;
     int j = j0 + rl;
     // the pair / row just past the grid's end is the periodic wrap: ring only
     const bool ringx = pl < 0 || pl >= FTX / 2 || x == d.nx;
     const bool ringy = rl < 0 || rl >= FTY || j == d.ny;
-    bool act = in_layout;             // loads its pair into LDS
+    bool act = in_layout;             // holds a pair of the grid
     if (x < 0) {
         if (bc.x) act = false; else x += d.nx;
     } else if (x >= d.nx) {
@@ -274,186 +337,165 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
         j = 0;
     }
     const bool owned = act && !ringx && !ringy;
-    // which first-colour cell of the pair the tile needs from this thread:
-    // 3 = both, 2 = only the second cell, 1 = only the first, 0 = none
-    int need = 0;
-    if (act && !(ringx && ringy))
-        need = !ringx ? 3 : (pl < 0 ? 2 : 1);
-    const bool dn_row = act && rl < 0 && !ringx;                        // loads the row below
-    const bool up_row = act && ringy && rl >= 0 && !ringx;              // loads the row above
-    const size_t sy = (size_t)d.nx;
-    const size_t sz = (size_t)d.nx * d.ny;
+    const bool dn_row = act && rl < 0;                 // publishes the row below it
+    const bool up_row = act && ringy && rl >= 0;       // publishes the row above it
     const int jm = (j == 0) ? d.ny - 1 : j - 1;
     const int jp = (j == d.ny - 1) ? 0 : j + 1;
     const bool wyl = bc.y && j == 0, wyh = bc.y && j == d.ny - 1;
-    const bool wxl = bc.x && x == 0, wxh = bc.x && x + 2 == d.nx;
-    const size_t rowc = (size_t)j * sy + x;
-    const size_t rowo = (size_t)(dn_row ? jm : jp) * sy + x;
-    const int lx = 2 * pl + 2;        // LDS column of the pair's first cell
-    const int ly = rl + 1;
+    const bool wxl = bc.x && x == 0;
+    const int jo = dn_row ? jm : (up_row ? jp : j);
+    const bool zo = up_row ? wyh : wyl;   // the y faces published in row lyo are walls
+    // byte offsets of the pair within a plane; OFF_NONE reads zero
+    const unsigned oc0 = (unsigned)(((size_t)j * d.nx + x) * sizeof(T));
+    const unsigned oo0 = (unsigned)(((size_t)jo * d.nx + x) * sizeof(T));
+    const unsigned oc = act ? oc0 : OFF_NONE;
+    const unsigned oo = act ? oo0 : OFF_NONE;
+    const unsigned ocy = (act && !wyl) ? oc0 : OFF_NONE;
+    const unsigned ooy = (act && !zo) ? oo0 : OFF_NONE;
+    const unsigned ost = owned ? oc0 : OFF_NONE;
+    const unsigned pbytes = (unsigned)((size_t)d.nx * d.ny * sizeof(T));
+    const int lx = 2 * pl + 4;        // LDS column of the pair's first cell
+    const int ly = rl + 2;            // LDS row of the pair
+    const int lyo = dn_row ? ly - 1 : (up_row ? ly + 1 : ly);
 
+    // plane q: its wrapped index, and whether it exists (walls end the grid)
     auto plane = [&](int q, int &qw) -> bool {
         qw = q;
         if (q < 0) {
-            if (bc.z) return false;
+            if (bc.z) { qw = 0; return false; }
             qw = q + d.nz;
         } else if (q >= d.nz) {
-            if (bc.z) return false;
+            if (bc.z) { qw = 0; return false; }
             qw = q - d.nz;
         }
         return true;
     };
-    auto ld2 = [&](const T *p, size_t i) -> T2 { return *reinterpret_cast<const T2 *>(p + i); };
-    auto load_in = [&](int q) -> PairIn<T> {
-        PairIn<T> v;
-        const T2 z2 = {T(0), T(0)};
-        v.e = z2; v.r = z2; v.bx = z2; v.by = z2; v.bz = z2; v.eo = z2; v.byo = z2;
+    auto load_in = [&](int q, PairIn<T> &v) __attribute__((always_inline)) {
         int qw;
-        if (!act || !plane(q, qw))
-            return v;
-        const size_t base = (size_t)qw * sz;
-        if (!ZERO)
-            v.e = ld2(ein, base + rowc);
-        v.r = ld2(r, base + rowc);
-        v.bx = ld2(bx, base + rowc);
-        v.by = ld2(by, base + rowc);
-        v.bz = ld2(bz, base + rowc);
-        if (!ZERO && (dn_row || up_row))
-            v.eo = ld2(ein, base + rowo);
-        if (up_row)
-            v.byo = ld2(by, base + rowo);
-        if (bc.z && qw == 0)
-            v.bz = z2;                // the wall below plane 0
-        return v;
+        const unsigned nb = plane(q, qw) ? pbytes : 0u;
+        const size_t pb = (size_t)qw * pbytes;
+        auto rs = [&](const T *base, unsigned n) {
+            return plane_rsrc(reinterpret_cast<const char *>(base) + pb, n);
+        };
+        if (!ZERO) {
+            const auto re = rs(ein, nb);
+            v.e = ld_pair<T>(re, oc);
+            v.eo = ld_pair<T>(re, oo);
+        }
+        v.r = ld_pair<T>(rs(r, nb), oc);
+        v.bx = ld_pair<T>(rs(bx, nb), oc);
+        const auto ry = rs(by, nb);
+        v.by = ld_pair<T>(ry, ocy);
+        v.byo = ld_pair<T>(ry, ooy);
+        v.bz = ld_pair<T>(rs(bz, (bc.z && qw == 0) ? 0u : nb), oc);   // the wall below plane 0
     };
-    auto publish = [&](int slot, const PairIn<T> &v) {
-        if (!in_layout)
+    auto pick = [](int o, T2 v) -> C { return C(o ? v.y : v.x); };
+    // Only active threads write LDS: the positions of inactive ones (past a
+    // wall, past a ragged grid end) keep the zeros of the initial fill, and
+    // the row a wrapping ring row publishes beyond itself may be the own row
+    // of an inactive thread.
+    auto publish = [&](int slot, const PairIn<T> &v) __attribute__((always_inline)) {
+        if (!act)
             return;
-        SE[slot][ly][lx] = C(v.e.x);
-        SE[slot][ly][lx + 1] = C(v.e.y);
-        SX[slot][ly][lx] = C(v.bx.x);
+        if (!ZERO) {
+            SE[slot][ly][lx] = C(v.e.x);
+            SE[slot][ly][lx + 1] = C(v.e.y);
+            SE[slot][lyo][lx] = C(v.eo.x);
+            SE[slot][lyo][lx + 1] = C(v.eo.y);
+        }
+        SX[slot][ly][lx] = wxl ? C(0) : C(v.bx.x);
         SX[slot][ly][lx + 1] = C(v.bx.y);
         SY[slot][ly][lx] = C(v.by.x);
         SY[slot][ly][lx + 1] = C(v.by.y);
+        SY[slot][lyo][lx] = C(v.byo.x);
+        SY[slot][lyo][lx + 1] = C(v.byo.y);
     };
 
-    // pipeline: inputs of planes k-1, k, k+1 resident, k+2 in flight
-    PairIn<T> pm = load_in(k0 - 2), pc = load_in(k0 - 1), pn = load_in(k0), pf;
-    publish((k0 - 1) & 1, pc);
-    __syncthreads();
-    C red_km2 = C(0), red_km1 = C(0);
-    C bxh_prev = C(0), byh_prev = C(0);   // high x / y faces of the second-colour cell, plane k-1
+    // padding columns and rows read as zero
+    for (int i = tid; i < 2 * FLR * FLW; i += FTHREADS) {
+        (&SE[0][0][0])[i] = C(0);
+        (&SX[0][0][0])[i] = C(0);
+        (&SY[0][0][0])[i] = C(0);
+    }
+    for (int i = tid; i < 3 * FLR * FLW; i += FTHREADS)
+        (&RED[0][0][0])[i] = C(0);
 
-    for (int k = k0 - 1; k <= k1; ++k) {
-        pf = load_in(k + 2);
+    C red_km2 = C(0), red_km1 = C(0);
+    // in-plane faces of the second-colour cell of plane k-1 (read at step k-1)
+    C sxl = C(0), sxh = C(0), syl = C(0), syh = C(0);
+
+    // One plane step: inputs of planes k-1 (pm), k (pc), k+1 (pn) resident,
+    // plane k+1+FPD (pf) loaded here and left in flight for FPD steps.
+    auto step = [&](int k, PairIn<T> &pm, PairIn<T> &pc, PairIn<T> &pn, PairIn<T> &pf)
+                    __attribute__((always_inline)) {
+        load_in(k + 1 + FPD, pf);
         const int si = k & 1;
         int kw;
         const bool kin = act && plane(k, kw);
-        const int o = (c0 + j + (kin ? kw : k)) & 1;     // first-colour cell of the pair in plane k
+        const int o = (c0 + j + k) & 1;   // first-colour cell of the pair in plane k
         // phase A: first colour of plane k
-        C red = C(0);
-        if (kin && (need & (1 << o))) {
-            const int cx = lx + o;
-            C xl, xh, yl, yh, zl, zh, rr, exm, exp, eym, eyp, ezm, ezp;
-            if (o == 0) {
-                xl = wxl ? C(0) : C(pc.bx.x);
-                xh = C(pc.bx.y);
-                yl = wyl ? C(0) : C(pc.by.x);
-                zl = C(pc.bz.x);
-                zh = C(pn.bz.x);
-                rr = C(pc.r.x);
-                exp = C(pc.e.y);
-                ezm = C(pm.e.x);
-                ezp = C(pn.e.x);
-            } else {
-                xl = C(pc.bx.y);
-                xh = wxh ? C(0) : SX[si][ly][lx + 2];
-                yl = wyl ? C(0) : C(pc.by.y);
-                zl = C(pc.bz.y);
-                zh = C(pn.bz.y);
-                rr = C(pc.r.y);
-                exm = C(pc.e.x);
-                ezm = C(pm.e.y);
-                ezp = C(pn.e.y);
-            }
-            if (o == 0)
-                exm = SE[si][ly][cx - 1];
-            else
-                exp = SE[si][ly][cx + 1];
-            if (up_row) {
-                yh = wyh ? C(0) : C(o == 0 ? pc.byo.x : pc.byo.y);
-                eyp = C(o == 0 ? pc.eo.x : pc.eo.y);
-            } else {
-                yh = wyh ? C(0) : SY[si][ly + 1][cx];
-                eyp = SE[si][ly + 1][cx];
-            }
-            eym = dn_row ? C(o == 0 ? pc.eo.x : pc.eo.y) : SE[si][ly - 1][cx];
-            const C diag = (xl + xh) + (yl + yh) + (zl + zh);
-            C s = C(0);
-            if (!ZERO)
-                s = xl * exm + xh * exp + yl * eym + yh * eyp + zl * ezm + zh * ezp;
-            red = (s - h2 * rr) / diag;
-        }
-        // the second-colour cell of this plane (used in phase B at the next
-        // step) needs its high x / y faces from the neighbours' LDS entries
-        C bxh_cur = C(0), byh_cur = C(0);
-        if (owned) {
-            const int ob = 1 - o;
-            bxh_cur = ob == 0 ? C(pc.bx.y) : (wxh ? C(0) : SX[si][ly][lx + 2]);
-            byh_cur = wyh ? C(0) : SY[si][ly + 1][lx + ob];
-        }
-        const int sa = slot3(k);
-        if (in_layout) {
-            RED[sa][ly][lx + o] = red;
-            RED[sa][ly][lx + 1 - o] = C(0);
-        }
+        const int ca = lx + o;
+        const C xl = SX[si][ly][ca], xh = SX[si][ly][ca + 1];
+        const C yl = SY[si][ly][ca], yh = SY[si][ly + 1][ca];
+        const C zl = pick(o, pc.bz), zh = pick(o, pn.bz);
+        const C diag = (xl + xh) + (yl + yh) + (zl + zh);
+        C s = C(0);
+        if (!ZERO)
+            s = xl * SE[si][ly][ca - 1] + xh * SE[si][ly][ca + 1] + yl * SE[si][ly - 1][ca] +
+                yh * SE[si][ly + 1][ca] + zl * pick(o, pm.e) + zh * pick(o, pn.e);
+        const C val = (s - h2 * pick(o, pc.r)) / diag;
+        const C red = kin ? val : C(0);   // a missing plane has no faces: 0/0
+        // in-plane faces of this plane's second-colour cell, for phase B at
+        // the next step (the slot is overwritten before then)
+        const int cb = lx + 1 - o;
+        const C nxl = SX[si][ly][cb], nxh = SX[si][ly][cb + 1];
+        const C nyl = SY[si][ly][cb], nyh = SY[si][ly + 1][cb];
+        if (act)
+            RED[slot3(k)][ly][ca] = red;
         publish(si ^ 1, pn);          // plane k+1 for the next step's phase A
         __syncthreads();
-        // phase B: second colour of plane k-1, then store the finished pair
+        // phase B: second colour of plane k-1 (at the column of this plane's
+        // first colour); the store of a thread outside the tile is dropped
         const int kb = k - 1;
-        if (owned && kb >= k0) {
+        if (kb >= k0) {
             const int sb = slot3(kb);
-            const int ob = o;                            // second-colour cell in plane k-1
-            const int cx = lx + ob;
-            C xl, xh, yl, zl, zh, rr;
-            if (ob == 0) {
-                xl = wxl ? C(0) : C(pm.bx.x);
-                yl = wyl ? C(0) : C(pm.by.x);
-                zl = C(pm.bz.x);
-                zh = C(pc.bz.x);
-                rr = C(pm.r.x);
-            } else {
-                xl = C(pm.bx.y);
-                yl = wyl ? C(0) : C(pm.by.y);
-                zl = C(pm.bz.y);
-                zh = C(pc.bz.y);
-                rr = C(pm.r.y);
-            }
-            xh = bxh_prev;
-            const C yh = byh_prev;
-            const C s = xl * RED[sb][ly][cx - 1] + xh * RED[sb][ly][cx + 1] +
-                        yl * RED[sb][ly - 1][cx] + yh * RED[sb][ly + 1][cx] + zl * red_km2 +
-                        zh * red;
-            const C diag = (xl + xh) + (yl + yh) + (zl + zh);
-            const C blk = (s - h2 * rr) / diag;
+            const C bzl = pick(o, pm.bz), bzh = pick(o, pc.bz);
+            const C sbv = sxl * RED[sb][ly][ca - 1] + sxh * RED[sb][ly][ca + 1] +
+                          syl * RED[sb][ly - 1][ca] + syh * RED[sb][ly + 1][ca] + bzl * red_km2 +
+                          bzh * red;
+            const C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
+            const C blk = (sbv - h2 * pick(o, pm.r)) / dg;
             T2 outv;
-            if (ob == 0) {
-                outv.x = static_cast<T>(blk);
-                outv.y = static_cast<T>(red_km1);
-            } else {
-                outv.x = static_cast<T>(red_km1);
-                outv.y = static_cast<T>(blk);
-            }
-            *reinterpret_cast<T2 *>(eout + (size_t)kb * sz + rowc) = outv;
+            outv.x = static_cast<T>(o ? red_km1 : blk);
+            outv.y = static_cast<T>(o ? blk : red_km1);
+            st_pair<T>(plane_rsrc(reinterpret_cast<const char *>(eout) + (size_t)kb * pbytes, pbytes),
+                       ost, outv);
         }
-        // rotate the pipeline
         red_km2 = red_km1;
         red_km1 = red;
-        bxh_prev = bxh_cur;
-        byh_prev = byh_cur;
-        pm = pc;
-        pc = pn;
-        pn = pf;
+        sxl = nxl;
+        sxh = nxh;
+        syl = nyl;
+        syh = nyh;
+    };
+
+    // FNB input buffers rotate through the roles (k-1, k, k+1, and the planes
+    // in flight); the loop is unrolled by FNB so no buffer with loads in
+    // flight is ever copied
+    PairIn<T> buf[FNB];
+#pragma unroll
+    for (int u = 0; u < FNB - 1; ++u)
+        load_in(k0 - 2 + u, buf[u]);
+    __syncthreads();                  // the zero fill is complete
+    publish((k0 - 1) & 1, buf[1]);
+    __syncthreads();
+    for (int k = k0 - 1;;) {
+#pragma unroll
+        for (int u = 0; u < FNB; ++u) {
+            step(k, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB], buf[(u + FNB - 1) % FNB]);
+            if (++k > k1)
+                return;
+        }
     }
 }
 
@@ -597,75 +639,115 @@ struct TailArgs {
     int ncoarse;
 };
 
-template <typename T>
-__device__ void tail_gs(const TailArgs<T> &a, int l, int colour, bool zero)
+// Tail levels live in LDS: corrections and right-hand sides always, face
+// coefficients too when the arithmetic is FP32 (for FP64 they are read from
+// global memory, where they stay in L2).  Level q occupies cells
+// [off[q], off[q] + cells(d[q])) of each array.
+constexpr int TAIL_LDS = 4736;            // >= 4096 * (1 + 1/8 + 1/64 + ...)
+
+// 32-bit index helpers for the tail (all tail levels have < 2^31 cells)
+struct Nb32 {
+    int c, xm, xp, ym, yp, zm, zp;
+    bool wxl, wxh, wyl, wyh, wzl, wzh;
+};
+
+__device__ __forceinline__ Nb32 nb32(Dims d, Bc bc, int c)
 {
-    using C = typename Acc<T>::type;
-    const Dims d = a.d[l];
-    const size_t n = cells(d);
-    const C h2 = (C)a.h2[l];
-    for (size_t c = threadIdx.x; c < n; c += blockDim.x) {
-        const int i = (int)(c % d.nx), j = (int)((c / d.nx) % d.ny), k = (int)(c / ((size_t)d.nx * d.ny));
-        if (((i + j + k) & 1) != colour)
+    const unsigned nx = d.nx, nxy = (unsigned)d.nx * d.ny;
+    const int k = (int)((unsigned)c / nxy);
+    const int rem = c - k * (int)nxy;
+    const int j = (int)((unsigned)rem / nx);
+    const int i = rem - j * (int)nx;
+    Nb32 n;
+    n.c = c;
+    n.xm = c - i + (i == 0 ? d.nx - 1 : i - 1);
+    n.xp = c - i + (i == d.nx - 1 ? 0 : i + 1);
+    n.ym = c + ((j == 0 ? d.ny - 1 : j - 1) - j) * d.nx;
+    n.yp = c + ((j == d.ny - 1 ? 0 : j + 1) - j) * d.nx;
+    n.zm = c + ((k == 0 ? d.nz - 1 : k - 1) - k) * (int)nxy;
+    n.zp = c + ((k == d.nz - 1 ? 0 : k + 1) - k) * (int)nxy;
+    n.wxl = bc.x && i == 0;
+    n.wxh = bc.x && i == d.nx - 1;
+    n.wyl = bc.y && j == 0;
+    n.wyh = bc.y && j == d.ny - 1;
+    n.wzl = bc.z && k == 0;
+    n.wzh = bc.z && k == d.nz - 1;
+    return n;
+}
+
+template <typename C, typename TB>
+__device__ __forceinline__ void tl_gs(Dims d, Bc bc, const TB *bx, const TB *by, const TB *bz,
+                                      const C *r, C *e, C h2, int colour, bool zero)
+{
+    const int n = (int)cells(d);
+    const unsigned nx = d.nx, nxy = (unsigned)d.nx * d.ny;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const unsigned k = (unsigned)c / nxy, rem = (unsigned)c - k * nxy;
+        const unsigned j = rem / nx, i = rem - j * nx;
+        if (((i + j + k) & 1u) != (unsigned)colour)
             continue;
-        const Nb nb = neighbours(d, a.bc, i, j, k);
-        const Links<T> L = links(nb, a.b[l][0], a.b[l][1], a.b[l][2]);
-        const C diag = (L.xl + L.xh) + (L.yl + L.yh) + (L.zl + L.zh);
-        const T *e = a.e[l];
+        const Nb32 nb = nb32(d, bc, c);
+        const C xl = nb.wxl ? C(0) : C(bx[nb.c]), xh = nb.wxh ? C(0) : C(bx[nb.xp]);
+        const C yl = nb.wyl ? C(0) : C(by[nb.c]), yh = nb.wyh ? C(0) : C(by[nb.yp]);
+        const C zl = nb.wzl ? C(0) : C(bz[nb.c]), zh = nb.wzh ? C(0) : C(bz[nb.zp]);
+        const C diag = (xl + xh) + (yl + yh) + (zl + zh);
         C s = C(0);
         if (!zero)
-            s = L.xl * ld(e, nb.xm) + L.xh * ld(e, nb.xp) + L.yl * ld(e, nb.ym) +
-                L.yh * ld(e, nb.yp) + L.zl * ld(e, nb.zm) + L.zh * ld(e, nb.zp);
-        a.e[l][c] = static_cast<T>((s - h2 * ld(a.r[l], c)) / diag);
+            s = xl * e[nb.xm] + xh * e[nb.xp] + yl * e[nb.ym] + yh * e[nb.yp] + zl * e[nb.zm] +
+                zh * e[nb.zp];
+        e[c] = (s - h2 * r[c]) / diag;
     }
     __syncthreads();
 }
 
-template <typename T>
-__device__ void tail_restrict(const TailArgs<T> &a, int l)
+template <typename C, typename TB>
+__device__ __forceinline__ void tl_restrict(Dims fd, Bc bc, const TB *bx, const TB *by, const TB *bz,
+                                            const C *r, const C *e, C *rH, C ih2)
 {
-    using C = typename Acc<T>::type;
-    const Dims fd = a.d[l];
-    const Dims cd = a.d[l + 1];
-    const size_t nc = cells(cd);
-    const C ih2 = (C)(1.0 / a.h2[l]);
-    for (size_t cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-        const int I = (int)(cc % cd.nx), J = (int)((cc / cd.nx) % cd.ny),
-                  K = (int)(cc / ((size_t)cd.nx * cd.ny));
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int nc = (int)cells(cd);
+    const unsigned cnx = cd.nx, cnxy = (unsigned)cd.nx * cd.ny;
+    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
+        const unsigned K = (unsigned)cc / cnxy, rem = (unsigned)cc - K * cnxy;
+        const unsigned J = rem / cnx, I = rem - J * cnx;
+        const int f0 = (int)((2 * K * fd.ny + 2 * J) * fd.nx + 2 * I);
         C acc = C(0);
         for (int q = 0; q < 8; ++q) {
-            const Nb nb = neighbours(fd, a.bc, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1),
-                                     2 * K + (q >> 2));
-            const Links<T> L = links(nb, a.b[l][0], a.b[l][1], a.b[l][2]);
-            acc += ld(a.r[l], nb.c) - ih2 * flux_sum(nb, L, a.e[l]);
+            const int f = f0 + (q & 1) + ((q >> 1) & 1) * fd.nx + (q >> 2) * fd.nx * fd.ny;
+            const Nb32 nb = nb32(fd, bc, f);
+            const C xl = nb.wxl ? C(0) : C(bx[nb.c]), xh = nb.wxh ? C(0) : C(bx[nb.xp]);
+            const C yl = nb.wyl ? C(0) : C(by[nb.c]), yh = nb.wyh ? C(0) : C(by[nb.yp]);
+            const C zl = nb.wzl ? C(0) : C(bz[nb.c]), zh = nb.wzh ? C(0) : C(bz[nb.zp]);
+            const C ec = e[nb.c];
+            const C fl = xh * (e[nb.xp] - ec) - xl * (ec - e[nb.xm]) + yh * (e[nb.yp] - ec) -
+                         yl * (ec - e[nb.ym]) + zh * (e[nb.zp] - ec) - zl * (ec - e[nb.zm]);
+            acc += r[nb.c] - ih2 * fl;
         }
-        a.r[l + 1][cc] = static_cast<T>(acc * C(0.125));
+        rH[cc] = acc * C(0.125);
     }
     __syncthreads();
 }
 
-template <typename T>
-__device__ void tail_prolong(const TailArgs<T> &a, int l)
+template <typename C>
+__device__ __forceinline__ void tl_prolong(Dims fd, Bc bc, const C *eH, C *e)
 {
-    using C = typename Acc<T>::type;
-    const Dims fd = a.d[l];
-    const Dims cd = a.d[l + 1];
-    const size_t n = cells(fd);
-    const T *eH = a.e[l + 1];
-    for (size_t c = threadIdx.x; c < n; c += blockDim.x) {
-        const int i = (int)(c % fd.nx), j = (int)((c / fd.nx) % fd.ny), k = (int)(c / ((size_t)fd.nx * fd.ny));
-        const int I0 = i >> 1, I1 = other_parent(i, cd.nx, a.bc.x);
-        const int J0 = j >> 1, J1 = other_parent(j, cd.ny, a.bc.y);
-        const int K0 = k >> 1, K1 = other_parent(k, cd.nz, a.bc.z);
-        const size_t sy = cd.nx, sz = (size_t)cd.nx * cd.ny;
-        const size_t k0 = K0 * sz, k1 = K1 * sz, j0 = J0 * sy, j1 = J1 * sy;
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int n = (int)cells(fd);
+    const unsigned nx = fd.nx, nxy = (unsigned)fd.nx * fd.ny;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const unsigned k = (unsigned)c / nxy, rem = (unsigned)c - k * nxy;
+        const unsigned j = rem / nx, i = rem - j * nx;
+        const int I0 = i >> 1, I1 = other_parent(i, cd.nx, bc.x);
+        const int J0 = j >> 1, J1 = other_parent(j, cd.ny, bc.y);
+        const int K0 = k >> 1, K1 = other_parent(k, cd.nz, bc.z);
+        const int sy = cd.nx, sz = cd.nx * cd.ny;
+        const int k0 = K0 * sz, k1 = K1 * sz, j0 = J0 * sy, j1 = J1 * sy;
         const C w0 = C(0.75), w1 = C(0.25);
-        const C x00 = w0 * ld(eH, k0 + j0 + I0) + w1 * ld(eH, k0 + j0 + I1);
-        const C x01 = w0 * ld(eH, k0 + j1 + I0) + w1 * ld(eH, k0 + j1 + I1);
-        const C x10 = w0 * ld(eH, k1 + j0 + I0) + w1 * ld(eH, k1 + j0 + I1);
-        const C x11 = w0 * ld(eH, k1 + j1 + I0) + w1 * ld(eH, k1 + j1 + I1);
-        const C v = w0 * (w0 * x00 + w1 * x01) + w1 * (w0 * x10 + w1 * x11);
-        a.e[l][c] = static_cast<T>(ld(a.e[l], c) + v);
+        const C x00 = w0 * eH[k0 + j0 + I0] + w1 * eH[k0 + j0 + I1];
+        const C x01 = w0 * eH[k0 + j1 + I0] + w1 * eH[k0 + j1 + I1];
+        const C x10 = w0 * eH[k1 + j0 + I0] + w1 * eH[k1 + j0 + I1];
+        const C x11 = w0 * eH[k1 + j1 + I0] + w1 * eH[k1 + j1 + I1];
+        e[c] += w0 * (w0 * x00 + w1 * x01) + w1 * (w0 * x10 + w1 * x11);
     }
     __syncthreads();
 }
@@ -673,37 +755,80 @@ __device__ void tail_prolong(const TailArgs<T> &a, int l)
 template <typename T>
 __global__ __launch_bounds__(1024) void k_tail_cycle(TailArgs<T> a)
 {
+    using C = typename Acc<T>::type;
+    constexpr bool BLDS = sizeof(C) == 4;   // FP32 arithmetic: face coefficients in LDS too
+    __shared__ C E[TAIL_LDS];
+    __shared__ C Rr[TAIL_LDS];
+    __shared__ C Bs[BLDS ? 3 : 1][BLDS ? TAIL_LDS : 1];
     __shared__ double rs[1024];
     const int L = a.n;
+    // first cell of level q in the LDS arrays
+    auto off_of = [&](int q) -> int {
+        int o = 0;
+        for (int l = 0; l < q; ++l)
+            o += (int)cells(a.d[l]);
+        return o;
+    };
+    // stage the input right-hand side and the coefficients
+    for (int c = threadIdx.x; c < off_of(1); c += blockDim.x)
+        Rr[c] = ld(a.r[0], c);
+    if (BLDS)
+        for (int l = 0; l < L; ++l)
+            for (int m = 0; m < 3; ++m)
+                for (int c = threadIdx.x; c < off_of(l + 1) - off_of(l); c += blockDim.x)
+                    Bs[BLDS ? m : 0][BLDS ? off_of(l) + c : 0] = ld(a.b[l][m], c);
+    __syncthreads();
+    auto beta = [&](int l, int m) -> const C * { return &Bs[BLDS ? m : 0][BLDS ? off_of(l) : 0]; };
     for (int l = 0; l + 1 < L; ++l) {
+        const C h2 = (C)a.h2[l];
         for (int sw = 0; sw < a.nu_pre; ++sw) {
-            tail_gs(a, l, 0, sw == 0);
-            tail_gs(a, l, 1, false);
+            for (int colour = 0; colour < 2; ++colour) {
+                if (BLDS)
+                    tl_gs(a.d[l], a.bc, beta(l, 0), beta(l, 1), beta(l, 2), Rr + off_of(l), E + off_of(l),
+                          h2, colour, sw == 0 && colour == 0);
+                else
+                    tl_gs(a.d[l], a.bc, a.b[l][0], a.b[l][1], a.b[l][2], Rr + off_of(l), E + off_of(l), h2,
+                          colour, sw == 0 && colour == 0);
+            }
         }
-        tail_restrict(a, l);
+        if (BLDS)
+            tl_restrict(a.d[l], a.bc, beta(l, 0), beta(l, 1), beta(l, 2), Rr + off_of(l), E + off_of(l),
+                        Rr + off_of(l + 1), C(1) / h2);
+        else
+            tl_restrict(a.d[l], a.bc, a.b[l][0], a.b[l][1], a.b[l][2], Rr + off_of(l), E + off_of(l),
+                        Rr + off_of(l + 1), C(1) / h2);
     }
-    // coarsest level: e = A^+ r (FP64)
+    // coarsest level: e = A^+ r in FP64
     {
         const int n = a.ncoarse;
-        const T *r = a.r[L - 1];
         for (int t = threadIdx.x; t < n; t += blockDim.x)
-            rs[t] = static_cast<double>(r[t]);
+            rs[t] = static_cast<double>(Rr[off_of(L - 1) + t]);
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             double s = 0.0;
             for (int jj = 0; jj < n; ++jj)
                 s += a.pinv[(size_t)jj * n + i] * rs[jj];
-            a.e[L - 1][i] = static_cast<T>(s);
+            E[off_of(L - 1) + i] = static_cast<C>(s);
         }
         __syncthreads();
     }
     for (int l = L - 2; l >= 0; --l) {
-        tail_prolong(a, l);
+        const C h2 = (C)a.h2[l];
+        tl_prolong(a.d[l], a.bc, E + off_of(l + 1), E + off_of(l));
         for (int sw = 0; sw < a.nu_post; ++sw) {
-            tail_gs(a, l, 1, false);
-            tail_gs(a, l, 0, false);
+            for (int colour = 1; colour >= 0; --colour) {
+                if (BLDS)
+                    tl_gs(a.d[l], a.bc, beta(l, 0), beta(l, 1), beta(l, 2), Rr + off_of(l), E + off_of(l),
+                          h2, colour, false);
+                else
+                    tl_gs(a.d[l], a.bc, a.b[l][0], a.b[l][1], a.b[l][2], Rr + off_of(l), E + off_of(l), h2,
+                          colour, false);
+            }
         }
     }
+    // the correction of the tail's first level goes back to global memory
+    for (int c = threadIdx.x; c < off_of(1); c += blockDim.x)
+        a.e[0][c] = static_cast<T>(E[c]);
 }
 
 template <typename T>
@@ -1302,10 +1427,12 @@ void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *
                            e, (C)h2, colour);
 }
 
-// Workgroups of a kernel that the whole GPU holds at once (occupancy x CUs),
-// queried once per kernel and device.
-template <typename K>
-static long long resident_slots(K kernel, int block)
+// Workgroups of a fused-sweep kernel that the whole GPU holds at once
+// (occupancy x CUs), queried once per kernel instantiation and device.  The
+// cache lives in the (T, ZERO) instantiation: the two variants of one storage
+// type have the same function type but different register counts.
+template <typename T, bool ZERO>
+static long long fused_slots()
 {
     static long long cached[64] = {0};
     int dev = 0;
@@ -1314,7 +1441,8 @@ static long long resident_slots(K kernel, int block)
         dev = 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused<T, ZERO>, FTHREADS,
+                                                         0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1341,8 +1469,8 @@ static int fused_kz(Dims d, unsigned tiles, long long slots)
 template <typename T>
 void prepare_fused()
 {
-    (void)resident_slots(k_rbgs_fused<T, true>, FTHREADS);
-    (void)resident_slots(k_rbgs_fused<T, false>, FTHREADS);
+    (void)fused_slots<T, true>();
+    (void)fused_slots<T, false>();
 }
 
 template <typename T>
@@ -1352,8 +1480,7 @@ void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
 {
     using C = typename Acc<T>::type;
     const unsigned tx = (d.nx + FTX - 1) / FTX, ty = (d.ny + FTY - 1) / FTY;
-    const long long slots = zero ? resident_slots(k_rbgs_fused<T, true>, FTHREADS)
-                                 : resident_slots(k_rbgs_fused<T, false>, FTHREADS);
+    const long long slots = zero ? fused_slots<T, true>() : fused_slots<T, false>();
     const int kz = fused_kz(d, tx * ty, slots);
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty * tz);
