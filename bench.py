@@ -82,7 +82,7 @@ def summarize_db(path):
 
 
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "fused_rbgs_layer256.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2012_11744_amd", "csrc", "pp_kernels.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2012_11744_amd", "csrc", "pp_fused.hip")
 
 
 def counter_traffic():

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["pp_kernels.hip", "pp_api.hip"]
+SOURCES = ["pp_kernels.hip", "pp_fused.hip", "pp_api.hip"]
 LIB = os.path.join(HERE, "libpp.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

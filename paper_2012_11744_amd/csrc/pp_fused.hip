@@ -1,0 +1,428 @@
+// pp_fused.hip -- the fused red-black Gauss-Seidel sweep (gfx950), the
+// dominant kernel of the V-cycle: both colours of one sweep in one pass over
+// the level, out of place.
+//
+// The update is the seven-point Gauss-Seidel step of Sec. 3.7.1 with
+// relaxation 1 (the SOR iteration of that section with omega = 1), cells
+// coloured red ((i+j+k) even) and black; walls (Sec. 3.8) zero the link
+// coefficient of the wall face.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pp_device.h"
+#include "pp_internal.h"
+
+namespace pp {
+
+// ---------------------------------------------------------------------------
+// Fused red-black Gauss-Seidel sweep (both colours in one pass, out of place).
+//
+// A block owns an FTX x FTY tile of an x-y plane and marches along z through a
+// chunk of planes [k0, k1).  Each thread owns one x-pair of cells (2p, 2p+1)
+// of one row: at every plane exactly one cell of a pair has each colour.  At
+// step k a thread updates the first-colour cell of its pair in plane k and
+// publishes it in an LDS plane slot; after one barrier the tile threads
+// update the second-colour cell of plane k-1 from the slots (in-plane
+// neighbours) and from their own registers (the z neighbours, which are the
+// first-colour cells of the same pair in planes k-2 and k), and store the
+// finished pair of plane k-1.
+//
+// The threads of a one-pair / one-row ring around the tile, and the planes
+// k0-1 and k1, recompute first-colour values that belong to neighbouring
+// tiles and chunks from the same inputs, so blocks never read each other's
+// output (e_in is read only, e_out written only) and every cell gets the
+// update of a red-black sweep.  Every input cell is fetched from memory once
+// per sweep apart from the ring.
+//
+// The step has no data-dependent branches: every thread of the layout
+// computes the first-colour cell of its pair, reading in-plane neighbours
+// from LDS at a column chosen by the pair's colour parity; ring rows also
+// publish the row beyond them (two extra LDS rows), padding columns hold
+// zeros, and x-wall faces are zeroed as they are published.  Each plane is
+// read through buffer resources: a missing plane has an empty range, and an
+// inactive thread or a y-wall face uses an offset past the range, so those
+// values arrive as zero from the hardware range check and nothing is masked
+// after the load.  The loads of plane k+1+FPD therefore stay in flight across
+// FPD steps; the loop is unrolled by the buffer rotation period so no buffer
+// with loads in flight is copied.
+// ---------------------------------------------------------------------------
+constexpr int FTX = 64;                 // tile width in cells (32 pairs)
+constexpr int FTY = 16;                 // tile height in rows
+constexpr int FPX = FTX / 2 + 2;        // pairs per row including the ring pairs
+constexpr int FRY = FTY + 2;            // thread rows including the ring rows
+constexpr int FTHREADS = (FPX * FRY + 63) / 64 * 64;   // whole waves
+constexpr int FLW = FTX + 8;            // LDS row: cells i0-4 .. i0+FTX+3
+constexpr int FLR = FTY + 4;            // LDS rows: j0-2 .. j0+FTY+1
+
+// Planes of loads in flight beyond plane k+1, per storage type: two for FP32
+// (its loads are small, so it needs more of them in flight); one for FP64,
+// whose registers would otherwise spill, and for FP16 (measured best at one).
+template <typename T>
+struct FusedDepth {
+    static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+};
+
+// Inputs of one thread's pair at one plane, as loaded (storage precision).
+// eo / byo: e_in and beta_y of the row beyond a ring row (a copy of the own
+// row for the other threads).  Values a thread must treat as zero (inactive
+// thread, missing plane, wall faces of y and z) arrive as zero from the
+// buffer range check.
+template <typename T>
+struct PairIn {
+    using T2 = typename Vec2<T>::type;
+    T2 e, r, bx, by, bz, eo, byo;
+};
+
+// Buffer resource over one plane: loads at byte offsets >= `bytes` return
+// zero and stores there are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type ld_pair(__amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    using T2 = typename Vec2<T>::type;
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    else
+        return __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void st_pair(__amdgpu_buffer_rsrc_t rs, unsigned off,
+                                        typename Vec2<T>::type v)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b128(
+            __builtin_bit_cast(unsigned __attribute__((ext_vector_type(4))), v), rs, off, 0, 0);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(unsigned __attribute__((ext_vector_type(2))), v), rs, off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+}
+
+// an offset past every plane (planes of a fused sweep stay below 2^31 bytes)
+constexpr unsigned OFF_NONE = 0x80000000u;
+
+__device__ __forceinline__ int slot3(int k) { return ((k % 3) + 3) % 3; }
+
+// Block id -> (tile x, tile y, chunk), spreading contiguous ranges of tiles over
+// the 8 XCDs: consecutive workgroups are dispatched round-robin to the XCDs,
+// so workgroup b is given logical tile (b % 8) * (n / 8) + b / 8, which keeps
+// neighbouring tiles (which share halo lines) in one XCD's L2.  The grid is
+// (tiles of a plane) x (z chunks); b is the linear workgroup index.
+__device__ __forceinline__ void xcd_tile(unsigned tx_tiles, unsigned ty_tiles, int &bxi, int &byi,
+                                         int &bzi)
+{
+    const unsigned nb = gridDim.x * gridDim.y;
+    unsigned b = blockIdx.x + gridDim.x * blockIdx.y;
+    const unsigned full = nb & ~7u;
+    if (b < full)
+        b = (b & 7u) * (full >> 3) + (b >> 3);
+    bxi = (int)(b % tx_tiles);
+    byi = (int)((b / tx_tiles) % ty_tiles);
+    bzi = (int)(b / (tx_tiles * ty_tiles));
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T *__restrict__ bx,
+                                                         const T *__restrict__ by,
+                                                         const T *__restrict__ bz,
+                                                         const T *__restrict__ r,
+                                                         const T *__restrict__ ein,
+                                                         T *__restrict__ eout,
+                                                         typename Acc<T>::type h2, int c0, int kz,
+                                                         unsigned tx_tiles, unsigned ty_tiles)
+{
+    using C = typename Acc<T>::type;
+    using T2 = typename Vec2<T>::type;
+    constexpr int FPD = FusedDepth<T>::value;   // planes of loads in flight beyond k+1
+    constexpr int FNB = FPD + 3;                // input buffers: k-1, k, k+1 and those in flight
+    // LDS: e_in, beta_x and beta_y of planes k and k+1 (two slots) for the
+    // in-plane neighbours, and the first-colour values of planes k-2..k
+    __shared__ C SE[2][FLR][FLW];
+    __shared__ C SX[2][FLR][FLW];
+    __shared__ C SY[2][FLR][FLW];
+    __shared__ C RED[3][FLR][FLW];
+    int bxi, byi, bzi;
+    xcd_tile(tx_tiles, ty_tiles, bxi, byi, bzi);
+    const int i0 = bxi * FTX, j0 = byi * FTY;
+    const int k0 = bzi * kz;
+    const int k1 = min(k0 + kz, d.nz);
+
+    const int tid = threadIdx.x;
+    const bool in_layout = tid < FPX * FRY;
+    // threads past the layout shadow thread 0 (inactive: they publish and
+    // store nothing, and their LDS reads stay inside the arrays)
+    const int tl = in_layout ? tid : 0;
+    const int pl = tl % FPX - 1;      // pair within the tile; -1 and FTX/2 are ring pairs
+    const int rl = tl / FPX - 1;      // row within the tile; -1 and FTY are ring rows
+    int x = i0 + 2 * pl;
+    int j = j0 + rl;
+    // the pair / row just past the grid's end is the periodic wrap: ring only
+    const bool ringx = pl < 0 || pl >= FTX / 2 || x == d.nx;
+    const bool ringy = rl < 0 || rl >= FTY || j == d.ny;
+    bool act = in_layout;             // holds a pair of the grid
+    if (x < 0) {
+        if (bc.x) act = false; else x += d.nx;
+    } else if (x >= d.nx) {
+        if (bc.x || x > d.nx) act = false; else x = 0;
+    }
+    if (j < 0) {
+        if (bc.y) act = false; else j += d.ny;
+    } else if (j >= d.ny) {
+        if (bc.y || j > d.ny) act = false; else j = 0;
+    }
+    if (!act) {
+        x = 0;
+        j = 0;
+    }
+    const bool owned = act && !ringx && !ringy;
+    const bool dn_row = act && rl < 0;                 // publishes the row below it
+    const bool up_row = act && ringy && rl >= 0;       // publishes the row above it
+    const int jm = (j == 0) ? d.ny - 1 : j - 1;
+    const int jp = (j == d.ny - 1) ? 0 : j + 1;
+    const bool wyl = bc.y && j == 0, wyh = bc.y && j == d.ny - 1;
+    const bool wxl = bc.x && x == 0;
+    const int jo = dn_row ? jm : (up_row ? jp : j);
+    const bool zo = up_row ? wyh : wyl;   // the y faces published in row lyo are walls
+    // byte offsets of the pair within a plane; OFF_NONE reads zero
+    const unsigned oc0 = (unsigned)(((size_t)j * d.nx + x) * sizeof(T));
+    const unsigned oo0 = (unsigned)(((size_t)jo * d.nx + x) * sizeof(T));
+    const unsigned oc = act ? oc0 : OFF_NONE;
+    const unsigned oo = act ? oo0 : OFF_NONE;
+    const unsigned ocy = (act && !wyl) ? oc0 : OFF_NONE;
+    const unsigned ooy = (act && !zo) ? oo0 : OFF_NONE;
+    const unsigned ost = owned ? oc0 : OFF_NONE;
+    const unsigned pbytes = (unsigned)((size_t)d.nx * d.ny * sizeof(T));
+    const int lx = 2 * pl + 4;        // LDS column of the pair's first cell
+    const int ly = rl + 2;            // LDS row of the pair
+    const int lyo = dn_row ? ly - 1 : (up_row ? ly + 1 : ly);
+
+    // plane q: its wrapped index, and whether it exists (walls end the grid)
+    auto plane = [&](int q, int &qw) -> bool {
+        qw = q;
+        if (q < 0) {
+            if (bc.z) { qw = 0; return false; }
+            qw = q + d.nz;
+        } else if (q >= d.nz) {
+            if (bc.z) { qw = 0; return false; }
+            qw = q - d.nz;
+        }
+        return true;
+    };
+    auto load_in = [&](int q, PairIn<T> &v) __attribute__((always_inline)) {
+        int qw;
+        const unsigned nb = plane(q, qw) ? pbytes : 0u;
+        const size_t pb = (size_t)qw * pbytes;
+        auto rs = [&](const T *base, unsigned n) {
+            return plane_rsrc(reinterpret_cast<const char *>(base) + pb, n);
+        };
+        if (!ZERO) {
+            const auto re = rs(ein, nb);
+            v.e = ld_pair<T>(re, oc);
+            v.eo = ld_pair<T>(re, oo);
+        }
+        v.r = ld_pair<T>(rs(r, nb), oc);
+        v.bx = ld_pair<T>(rs(bx, nb), oc);
+        const auto ry = rs(by, nb);
+        v.by = ld_pair<T>(ry, ocy);
+        v.byo = ld_pair<T>(ry, ooy);
+        v.bz = ld_pair<T>(rs(bz, (bc.z && qw == 0) ? 0u : nb), oc);   // the wall below plane 0
+    };
+    auto pick = [](int o, T2 v) -> C { return C(o ? v.y : v.x); };
+    // Only active threads write LDS: the positions of inactive ones (past a
+    // wall, past a ragged grid end) keep the zeros of the initial fill, and
+    // the row a wrapping ring row publishes beyond itself may be the own row
+    // of an inactive thread.
+    auto publish = [&](int slot, const PairIn<T> &v) __attribute__((always_inline)) {
+        if (!act)
+            return;
+        if (!ZERO) {
+            SE[slot][ly][lx] = C(v.e.x);
+            SE[slot][ly][lx + 1] = C(v.e.y);
+            SE[slot][lyo][lx] = C(v.eo.x);
+            SE[slot][lyo][lx + 1] = C(v.eo.y);
+        }
+        SX[slot][ly][lx] = wxl ? C(0) : C(v.bx.x);
+        SX[slot][ly][lx + 1] = C(v.bx.y);
+        SY[slot][ly][lx] = C(v.by.x);
+        SY[slot][ly][lx + 1] = C(v.by.y);
+        SY[slot][lyo][lx] = C(v.byo.x);
+        SY[slot][lyo][lx + 1] = C(v.byo.y);
+    };
+
+    // padding columns and rows read as zero
+    for (int i = tid; i < 2 * FLR * FLW; i += FTHREADS) {
+        (&SE[0][0][0])[i] = C(0);
+        (&SX[0][0][0])[i] = C(0);
+        (&SY[0][0][0])[i] = C(0);
+    }
+    for (int i = tid; i < 3 * FLR * FLW; i += FTHREADS)
+        (&RED[0][0][0])[i] = C(0);
+
+    C red_km2 = C(0), red_km1 = C(0);
+    // in-plane faces of the second-colour cell of plane k-1 (read at step k-1)
+    C sxl = C(0), sxh = C(0), syl = C(0), syh = C(0);
+
+    // One plane step: inputs of planes k-1 (pm), k (pc), k+1 (pn) resident,
+    // plane k+1+FPD (pf) loaded here and left in flight for FPD steps.
+    auto step = [&](int k, PairIn<T> &pm, PairIn<T> &pc, PairIn<T> &pn, PairIn<T> &pf)
+                    __attribute__((always_inline)) {
+        load_in(k + 1 + FPD, pf);
+        const int si = k & 1;
+        int kw;
+        const bool kin = act && plane(k, kw);
+        const int o = (c0 + j + k) & 1;   // first-colour cell of the pair in plane k
+        // phase A: first colour of plane k
+        const int ca = lx + o;
+        const C xl = SX[si][ly][ca], xh = SX[si][ly][ca + 1];
+        const C yl = SY[si][ly][ca], yh = SY[si][ly + 1][ca];
+        const C zl = pick(o, pc.bz), zh = pick(o, pn.bz);
+        const C diag = (xl + xh) + (yl + yh) + (zl + zh);
+        C s = C(0);
+        if (!ZERO)
+            s = xl * SE[si][ly][ca - 1] + xh * SE[si][ly][ca + 1] + yl * SE[si][ly - 1][ca] +
+                yh * SE[si][ly + 1][ca] + zl * pick(o, pm.e) + zh * pick(o, pn.e);
+        const C val = (s - h2 * pick(o, pc.r)) / diag;
+        const C red = kin ? val : C(0);   // a missing plane has no faces: 0/0
+        // in-plane faces of this plane's second-colour cell, for phase B at
+        // the next step (the slot is overwritten before then)
+        const int cb = lx + 1 - o;
+        const C nxl = SX[si][ly][cb], nxh = SX[si][ly][cb + 1];
+        const C nyl = SY[si][ly][cb], nyh = SY[si][ly + 1][cb];
+        if (act)
+            RED[slot3(k)][ly][ca] = red;
+        publish(si ^ 1, pn);          // plane k+1 for the next step's phase A
+        __syncthreads();
+        // phase B: second colour of plane k-1 (at the column of this plane's
+        // first colour); the store of a thread outside the tile is dropped
+        const int kb = k - 1;
+        if (kb >= k0) {
+            const int sb = slot3(kb);
+            const C bzl = pick(o, pm.bz), bzh = pick(o, pc.bz);
+            const C sbv = sxl * RED[sb][ly][ca - 1] + sxh * RED[sb][ly][ca + 1] +
+                          syl * RED[sb][ly - 1][ca] + syh * RED[sb][ly + 1][ca] + bzl * red_km2 +
+                          bzh * red;
+            const C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
+            const C blk = (sbv - h2 * pick(o, pm.r)) / dg;
+            T2 outv;
+            outv.x = static_cast<T>(o ? red_km1 : blk);
+            outv.y = static_cast<T>(o ? blk : red_km1);
+            st_pair<T>(plane_rsrc(reinterpret_cast<const char *>(eout) + (size_t)kb * pbytes, pbytes),
+                       ost, outv);
+        }
+        red_km2 = red_km1;
+        red_km1 = red;
+        sxl = nxl;
+        sxh = nxh;
+        syl = nyl;
+        syh = nyh;
+    };
+
+    // FNB input buffers rotate through the roles (k-1, k, k+1, and the planes
+    // in flight); the loop is unrolled by FNB so no buffer with loads in
+    // flight is ever copied
+    PairIn<T> buf[FNB];
+#pragma unroll
+    for (int u = 0; u < FNB - 1; ++u)
+        load_in(k0 - 2 + u, buf[u]);
+    __syncthreads();                  // the zero fill is complete
+    publish((k0 - 1) & 1, buf[1]);
+    __syncthreads();
+    for (int k = k0 - 1;;) {
+#pragma unroll
+        for (int u = 0; u < FNB; ++u) {
+            step(k, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB], buf[(u + FNB - 1) % FNB]);
+            if (++k > k1)
+                return;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launcher
+// ---------------------------------------------------------------------------
+
+// Workgroups of a fused-sweep kernel that the whole GPU holds at once
+// (occupancy x CUs), queried once per kernel instantiation and device.  The
+// cache lives in the (T, ZERO) instantiation: the two variants of one storage
+// type have the same function type but different register counts.
+template <typename T, bool ZERO>
+static long long fused_slots()
+{
+    static long long cached[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64)
+        dev = 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused<T, ZERO>, FTHREADS,
+                                                         0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 256;
+        cached[dev] = (long long)per_cu * cus;
+    }
+    return cached[dev];
+}
+
+// Chunk length along z: the smallest chunk (fewest redundant halo planes)
+// whose workgroups all fit on the GPU at once, so a sweep runs as a single
+// round of resident workgroups with no tail.
+static int fused_kz(Dims d, unsigned tiles, long long slots)
+{
+    long long kz = ((long long)d.nz * tiles + slots - 1) / slots;
+    if (kz < 4)
+        kz = 4;
+    if (kz > d.nz)
+        kz = d.nz;
+    return (int)kz;
+}
+
+template <typename T>
+void prepare_fused()
+{
+    (void)fused_slots<T, true>();
+    (void)fused_slots<T, false>();
+}
+
+template <typename T>
+void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
+                       const T *ein, T *eout, double h2, int first_colour, bool zero,
+                       hipStream_t s)
+{
+    using C = typename Acc<T>::type;
+    const unsigned tx = (d.nx + FTX - 1) / FTX, ty = (d.ny + FTY - 1) / FTY;
+    const long long slots = zero ? fused_slots<T, true>() : fused_slots<T, false>();
+    const int kz = fused_kz(d, tx * ty, slots);
+    const unsigned tz = (d.nz + kz - 1) / kz;
+    const dim3 grid(tx * ty, tz);   // distinct shapes per level in profiles
+    if (zero)
+        hipLaunchKernelGGL((k_rbgs_fused<T, true>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz,
+                           r, ein, eout, (C)h2, first_colour, kz, tx, ty);
+    else
+        hipLaunchKernelGGL((k_rbgs_fused<T, false>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz,
+                           r, ein, eout, (C)h2, first_colour, kz, tx, ty);
+}
+
+#define PP_INSTANTIATE_FUSED(T)                                                                  \
+    template void prepare_fused<T>();                                                           \
+    template void launch_rbgs_fused<T>(Dims, Bc, const T *, const T *, const T *, const T *,    \
+                                       const T *, T *, double, int, bool, hipStream_t);
+
+PP_INSTANTIATE_FUSED(double)
+PP_INSTANTIATE_FUSED(float)
+PP_INSTANTIATE_FUSED(_Float16)
+
+}  // namespace pp

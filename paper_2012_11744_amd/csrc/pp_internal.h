@@ -29,7 +29,7 @@ __host__ __device__ inline size_t cells(Dims d) { return (size_t)d.nx * d.ny * d
 // levels handled by the single-workgroup tail of the V-cycle
 constexpr int TAIL_MAX = 8;
 constexpr size_t TAIL_CELLS = 4096;       // a level joins the tail at or below this size
-constexpr size_t FUSED_MIN_CELLS = (size_t)1 << 21;   // fused sweeps above 128^3 cells
+constexpr size_t FUSED_MIN_CELLS = (size_t)1 << 18;   // fused sweeps above 64^3 cells
 
 // The fused sweep addresses a plane through 32-bit byte offsets with one
 // reserved out-of-range value: planes must stay below 2^31 bytes.
