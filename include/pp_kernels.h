@@ -58,7 +58,9 @@ int pp_k_resid_restrict(const pp_grid *grid, const double *beta_x, const double 
                         const double *beta_z, const double *e, const double *r, double *rH,
                         void *hip_stream);
 
-/* e += P eH, trilinear cell-centred prolongation.  grid: the fine grid. */
+/* e += P eH, trilinear cell-centred prolongation (3/4 parent, 1/4 the next
+ * coarse cell per axis; at a wall the parent itself).  grid: the fine grid
+ * (all n even); eH has n/2 cells per direction; e 16-byte aligned. */
 int pp_k_prolong_add(const pp_grid *grid, const double *eH, double *e, void *hip_stream);
 
 /* Coarse face coefficients: mean of the 4 fine faces of each coarse face

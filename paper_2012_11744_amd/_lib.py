@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("warm_start", ctypes.c_int32),
-                ("fallback", ctypes.c_int32), ("coarse_graph", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("coarse_graph", ctypes.c_int32),
+                ("nu_coarse", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -211,6 +211,8 @@ int validate_opts(const pp_opts *o)
         return fail(PP_EINVAL, "opts.fallback must be 0 or 1");
     if (o->coarse_graph != 0 && o->coarse_graph != 1)
         return fail(PP_EINVAL, "opts.coarse_graph must be 0 or 1");
+    if (o->nu_coarse < 1 || o->nu_coarse > 16)
+        return fail(PP_EINVAL, "opts.nu_coarse must be in 1..16");
     return PP_OK;
 }
 
@@ -551,7 +553,7 @@ void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
         r[q] = v.r;
         v.cur = v.e;
     }
-    launch_tail<T>(n, d, h2, b, e, r, c->bc, c->opts.nu_pre, c->opts.nu_post, c->pinv, c->ncoarse,
+    launch_tail<T>(n, d, h2, b, e, r, c->bc, c->opts.nu_coarse, c->opts.nu_coarse, c->pinv, c->ncoarse,
                    s);
 }
 
@@ -700,14 +702,15 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
             S.st->vcycles++;
         launch_dot_rz<T>(c->d, c->r64, (const T *)v0.cur, c->part, s);
         launch_finalize(c->part, c->pstride, np, OP_RZ, 0, (double)c->N, first ? 1 : 0, c->scal, s);
+        int npd;
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
-            launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
-                                (const T *)v0.cur, dold, dnew, c->q64, c->scal, first, ih2,
-                                c->part, s);
+            npd = launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                                      (const T *)v0.cur, dold, dnew, c->q64, c->scal, first, ih2,
+                                      c->part, s);
         }
         first = false;
-        launch_finalize(c->part, c->pstride, np, OP_ALPHA, 0, (double)c->N, 0, c->scal, s);
+        launch_finalize(c->part, c->pstride, npd, OP_ALPHA, 0, (double)c->N, 0, c->scal, s);
         {
             KT t(c, PP_KT_OUTER_UPDATE, true);
             launch_pcg_update<T>(c->d, dnew, c->q64, x, c->r64, (T *)v0.r, (const T *)v0.cur, c->scal,
@@ -884,6 +887,7 @@ void pp_opts_default(pp_opts *o)
     o->warm_start = 0;
     o->fallback = 1;
     o->coarse_graph = 1;
+    o->nu_coarse = 4;
 }
 
 const char *pp_strerror(int status)
@@ -1193,6 +1197,8 @@ int pp_k_prolong_add(const pp_grid *grid, const double *eH, double *e, void *hip
     for (int m = 0; m < 3; ++m)
         if (grid->n[m] % 2)
             return fail(PP_EINVAL, "pp_k_prolong_add: the fine grid needs even cell counts");
+    if ((uintptr_t)e & 15)
+        return fail(PP_EINVAL, "pp_k_prolong_add: e must be 16-byte aligned (x-pairs are vectors)");
     launch_prolong<double>(to_dims(grid), to_bc(grid), eH, e, (hipStream_t)hip_stream);
     return check_launch("pp_k_prolong_add");
 }

@@ -165,10 +165,11 @@ template <typename T>
 void launch_axpy_T(size_t n, const T *e, double *x, const double *scal, hipStream_t s);
 template <typename T>
 void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_t s);
+// returns the number of partial sums written (at most grid_blocks(red_grid(d)))
 template <typename T>
-void launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                      const T *z, const double *dold, double *dnew, double *q, const double *scal,
-                      bool first, double ih2, double *part, hipStream_t s);
+int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                     const T *z, const double *dold, double *dnew, double *q, const double *scal,
+                     bool first, double ih2, double *part, hipStream_t s);
 template <typename T>
 void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, double *r, T *rT,
                        const T *zold, const double *scal, double *part, size_t pstride,

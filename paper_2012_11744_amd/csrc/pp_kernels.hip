@@ -222,31 +222,61 @@ __device__ __forceinline__ int other_parent(int i, int nH, int wall)
 }
 
 // e += P eH: cell-centred trilinear interpolation (3/4 parent, 1/4 the next
-// coarse cell on the fine cell's side, per axis).
+// coarse cell on the fine cell's side, per axis; at a wall the parent itself).
+// One thread per coarse cell updates its 2 x 2 x 2 children: it reads the
+// 3 x 3 x 3 coarse neighbourhood once, interpolates along x, then y, then z,
+// and adds to the children as four x-pairs (vector read-modify-write).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_prolong(Dims fd, Bc bc, const T *__restrict__ eH,
                                                    T *__restrict__ e)
 {
     using C = typename Acc<T>::type;
+    using T2 = typename Vec2<T>::type;
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= fd.nx || j >= fd.ny)
+    const int I = blockIdx.x * BX + threadIdx.x;
+    const int J = blockIdx.y * BY + threadIdx.y;
+    const int K = blockIdx.z;
+    if (I >= cd.nx || J >= cd.ny)
         return;
-    const int I0 = i >> 1, I1 = other_parent(i, cd.nx, bc.x);
-    const int J0 = j >> 1, J1 = other_parent(j, cd.ny, bc.y);
-    const int K0 = k >> 1, K1 = other_parent(k, cd.nz, bc.z);
+    // the other parent of the low (0) and high (1) child along each axis
+    const int Im = other_parent(2 * I, cd.nx, bc.x), Ip = other_parent(2 * I + 1, cd.nx, bc.x);
+    const int Jn[2] = {other_parent(2 * J, cd.ny, bc.y), other_parent(2 * J + 1, cd.ny, bc.y)};
+    const int Kn[2] = {other_parent(2 * K, cd.nz, bc.z), other_parent(2 * K + 1, cd.nz, bc.z)};
     const size_t sy = cd.nx, sz = (size_t)cd.nx * cd.ny;
-    const size_t k0 = K0 * sz, k1 = K1 * sz, j0 = J0 * sy, j1 = J1 * sy;
     const C a = C(0.75), b = C(0.25);
-    const C x00 = a * ld(eH, k0 + j0 + I0) + b * ld(eH, k0 + j0 + I1);
-    const C x01 = a * ld(eH, k0 + j1 + I0) + b * ld(eH, k0 + j1 + I1);
-    const C x10 = a * ld(eH, k1 + j0 + I0) + b * ld(eH, k1 + j0 + I1);
-    const C x11 = a * ld(eH, k1 + j1 + I0) + b * ld(eH, k1 + j1 + I1);
-    const C v = a * (a * x00 + b * x01) + b * (a * x10 + b * x11);
-    const size_t c = ((size_t)k * fd.ny + j) * fd.nx + i;
-    e[c] = static_cast<T>(ld(e, c) + v);
+    // x-interpolated values of the coarse rows (k, j): [0] for child 2I, [1] for 2I+1
+    auto xrow = [&](int kk, int jj, C (&out)[2]) {
+        const size_t r0 = (size_t)kk * sz + (size_t)jj * sy;
+        const C c0 = ld(eH, r0 + I);
+        out[0] = a * c0 + b * ld(eH, r0 + Im);
+        out[1] = a * c0 + b * ld(eH, r0 + Ip);
+    };
+    C X[3][3][2];                      // [z: K, Kn0, Kn1][y: J, Jn0, Jn1][x child]
+    const int ks[3] = {K, Kn[0], Kn[1]}, js[3] = {J, Jn[0], Jn[1]};
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+            xrow(ks[u], js[v], X[u][v]);
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz) {
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+            const size_t c = ((size_t)(2 * K + cz) * fd.ny + (2 * J + cy)) * fd.nx + 2 * I;
+            T2 *ep = reinterpret_cast<T2 *>(e + c);
+            T2 ev = *ep;
+            C v[2];
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const C y0 = a * X[0][0][cx] + b * X[0][1 + cy][cx];
+                const C y1 = a * X[1 + cz][0][cx] + b * X[1 + cz][1 + cy][cx];
+                v[cx] = a * y0 + b * y1;
+            }
+            ev.x = static_cast<T>(C(ev.x) + v[0]);
+            ev.y = static_cast<T>(C(ev.y) + v[1]);
+            *ep = ev;
+        }
+    }
 }
 
 // Coarsest level: e = A^+ r with the FP64 pseudo-inverse (symmetric, n <= 1024).
@@ -1088,7 +1118,8 @@ void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz
 template <typename T>
 void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_prolong<T>), cell_grid(fd), kBlock, 0, s, fd, bc, eH, e);
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    hipLaunchKernelGGL((k_prolong<T>), cell_grid(cd), kBlock, 0, s, fd, bc, eH, e);
 }
 
 template <typename T>
@@ -1271,9 +1302,9 @@ void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_
 
 
 template <typename T>
-void launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                      const T *z, const double *dold, double *dnew, double *q, const double *scal,
-                      bool first, double ih2, double *part, hipStream_t s)
+int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                     const T *z, const double *dold, double *dnew, double *q, const double *scal,
+                     bool first, double ih2, double *part, hipStream_t s)
 {
     if (first)
         hipLaunchKernelGGL((k_dir_apply<T, true>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
@@ -1281,6 +1312,7 @@ void launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const d
     else
         hipLaunchKernelGGL((k_dir_apply<T, false>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
                            dold, dnew, q, scal, ih2, part);
+    return (int)grid_blocks(red_grid(d));
 }
 
 template <typename T>
@@ -1318,7 +1350,7 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStrea
     template void launch_scale_T<T>(size_t, const double *, T *, const double *, hipStream_t);  \
     template void launch_axpy_T<T>(size_t, const T *, double *, const double *, hipStream_t);   \
     template void launch_dot_rz<T>(Dims, const double *, const T *, double *, hipStream_t);     \
-    template void launch_dir_apply<T>(Dims, Bc, const double *, const double *, const double *, \
+    template int launch_dir_apply<T>(Dims, Bc, const double *, const double *, const double *,  \
                                       const T *, const double *, double *, double *,            \
                                       const double *, bool, double, double *, hipStream_t);     \
     template void launch_pcg_update<T>(Dims, const double *, const double *, double *, double *, \

@@ -72,7 +72,8 @@ class Solver:
     def __init__(self, beta: Sequence[torch.Tensor], h: float, bc: Sequence[int],
                  precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
                  max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
-                 coarse_graph: bool = True, stream: Optional[torch.cuda.Stream] = None):
+                 coarse_graph: bool = True, nu_coarse: int = 4,
+                 stream: Optional[torch.cuda.Stream] = None):
         lib = L.load()
         self._lib = lib
         self.shape = tuple(beta[0].shape)
@@ -91,6 +92,7 @@ class Solver:
         o.warm_start = int(bool(warm_start))
         o.fallback = int(bool(fallback))
         o.coarse_graph = int(bool(coarse_graph))
+        o.nu_coarse = nu_coarse
         self.opts = o
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()

@@ -53,7 +53,7 @@ def test_opts_default(lib):
     o = L.Opts()
     lib.pp_opts_default(ctypes.byref(o))
     assert (o.precision, o.outer, o.nu_pre, o.nu_post, o.max_outer, o.warm_start, o.fallback,
-            o.coarse_graph) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1, 1)
+            o.coarse_graph, o.nu_coarse) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1, 1, 4)
 
 
 def _grid(n=(8, 8, 8), h=0.125, bc=(0, 0, 0)):
@@ -95,7 +95,8 @@ def test_setup_rejects_null_and_bad_options(lib):
     assert lib.pp_setup(None, fake, fake, fake, None, None, ctypes.byref(ctx)) == L.PP_EINVAL
     assert lib.pp_setup(ctypes.byref(g), fake, fake, fake, None, None, None) == L.PP_EINVAL
     for field, bad in (("precision", 7), ("outer", 3), ("nu_pre", 0), ("nu_post", 17),
-                       ("max_outer", 0), ("warm_start", 2), ("coarse_graph", 5)):
+                       ("max_outer", 0), ("warm_start", 2), ("coarse_graph", 5),
+                       ("nu_coarse", 0), ("nu_coarse", 17)):
         o = L.Opts()
         lib.pp_opts_default(ctypes.byref(o))
         setattr(o, field, bad)
@@ -131,5 +132,6 @@ def test_kernel_entries_validate(lib):
                                  None) == L.PP_EINVAL      # bad colour
     assert lib.pp_k_resid_restrict(ctypes.byref(g2), fake, fake, fake, fake, fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g2), fake, fake, None) == L.PP_EINVAL
+    assert lib.pp_k_prolong_add(ctypes.byref(g), fake, ctypes.c_void_p(0x1008), None) == L.PP_EINVAL   # e misaligned
     assert lib.pp_k_copy(None, fake, 10, None) == L.PP_EINVAL
     assert lib.pp_k_copy(fake, fake, 0, None) == L.PP_OK   # nothing to do
