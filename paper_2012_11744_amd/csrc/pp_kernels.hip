@@ -322,190 +322,236 @@ struct TailArgs {
 // global memory, where they stay in L2).  Level q occupies cells
 // [off[q], off[q] + cells(d[q])) of each array.
 constexpr int TAIL_LDS = 4736;            // >= 4096 * (1 + 1/8 + 1/64 + ...)
+constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_PAIRS = 2;             // x-pairs per thread: 4096 cells / 2 / 1024
 
-// 32-bit index helpers for the tail (all tail levels have < 2^31 cells)
-struct Nb32 {
-    int c, xm, xp, ym, yp, zm, zp;
-    bool wxl, wxh, wyl, wyh, wzl, wzh;
+// One x-pair (cells i0, i0+1 of a row) of a smoothed tail level, as a thread
+// holds it during a visit of that level: LDS indices of the pair and of its
+// neighbours (level-relative, wraps resolved), the face coefficients with
+// walls zeroed, the right-hand side and the diagonal.
+template <typename C>
+struct TPair {
+    int c;                     // first cell
+    int xm, xp;                // the cell left of the pair, the cell right of it
+    int ym, yp, zm, zp;        // offsets of the y and z neighbours (the same for both cells)
+    int par;                   // colour of the first cell: (j + k) & 1
+    bool on;
+    C fx0, fx1, fx2;           // x faces: low of cell 0, between the cells, high of cell 1
+    C fyl[2], fyh[2], fzl[2], fzh[2];
+    C r[2], dg[2];
 };
 
-__device__ __forceinline__ Nb32 nb32(Dims d, Bc bc, int c)
-{
-    const unsigned nx = d.nx, nxy = (unsigned)d.nx * d.ny;
-    const int k = (int)((unsigned)c / nxy);
-    const int rem = c - k * (int)nxy;
-    const int j = (int)((unsigned)rem / nx);
-    const int i = rem - j * (int)nx;
-    Nb32 n;
-    n.c = c;
-    n.xm = c - i + (i == 0 ? d.nx - 1 : i - 1);
-    n.xp = c - i + (i == d.nx - 1 ? 0 : i + 1);
-    n.ym = c + ((j == 0 ? d.ny - 1 : j - 1) - j) * d.nx;
-    n.yp = c + ((j == d.ny - 1 ? 0 : j + 1) - j) * d.nx;
-    n.zm = c + ((k == 0 ? d.nz - 1 : k - 1) - k) * (int)nxy;
-    n.zp = c + ((k == d.nz - 1 ? 0 : k + 1) - k) * (int)nxy;
-    n.wxl = bc.x && i == 0;
-    n.wxh = bc.x && i == d.nx - 1;
-    n.wyl = bc.y && j == 0;
-    n.wyh = bc.y && j == d.ny - 1;
-    n.wzl = bc.z && k == 0;
-    n.wzh = bc.z && k == d.nz - 1;
-    return n;
-}
-
 template <typename C, typename TB>
-__device__ __forceinline__ void tl_gs(Dims d, Bc bc, const TB *bx, const TB *by, const TB *bz,
-                                      const C *r, C *e, C h2, int colour, bool zero)
+__device__ __forceinline__ void tp_load(TPair<C> &P, Dims d, Bc bc, int p, const TB *bx,
+                                        const TB *by, const TB *bz, const C *R)
 {
-    const int n = (int)cells(d);
-    const unsigned nx = d.nx, nxy = (unsigned)d.nx * d.ny;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const unsigned k = (unsigned)c / nxy, rem = (unsigned)c - k * nxy;
-        const unsigned j = rem / nx, i = rem - j * nx;
-        if (((i + j + k) & 1u) != (unsigned)colour)
-            continue;
-        const Nb32 nb = nb32(d, bc, c);
-        const C xl = nb.wxl ? C(0) : C(bx[nb.c]), xh = nb.wxh ? C(0) : C(bx[nb.xp]);
-        const C yl = nb.wyl ? C(0) : C(by[nb.c]), yh = nb.wyh ? C(0) : C(by[nb.yp]);
-        const C zl = nb.wzl ? C(0) : C(bz[nb.c]), zh = nb.wzh ? C(0) : C(bz[nb.zp]);
-        const C diag = (xl + xh) + (yl + yh) + (zl + zh);
-        C s = C(0);
-        if (!zero)
-            s = xl * e[nb.xm] + xh * e[nb.xp] + yl * e[nb.ym] + yh * e[nb.yp] + zl * e[nb.zm] +
-                zh * e[nb.zp];
-        e[c] = (s - h2 * r[c]) / diag;
+    const int hx = d.nx / 2;
+    const int npairs = hx * d.ny * d.nz;
+    P.on = p < npairs;
+    if (!P.on)
+        p = 0;
+    const int k = p / (hx * d.ny);
+    const int rem = p - k * hx * d.ny;
+    const int j = rem / hx;
+    const int i0 = 2 * (rem - j * hx);
+    const int nxy = d.nx * d.ny;
+    const int c = (k * d.ny + j) * d.nx + i0;
+    P.c = c;
+    P.par = (j + k) & 1;
+    P.xm = i0 == 0 ? c + d.nx - 1 : c - 1;
+    P.xp = i0 + 2 == d.nx ? c + 2 - d.nx : c + 2;
+    P.ym = j == 0 ? (d.ny - 1) * d.nx : -d.nx;
+    P.yp = j == d.ny - 1 ? -(d.ny - 1) * d.nx : d.nx;
+    P.zm = k == 0 ? (d.nz - 1) * nxy : -nxy;
+    P.zp = k == d.nz - 1 ? -(d.nz - 1) * nxy : nxy;
+    const bool wxl = bc.x && i0 == 0, wxh = bc.x && i0 + 2 == d.nx;
+    const bool wyl = bc.y && j == 0, wyh = bc.y && j == d.ny - 1;
+    const bool wzl = bc.z && k == 0, wzh = bc.z && k == d.nz - 1;
+    P.fx0 = wxl ? C(0) : C(bx[c]);
+    P.fx1 = C(bx[c + 1]);
+    P.fx2 = wxh ? C(0) : C(bx[P.xp]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        P.fyl[q] = wyl ? C(0) : C(by[c + q]);
+        P.fyh[q] = wyh ? C(0) : C(by[c + q + P.yp]);
+        P.fzl[q] = wzl ? C(0) : C(bz[c + q]);
+        P.fzh[q] = wzh ? C(0) : C(bz[c + q + P.zp]);
+        P.r[q] = R[c + q];
     }
-    __syncthreads();
+    P.dg[0] = (P.fx0 + P.fx1) + (P.fyl[0] + P.fyh[0]) + (P.fzl[0] + P.fzh[0]);
+    P.dg[1] = (P.fx1 + P.fx2) + (P.fyl[1] + P.fyh[1]) + (P.fzl[1] + P.fzh[1]);
 }
 
-template <typename C, typename TB>
-__device__ __forceinline__ void tl_restrict(Dims fd, Bc bc, const TB *bx, const TB *by, const TB *bz,
-                                            const C *r, const C *e, C *rH, C ih2)
-{
-    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    const int nc = (int)cells(cd);
-    const unsigned cnx = cd.nx, cnxy = (unsigned)cd.nx * cd.ny;
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-        const unsigned K = (unsigned)cc / cnxy, rem = (unsigned)cc - K * cnxy;
-        const unsigned J = rem / cnx, I = rem - J * cnx;
-        const int f0 = (int)((2 * K * fd.ny + 2 * J) * fd.nx + 2 * I);
-        C acc = C(0);
-        for (int q = 0; q < 8; ++q) {
-            const int f = f0 + (q & 1) + ((q >> 1) & 1) * fd.nx + (q >> 2) * fd.nx * fd.ny;
-            const Nb32 nb = nb32(fd, bc, f);
-            const C xl = nb.wxl ? C(0) : C(bx[nb.c]), xh = nb.wxh ? C(0) : C(bx[nb.xp]);
-            const C yl = nb.wyl ? C(0) : C(by[nb.c]), yh = nb.wyh ? C(0) : C(by[nb.yp]);
-            const C zl = nb.wzl ? C(0) : C(bz[nb.c]), zh = nb.wzh ? C(0) : C(bz[nb.zp]);
-            const C ec = e[nb.c];
-            const C fl = xh * (e[nb.xp] - ec) - xl * (ec - e[nb.xm]) + yh * (e[nb.yp] - ec) -
-                         yl * (ec - e[nb.ym]) + zh * (e[nb.zp] - ec) - zl * (ec - e[nb.zm]);
-            acc += r[nb.c] - ih2 * fl;
-        }
-        rH[cc] = acc * C(0.125);
-    }
-    __syncthreads();
-}
-
+// Gauss-Seidel update of the cell of colour `colour` in the pair (eq.
+// beta_pressure with relaxation 1); zero: e is zero on entry.
 template <typename C>
-__device__ __forceinline__ void tl_prolong(Dims fd, Bc bc, const C *eH, C *e)
+__device__ __forceinline__ void tp_gs(const TPair<C> &P, C *E, C h2, int colour, bool zero)
 {
-    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    const int n = (int)cells(fd);
-    const unsigned nx = fd.nx, nxy = (unsigned)fd.nx * fd.ny;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const unsigned k = (unsigned)c / nxy, rem = (unsigned)c - k * nxy;
-        const unsigned j = rem / nx, i = rem - j * nx;
-        const int I0 = i >> 1, I1 = other_parent(i, cd.nx, bc.x);
-        const int J0 = j >> 1, J1 = other_parent(j, cd.ny, bc.y);
-        const int K0 = k >> 1, K1 = other_parent(k, cd.nz, bc.z);
-        const int sy = cd.nx, sz = cd.nx * cd.ny;
-        const int k0 = K0 * sz, k1 = K1 * sz, j0 = J0 * sy, j1 = J1 * sy;
-        const C w0 = C(0.75), w1 = C(0.25);
-        const C x00 = w0 * eH[k0 + j0 + I0] + w1 * eH[k0 + j0 + I1];
-        const C x01 = w0 * eH[k0 + j1 + I0] + w1 * eH[k0 + j1 + I1];
-        const C x10 = w0 * eH[k1 + j0 + I0] + w1 * eH[k1 + j0 + I1];
-        const C x11 = w0 * eH[k1 + j1 + I0] + w1 * eH[k1 + j1 + I1];
-        e[c] += w0 * (w0 * x00 + w1 * x01) + w1 * (w0 * x10 + w1 * x11);
+    if (!P.on)
+        return;
+    const int q = colour == P.par ? 0 : 1;
+    const int c = P.c + q;
+    const C xl = q == 0 ? P.fx0 : P.fx1, xh = q == 0 ? P.fx1 : P.fx2;
+    C s = C(0);
+    if (!zero)
+        s = xl * E[q == 0 ? P.xm : P.c] + xh * E[q == 0 ? P.c + 1 : P.xp] + P.fyl[q] * E[c + P.ym] +
+            P.fyh[q] * E[c + P.yp] + P.fzl[q] * E[c + P.zm] + P.fzh[q] * E[c + P.zp];
+    E[c] = (s - h2 * P.r[q]) / P.dg[q];
+}
+
+// r - A e at the two cells of the pair, summed (the restriction adds four pairs)
+template <typename C>
+__device__ __forceinline__ C tp_residual_sum(const TPair<C> &P, const C *E, C ih2)
+{
+    C acc = C(0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = P.c + q;
+        const C xl = q == 0 ? P.fx0 : P.fx1, xh = q == 0 ? P.fx1 : P.fx2;
+        const C ec = E[c];
+        const C exm = E[q == 0 ? P.xm : P.c], exp = E[q == 0 ? P.c + 1 : P.xp];
+        const C fl = xh * (exp - ec) - xl * (ec - exm) + P.fyh[q] * (E[c + P.yp] - ec) -
+                     P.fyl[q] * (ec - E[c + P.ym]) + P.fzh[q] * (E[c + P.zp] - ec) -
+                     P.fzl[q] * (ec - E[c + P.zm]);
+        acc += P.r[q] - ih2 * fl;
     }
-    __syncthreads();
+    return acc;
+}
+
+// e += P eH on the pair's two cells (cell-centred trilinear, as k_prolong)
+template <typename C>
+__device__ __forceinline__ void tp_prolong(const TPair<C> &P, Dims fd, Bc bc, const C *EH, C *E)
+{
+    if (!P.on)
+        return;
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int nxy = fd.nx * fd.ny;
+    const int k = P.c / nxy, rem = P.c - k * nxy;
+    const int j = rem / fd.nx, i0 = rem - j * fd.nx;
+    const int I = i0 >> 1, Im = other_parent(i0, cd.nx, bc.x), Ip = other_parent(i0 + 1, cd.nx, bc.x);
+    const int J0 = j >> 1, J1 = other_parent(j, cd.ny, bc.y);
+    const int K0 = k >> 1, K1 = other_parent(k, cd.nz, bc.z);
+    const int sy = cd.nx, sz = cd.nx * cd.ny;
+    const C a = C(0.75), b = C(0.25);
+    const int rows[4] = {K0 * sz + J0 * sy, K0 * sz + J1 * sy, K1 * sz + J0 * sy, K1 * sz + J1 * sy};
+    C x0[4], x1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const C cI = EH[rows[u] + I];
+        x0[u] = a * cI + b * EH[rows[u] + Im];
+        x1[u] = a * cI + b * EH[rows[u] + Ip];
+    }
+    E[P.c] += a * (a * x0[0] + b * x0[1]) + b * (a * x0[2] + b * x0[3]);
+    E[P.c + 1] += a * (a * x1[0] + b * x1[1]) + b * (a * x1[2] + b * x1[3]);
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_tail_cycle(TailArgs<T> a)
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
 {
     using C = typename Acc<T>::type;
     constexpr bool BLDS = sizeof(C) == 4;   // FP32 arithmetic: face coefficients in LDS too
     __shared__ C E[TAIL_LDS];
     __shared__ C Rr[TAIL_LDS];
     __shared__ C Bs[BLDS ? 3 : 1][BLDS ? TAIL_LDS : 1];
+    __shared__ C Sp[TAIL_LDS / 2];          // per-pair residual sums
     __shared__ double rs[1024];
     const int L = a.n;
-    // first cell of level q in the LDS arrays
-    auto off_of = [&](int q) -> int {
-        int o = 0;
-        for (int l = 0; l < q; ++l)
-            o += (int)cells(a.d[l]);
-        return o;
-    };
+    const int tid = threadIdx.x;
+    int off[TAIL_MAX + 1];                  // first cell of level q in the LDS arrays
+    off[0] = 0;
+    for (int l = 0; l < L; ++l)
+        off[l + 1] = off[l] + (int)cells(a.d[l]);
     // stage the input right-hand side and the coefficients
-    for (int c = threadIdx.x; c < off_of(1); c += blockDim.x)
+    for (int c = tid; c < off[1]; c += TAIL_THREADS)
         Rr[c] = ld(a.r[0], c);
     if (BLDS)
         for (int l = 0; l < L; ++l)
             for (int m = 0; m < 3; ++m)
-                for (int c = threadIdx.x; c < off_of(l + 1) - off_of(l); c += blockDim.x)
-                    Bs[BLDS ? m : 0][BLDS ? off_of(l) + c : 0] = ld(a.b[l][m], c);
+                for (int c = tid; c < off[l + 1] - off[l]; c += TAIL_THREADS)
+                    Bs[BLDS ? m : 0][BLDS ? off[l] + c : 0] = ld(a.b[l][m], c);
     __syncthreads();
-    auto beta = [&](int l, int m) -> const C * { return &Bs[BLDS ? m : 0][BLDS ? off_of(l) : 0]; };
+    TPair<C> P[TAIL_PAIRS];
+    auto visit = [&](int l) {
+#pragma unroll
+        for (int u = 0; u < TAIL_PAIRS; ++u) {
+            if (BLDS)
+                tp_load(P[u], a.d[l], a.bc, tid + u * TAIL_THREADS, &Bs[0][BLDS ? off[l] : 0],
+                        &Bs[BLDS ? 1 : 0][BLDS ? off[l] : 0], &Bs[BLDS ? 2 : 0][BLDS ? off[l] : 0],
+                        Rr + off[l]);
+            else
+                tp_load(P[u], a.d[l], a.bc, tid + u * TAIL_THREADS, a.b[l][0], a.b[l][1], a.b[l][2],
+                        Rr + off[l]);
+        }
+    };
     for (int l = 0; l + 1 < L; ++l) {
         const C h2 = (C)a.h2[l];
-        for (int sw = 0; sw < a.nu_pre; ++sw) {
+        C *El = E + off[l];
+        visit(l);
+        for (int sw = 0; sw < a.nu_pre; ++sw)
             for (int colour = 0; colour < 2; ++colour) {
-                if (BLDS)
-                    tl_gs(a.d[l], a.bc, beta(l, 0), beta(l, 1), beta(l, 2), Rr + off_of(l), E + off_of(l),
-                          h2, colour, sw == 0 && colour == 0);
-                else
-                    tl_gs(a.d[l], a.bc, a.b[l][0], a.b[l][1], a.b[l][2], Rr + off_of(l), E + off_of(l), h2,
-                          colour, sw == 0 && colour == 0);
+#pragma unroll
+                for (int u = 0; u < TAIL_PAIRS; ++u)
+                    tp_gs(P[u], El, h2, colour, sw == 0 && colour == 0);
+                __syncthreads();
             }
+        // restriction: residual sums per pair, then four pairs per coarse cell
+        const int np = (int)cells(a.d[l]) / 2;
+#pragma unroll
+        for (int u = 0; u < TAIL_PAIRS; ++u)
+            if (P[u].on)
+                Sp[tid + u * TAIL_THREADS] = tp_residual_sum(P[u], El, C(1) / h2);
+        __syncthreads();
+        const Dims fd = a.d[l];
+        const int hx = fd.nx / 2;
+        const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+        for (int cc = tid; cc < (int)cells(cd); cc += TAIL_THREADS) {
+            const int K = cc / (cd.nx * cd.ny), rem = cc - K * cd.nx * cd.ny;
+            const int J = rem / cd.nx, I = rem - J * cd.nx;
+            const int p00 = ((2 * K) * fd.ny + 2 * J) * hx + I;
+            const int sy = hx, sz = hx * fd.ny;
+            Rr[off[l + 1] + cc] = C(0.125) * ((Sp[p00] + Sp[p00 + sy]) + (Sp[p00 + sz] + Sp[p00 + sz + sy]));
         }
-        if (BLDS)
-            tl_restrict(a.d[l], a.bc, beta(l, 0), beta(l, 1), beta(l, 2), Rr + off_of(l), E + off_of(l),
-                        Rr + off_of(l + 1), C(1) / h2);
-        else
-            tl_restrict(a.d[l], a.bc, a.b[l][0], a.b[l][1], a.b[l][2], Rr + off_of(l), E + off_of(l),
-                        Rr + off_of(l + 1), C(1) / h2);
+        (void)np;
+        __syncthreads();
     }
-    // coarsest level: e = A^+ r in FP64
+    // coarsest level: e = A^+ r in FP64, g threads per output reduced by shuffles
     {
         const int n = a.ncoarse;
-        for (int t = threadIdx.x; t < n; t += blockDim.x)
-            rs[t] = static_cast<double>(Rr[off_of(L - 1) + t]);
+        for (int t = tid; t < n; t += TAIL_THREADS)
+            rs[t] = static_cast<double>(Rr[off[L - 1] + t]);
         __syncthreads();
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            double s = 0.0;
-            for (int jj = 0; jj < n; ++jj)
-                s += a.pinv[(size_t)jj * n + i] * rs[jj];
-            E[off_of(L - 1) + i] = static_cast<C>(s);
-        }
+        int g = 1;
+        while (g < 64 && 2 * g * n <= TAIL_THREADS)
+            g *= 2;
+        const int outp = tid / g, lane = tid % g;
+        double s = 0.0;
+        if (outp < n)
+            for (int jj = lane; jj < n; jj += g)
+                s += a.pinv[(size_t)jj * n + outp] * rs[jj];
+        for (int o = g >> 1; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, 64);
+        if (lane == 0 && outp < n)
+            E[off[L - 1] + outp] = static_cast<C>(s);
         __syncthreads();
     }
     for (int l = L - 2; l >= 0; --l) {
         const C h2 = (C)a.h2[l];
-        tl_prolong(a.d[l], a.bc, E + off_of(l + 1), E + off_of(l));
-        for (int sw = 0; sw < a.nu_post; ++sw) {
+        C *El = E + off[l];
+        visit(l);
+#pragma unroll
+        for (int u = 0; u < TAIL_PAIRS; ++u)
+            tp_prolong(P[u], a.d[l], a.bc, E + off[l + 1], El);
+        __syncthreads();
+        for (int sw = 0; sw < a.nu_post; ++sw)
             for (int colour = 1; colour >= 0; --colour) {
-                if (BLDS)
-                    tl_gs(a.d[l], a.bc, beta(l, 0), beta(l, 1), beta(l, 2), Rr + off_of(l), E + off_of(l),
-                          h2, colour, false);
-                else
-                    tl_gs(a.d[l], a.bc, a.b[l][0], a.b[l][1], a.b[l][2], Rr + off_of(l), E + off_of(l), h2,
-                          colour, false);
+#pragma unroll
+                for (int u = 0; u < TAIL_PAIRS; ++u)
+                    tp_gs(P[u], El, h2, colour, false);
+                __syncthreads();
             }
-        }
     }
     // the correction of the tail's first level goes back to global memory
-    for (int c = threadIdx.x; c < off_of(1); c += blockDim.x)
+    for (int c = tid; c < off[1]; c += TAIL_THREADS)
         a.e[0][c] = static_cast<T>(E[c]);
 }
 
@@ -1142,7 +1188,7 @@ void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*
     a.nu_post = nu_post;
     a.pinv = pinv;
     a.ncoarse = ncoarse;
-    hipLaunchKernelGGL((k_tail_cycle<T>), dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL((k_tail_cycle<T>), dim3(1), dim3(TAIL_THREADS), 0, s, a);
 }
 
 template <typename T>
