@@ -16,6 +16,20 @@ and 1 = wall):
   rbsor(...)                        the paper's red-black SOR (eq. beta_pressure)
   adjoint(beta, bc, h, p, gp, tol)  dL/d rhs and dL/d beta for L = <gp, p>
 
+General operator A_g x = A x - sigma x (closed links beta = 0 on interior
+faces, Sec. 3.8; a diagonal sigma from the implicit viscous step, Sec. 3.2.3,
+or from free-surface Dirichlet branches, Sec. 3.7.5):
+
+  diagonal(beta, sigma, bc, h)      diagonal of -A_g
+  active(beta, sigma, bc, h)        cells with a positive diagonal
+  apply_gen(beta, sigma, bc, h, x)  A_g x
+  solve_gen(beta, sigma, bc, h, rhs, tol)
+                                    A_g p = rhs on the active cells (Jacobi CG)
+  project_gen(beta, bc, h, dt, us, p)
+                                    eq. fotm with closed links held at u = 0
+  divergence_gen(beta, u, bc, h, scale)
+                                    D u with closed links carrying no flux
+
 `dense` holds the brute-force dense solve used on tiny grids.
 """
 from __future__ import annotations
@@ -74,6 +88,11 @@ def _load():
         lib.ppo_adjoint.argtypes = [I64P, IP, D, P, P, P, P, P, D, ctypes.c_int, P, P, P, P,
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D)]
         lib.ppo_adjoint.restype = ctypes.c_int
+        lib.ppo_apply_gen.argtypes = [I64P, IP, D, P, P, P, P, P, P]
+        lib.ppo_apply_gen.restype = None
+        lib.ppo_solve_gen.argtypes = [I64P, IP, D, P, P, P, P, P, P, D, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D)]
+        lib.ppo_solve_gen.restype = ctypes.c_int
         lib.ppo_threads.argtypes = []
         lib.ppo_threads.restype = ctypes.c_int
         _lib = lib
@@ -196,3 +215,101 @@ def rhs_from_velocity(us, bc, h: float, dt: float) -> np.ndarray:
     """b = D u* / dt with its mean removed (eq. poisson right-hand side)."""
     b = divergence(us, bc, h, 1.0 / dt)
     return b - b.mean()
+
+
+# ---------------------------------------------------------------------------
+# general operator: closed links, diagonal term, excluded cells
+# ---------------------------------------------------------------------------
+
+def _sig(sigma, shape):
+    return None if sigma is None else _c(np.broadcast_to(np.asarray(sigma, dtype=np.float64), shape))
+
+
+def apply_gen(beta, sigma, bc, h: float, x: np.ndarray) -> np.ndarray:
+    """A_g x = A x - sigma x (sigma None means 0)."""
+    bx, by, bz = (_c(v) for v in beta)
+    x = _c(x)
+    sg = _sig(sigma, x.shape)
+    n, b = _grid(x.shape, bc)
+    y = np.empty_like(x)
+    _load().ppo_apply_gen(n, b, h, _p(bx), _p(by), _p(bz), None if sg is None else _p(sg), _p(x),
+                          _p(y))
+    return y
+
+
+def open_faces(beta, bc):
+    """Boolean masks of the open faces per direction: non-wall faces with beta > 0."""
+    out = []
+    for m, bm in enumerate(beta):
+        o = np.asarray(bm) > 0.0
+        if bc[m] == 1:
+            idx = [slice(None)] * 3
+            idx[2 - m] = 0
+            o = o.copy()
+            o[tuple(idx)] = False
+        out.append(o)
+    return out
+
+
+def diagonal(beta, sigma, bc, h: float) -> np.ndarray:
+    """Diagonal of -A_g: the open face coefficients of each cell / h^2 + sigma."""
+    shape = np.asarray(beta[0]).shape
+    o = open_faces(beta, bc)
+    d = np.zeros(shape)
+    for m in range(3):
+        ax = 2 - m
+        low = np.where(o[m], np.asarray(beta[m], dtype=np.float64), 0.0)
+        if bc[m] == 0:
+            high = np.roll(low, -1, axis=ax)          # low face of the next cell, wrapped
+        else:
+            high = np.zeros(shape)
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            src[ax] = slice(1, None)
+            dst[ax] = slice(0, -1)
+            high[tuple(dst)] = low[tuple(src)]        # the upper wall face is closed
+        d += low + high
+    d /= h * h
+    if sigma is not None:
+        d = d + np.broadcast_to(np.asarray(sigma, dtype=np.float64), shape)
+    return d
+
+
+def active(beta, sigma, bc, h: float) -> np.ndarray:
+    """Cells with a positive diagonal (an open face or sigma > 0)."""
+    return diagonal(beta, sigma, bc, h) > 0.0
+
+
+def solve_gen(beta, sigma, bc, h: float, rhs: np.ndarray, tol: float = 1e-13,
+              maxit: int = 1000000, p0: np.ndarray = None, check: bool = True):
+    """A_g p = rhs on the active cells; returns (p, iterations, rel_residual).
+
+    Singular when sigma vanishes on every active cell: then the mean of rhs
+    over the active cells is removed and p has zero mean there."""
+    bx, by, bz = (_c(v) for v in beta)
+    rhs = _c(rhs)
+    sg = _sig(sigma, rhs.shape)
+    p = np.zeros_like(rhs) if p0 is None else _c(p0).copy()
+    n, b = _grid(rhs.shape, bc)
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    rc = _load().ppo_solve_gen(n, b, h, _p(bx), _p(by), _p(bz), None if sg is None else _p(sg),
+                               _p(rhs), _p(p), tol, maxit, ctypes.byref(it), ctypes.byref(rel))
+    if check and rc != 0:
+        raise RuntimeError(f"oracle general solve did not reach tol={tol}: rel={rel.value:.3e} "
+                           f"after {it.value} iterations")
+    return p, it.value, rel.value
+
+
+def project_gen(beta, bc, h: float, dt: float, us, p: np.ndarray):
+    """eq. fotm on open faces; closed links (beta = 0) and walls carry u = 0
+    (the link flags of Sec. 3.8 multiply the velocity)."""
+    u = project(beta, bc, h, dt, us, p)
+    o = open_faces(beta, bc)
+    return tuple(np.where(o[m], u[m], 0.0) for m in range(3))
+
+
+def divergence_gen(beta, u, bc, h: float, scale: float = 1.0) -> np.ndarray:
+    """scale * D u with the velocity on closed links taken as 0 (Sec. 3.8)."""
+    o = open_faces(beta, bc)
+    return divergence(tuple(np.where(o[m], u[m], 0.0) for m in range(3)), bc, h, scale)

@@ -64,3 +64,39 @@ def solve(beta, bc, h, rhs):
     M[N, :N] = 1.0
     x = np.linalg.solve(M, np.concatenate([b, [0.0]]))
     return x[:N].reshape(beta[0].shape)
+
+
+def matrix_gen(beta, sigma, bc, h):
+    """Dense A_g = A - diag(sigma): faces as in `matrix` (a closed link has
+    beta = 0 and adds nothing), the diagonal term straight from its definition."""
+    A = matrix(beta, bc, h)
+    if sigma is not None:
+        sg = np.broadcast_to(np.asarray(sigma, dtype=np.float64), beta[0].shape).reshape(-1)
+        A[np.diag_indices_from(A)] -= sg
+    return A
+
+
+def solve_gen(beta, sigma, bc, h, rhs):
+    """A_g p = rhs restricted to the active cells (nonzero diagonal of A_g);
+    excluded cells get 0.  If sigma vanishes on the active cells the system
+    is singular: the bordered system fixes the mean of p over the active
+    cells to 0 after removing the mean of rhs there."""
+    A = matrix_gen(beta, sigma, bc, h)
+    act = np.abs(np.diag(A)) > 0.0
+    idx = np.nonzero(act)[0]
+    Aa = A[np.ix_(idx, idx)]
+    b = np.asarray(rhs, dtype=np.float64).reshape(-1)[idx]
+    sg = (np.zeros(A.shape[0]) if sigma is None else
+          np.broadcast_to(np.asarray(sigma, dtype=np.float64), beta[0].shape).reshape(-1))
+    out = np.zeros(A.shape[0])
+    if np.all(sg[idx] == 0.0):
+        b = b - b.mean()
+        n = len(idx)
+        M = np.zeros((n + 1, n + 1))
+        M[:n, :n] = Aa
+        M[:n, n] = 1.0
+        M[n, :n] = 1.0
+        out[idx] = np.linalg.solve(M, np.concatenate([b, [0.0]]))[:n]
+    else:
+        out[idx] = np.linalg.solve(Aa, b)
+    return out.reshape(beta[0].shape)

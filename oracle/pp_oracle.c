@@ -21,7 +21,11 @@
  *     (Sec. 3.8), and zero normal velocity on wall faces;
  *   - the paper's red-black Gauss-Seidel with over-relaxation
  *     (Sec. 3.7.1, eq. beta_pressure), used as a cross-check;
- *   - the adjoint of the solve: dL/d rhs and dL/d beta for L = <w, p>.
+ *   - the adjoint of the solve: dL/d rhs and dL/d beta for L = <w, p>;
+ *   - a general operator A - diag(sigma) with closed interior links (solid
+ *     link flags, Sec. 3.8), a diagonal term (the implicit viscous step,
+ *     Sec. 3.2.3; free-surface Dirichlet branches, Sec. 3.7.5) and excluded
+ *     cells, solved by Jacobi-preconditioned conjugate gradients.
  *
  * Layout: cell arrays (nz, ny, nx), C order, x fastest.  A face array for
  * direction m has the same shape; entry c is the LOW face of cell c in
@@ -792,5 +796,161 @@ EXPORT int ppo_adjoint(const int64_t *n, const int *bc, double h, const double *
             gb[m][c] = (grhs[c] - grhs[dn]) * (p[c] - p[dn]) / (h * h);
         }
     }
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* General operator: closed links, a diagonal term, excluded cells           */
+/* ------------------------------------------------------------------------ */
+/*
+ * (A_g x)[c] = (A x)[c] - sigma[c] x[c], with the face coefficients of A but
+ * interior faces allowed to be 0: a closed link.  Sec. 3.8 blocks the links
+ * of a solid by multiplying the link coefficients A1..A6 with the link flags,
+ * which is a zero coefficient and a Neumann condition on that face.  The
+ * diagonal sigma >= 0 enters in two places of the paper:
+ *   - the implicit viscous step (Sec. 3.2.3, eq. muelliptic),
+ *     U* - tau mu lap U* = U^n, divided by tau mu_c row by row, is a unit
+ *     coefficient Laplacian with sigma_c = 1 / (tau mu_c);
+ *   - a Dirichlet branch of the free-surface pressure discretisation
+ *     (Sec. 3.7.5, eq. mod_branches): the gradient to an excluded cell is
+ *     (p_s - p_c) / delta, so the face adds beta / (h delta) to sigma_c and
+ *     -beta p_s / (h delta) to the right-hand side, and its coefficient is 0.
+ * A cell with no open face and sigma = 0 is excluded: its row and column
+ * vanish and its value is 0.
+ */
+EXPORT void ppo_apply_gen(const int64_t *n, const int *bc, double h, const double *bx,
+                          const double *by, const double *bz, const double *sigma,
+                          const double *x, double *y)
+{
+    grid_t g = make_grid(n, bc, h);
+    const double *beta[3] = {bx, by, bz};
+    apply_A(&g, beta, x, y);
+    if (sigma) {
+        int64_t N = cells(&g);
+        for (int64_t c = 0; c < N; ++c)
+            y[c] -= sigma[c] * x[c];
+    }
+}
+
+/* diagonal of -A_g: the open face coefficients of the cell / h^2 + sigma */
+static void diag_gen(const grid_t *g, const double *const beta[3], const double *sigma,
+                     double *dg)
+{
+    int64_t N = cells(g);
+    double ih2 = 1.0 / (g->h * g->h);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        int64_t ijk[3];
+        coords(g, c, ijk);
+        double s = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            if (neighbour(g, ijk, m, +1) >= 0)
+                s += beta_high(g, beta, ijk, m);
+            if (neighbour(g, ijk, m, -1) >= 0)
+                s += beta_low(g, beta, ijk, m);
+        }
+        dg[c] = s * ih2 + (sigma ? sigma[c] : 0.0);
+    }
+}
+
+/* Solve A_g p = b on the active cells (positive diagonal) by conjugate
+ * gradients on -A_g, preconditioned by its diagonal (Jacobi).  When sigma
+ * vanishes on every active cell the operator is singular, with the constants
+ * on the active set as null space (the caller keeps the active set
+ * connected, as the paper's percolation check does): the mean of b over the
+ * active cells is removed and p is returned with zero mean there.  Excluded
+ * cells get p = 0.  p holds the initial guess on entry.  Returns 0 when
+ * ||b - A_g p|| <= tol ||b|| (b masked and, if singular, mean-free), 1
+ * otherwise; iters and relres report the iterations and that ratio. */
+EXPORT int ppo_solve_gen(const int64_t *n, const int *bc, double h, const double *bx,
+                         const double *by, const double *bz, const double *sigma,
+                         const double *rhs, double *p, double tol, int maxit, int *iters,
+                         double *relres)
+{
+    grid_t g = make_grid(n, bc, h);
+    const double *beta[3] = {bx, by, bz};
+    int64_t N = cells(&g);
+    double *dg = malloc(sizeof(double) * N), *b = malloc(sizeof(double) * N);
+    double *s = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
+    double *d = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * N);
+    diag_gen(&g, beta, sigma, dg);
+    int singular = 1;
+    int64_t nact = 0;
+    double bsum = 0.0;
+    for (int64_t c = 0; c < N; ++c) {
+        if (dg[c] > 0.0) {
+            ++nact;
+            bsum += rhs[c];
+            if (sigma && sigma[c] != 0.0)
+                singular = 0;
+        }
+    }
+    double bmean = (singular && nact) ? bsum / (double)nact : 0.0;
+    for (int64_t c = 0; c < N; ++c) {
+        b[c] = dg[c] > 0.0 ? rhs[c] - bmean : 0.0;
+        if (!(dg[c] > 0.0))
+            p[c] = 0.0;
+    }
+    double nb = norm2(b, N);
+    int rc = 1, it = 0;
+    double rel = 0.0;
+    if (nb == 0.0) {
+        memset(p, 0, sizeof(double) * N);
+        *iters = 0;
+        *relres = 0.0;
+        free(dg); free(b); free(s); free(z); free(d); free(q);
+        return 0;
+    }
+    /* K = -A_g is positive (semi)definite on the active set: K p = -b.
+     * s = -b - K p = -(b - A_g p) is the residual of that system. */
+    ppo_apply_gen(n, bc, h, bx, by, bz, sigma, p, q);
+    for (int64_t c = 0; c < N; ++c) {
+        s[c] = dg[c] > 0.0 ? -(b[c] - q[c]) : 0.0;
+        z[c] = dg[c] > 0.0 ? s[c] / dg[c] : 0.0;
+        d[c] = z[c];
+    }
+    double rs = dot(s, z, N);
+    while (it < maxit) {
+        rel = norm2(s, N) / nb;
+        if (rel <= tol)
+            break;
+        ppo_apply_gen(n, bc, h, bx, by, bz, sigma, d, q);
+        for (int64_t c = 0; c < N; ++c)
+            q[c] = dg[c] > 0.0 ? -q[c] : 0.0;       /* q = K d */
+        double dq = dot(d, q, N);
+        if (!(dq > 0.0))
+            break;
+        double alpha = rs / dq;
+        for (int64_t c = 0; c < N; ++c) {
+            p[c] += alpha * d[c];
+            s[c] -= alpha * q[c];
+            z[c] = dg[c] > 0.0 ? s[c] / dg[c] : 0.0;
+        }
+        double rs2 = dot(s, z, N);
+        double bet = rs2 / rs;
+        rs = rs2;
+        for (int64_t c = 0; c < N; ++c)
+            d[c] = z[c] + bet * d[c];
+        ++it;
+    }
+    if (singular && nact) {
+        double m = 0.0;
+        for (int64_t c = 0; c < N; ++c)
+            if (dg[c] > 0.0)
+                m += p[c];
+        m /= (double)nact;
+        for (int64_t c = 0; c < N; ++c)
+            if (dg[c] > 0.0)
+                p[c] -= m;
+    }
+    /* true residual */
+    ppo_apply_gen(n, bc, h, bx, by, bz, sigma, p, q);
+    for (int64_t c = 0; c < N; ++c)
+        s[c] = dg[c] > 0.0 ? b[c] - q[c] : 0.0;
+    rel = norm2(s, N) / nb;
+    rc = rel <= tol ? 0 : 1;
+    *iters = it;
+    *relres = rel;
+    free(dg); free(b); free(s); free(z); free(d); free(q);
     return rc;
 }
