@@ -126,8 +126,48 @@ int pp_face_coeffs(const pp_grid *grid, const double *rho, double *beta_x, doubl
 int pp_setup(const pp_grid *grid, const double *beta_x, const double *beta_y,
              const double *beta_z, const pp_opts *opts, void *hip_stream, pp_ctx **out);
 
+/* General operator (Sec. 3.8 solid link flags; Sec. 3.2.3 implicit viscous
+ * step; Sec. 3.7.5 free-surface Dirichlet branches):
+ *
+ *   (A_g x)_c = sum_m [beta_m(c+e_m)(x_{c+e_m} - x_c) - beta_m(c)(x_c - x_{c-e_m})] / h^2
+ *               - sigma_c x_c
+ *
+ * Differences from pp_setup:
+ *  - beta may be 0 on interior faces: a closed link (the paper's link flags
+ *    zero A1..A6 across a solid), a Neumann condition on that face.  Every
+ *    non-wall face must be a finite non-negative number.
+ *  - sigma (n cells, finite, >= 0) is a diagonal term; NULL means none.  The
+ *    implicit viscous step U* - tau mu lap U* = U^n, divided by tau mu_c row
+ *    by row, is this operator with beta = 1, sigma_c = 1/(tau mu_c) and
+ *    rhs = -U^n / (tau mu_c).  A free-surface Dirichlet branch (gradient
+ *    (p_s - p_c)/delta to the interface) is a closed link plus
+ *    sigma_c += beta/(h delta) and rhs_c -= beta p_s/(h delta).
+ *  - a cell with no open face and sigma = 0 is excluded: pp_solve returns 0
+ *    there and ignores its right-hand side.
+ *  - with no positive sigma the operator is singular, with the constants on
+ *    the active cells as null space: pp_solve removes the mean of the rhs
+ *    over the active cells and returns p with zero mean over them.  The
+ *    active cells must then be connected (the caller checks this, as the
+ *    paper leaves it to a separate percolation check); otherwise the solve
+ *    stalls and returns PP_ENOCONV.  With a positive sigma nothing is removed.
+ * On a context made here every later call uses A_g: pp_apply returns A_g x;
+ * pp_divergence gives closed links no flux; pp_project writes u = 0 on
+ * closed links (as on walls); pp_solve_adjoint writes g_beta = 0 on closed
+ * links, and dL/d sigma_c = g_rhs_c * p_c follows from its outputs.
+ * Returns as pp_setup; PP_EINVAL also when no cell is active. */
+int pp_setup_general(const pp_grid *grid, const double *beta_x, const double *beta_y,
+                     const double *beta_z, const double *sigma, const pp_opts *opts,
+                     void *hip_stream, pp_ctx **out);
+
+/* New coefficients for a context made by pp_setup_general (same grid);
+ * sigma must be NULL exactly when it was NULL at setup.  As pp_update_coeffs
+ * otherwise. */
+int pp_update_general(pp_ctx *ctx, const double *beta_x, const double *beta_y,
+                      const double *beta_z, const double *sigma);
+
 /* Replace the face coefficients of an existing context (same grid), rebuilding
- * the hierarchy in place without reallocating.  Same rules as pp_setup.  If
+ * the hierarchy in place without reallocating.  Same rules as pp_setup (as
+ * pp_update_general with sigma NULL for a general context without sigma).  If
  * the coefficients are rejected (PP_EINVAL: a non-wall face that is not a
  * finite positive number), the context's coefficients are undefined until a
  * later successful update. */

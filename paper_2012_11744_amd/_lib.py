@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = [
-    "pp_opts_default", "pp_face_coeffs", "pp_setup", "pp_update_coeffs", "pp_divergence",
+    "pp_opts_default", "pp_face_coeffs", "pp_setup", "pp_setup_general", "pp_update_coeffs",
+    "pp_update_general", "pp_divergence",
     "pp_apply", "pp_solve", "pp_project", "pp_solve_adjoint", "pp_levels", "pp_level_dims",
     "pp_memory", "pp_destroy", "pp_strerror", "pp_last_error",
     "pp_k_smooth", "pp_k_smooth_fused", "pp_k_resid_restrict", "pp_k_prolong_add", "pp_k_coarsen_beta", "pp_vcycle",
@@ -94,7 +95,9 @@ def load():
         "pp_opts_default": (None, [OP]),
         "pp_face_coeffs": (I, [GP, P, P, P, P, P]),
         "pp_setup": (I, [GP, P, P, P, OP, P, ctypes.POINTER(P)]),
+        "pp_setup_general": (I, [GP, P, P, P, P, OP, P, ctypes.POINTER(P)]),
         "pp_update_coeffs": (I, [P, P, P, P]),
+        "pp_update_general": (I, [P, P, P, P, P]),
         "pp_divergence": (I, [P, P, P, P, D, P]),
         "pp_apply": (I, [P, P, P]),
         "pp_solve": (I, [P, P, P, D, SP]),

@@ -74,6 +74,7 @@ struct LevelBuf {
     void *e;      // correction, ping-pong pair with e2 (sweeps are out of place)
     void *e2;
     void *r;
+    void *s;      // diagonal term of the general operator (storage type), or null
     void *cur;    // whichever of e / e2 holds the current correction
 };
 
@@ -104,6 +105,15 @@ struct pp_ctx {
     Dims ld[MAXLEV];
     double lh[MAXLEV];
     double *chain[MAXLEV][3];   // FP64 face coefficients per level; chain[0] = the fine copy
+    // general operator A - diag(sigma) (pp_setup_general): closed links
+    // allowed; sigma per level in FP64 (coarse sigma = mean of the 8
+    // children); the active cells of level 0 and their count
+    bool gen;
+    bool sig_on;                 // sigma arrays exist
+    bool singular;               // sigma is 0 everywhere: constants on the active cells are the null space
+    double *sig[MAXLEV];
+    unsigned char *act;
+    double nact;
     Hier hmix;                   // FP32 / FP16 hierarchy (mixed precision)
     Hier h64;                    // FP64 hierarchy (FP64 mode, and the mixed-mode fallback)
     double *pinv;
@@ -283,22 +293,55 @@ int alloc_hier(pp_ctx *c, Hier &H, int st)
         PP_TRY(dev_alloc(c, &v.e, n * sb));
         PP_TRY(dev_alloc(c, &v.e2, n * sb));
         PP_TRY(dev_alloc(c, &v.r, n * sb));
+        v.s = nullptr;
+        if (c->sig_on)          // h^2 sigma of the level, in the storage type
+            PP_TRY(dev_alloc(c, &v.s, n * sb));
         v.cur = v.e;
     }
     return PP_OK;
 }
 
+int read_scal(pp_ctx *c);
+
 int fill_hier(pp_ctx *c, Hier &H, int from)
 {
-    if (!H.present || H.st == ST_F64)
+    if (!H.present)
         return PP_OK;
-    for (int l = from; l < c->nlev; ++l) {
-        const size_t n = cells(c->ld[l]);
-        for (int m = 0; m < 3; ++m) {
-            if (H.st == ST_F32)
-                launch_convert<float>(n, c->chain[l][m], (float *)H.lev[l].b[m], c->stream);
+    if (H.st != ST_F64) {
+        for (int l = from; l < c->nlev; ++l) {
+            const size_t n = cells(c->ld[l]);
+            for (int m = 0; m < 3; ++m) {
+                if (H.st == ST_F32)
+                    launch_convert<float>(n, c->chain[l][m], (float *)H.lev[l].b[m], c->stream);
+                else
+                    launch_convert<_Float16>(n, c->chain[l][m], (_Float16 *)H.lev[l].b[m], c->stream);
+            }
+        }
+    }
+    if (c->sig_on) {
+        // the V-cycle keeps h^2 sigma: the unit of the face coefficients in the
+        // smoother; FP16 storage must hold it (|h^2 sigma| < 6e4)
+        const double limit = H.st == ST_F16 ? 6.0e4 : (H.st == ST_F32 ? 1.0e38 : INFINITY);
+        const int maxb = (int)(2 * c->pstride);
+        for (int l = 0; l < c->nlev; ++l) {
+            const size_t n = cells(c->ld[l]);
+            const double h2 = c->lh[l] * c->lh[l];
+            int np;
+            if (H.st == ST_F64)
+                np = launch_convert_scaled<double>(n, c->sig[l], h2, limit, (double *)H.lev[l].s,
+                                                   c->part, maxb, c->stream);
+            else if (H.st == ST_F32)
+                np = launch_convert_scaled<float>(n, c->sig[l], h2, limit, (float *)H.lev[l].s,
+                                                  c->part, maxb, c->stream);
             else
-                launch_convert<_Float16>(n, c->chain[l][m], (_Float16 *)H.lev[l].b[m], c->stream);
+                np = launch_convert_scaled<_Float16>(n, c->sig[l], h2, limit, (_Float16 *)H.lev[l].s,
+                                                     c->part, maxb, c->stream);
+            launch_finalize(c->part, c->pstride, np, OP_STORE, S_COUNT, (double)n, 0, c->scal,
+                            c->stream);
+            PP_TRY(read_scal(c));
+            if (c->hscal[S_COUNT] != 0.0)
+                return fail(PP_EINVAL, "sigma: h^2 sigma of level " + std::to_string(l) +
+                                           " does not fit the storage precision (use FP32 or FP64)");
         }
     }
     return check_launch("convert coefficients");
@@ -324,9 +367,13 @@ int cholesky(std::vector<double> &a, int n)
     return 0;
 }
 
-// FP64 pseudo-inverse of the coarsest operator A (singular, constants in the
-// null space): with K = -A + (s/n) 1 1^T positive definite,
-// A^+ = (1/(s n)) 1 1^T - K^-1.
+// FP64 pseudo-inverse of the coarsest operator.  The pressure operator A is
+// singular (constants in the null space): with K = -A + (s/n) 1 1^T positive
+// definite, A^+ = (1/(s n)) 1 1^T - K^-1.  For the general operator
+// A - diag(sigma) the same is done on the active coarse cells (a nonzero
+// diagonal); when sigma is present the operator is definite there and
+// A^+ = -K^-1 with K = -A + diag(sigma).  Excluded cells get zero rows and
+// columns.
 int build_pinv(pp_ctx *c)
 {
     const int L = c->nlev - 1;
@@ -339,6 +386,10 @@ int build_pinv(pp_ctx *c)
         PP_HIP(hipMemcpyAsync(b[m].data(), c->chain[L][m], sizeof(double) * n, hipMemcpyDeviceToHost,
                               c->stream));
     }
+    std::vector<double> sg(n, 0.0);
+    if (c->sig_on)
+        PP_HIP(hipMemcpyAsync(sg.data(), c->sig[L], sizeof(double) * n, hipMemcpyDeviceToHost,
+                              c->stream));
     PP_HIP(hipStreamSynchronize(c->stream));
     std::vector<double> A((size_t)n * n, 0.0);
     const int nn[3] = {d.nx, d.ny, d.nz};
@@ -363,35 +414,43 @@ int build_pinv(pp_ctx *c)
                     A[(size_t)Lc * n + Lc] -= w;
                     A[(size_t)Lc * n + R] += w;
                 }
+                A[(size_t)R * n + R] -= sg[R];
             }
-    double s = 0.0;
+    std::vector<int> idx;
     for (int i = 0; i < n; ++i)
-        s = std::max(s, -A[(size_t)i * n + i]);
-    if (!(s > 0.0))
+        if (A[(size_t)i * n + i] < 0.0)
+            idx.push_back(i);
+    const int na = (int)idx.size();
+    if (na == 0)
         return fail(PP_EINVAL, "coarsest operator is zero");
-    std::vector<double> K((size_t)n * n);
-    for (size_t i = 0; i < (size_t)n * n; ++i)
-        K[i] = -A[i] + s / n;
-    if (cholesky(K, n) != 0)
+    const bool singular = !c->gen || c->singular;
+    double s = 0.0;
+    for (int i = 0; i < na; ++i)
+        s = std::max(s, -A[(size_t)idx[i] * n + idx[i]]);
+    std::vector<double> K((size_t)na * na);
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < na; ++j)
+            K[(size_t)i * na + j] = -A[(size_t)idx[i] * n + idx[j]] + (singular ? s / na : 0.0);
+    if (cholesky(K, na) != 0)
         return fail(PP_EINVAL, "coarsest operator is not definite on mean-zero fields "
                                "(disconnected domain?)");
-    std::vector<double> P((size_t)n * n);
-    std::vector<double> y(n);
-    for (int col = 0; col < n; ++col) {
-        for (int i = 0; i < n; ++i) {
+    std::vector<double> P((size_t)n * n, 0.0);
+    std::vector<double> y(na);
+    for (int col = 0; col < na; ++col) {
+        for (int i = 0; i < na; ++i) {
             double t = (i == col) ? 1.0 : 0.0;
             for (int kk = 0; kk < i; ++kk)
-                t -= K[(size_t)i * n + kk] * y[kk];
-            y[i] = t / K[(size_t)i * n + i];
+                t -= K[(size_t)i * na + kk] * y[kk];
+            y[i] = t / K[(size_t)i * na + i];
         }
-        for (int i = n - 1; i >= 0; --i) {
+        for (int i = na - 1; i >= 0; --i) {
             double t = y[i];
-            for (int kk = i + 1; kk < n; ++kk)
-                t -= K[(size_t)kk * n + i] * y[kk];
-            y[i] = t / K[(size_t)i * n + i];
+            for (int kk = i + 1; kk < na; ++kk)
+                t -= K[(size_t)kk * na + i] * y[kk];
+            y[i] = t / K[(size_t)i * na + i];
         }
-        for (int i = 0; i < n; ++i)
-            P[(size_t)i * n + col] = 1.0 / (s * n) - y[i];
+        for (int i = 0; i < na; ++i)
+            P[(size_t)idx[i] * n + idx[col]] = (singular ? 1.0 / (s * na) : 0.0) - y[i];
     }
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) {
@@ -413,6 +472,60 @@ int read_scal(pp_ctx *c)
 }
 
 int nparts(pp_ctx *c) { return (int)grid_blocks(red_grid(c->d)); }
+
+// General operator: copy and check beta (closed links allowed) and sigma,
+// mark the active cells, coarsen both through the levels, fill the storage
+// hierarchies and build the coarsest pseudo-inverse.
+int load_coeffs_general(pp_ctx *c, const double *bx, const double *by, const double *bz,
+                        const double *sg)
+{
+    const double *src[3] = {bx, by, bz};
+    for (int m = 0; m < 3; ++m)
+        PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N, hipMemcpyDeviceToDevice,
+                              c->stream));
+    launch_zero_walls(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->stream);
+    launch_check_beta(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], true, c->part,
+                      c->stream);
+    launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_COUNT, (double)c->N, 0, c->scal,
+                    c->stream);
+    if (c->sig_on) {
+        PP_HIP(hipMemcpyAsync(c->sig[0], sg, sizeof(double) * c->N, hipMemcpyDeviceToDevice,
+                              c->stream));
+        launch_check_sigma(c->d, c->sig[0], c->part, c->pstride, c->stream);
+        launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_SBAD, (double)c->N, 0, c->scal,
+                        c->stream);
+        launch_finalize(c->part + c->pstride, c->pstride, nparts(c), OP_STORE, S_SPOS, (double)c->N,
+                        0, c->scal, c->stream);
+    }
+    launch_active(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                  c->sig_on ? c->sig[0] : nullptr, c->act, c->part, c->stream);
+    launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_NACT, (double)c->N, 0, c->scal,
+                    c->stream);
+    PP_TRY(check_launch("coefficient check"));
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+        launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
+                            c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2], c->stream);
+        if (c->sig_on)
+            launch_coarsen_sigma(c->ld[l], c->sig[l], c->sig[l + 1], c->stream);
+    }
+    PP_TRY(check_launch("coarsen coefficients"));
+    PP_TRY(read_scal(c));
+    if (c->hscal[S_COUNT] != 0.0)
+        return fail(PP_EINVAL, "beta: " + std::to_string((long long)c->hscal[S_COUNT]) +
+                                   " non-wall faces are not finite non-negative numbers");
+    if (c->sig_on && c->hscal[S_SBAD] != 0.0)
+        return fail(PP_EINVAL, "sigma: " + std::to_string((long long)c->hscal[S_SBAD]) +
+                                   " entries are not finite non-negative numbers");
+    PP_TRY(fill_hier(c, c->hmix, 0));
+    PP_TRY(fill_hier(c, c->h64, 0));
+    PP_TRY(read_scal(c));
+    c->singular = !(c->sig_on && c->hscal[S_SPOS] > 0.0);
+    c->nact = c->hscal[S_NACT];
+    if (!(c->nact > 0.0))
+        return fail(PP_EINVAL, "no cell has an open face or a diagonal term");
+    PP_TRY(build_pinv(c));
+    return PP_OK;
+}
 
 int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 {
@@ -447,8 +560,8 @@ int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
             PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N,
                                   hipMemcpyDeviceToDevice, c->stream));
         launch_zero_walls(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->stream);
-        launch_check_beta(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->part,
-                          c->stream);
+        launch_check_beta(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], false,
+                          c->part, c->stream);
         launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_COUNT, (double)c->N, 0,
                         c->scal, c->stream);
     }
@@ -487,20 +600,22 @@ void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s)
             void *out = (cur == v.e) ? v.e2 : v.e;
             KT t(c, PP_KT_SMOOTH, l == 0);
             launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
-                                 h2, 0, sw == 0, s);
+                                 (const T *)v.s, h2, 0, sw == 0, s);
             cur = out;
         }
         v.cur = cur;
     } else {
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 0, sw == 0, s);
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, h2, 1, false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2, 0,
+                           sw == 0, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2, 1,
+                           false, s);
         }
         v.cur = v.e;
     }
     KT t(c, PP_KT_RESTRICT, l == 0);
     launch_resid_restrict<T>(v.d, c->bc, b0, b1, b2, (const T *)v.cur, (const T *)v.r,
-                             (T *)H.lev[l + 1].r, 1.0 / h2, s);
+                             (const T *)v.s, (T *)H.lev[l + 1].r, 1.0 / h2, s);
 }
 
 // prolongation + correction from level l + 1, then nu_post sweeps (black
@@ -521,14 +636,16 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
             void *out = (cur == v.e) ? v.e2 : v.e;
             KT t(c, PP_KT_SMOOTH, l == 0);
             launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
-                                 h2, 1, false, s);
+                                 (const T *)v.s, h2, 1, false, s);
             cur = out;
         }
         v.cur = cur;
     } else {
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, h2, 1, false, s);
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, h2, 0, false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2, 1,
+                           false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2, 0,
+                           false, s);
         }
     }
 }
@@ -543,6 +660,7 @@ void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
     const void *b[TAIL_MAX][3];
     void *e[TAIL_MAX];
     void *r[TAIL_MAX];
+    const void *sg[TAIL_MAX];
     for (int q = 0; q < n; ++q) {
         LevelBuf &v = H.lev[t + q];
         d[q] = v.d;
@@ -551,10 +669,11 @@ void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
             b[q][m] = v.b[m];
         e[q] = v.e;
         r[q] = v.r;
+        sg[q] = v.s;
         v.cur = v.e;
     }
-    launch_tail<T>(n, d, h2, b, e, r, c->bc, c->opts.nu_coarse, c->opts.nu_coarse, c->pinv, c->ncoarse,
-                   s);
+    launch_tail<T>(n, d, h2, b, e, r, sg, c->bc, c->opts.nu_coarse, c->opts.nu_coarse, c->pinv,
+                   c->ncoarse, s);
 }
 
 // the V-cycle restricted to levels from .. L-1 (input: lev[from].r)
@@ -673,7 +792,8 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
     launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs, c->scal, x,
-                    zero_x, c->r64, ih2, c->part, c->pstride, c->stream);
+                    zero_x, c->sig_on ? c->sig[0] : nullptr, c->gen ? c->act : nullptr, c->r64, ih2,
+                    c->part, c->pstride, c->stream);
     launch_finalize(c->part, c->pstride, nparts(c), OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
     PP_TRY(check_launch("residual"));
     PP_TRY(read_scal(c));
@@ -706,8 +826,9 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
             npd = launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
-                                      (const T *)v0.cur, dold, dnew, c->q64, c->scal, first, ih2,
-                                      c->part, s);
+                                      (const T *)v0.cur, dold, dnew, c->q64,
+                                      c->sig_on ? c->sig[0] : nullptr, c->scal, first, ih2, c->part,
+                                      s);
         }
         first = false;
         launch_finalize(c->part, c->pstride, npd, OP_ALPHA, 0, (double)c->N, 0, c->scal, s);
@@ -751,7 +872,8 @@ int dc_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, SolveS
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
             launch_residual_T<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs,
-                                 c->scal, x, (T *)v0.r, ih2, c->part, s);
+                                 c->scal, x, c->sig_on ? c->sig[0] : nullptr,
+                                 c->gen ? c->act : nullptr, (T *)v0.r, ih2, c->part, s);
         }
         launch_finalize(c->part, c->pstride, np, OP_DC, 0, (double)c->N, 0, c->scal, s);
         PP_TRY(check_launch("defect-correction iteration"));
@@ -783,12 +905,19 @@ int run_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, Solve
     }
 }
 
+// Singular operator: remove the mean of x (over the active cells of the
+// general operator).  General operator: excluded cells are set to 0.
 int gauge(pp_ctx *c, double *x)
 {
-    launch_sum(c->d, x, c->part, c->stream);
-    launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_XMEAN, (double)c->N, 0, c->scal,
-                    c->stream);
-    launch_sub_mean(c->N, x, c->scal, S_XMEAN, c->stream);
+    const unsigned char *act = c->gen ? c->act : nullptr;
+    if (!c->gen || c->singular) {
+        launch_sum(c->d, x, act, c->part, c->stream);
+        launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_XMEAN,
+                        c->gen ? c->nact : (double)c->N, 0, c->scal, c->stream);
+        launch_sub_mean(c->N, x, c->scal, S_XMEAN, act, c->stream);
+    } else {
+        launch_sub_mean(c->N, x, c->scal, -1, act, c->stream);
+    }
     return check_launch("gauge");
 }
 
@@ -799,9 +928,17 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
         std::memset(st, 0, sizeof(*st));
     }
     SolveState S{0.0, 0.0, INFINITY, 0, st};
-    launch_sum(c->d, rhs, c->part, c->stream);
-    launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_MEAN, (double)c->N, 0, c->scal,
-                    c->stream);
+    // the mean of the right-hand side is removed when the operator is
+    // singular (over the active cells for the general operator)
+    if (!c->gen || c->singular) {
+        launch_sum(c->d, rhs, c->gen ? c->act : nullptr, c->part, c->stream);
+        launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_MEAN,
+                        c->gen ? c->nact : (double)c->N, 0, c->scal, c->stream);
+    } else {
+        launch_fill(c->scal + S_MEAN, 1, 0.0, c->stream);
+    }
+    if (c->gen && warm)
+        launch_mask(c->N, x, c->act, c->stream);   // excluded cells of a warm start are not read
     PP_TRY(true_residual(c, rhs, x, !warm, S));
     int rc = PP_OK;
     if (!(S.nb > 0.0)) {
@@ -934,8 +1071,12 @@ void pp_destroy(pp_ctx *c)
     delete c;
 }
 
-int pp_setup(const pp_grid *grid, const double *bx, const double *by, const double *bz,
-             const pp_opts *opts, void *hip_stream, pp_ctx **out)
+}  // extern "C"
+
+namespace {
+
+int setup_impl(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+               const double *sg, bool gen, const pp_opts *opts, void *hip_stream, pp_ctx **out)
 {
     if (!out)
         return fail(PP_EINVAL, "pp_setup: out is NULL");
@@ -968,6 +1109,13 @@ int pp_setup(const pp_grid *grid, const double *bx, const double *by, const doub
     c->ncoarse = (int)cells(ld[nlev - 1]);
     c->timing = false;
     c->ev_used = 0;
+    c->gen = gen;
+    c->sig_on = gen && sg != nullptr;
+    c->singular = true;
+    c->act = nullptr;
+    c->nact = (double)c->N;
+    for (int l = 0; l < MAXLEV; ++l)
+        c->sig[l] = nullptr;
     int rc = PP_OK;
     auto bail = [&](int code) {
         pp_destroy(c);
@@ -976,6 +1124,10 @@ int pp_setup(const pp_grid *grid, const double *bx, const double *by, const doub
     for (int l = 0; l < nlev && rc == PP_OK; ++l)
         for (int m = 0; m < 3 && rc == PP_OK; ++m)
             rc = dev_alloc_t(c, &c->chain[l][m], sizeof(double) * cells(ld[l]));
+    for (int l = 0; l < nlev && rc == PP_OK && c->sig_on; ++l)
+        rc = dev_alloc_t(c, &c->sig[l], sizeof(double) * cells(ld[l]));
+    if (rc == PP_OK && gen)
+        rc = dev_alloc_t(c, &c->act, c->N);
     if (rc == PP_OK && (o.precision == PP_FP64 || o.fallback))
         rc = alloc_hier(c, c->h64, ST_F64);
     if (rc == PP_OK && o.precision != PP_FP64)
@@ -1004,7 +1156,7 @@ int pp_setup(const pp_grid *grid, const double *bx, const double *by, const doub
     }
     if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
         return bail(fail(PP_EHIP, "hipMemsetAsync failed"));
-    rc = load_coeffs(c, bx, by, bz);
+    rc = gen ? load_coeffs_general(c, bx, by, bz, sg) : load_coeffs(c, bx, by, bz);
     if (rc == PP_OK)
         rc = capture_graphs(c);
     if (rc != PP_OK)
@@ -1013,12 +1165,50 @@ int pp_setup(const pp_grid *grid, const double *bx, const double *by, const doub
     return PP_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pp_setup(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+             const pp_opts *opts, void *hip_stream, pp_ctx **out)
+{
+    return setup_impl(grid, bx, by, bz, nullptr, false, opts, hip_stream, out);
+}
+
+int pp_setup_general(const pp_grid *grid, const double *bx, const double *by, const double *bz,
+                     const double *sigma, const pp_opts *opts, void *hip_stream, pp_ctx **out)
+{
+    return setup_impl(grid, bx, by, bz, sigma, true, opts, hip_stream, out);
+}
+
 int pp_update_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 {
     PP_TRY(check_ctx(c));
     if (!bx || !by || !bz)
         return fail(PP_EINVAL, "pp_update_coeffs: NULL beta array");
+    if (c->gen) {
+        if (c->sig_on)
+            return fail(PP_EINVAL, "pp_update_coeffs: the context has a diagonal term; use "
+                                   "pp_update_general");
+        return load_coeffs_general(c, bx, by, bz, nullptr);
+    }
     return load_coeffs(c, bx, by, bz);
+}
+
+int pp_update_general(pp_ctx *c, const double *bx, const double *by, const double *bz,
+                      const double *sigma)
+{
+    PP_TRY(check_ctx(c));
+    if (!c->gen)
+        return fail(PP_EINVAL, "pp_update_general: the context was made by pp_setup");
+    if (!bx || !by || !bz)
+        return fail(PP_EINVAL, "pp_update_general: NULL beta array");
+    if ((sigma != nullptr) != c->sig_on)
+        return fail(PP_EINVAL, c->sig_on ? "pp_update_general: the context has a diagonal term: "
+                                           "sigma must be given"
+                                         : "pp_update_general: the context has no diagonal term: "
+                                           "sigma must be NULL");
+    return load_coeffs_general(c, bx, by, bz, sigma);
 }
 
 int pp_divergence(pp_ctx *c, const double *ux, const double *uy, const double *uz, double scale,
@@ -1029,7 +1219,9 @@ int pp_divergence(pp_ctx *c, const double *ux, const double *uy, const double *u
         return fail(PP_EINVAL, "pp_divergence: NULL array");
     if (!std::isfinite(scale))
         return fail(PP_EINVAL, "pp_divergence: scale must be finite");
-    launch_divergence(c->d, c->bc, ux, uy, uz, scale / c->grid.h, out, c->stream);
+    const double *const *bt = c->chain[0];
+    launch_divergence(c->d, c->bc, ux, uy, uz, scale / c->grid.h, c->gen ? bt[0] : nullptr,
+                      c->gen ? bt[1] : nullptr, c->gen ? bt[2] : nullptr, out, c->stream);
     return check_launch("pp_divergence");
 }
 
@@ -1040,8 +1232,8 @@ int pp_apply(pp_ctx *c, const double *x, double *y)
         return fail(PP_EINVAL, "pp_apply: NULL array");
     if (x == y)
         return fail(PP_EINVAL, "pp_apply: x and out must not alias");
-    launch_apply(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], x, y,
-                 1.0 / (c->grid.h * c->grid.h), c->stream);
+    launch_apply(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], x,
+                 c->sig_on ? c->sig[0] : nullptr, y, 1.0 / (c->grid.h * c->grid.h), c->stream);
     return check_launch("pp_apply");
 }
 
@@ -1085,8 +1277,10 @@ int pp_solve_adjoint(pp_ctx *c, const double *p, const double *gp, double tol, d
     int rc = solve_impl(c, gp, grhs, tol, st, false);
     if (rc != PP_OK && rc != PP_ENOCONV)
         return rc;
-    launch_adjoint_faces(c->d, c->bc, grhs, p, 1.0 / (c->grid.h * c->grid.h), gbx, gby, gbz,
-                         c->stream);
+    const double *const *bt = c->chain[0];
+    launch_adjoint_faces(c->d, c->bc, grhs, p, 1.0 / (c->grid.h * c->grid.h),
+                         c->gen ? bt[0] : nullptr, c->gen ? bt[1] : nullptr,
+                         c->gen ? bt[2] : nullptr, gbx, gby, gbz, c->stream);
     PP_TRY(check_launch("adjoint faces"));
     return rc;
 }
@@ -1140,8 +1334,8 @@ int pp_k_smooth(const pp_grid *grid, const double *bx, const double *by, const d
     const double h2 = grid->h * grid->h;
     hipStream_t s = (hipStream_t)hip_stream;
     for (int sw = 0; sw < sweeps; ++sw) {
-        launch_rbgs<double>(d, bc, bx, by, bz, r, e, h2, 0, zero_init && sw == 0, s);
-        launch_rbgs<double>(d, bc, bx, by, bz, r, e, h2, 1, false, s);
+        launch_rbgs<double>(d, bc, bx, by, bz, r, e, nullptr, h2, 0, zero_init && sw == 0, s);
+        launch_rbgs<double>(d, bc, bx, by, bz, r, e, nullptr, h2, 1, false, s);
     }
     return check_launch("pp_k_smooth");
 }
@@ -1167,7 +1361,7 @@ int pp_k_smooth_fused(const pp_grid *grid, const double *bx, const double *by, c
             return fail(PP_EINVAL, "pp_k_smooth_fused: periodic directions need an even cell count");
     if (!fused_plane_fits(to_dims(grid), sizeof(double)))
         return fail(PP_EINVAL, "pp_k_smooth_fused: an x-y plane must stay below 2^31 bytes");
-    launch_rbgs_fused<double>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in, e_out,
+    launch_rbgs_fused<double>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in, e_out, nullptr,
                               grid->h * grid->h, first_colour, zero_init != 0,
                               (hipStream_t)hip_stream);
     return check_launch("pp_k_smooth_fused");
@@ -1184,7 +1378,7 @@ int pp_k_resid_restrict(const pp_grid *grid, const double *bx, const double *by,
     for (int m = 0; m < 3; ++m)
         if (grid->n[m] % 2)
             return fail(PP_EINVAL, "pp_k_resid_restrict: the fine grid needs even cell counts");
-    launch_resid_restrict<double>(to_dims(grid), to_bc(grid), bx, by, bz, e, r, rH,
+    launch_resid_restrict<double>(to_dims(grid), to_bc(grid), bx, by, bz, e, r, nullptr, rH,
                                   1.0 / (grid->h * grid->h), (hipStream_t)hip_stream);
     return check_launch("pp_k_resid_restrict");
 }

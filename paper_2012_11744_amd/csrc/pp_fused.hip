@@ -72,6 +72,7 @@ template <typename T>
 struct PairIn {
     using T2 = typename Vec2<T>::type;
     T2 e, r, bx, by, bz, eo, byo;
+    T2 sg;                     // diagonal term (general operator only)
 };
 
 // Buffer resource over one plane: loads at byte offsets >= `bytes` return
@@ -131,13 +132,17 @@ __device__ __forceinline__ void xcd_tile(unsigned tx_tiles, unsigned ty_tiles, i
     bzi = (int)(b / (tx_tiles * ty_tiles));
 }
 
-template <typename T, bool ZERO>
+// SIG: the general operator's diagonal term, stored as h^2 sigma, is read
+// with the other inputs and added to the diagonal.  In every variant a cell with a
+// zero diagonal (no open face, no diagonal term) is excluded and gets 0.
+template <typename T, bool ZERO, bool SIG>
 __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T *__restrict__ bx,
                                                          const T *__restrict__ by,
                                                          const T *__restrict__ bz,
                                                          const T *__restrict__ r,
                                                          const T *__restrict__ ein,
                                                          T *__restrict__ eout,
+                                                         const T *__restrict__ sg,
                                                          typename Acc<T>::type h2, int c0, int kz,
                                                          unsigned tx_tiles, unsigned ty_tiles)
 {
@@ -236,6 +241,8 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
         v.by = ld_pair<T>(ry, ocy);
         v.byo = ld_pair<T>(ry, ooy);
         v.bz = ld_pair<T>(rs(bz, (bc.z && qw == 0) ? 0u : nb), oc);   // the wall below plane 0
+        if (SIG)
+            v.sg = ld_pair<T>(rs(sg, nb), oc);
     };
     auto pick = [](int o, T2 v) -> C { return C(o ? v.y : v.x); };
     // Only active threads write LDS: the positions of inactive ones (past a
@@ -286,13 +293,16 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
         const C xl = SX[si][ly][ca], xh = SX[si][ly][ca + 1];
         const C yl = SY[si][ly][ca], yh = SY[si][ly + 1][ca];
         const C zl = pick(o, pc.bz), zh = pick(o, pn.bz);
-        const C diag = (xl + xh) + (yl + yh) + (zl + zh);
+        C diag = (xl + xh) + (yl + yh) + (zl + zh);
+        if (SIG)
+            diag += pick(o, pc.sg);          // h^2 sigma
         C s = C(0);
         if (!ZERO)
             s = xl * SE[si][ly][ca - 1] + xh * SE[si][ly][ca + 1] + yl * SE[si][ly - 1][ca] +
                 yh * SE[si][ly + 1][ca] + zl * pick(o, pm.e) + zh * pick(o, pn.e);
         const C val = (s - h2 * pick(o, pc.r)) / diag;
-        const C red = kin ? val : C(0);   // a missing plane has no faces: 0/0
+        // a missing plane (0/0) and an excluded cell (zero diagonal) get 0
+        const C red = (kin && diag > C(0)) ? val : C(0);
         // in-plane faces of this plane's second-colour cell, for phase B at
         // the next step (the slot is overwritten before then)
         const int cb = lx + 1 - o;
@@ -311,8 +321,10 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
             const C sbv = sxl * RED[sb][ly][ca - 1] + sxh * RED[sb][ly][ca + 1] +
                           syl * RED[sb][ly - 1][ca] + syh * RED[sb][ly + 1][ca] + bzl * red_km2 +
                           bzh * red;
-            const C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
-            const C blk = (sbv - h2 * pick(o, pm.r)) / dg;
+            C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
+            if (SIG)
+                dg += pick(o, pm.sg);
+            const C blk = dg > C(0) ? (sbv - h2 * pick(o, pm.r)) / dg : C(0);
             T2 outv;
             outv.x = static_cast<T>(o ? red_km1 : blk);
             outv.y = static_cast<T>(o ? blk : red_km1);
@@ -355,7 +367,7 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
 // (occupancy x CUs), queried once per kernel instantiation and device.  The
 // cache lives in the (T, ZERO) instantiation: the two variants of one storage
 // type have the same function type but different register counts.
-template <typename T, bool ZERO>
+template <typename T, bool ZERO, bool SIG>
 static long long fused_slots()
 {
     static long long cached[64] = {0};
@@ -365,8 +377,8 @@ static long long fused_slots()
         dev = 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused<T, ZERO>, FTHREADS,
-                                                         0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused<T, ZERO, SIG>,
+                                                         FTHREADS, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -393,33 +405,45 @@ static int fused_kz(Dims d, unsigned tiles, long long slots)
 template <typename T>
 void prepare_fused()
 {
-    (void)fused_slots<T, true>();
-    (void)fused_slots<T, false>();
+    (void)fused_slots<T, true, false>();
+    (void)fused_slots<T, false, false>();
+    (void)fused_slots<T, true, true>();
+    (void)fused_slots<T, false, true>();
 }
 
 template <typename T>
 void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
-                       const T *ein, T *eout, double h2, int first_colour, bool zero,
+                       const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
                        hipStream_t s)
 {
     using C = typename Acc<T>::type;
     const unsigned tx = (d.nx + FTX - 1) / FTX, ty = (d.ny + FTY - 1) / FTY;
-    const long long slots = zero ? fused_slots<T, true>() : fused_slots<T, false>();
+    const long long slots = sg ? (zero ? fused_slots<T, true, true>() : fused_slots<T, false, true>())
+                               : (zero ? fused_slots<T, true, false>() : fused_slots<T, false, false>());
     const int kz = fused_kz(d, tx * ty, slots);
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty, tz);   // distinct shapes per level in profiles
-    if (zero)
-        hipLaunchKernelGGL((k_rbgs_fused<T, true>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz,
-                           r, ein, eout, (C)h2, first_colour, kz, tx, ty);
-    else
-        hipLaunchKernelGGL((k_rbgs_fused<T, false>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz,
-                           r, ein, eout, (C)h2, first_colour, kz, tx, ty);
+#define PP_FUSED_LAUNCH(Z, S)                                                                  \
+    hipLaunchKernelGGL((k_rbgs_fused<T, Z, S>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz, r, \
+                       ein, eout, sg, (C)h2, first_colour, kz, tx, ty)
+    if (sg) {
+        if (zero)
+            PP_FUSED_LAUNCH(true, true);
+        else
+            PP_FUSED_LAUNCH(false, true);
+    } else {
+        if (zero)
+            PP_FUSED_LAUNCH(true, false);
+        else
+            PP_FUSED_LAUNCH(false, false);
+    }
+#undef PP_FUSED_LAUNCH
 }
 
 #define PP_INSTANTIATE_FUSED(T)                                                                  \
     template void prepare_fused<T>();                                                           \
     template void launch_rbgs_fused<T>(Dims, Bc, const T *, const T *, const T *, const T *,    \
-                                       const T *, T *, double, int, bool, hipStream_t);
+                                       const T *, T *, const T *, double, int, bool, hipStream_t);
 
 PP_INSTANTIATE_FUSED(double)
 PP_INSTANTIATE_FUSED(float)

@@ -75,6 +75,9 @@ enum Slot {
     S_XMEAN = 9,    // mean of the iterate (gauge)
     S_COUNT = 10,   // generic count (validation)
     S_DQ = 11,
+    S_SBAD = 12,    // sigma entries that are not finite non-negative (validation)
+    S_SPOS = 13,    // positive sigma entries
+    S_NACT = 14,    // active cells of the general operator
     S_NSLOTS = 16
 };
 
@@ -89,11 +92,15 @@ enum FinalizeOp {
 };
 
 // ---------------------------------------------------------------------------
-// launchers (pp_kernels.hip); T is the storage type of V-cycle data
+// launchers (pp_kernels.hip); T is the storage type of V-cycle data.  `sg` is
+// the diagonal term of the general operator A - diag(sigma) on that level,
+// stored as h^2 sigma (the unit of the face coefficients in the smoother), or
+// null for the pressure operator; cells with no open face and no diagonal
+// term are excluded (their correction stays 0).
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e, double h2,
-                 int colour, bool zero, hipStream_t s);
+void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e,
+                 const T *sg, double h2, int colour, bool zero, hipStream_t s);
 // query (once) the occupancy figures the fused sweep's launch geometry uses;
 // called before stream capture so that capture records kernel launches only
 template <typename T>
@@ -102,11 +109,11 @@ void prepare_fused();
 // updates red ((i+j+k) even) first, 1 black first; zero: e_in treated as 0
 template <typename T>
 void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
-                       const T *ein, T *eout, double h2, int first_colour, bool zero,
+                       const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
                        hipStream_t s);
 template <typename T>
 void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
-                           const T *r, T *rH, double ih2, hipStream_t s);
+                           const T *r, const T *sg, T *rH, double ih2, hipStream_t s);
 template <typename T>
 void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s);
 template <typename T>
@@ -115,12 +122,17 @@ void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s)
 // input r[0], output e[0] (in place; every level's e is overwritten)
 template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
-                 void *const *r, Bc bc, int nu_pre, int nu_post, const double *pinv, int ncoarse,
-                 hipStream_t s);
+                 void *const *r, const void *const *sg, Bc bc, int nu_pre, int nu_post,
+                 const double *pinv, int ncoarse, hipStream_t s);
 template <typename T>
 void launch_convert(size_t n, const double *src, T *dst, hipStream_t s);
 template <typename T>
 void launch_to_double(size_t n, const T *src, double *dst, hipStream_t s);
+// dst = scale * src in the storage type; partials (one per block, at most
+// max_blocks, count returned) of the entries whose magnitude is not below `limit`
+template <typename T>
+int launch_convert_scaled(size_t n, const double *src, double scale, double limit, T *dst,
+                          double *part, int max_blocks, hipStream_t s);
 
 void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, const double *bz,
                          double *hx, double *hy, double *hz, hipStream_t s);
@@ -131,34 +143,49 @@ template <typename T>
 int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
                        T *const dstT[3], double *const coarse[3], double *part, hipStream_t s);
 void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s);
+// partials of the count of non-wall faces that are not finite positive
+// numbers (finite non-negative with allow_zero: closed links allowed)
 void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                       double *part, hipStream_t s);
+                       bool allow_zero, double *part, hipStream_t s);
+// partials: [0] sigma entries that are not finite non-negative, [pstride +]
+// positive entries
+void launch_check_sigma(Dims d, const double *sg, double *part, size_t pstride, hipStream_t s);
+// act = cells with an open face or sigma > 0; partials of their count
+void launch_active(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                   const double *sg, unsigned char *act, double *part, hipStream_t s);
+void launch_coarsen_sigma(Dims fd, const double *sg, double *sH, hipStream_t s);
+void launch_mask(size_t n, double *x, const unsigned char *act, hipStream_t s);
 void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by, double *bz,
                         hipStream_t s);
+// bx/by/bz may be null; when given, closed links (beta = 0) carry no flux
 void launch_divergence(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
-                       double scale_over_h, double *out, hipStream_t s);
+                       double scale_over_h, const double *bx, const double *by, const double *bz,
+                       double *out, hipStream_t s);
 void launch_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                  const double *x, double *y, double ih2, hipStream_t s);
+                  const double *x, const double *sg, double *y, double ih2, hipStream_t s);
 void launch_project(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                     const double *usx, const double *usy, const double *usz, const double *p,
                     double dt_over_h, double *ux, double *uy, double *uz, hipStream_t s);
 void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, double ih2,
-                          double *gx, double *gy, double *gz, hipStream_t s);
+                          const double *bx, const double *by, const double *bz, double *gx,
+                          double *gy, double *gz, hipStream_t s);
 void launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
 void launch_fill(double *x, size_t n, double v, hipStream_t s);
 
 // reductions and outer-loop kernels (FP64); `part` holds one partial sum per
 // block and quantity, quantity q at part[q * pstride + block]
-void launch_sum(Dims d, const double *x, double *part, hipStream_t s);
+// act may be null (every cell); otherwise only active cells are summed
+void launch_sum(Dims d, const double *x, const unsigned char *act, double *part, hipStream_t s);
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
                      double ncells, int first, double *scal, hipStream_t s);
 void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const double *b, const double *scal, double *x, bool zero_x, double *r64,
-                     double ih2, double *part, size_t pstride, hipStream_t s);
+                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,
+                     const unsigned char *act, double *r64, double ih2, double *part,
+                     size_t pstride, hipStream_t s);
 template <typename T>
 void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                       const double *b, const double *scal, const double *x, T *rT, double ih2,
-                       double *part, hipStream_t s);
+                       const double *b, const double *scal, const double *x, const double *sg,
+                       const unsigned char *act, T *rT, double ih2, double *part, hipStream_t s);
 template <typename T>
 void launch_scale_T(size_t n, const double *r, T *rT, const double *scal, hipStream_t s);
 template <typename T>
@@ -168,12 +195,14 @@ void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_
 // returns the number of partial sums written (at most grid_blocks(red_grid(d)))
 template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const T *z, const double *dold, double *dnew, double *q, const double *scal,
-                     bool first, double ih2, double *part, hipStream_t s);
+                     const T *z, const double *dold, double *dnew, double *q, const double *sg,
+                     const double *scal, bool first, double ih2, double *part, hipStream_t s);
 template <typename T>
 void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, double *r, T *rT,
                        const T *zold, const double *scal, double *part, size_t pstride,
                        hipStream_t s);
-void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStream_t s);
+// x -= scal[slot] (slot < 0: nothing); with act, excluded cells are set to 0
+void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const unsigned char *act,
+                     hipStream_t s);
 
 }  // namespace pp

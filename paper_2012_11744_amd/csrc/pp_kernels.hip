@@ -125,6 +125,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restri
                                                 const T *__restrict__ by,
                                                 const T *__restrict__ bz,
                                                 const T *__restrict__ r, T *e,
+                                                const T *__restrict__ sg,
                                                 typename Acc<T>::type h2, int colour)
 {
     using C = typename Acc<T>::type;
@@ -138,13 +139,16 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restri
         return;
     const Nb n = neighbours(d, bc, i, j, k);
     const Links<T> L = links(n, bx, by, bz);
-    const C diag = (L.xl + L.xh) + (L.yl + L.yh) + (L.zl + L.zh);
+    C diag = (L.xl + L.xh) + (L.yl + L.yh) + (L.zl + L.zh);
+    if (sg)
+        diag += ld(sg, n.c);        // h^2 sigma: the general operator's diagonal term
     C s = C(0);
     if (!ZERO) {
         s = L.xl * ld(e, n.xm) + L.xh * ld(e, n.xp) + L.yl * ld(e, n.ym) + L.yh * ld(e, n.yp) +
             L.zl * ld(e, n.zm) + L.zh * ld(e, n.zp);
     }
-    e[n.c] = static_cast<T>((s - h2 * ld(r, n.c)) / diag);
+    // a cell with no open face and no diagonal term is excluded: it stays 0
+    e[n.c] = static_cast<T>(diag > C(0) ? (s - h2 * ld(r, n.c)) / diag : C(0));
 }
 
 // rH = mean over the 8 children of (r - A e).  One thread per coarse cell;
@@ -156,6 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const 
                                                           const T *__restrict__ bz,
                                                           const T *__restrict__ e,
                                                           const T *__restrict__ r,
+                                                          const T *__restrict__ sg,
                                                           T *__restrict__ rH,
                                                           typename Acc<T>::type ih2)
 {
@@ -206,7 +211,15 @@ __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const 
                          (wyl ? C(0) : C(ylo.y)) * (e1 - C(eym.y)) +
                          (wzh ? C(0) : C(zhi.y)) * (C(ezp.y) - e1) -
                          (wzl ? C(0) : C(zlo.y)) * (e1 - C(ezm.y));
-            acc += (C(rr.x) - ih2 * f0) + (C(rr.y) - ih2 * f1);
+            // r - A e; the general operator's diagonal term sg = h^2 sigma
+            // adds + sigma e = ih2 sg e
+            C s0 = C(0), s1 = C(0);
+            if (sg) {
+                const T2 sv = ld2(sg, c);
+                s0 = ih2 * (C(sv.x) * e0);
+                s1 = ih2 * (C(sv.y) * e1);
+            }
+            acc += (C(rr.x) - ih2 * f0 + s0) + (C(rr.y) - ih2 * f1 + s1);
         }
     }
     rH[((size_t)K * cd.ny + J) * cd.nx + I] = static_cast<T>(acc * C(0.125));
@@ -311,6 +324,7 @@ struct TailArgs {
     const T *b[TAIL_MAX][3];
     T *e[TAIL_MAX];
     T *r[TAIL_MAX];
+    const T *s[TAIL_MAX];      // diagonal term of the general operator, or null
     Bc bc;
     int nu_pre, nu_post;
     const double *pinv;        // pseudo-inverse of the coarsest operator
@@ -338,12 +352,14 @@ struct TPair {
     bool on;
     C fx0, fx1, fx2;           // x faces: low of cell 0, between the cells, high of cell 1
     C fyl[2], fyh[2], fzl[2], fzh[2];
-    C r[2], dg[2];
+    C r[2], sg[2];
+    C dg[2];                   // sum of the face coefficients + h^2 sigma
 };
 
-template <typename C, typename TB>
+template <typename C, typename TB, typename TS>
 __device__ __forceinline__ void tp_load(TPair<C> &P, Dims d, Bc bc, int p, const TB *bx,
-                                        const TB *by, const TB *bz, const C *R)
+                                        const TB *by, const TB *bz, const C *R, const TS *sg,
+                                        C h2)
 {
     const int hx = d.nx / 2;
     const int npairs = hx * d.ny * d.nz;
@@ -377,9 +393,14 @@ __device__ __forceinline__ void tp_load(TPair<C> &P, Dims d, Bc bc, int p, const
         P.fzl[q] = wzl ? C(0) : C(bz[c + q]);
         P.fzh[q] = wzh ? C(0) : C(bz[c + q + P.zp]);
         P.r[q] = R[c + q];
+        P.sg[q] = sg ? C(sg[c + q]) : C(0);
     }
     P.dg[0] = (P.fx0 + P.fx1) + (P.fyl[0] + P.fyh[0]) + (P.fzl[0] + P.fzh[0]);
     P.dg[1] = (P.fx1 + P.fx2) + (P.fyl[1] + P.fyh[1]) + (P.fzl[1] + P.fzh[1]);
+    if (sg) {                  // h^2 sigma, the general operator's diagonal term
+        P.dg[0] += P.sg[0];
+        P.dg[1] += P.sg[1];
+    }
 }
 
 // Gauss-Seidel update of the cell of colour `colour` in the pair (eq.
@@ -396,7 +417,8 @@ __device__ __forceinline__ void tp_gs(const TPair<C> &P, C *E, C h2, int colour,
     if (!zero)
         s = xl * E[q == 0 ? P.xm : P.c] + xh * E[q == 0 ? P.c + 1 : P.xp] + P.fyl[q] * E[c + P.ym] +
             P.fyh[q] * E[c + P.yp] + P.fzl[q] * E[c + P.zm] + P.fzh[q] * E[c + P.zp];
-    E[c] = (s - h2 * P.r[q]) / P.dg[q];
+    // a cell with no open face and no diagonal term is excluded: it stays 0
+    E[c] = P.dg[q] > C(0) ? (s - h2 * P.r[q]) / P.dg[q] : C(0);
 }
 
 // r - A e at the two cells of the pair, summed (the restriction adds four pairs)
@@ -413,7 +435,7 @@ __device__ __forceinline__ C tp_residual_sum(const TPair<C> &P, const C *E, C ih
         const C fl = xh * (exp - ec) - xl * (ec - exm) + P.fyh[q] * (E[c + P.yp] - ec) -
                      P.fyl[q] * (ec - E[c + P.ym]) + P.fzh[q] * (E[c + P.zp] - ec) -
                      P.fzl[q] * (ec - E[c + P.zm]);
-        acc += P.r[q] - ih2 * fl;
+        acc += P.r[q] - ih2 * fl + ih2 * (P.sg[q] * ec);
     }
     return acc;
 }
@@ -474,13 +496,14 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
     auto visit = [&](int l) {
 #pragma unroll
         for (int u = 0; u < TAIL_PAIRS; ++u) {
+            const C h2 = (C)a.h2[l];
             if (BLDS)
                 tp_load(P[u], a.d[l], a.bc, tid + u * TAIL_THREADS, &Bs[0][BLDS ? off[l] : 0],
                         &Bs[BLDS ? 1 : 0][BLDS ? off[l] : 0], &Bs[BLDS ? 2 : 0][BLDS ? off[l] : 0],
-                        Rr + off[l]);
+                        Rr + off[l], a.s[l], h2);
             else
                 tp_load(P[u], a.d[l], a.bc, tid + u * TAIL_THREADS, a.b[l][0], a.b[l][1], a.b[l][2],
-                        Rr + off[l]);
+                        Rr + off[l], a.s[l], h2);
         }
     };
     for (int l = 0; l + 1 < L; ++l) {
@@ -561,6 +584,31 @@ __global__ void k_convert(size_t n, const double *__restrict__ src, T *__restric
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
         dst[i] = static_cast<T>(src[i]);
+}
+
+// dst = scale * src, counting (partials) the entries whose magnitude reaches
+// `limit` in the storage type (FP16 range checks)
+template <typename T>
+__global__ __launch_bounds__(256) void k_convert_scaled(size_t n, const double *__restrict__ src,
+                                                         double scale, double limit,
+                                                         T *__restrict__ dst, double *part)
+{
+    __shared__ double sm[4];
+    double over = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double v = scale * src[i];
+        if (!(fabs(v) < limit))
+            over += 1.0;
+        dst[i] = static_cast<T>(v);
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        over += __shfl_xor(over, o, 64);
+    if ((threadIdx.x & 63) == 0)
+        sm[threadIdx.x >> 6] = over;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
 }
 
 template <typename T>
@@ -689,7 +737,8 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
 // counts non-wall faces whose beta is not a finite positive number
 __global__ __launch_bounds__(BLOCK) void k_check_beta(Dims d, Bc bc, const double *__restrict__ bx,
                                                       const double *__restrict__ by,
-                                                      const double *__restrict__ bz, double *part)
+                                                      const double *__restrict__ bz, int allow_zero,
+                                                      double *part)
 {
     __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
@@ -702,11 +751,87 @@ __global__ __launch_bounds__(BLOCK) void k_check_beta(Dims d, Bc bc, const doubl
             const double b[3] = {bx[c], by[c], bz[c]};
             const bool wall[3] = {bc.x && i == 0, bc.y && j == 0, bc.z && k == 0};
             for (int m = 0; m < 3; ++m)
-                if (!wall[m] && !(b[m] > 0.0 && b[m] < INFINITY))
+                if (!wall[m] && !((allow_zero ? b[m] >= 0.0 : b[m] > 0.0) && b[m] < INFINITY))
                     v[0] += 1.0;
         }
     }
     block_partials<1>(v, sm, part, 0);
+}
+
+// General operator: partials of the count of sigma entries that are not
+// finite non-negative numbers, and of the count of positive ones.
+__global__ __launch_bounds__(BLOCK) void k_check_sigma(Dims d, const double *__restrict__ sg,
+                                                       double *part, size_t pstride)
+{
+    __shared__ double sm[2][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    double v[2] = {0.0, 0.0};
+    if (i < d.nx && j < d.ny) {
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const double x = sg[((size_t)k * d.ny + j) * d.nx + i];
+            if (!(x >= 0.0 && x < INFINITY))
+                v[0] += 1.0;
+            if (x > 0.0)
+                v[1] += 1.0;
+        }
+    }
+    block_partials<2>(v, sm, part, pstride);
+}
+
+// act[c] = 1 for a cell of the system (an open face or sigma > 0), else 0;
+// partials of the count of active cells
+__global__ __launch_bounds__(BLOCK) void k_active(Dims d, Bc bc, const double *__restrict__ bx,
+                                                  const double *__restrict__ by,
+                                                  const double *__restrict__ bz,
+                                                  const double *__restrict__ sg,
+                                                  unsigned char *__restrict__ act, double *part)
+{
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny) {
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const Nb n = neighbours(d, bc, i, j, k);
+            const Links<double> L = links(n, bx, by, bz);
+            const double dg = (L.xl + L.xh) + (L.yl + L.yh) + (L.zl + L.zh) + (sg ? sg[n.c] : 0.0);
+            const bool a = dg > 0.0;
+            act[n.c] = a ? 1 : 0;
+            v[0] += a ? 1.0 : 0.0;
+        }
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
+// coarse diagonal term = mean of the 8 children (the restriction is the mean)
+__global__ __launch_bounds__(BLOCK) void k_coarsen_sigma(Dims fd, const double *__restrict__ sg,
+                                                         double *__restrict__ sH)
+{
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int I = blockIdx.x * BX + threadIdx.x;
+    const int J = blockIdx.y * BY + threadIdx.y;
+    const int K = blockIdx.z;
+    if (I >= cd.nx || J >= cd.ny)
+        return;
+    double acc = 0.0;
+    for (int dk = 0; dk < 2; ++dk)
+        for (int dj = 0; dj < 2; ++dj) {
+            const size_t c = ((size_t)(2 * K + dk) * fd.ny + (2 * J + dj)) * fd.nx + 2 * I;
+            acc += sg[c] + sg[c + 1];
+        }
+    sH[((size_t)K * cd.ny + J) * cd.nx + I] = 0.125 * acc;
+}
+
+// x = 0 on the excluded cells of the general operator
+__global__ void k_mask(size_t n, double *__restrict__ x, const unsigned char *__restrict__ act)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        if (!act[i])
+            x[i] = 0.0;
 }
 
 // beta_m[c] = 2 / (rho[c - e_m] + rho[c]); 0 on wall faces
@@ -727,10 +852,15 @@ __global__ __launch_bounds__(BLOCK) void k_face_coeffs(Dims d, Bc bc, const doub
     bz[n.c] = (bc.z && k == 0) ? 0.0 : 2.0 / (rho[n.zm] + rc);
 }
 
-// out = scale/h * sum_m (u_m(high face) - u_m(low face)), wall faces 0
+// out = scale/h * sum_m (u_m(high face) - u_m(low face)), wall faces 0; with
+// face coefficients given (the general operator), closed links (beta = 0)
+// carry no flux either
 __global__ __launch_bounds__(BLOCK) void k_divergence(Dims d, Bc bc, const double *__restrict__ ux,
                                                       const double *__restrict__ uy,
                                                       const double *__restrict__ uz, double s_h,
+                                                      const double *__restrict__ bx,
+                                                      const double *__restrict__ by,
+                                                      const double *__restrict__ bz,
                                                       double *__restrict__ out)
 {
     const int i = blockIdx.x * BX + threadIdx.x;
@@ -739,9 +869,17 @@ __global__ __launch_bounds__(BLOCK) void k_divergence(Dims d, Bc bc, const doubl
     if (i >= d.nx || j >= d.ny)
         return;
     const Nb n = neighbours(d, bc, i, j, k);
-    const double xl = n.wxl ? 0.0 : ux[n.c], xh = n.wxh ? 0.0 : ux[n.xp];
-    const double yl = n.wyl ? 0.0 : uy[n.c], yh = n.wyh ? 0.0 : uy[n.yp];
-    const double zl = n.wzl ? 0.0 : uz[n.c], zh = n.wzh ? 0.0 : uz[n.zp];
+    double xl = n.wxl ? 0.0 : ux[n.c], xh = n.wxh ? 0.0 : ux[n.xp];
+    double yl = n.wyl ? 0.0 : uy[n.c], yh = n.wyh ? 0.0 : uy[n.yp];
+    double zl = n.wzl ? 0.0 : uz[n.c], zh = n.wzh ? 0.0 : uz[n.zp];
+    if (bx) {
+        xl = bx[n.c] == 0.0 ? 0.0 : xl;
+        xh = bx[n.xp] == 0.0 ? 0.0 : xh;
+        yl = by[n.c] == 0.0 ? 0.0 : yl;
+        yh = by[n.yp] == 0.0 ? 0.0 : yh;
+        zl = bz[n.c] == 0.0 ? 0.0 : zl;
+        zh = bz[n.zp] == 0.0 ? 0.0 : zh;
+    }
     out[n.c] = s_h * ((xh - xl) + (yh - yl) + (zh - zl));
 }
 
@@ -749,6 +887,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, Bc bc, const double *__
                                                  const double *__restrict__ by,
                                                  const double *__restrict__ bz,
                                                  const double *__restrict__ x,
+                                                 const double *__restrict__ sg,
                                                  double *__restrict__ y, double ih2)
 {
     const int i = blockIdx.x * BX + threadIdx.x;
@@ -758,10 +897,14 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, Bc bc, const double *__
         return;
     const Nb n = neighbours(d, bc, i, j, k);
     const Links<double> L = links(n, bx, by, bz);
-    y[n.c] = ih2 * flux_sum(n, L, x);
+    double v = ih2 * flux_sum(n, L, x);
+    if (sg)
+        v -= sg[n.c] * x[n.c];
+    y[n.c] = v;
 }
 
-// u_m = us_m - dt beta_m G_m p on non-wall faces, 0 on wall faces (eq. fotm).
+// u_m = us_m - dt beta_m G_m p on open faces, 0 on wall faces and on closed
+// links (beta = 0: the link flags multiply the velocity) (eq. fotm).
 // u may alias us: each thread reads and writes only its own entries.
 __global__ __launch_bounds__(BLOCK) void k_project(Dims d, Bc bc, const double *__restrict__ bx,
                                                    const double *__restrict__ by,
@@ -777,9 +920,10 @@ __global__ __launch_bounds__(BLOCK) void k_project(Dims d, Bc bc, const double *
         return;
     const Nb n = neighbours(d, bc, i, j, k);
     const double pc = p[n.c];
-    const double vx = n.wxl ? 0.0 : usx[n.c] - dt_h * bx[n.c] * (pc - p[n.xm]);
-    const double vy = n.wyl ? 0.0 : usy[n.c] - dt_h * by[n.c] * (pc - p[n.ym]);
-    const double vz = n.wzl ? 0.0 : usz[n.c] - dt_h * bz[n.c] * (pc - p[n.zm]);
+    const double fx = bx[n.c], fy = by[n.c], fz = bz[n.c];
+    const double vx = (n.wxl || fx == 0.0) ? 0.0 : usx[n.c] - dt_h * fx * (pc - p[n.xm]);
+    const double vy = (n.wyl || fy == 0.0) ? 0.0 : usy[n.c] - dt_h * fy * (pc - p[n.ym]);
+    const double vz = (n.wzl || fz == 0.0) ? 0.0 : usz[n.c] - dt_h * fz * (pc - p[n.zm]);
     ux[n.c] = vx;
     uy[n.c] = vy;
     uz[n.c] = vz;
@@ -788,6 +932,9 @@ __global__ __launch_bounds__(BLOCK) void k_project(Dims d, Bc bc, const double *
 // g_beta_m = G_m lambda * G_m p on non-wall faces, 0 on walls
 __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(Dims d, Bc bc, const double *__restrict__ lam,
                                                          const double *__restrict__ p, double ih2,
+                                                         const double *__restrict__ bx,
+                                                         const double *__restrict__ by,
+                                                         const double *__restrict__ bz,
                                                          double *__restrict__ gx,
                                                          double *__restrict__ gy,
                                                          double *__restrict__ gz)
@@ -799,9 +946,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(Dims d, Bc bc, const do
         return;
     const Nb n = neighbours(d, bc, i, j, k);
     const double lc = lam[n.c], pc = p[n.c];
-    gx[n.c] = n.wxl ? 0.0 : ih2 * (lc - lam[n.xm]) * (pc - p[n.xm]);
-    gy[n.c] = n.wyl ? 0.0 : ih2 * (lc - lam[n.ym]) * (pc - p[n.ym]);
-    gz[n.c] = n.wzl ? 0.0 : ih2 * (lc - lam[n.zm]) * (pc - p[n.zm]);
+    const bool cx = bx && bx[n.c] == 0.0, cy = by && by[n.c] == 0.0, cz = bz && bz[n.c] == 0.0;
+    gx[n.c] = (n.wxl || cx) ? 0.0 : ih2 * (lc - lam[n.xm]) * (pc - p[n.xm]);
+    gy[n.c] = (n.wyl || cy) ? 0.0 : ih2 * (lc - lam[n.ym]) * (pc - p[n.ym]);
+    gz[n.c] = (n.wzl || cz) ? 0.0 : ih2 * (lc - lam[n.zm]) * (pc - p[n.zm]);
 }
 
 // Streaming copy: 16-byte accesses, four independent loads per thread in
@@ -846,7 +994,8 @@ __global__ void k_fill(double *__restrict__ x, size_t n, double v)
 // outer-loop kernels (FP64) and reductions
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(BLOCK) void k_sum(Dims d, const double *__restrict__ x, double *part)
+__global__ __launch_bounds__(BLOCK) void k_sum(Dims d, const double *__restrict__ x,
+                                               const unsigned char *__restrict__ act, double *part)
 {
     __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
@@ -854,8 +1003,11 @@ __global__ __launch_bounds__(BLOCK) void k_sum(Dims d, const double *__restrict_
     double v[1] = {0.0};
     if (i < d.nx && j < d.ny) {
         const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
-        for (int k = blockIdx.z * RZ; k < ke; ++k)
-            v[0] += x[((size_t)k * d.ny + j) * d.nx + i];
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
+            if (!act || act[c])
+                v[0] += x[c];
+        }
     }
     block_partials<1>(v, sm, part, 0);
 }
@@ -938,6 +1090,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
                                                     const double *__restrict__ bz,
                                                     const double *__restrict__ b,
                                                     const double *__restrict__ scal, double *x,
+                                                    const double *__restrict__ sg,
+                                                    const unsigned char *__restrict__ act,
                                                     double *__restrict__ r64, double ih2,
                                                     double *part, size_t pstride)
 {
@@ -950,13 +1104,16 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
         const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
         for (int k = blockIdx.z * RZ; k < ke; ++k) {
             const Nb n = neighbours(d, bc, i, j, k);
-            const double bm = b[n.c] - mean;
+            // the right-hand side of an excluded cell is not part of the system
+            const double bm = (act && !act[n.c]) ? 0.0 : b[n.c] - mean;
             double ax = 0.0;
             if (ZEROX) {
                 x[n.c] = 0.0;
             } else {
                 const Links<double> L = links(n, bx, by, bz);
                 ax = ih2 * flux_sum(n, L, x);
+                if (sg)
+                    ax -= sg[n.c] * x[n.c];
             }
             const double r = bm - ax;
             r64[n.c] = r;
@@ -975,6 +1132,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual_T(Dims d, Bc bc, const doubl
                                                       const double *__restrict__ b,
                                                       const double *__restrict__ scal,
                                                       const double *__restrict__ x,
+                                                      const double *__restrict__ sg,
+                                                      const unsigned char *__restrict__ act,
                                                       T *__restrict__ rT, double ih2, double *part)
 {
     __shared__ double sm[1][BLOCK / 64];
@@ -988,7 +1147,11 @@ __global__ __launch_bounds__(BLOCK) void k_residual_T(Dims d, Bc bc, const doubl
         for (int k = blockIdx.z * RZ; k < ke; ++k) {
             const Nb n = neighbours(d, bc, i, j, k);
             const Links<double> L = links(n, bx, by, bz);
-            const double r = (b[n.c] - mean) - ih2 * flux_sum(n, L, x);
+            double ax = ih2 * flux_sum(n, L, x);
+            if (sg)
+                ax -= sg[n.c] * x[n.c];
+            const double bm = (act && !act[n.c]) ? 0.0 : b[n.c] - mean;
+            const double r = bm - ax;
             rT[n.c] = static_cast<T>(r * inv);
             v[0] += r * r;
         }
@@ -1051,6 +1214,7 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
                                                      const double *__restrict__ dold,
                                                      double *__restrict__ dnew,
                                                      double *__restrict__ q,
+                                                     const double *__restrict__ sg,
                                                      const double *__restrict__ scal, double ih2,
                                                      double *part)
 {
@@ -1073,7 +1237,9 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
             const double f = L.xh * (dv(n.xp) - dc) - L.xl * (dc - dv(n.xm)) +
                              L.yh * (dv(n.yp) - dc) - L.yl * (dc - dv(n.ym)) +
                              L.zh * (dv(n.zp) - dc) - L.zl * (dc - dv(n.zm));
-            const double qq = ih2 * f;
+            double qq = ih2 * f;
+            if (sg)
+                qq -= sg[n.c] * dc;
             dnew[n.c] = dc;
             q[n.c] = qq;
             v[0] += dc * qq;
@@ -1114,12 +1280,13 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__re
     block_partials<2>(v, sm, part, pstride);
 }
 
-__global__ void k_sub_mean(size_t n, double *__restrict__ x, const double *__restrict__ scal, int slot)
+__global__ void k_sub_mean(size_t n, double *__restrict__ x, const double *__restrict__ scal, int slot,
+                           const unsigned char *__restrict__ act)
 {
-    const double m = scal[slot];
+    const double m = slot >= 0 ? scal[slot] : 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
-        x[i] -= m;
+        x[i] = (act && !act[i]) ? 0.0 : x[i] - m;
 }
 
 // ---------------------------------------------------------------------------
@@ -1139,26 +1306,26 @@ static inline dim3 flat_grid(size_t n)
 static const dim3 kBlock(BX, BY, 1);
 
 template <typename T>
-void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e, double h2,
-                 int colour, bool zero, hipStream_t s)
+void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e,
+                 const T *sg, double h2, int colour, bool zero, hipStream_t s)
 {
     using C = typename Acc<T>::type;
     if (zero)
         hipLaunchKernelGGL((k_rbgs<T, true>), colour_grid(d), kBlock, 0, s, d, bc, bx, by, bz, r, e,
-                           (C)h2, colour);
+                           sg, (C)h2, colour);
     else
         hipLaunchKernelGGL((k_rbgs<T, false>), colour_grid(d), kBlock, 0, s, d, bc, bx, by, bz, r,
-                           e, (C)h2, colour);
+                           e, sg, (C)h2, colour);
 }
 
 template <typename T>
 void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
-                           const T *r, T *rH, double ih2, hipStream_t s)
+                           const T *r, const T *sg, T *rH, double ih2, hipStream_t s)
 {
     using C = typename Acc<T>::type;
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     hipLaunchKernelGGL((k_resid_restrict<T>), cell_grid(cd), kBlock, 0, s, fd, bc, bx, by, bz, e, r,
-                       rH, (C)ih2);
+                       sg, rH, (C)ih2);
 }
 
 template <typename T>
@@ -1170,8 +1337,8 @@ void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s)
 
 template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
-                 void *const *r, Bc bc, int nu_pre, int nu_post, const double *pinv, int ncoarse,
-                 hipStream_t s)
+                 void *const *r, const void *const *sg, Bc bc, int nu_pre, int nu_post,
+                 const double *pinv, int ncoarse, hipStream_t s)
 {
     TailArgs<T> a;
     a.n = nlev;
@@ -1182,6 +1349,7 @@ void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*
             a.b[l][m] = (const T *)b[l][m];
         a.e[l] = (T *)e[l];
         a.r[l] = (T *)r[l];
+        a.s[l] = (const T *)sg[l];
     }
     a.bc = bc;
     a.nu_pre = nu_pre;
@@ -1198,6 +1366,17 @@ void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s)
     if (threads > 1024)
         threads = 1024;
     hipLaunchKernelGGL((k_coarsest<T>), dim3(1), dim3(threads), 0, s, n, pinv, r, e);
+}
+
+template <typename T>
+int launch_convert_scaled(size_t n, const double *src, double scale, double limit, T *dst,
+                          double *part, int max_blocks, hipStream_t s)
+{
+    dim3 g = flat_grid(n);
+    if ((int)g.x > max_blocks)
+        g.x = max_blocks;                 // the loop strides over the rest
+    hipLaunchKernelGGL((k_convert_scaled<T>), g, dim3(256), 0, s, n, src, scale, limit, dst, part);
+    return (int)g.x;
 }
 
 template <typename T>
@@ -1242,9 +1421,32 @@ int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const
 }
 
 void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                       double *part, hipStream_t s)
+                       bool allow_zero, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check_beta, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, part);
+    hipLaunchKernelGGL(k_check_beta, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz,
+                       allow_zero ? 1 : 0, part);
+}
+
+void launch_check_sigma(Dims d, const double *sg, double *part, size_t pstride, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_sigma, red_grid(d), kBlock, 0, s, d, sg, part, pstride);
+}
+
+void launch_active(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                   const double *sg, unsigned char *act, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_active, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, sg, act, part);
+}
+
+void launch_coarsen_sigma(Dims fd, const double *sg, double *sH, hipStream_t s)
+{
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    hipLaunchKernelGGL(k_coarsen_sigma, cell_grid(cd), kBlock, 0, s, fd, sg, sH);
+}
+
+void launch_mask(size_t n, double *x, const unsigned char *act, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mask, flat_grid(n), dim3(256), 0, s, n, x, act);
 }
 
 void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by, double *bz,
@@ -1254,16 +1456,17 @@ void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by
 }
 
 void launch_divergence(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
-                       double scale_over_h, double *out, hipStream_t s)
+                       double scale_over_h, const double *bx, const double *by, const double *bz,
+                       double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_divergence, cell_grid(d), kBlock, 0, s, d, bc, ux, uy, uz, scale_over_h,
-                       out);
+                       bx, by, bz, out);
 }
 
 void launch_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                  const double *x, double *y, double ih2, hipStream_t s)
+                  const double *x, const double *sg, double *y, double ih2, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_apply, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, x, y, ih2);
+    hipLaunchKernelGGL(k_apply, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, x, sg, y, ih2);
 }
 
 void launch_project(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
@@ -1275,9 +1478,11 @@ void launch_project(Dims d, Bc bc, const double *bx, const double *by, const dou
 }
 
 void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, double ih2,
-                          double *gx, double *gy, double *gz, hipStream_t s)
+                          const double *bx, const double *by, const double *bz, double *gx,
+                          double *gy, double *gz, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adjoint_faces, cell_grid(d), kBlock, 0, s, d, bc, lam, p, ih2, gx, gy, gz);
+    hipLaunchKernelGGL(k_adjoint_faces, cell_grid(d), kBlock, 0, s, d, bc, lam, p, ih2, bx, by, bz,
+                       gx, gy, gz);
 }
 
 void launch_copy(const double *src, double *dst, size_t n, hipStream_t s)
@@ -1295,9 +1500,9 @@ void launch_fill(double *x, size_t n, double v, hipStream_t s)
     hipLaunchKernelGGL(k_fill, flat_grid(n), dim3(256), 0, s, x, n, v);
 }
 
-void launch_sum(Dims d, const double *x, double *part, hipStream_t s)
+void launch_sum(Dims d, const double *x, const unsigned char *act, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum, red_grid(d), kBlock, 0, s, d, x, part);
+    hipLaunchKernelGGL(k_sum, red_grid(d), kBlock, 0, s, d, x, act, part);
 }
 
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
@@ -1308,24 +1513,25 @@ void launch_finalize(const double *part, size_t pstride, int nparts, int op, int
 }
 
 void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const double *b, const double *scal, double *x, bool zero_x, double *r64,
-                     double ih2, double *part, size_t pstride, hipStream_t s)
+                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,
+                     const unsigned char *act, double *r64, double ih2, double *part,
+                     size_t pstride, hipStream_t s)
 {
     if (zero_x)
         hipLaunchKernelGGL(k_residual<true>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal,
-                           x, r64, ih2, part, pstride);
+                           x, sg, act, r64, ih2, part, pstride);
     else
         hipLaunchKernelGGL(k_residual<false>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b,
-                           scal, x, r64, ih2, part, pstride);
+                           scal, x, sg, act, r64, ih2, part, pstride);
 }
 
 template <typename T>
 void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                       const double *b, const double *scal, const double *x, T *rT, double ih2,
-                       double *part, hipStream_t s)
+                       const double *b, const double *scal, const double *x, const double *sg,
+                       const unsigned char *act, T *rT, double ih2, double *part, hipStream_t s)
 {
     hipLaunchKernelGGL((k_residual_T<T>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal, x,
-                       rT, ih2, part);
+                       sg, act, rT, ih2, part);
 }
 
 template <typename T>
@@ -1349,15 +1555,15 @@ void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_
 
 template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const T *z, const double *dold, double *dnew, double *q, const double *scal,
-                     bool first, double ih2, double *part, hipStream_t s)
+                     const T *z, const double *dold, double *dnew, double *q, const double *sg,
+                     const double *scal, bool first, double ih2, double *part, hipStream_t s)
 {
     if (first)
         hipLaunchKernelGGL((k_dir_apply<T, true>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
-                           dold, dnew, q, scal, ih2, part);
+                           dold, dnew, q, sg, scal, ih2, part);
     else
         hipLaunchKernelGGL((k_dir_apply<T, false>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
-                           dold, dnew, q, scal, ih2, part);
+                           dold, dnew, q, sg, scal, ih2, part);
     return (int)grid_blocks(red_grid(d));
 }
 
@@ -1370,35 +1576,40 @@ void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, d
                        scal, part, pstride);
 }
 
-void launch_sub_mean(size_t n, double *x, const double *scal, int slot, hipStream_t s)
+void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const unsigned char *act,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sub_mean, flat_grid(n), dim3(256), 0, s, n, x, scal, slot);
+    hipLaunchKernelGGL(k_sub_mean, flat_grid(n), dim3(256), 0, s, n, x, scal, slot, act);
 }
 
 // explicit instantiations for the three storage types
 #define PP_INSTANTIATE(T)                                                                        \
     template void launch_rbgs<T>(Dims, Bc, const T *, const T *, const T *, const T *, T *,     \
-                                 double, int, bool, hipStream_t);                               \
+                                 const T *, double, int, bool, hipStream_t);                    \
     template void launch_resid_restrict<T>(Dims, Bc, const T *, const T *, const T *, const T *, \
-                                           const T *, T *, double, hipStream_t);                \
+                                           const T *, const T *, T *, double, hipStream_t);     \
     template void launch_prolong<T>(Dims, Bc, const T *, T *, hipStream_t);                     \
     template int launch_load_coeffs<T>(Dims, Bc, const double *const[3], double *const[3],      \
                                        T *const[3], double *const[3], double *, hipStream_t);   \
     template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
     template void launch_tail<T>(int, const Dims *, const double *, const void *const (*)[3],   \
-                                 void *const *, void *const *, Bc, int, int, const double *,     \
-                                 int, hipStream_t);                                             \
+                                 void *const *, void *const *, const void *const *, Bc, int,    \
+                                 int, const double *, int, hipStream_t);                        \
     template void launch_convert<T>(size_t, const double *, T *, hipStream_t);                  \
+    template int launch_convert_scaled<T>(size_t, const double *, double, double, T *, double *, \
+                                          int, hipStream_t);                                    \
     template void launch_to_double<T>(size_t, const T *, double *, hipStream_t);                \
     template void launch_residual_T<T>(Dims, Bc, const double *, const double *, const double *, \
-                                       const double *, const double *, const double *, T *,     \
-                                       double, double *, hipStream_t);                          \
+                                       const double *, const double *, const double *,          \
+                                       const double *, const unsigned char *, T *, double,      \
+                                       double *, hipStream_t);                                  \
     template void launch_scale_T<T>(size_t, const double *, T *, const double *, hipStream_t);  \
     template void launch_axpy_T<T>(size_t, const T *, double *, const double *, hipStream_t);   \
     template void launch_dot_rz<T>(Dims, const double *, const T *, double *, hipStream_t);     \
     template int launch_dir_apply<T>(Dims, Bc, const double *, const double *, const double *,  \
                                       const T *, const double *, double *, double *,            \
-                                      const double *, bool, double, double *, hipStream_t);     \
+                                      const double *, const double *, bool, double, double *,   \
+                                      hipStream_t);                                             \
     template void launch_pcg_update<T>(Dims, const double *, const double *, double *, double *, \
                                        T *, const T *, const double *, double *, size_t,        \
                                        hipStream_t);

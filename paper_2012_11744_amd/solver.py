@@ -67,13 +67,19 @@ def face_coeffs(rho: torch.Tensor, h: float, bc: Sequence[int],
 
 
 class Solver:
-    """A solver context for one set of face coefficients beta = 1/rho_f."""
+    """A solver context for one set of face coefficients beta = 1/rho_f.
+
+    With `sigma` (a cell field >= 0) or `general=True` the context holds the
+    general operator A x - sigma x, where interior faces may also be closed
+    (beta = 0) and cells with no open face and no sigma are excluded (see
+    pp_setup_general in include/pp.h)."""
 
     def __init__(self, beta: Sequence[torch.Tensor], h: float, bc: Sequence[int],
                  precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
                  max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
                  coarse_graph: bool = True, nu_coarse: int = 4,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None,
+                 sigma: Optional[torch.Tensor] = None, general: bool = False):
         lib = L.load()
         self._lib = lib
         self.shape = tuple(beta[0].shape)
@@ -97,9 +103,19 @@ class Solver:
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._ctx = ctypes.c_void_p()
-        L.check(lib.pp_setup(ctypes.byref(self.grid), _ptr(beta[0]), _ptr(beta[1]), _ptr(beta[2]),
-                             ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
-                             ctypes.byref(self._ctx)), "pp_setup")
+        self.general = bool(general) or sigma is not None
+        self.has_sigma = sigma is not None
+        if self.general:
+            if sigma is not None:
+                _check_field(sigma, self.shape, "sigma")
+            L.check(lib.pp_setup_general(ctypes.byref(self.grid), _ptr(beta[0]), _ptr(beta[1]),
+                                         _ptr(beta[2]), None if sigma is None else _ptr(sigma),
+                                         ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(self._ctx)), "pp_setup_general")
+        else:
+            L.check(lib.pp_setup(ctypes.byref(self.grid), _ptr(beta[0]), _ptr(beta[1]), _ptr(beta[2]),
+                                 ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(self._ctx)), "pp_setup")
         self.last_stats = None
 
     # -- lifetime ---------------------------------------------------------
@@ -143,9 +159,17 @@ class Solver:
         _check_field(t, self.shape, name)
         return _ptr(t)
 
-    def update_coeffs(self, beta: Sequence[torch.Tensor]) -> None:
-        L.check(self._lib.pp_update_coeffs(self._ctx, *(self._field(b, "beta") for b in beta)),
-                "pp_update_coeffs")
+    def update_coeffs(self, beta: Sequence[torch.Tensor],
+                      sigma: Optional[torch.Tensor] = None) -> None:
+        if self.general:
+            L.check(self._lib.pp_update_general(self._ctx, *(self._field(b, "beta") for b in beta),
+                                                None if sigma is None else self._field(sigma, "sigma")),
+                    "pp_update_general")
+        else:
+            if sigma is not None:
+                raise ValueError("sigma needs a context made with sigma or general=True")
+            L.check(self._lib.pp_update_coeffs(self._ctx, *(self._field(b, "beta") for b in beta)),
+                    "pp_update_coeffs")
 
     def divergence(self, u: Sequence[torch.Tensor], scale: float = 1.0,
                    out: Optional[torch.Tensor] = None) -> torch.Tensor:

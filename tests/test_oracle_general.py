@@ -7,32 +7,13 @@ and excluded cells.  Each pin checks the oracle against something it does not
 compute itself: a dense matrix assembled face by face, a closed-form
 eigenvalue, a discretely exact solution, or an identity of the projection.
 """
-import math
-
 import numpy as np
 import pytest
 
 import oracle
 from oracle import dense
 
-
-def _rand_case(shape, bc, seed, frac_closed=0.2, frac_sigma=0.5):
-    rng = np.random.default_rng(seed)
-    beta = [rng.uniform(0.5, 2.0, shape) for _ in range(3)]
-    for m in range(3):
-        beta[m][rng.random(shape) < frac_closed] = 0.0
-    sigma = rng.uniform(0.0, 3.0, shape) * (rng.random(shape) < frac_sigma)
-    # one cell with every link closed but sigma > 0 (active through sigma
-    # alone) and one with every link closed and sigma = 0 (excluded)
-    for (k, j, i), sg in (((1, 1, 1), 2.5), ((2, 2, 3), 0.0)):
-        beta[0][k, j, i] = 0.0
-        beta[0][k, j, (i + 1) % shape[2]] = 0.0
-        beta[1][k, j, i] = 0.0
-        beta[1][k, (j + 1) % shape[1], i] = 0.0
-        beta[2][k, j, i] = 0.0
-        beta[2][(k + 1) % shape[0], j, i] = 0.0
-        sigma[k, j, i] = sg
-    return beta, sigma
+from general_cases import bubble_dirichlet_case, close_links_of, mode, rand_case
 
 
 CASES = [((6, 4, 8), (1, 0, 1)), ((4, 6, 6), (0, 0, 0)), ((5, 6, 4), (1, 1, 1))]
@@ -40,7 +21,7 @@ CASES = [((6, 4, 8), (1, 0, 1)), ((4, 6, 6), (0, 0, 0)), ((5, 6, 4), (1, 1, 1))]
 
 @pytest.mark.parametrize("shape,bc", CASES)
 def test_apply_gen_matches_dense_assembly(shape, bc):
-    beta, sigma = _rand_case(shape, bc, 1)
+    beta, sigma = rand_case(shape, bc, 1)
     h = 0.1
     x = np.random.default_rng(2).standard_normal(shape)
     A = dense.matrix_gen(beta, sigma, bc, h)
@@ -56,7 +37,7 @@ def test_apply_gen_matches_dense_assembly(shape, bc):
 
 @pytest.mark.parametrize("shape,bc", CASES)
 def test_solve_gen_matches_dense_nonsingular(shape, bc):
-    beta, sigma = _rand_case(shape, bc, 3)
+    beta, sigma = rand_case(shape, bc, 3)
     h = 0.1
     rhs = np.random.default_rng(4).standard_normal(shape)
     p, it, rel = oracle.solve_gen(beta, sigma, bc, h, rhs, tol=1e-13)
@@ -73,44 +54,13 @@ def test_solve_gen_matches_dense_singular_with_solid():
     beta = [rng.uniform(0.5, 2.0, shape) for _ in range(3)]
     solid = np.zeros(shape, dtype=bool)
     solid[2:4, 1:3, 3:6] = True
-    _close_links_of(beta, solid, bc)
+    close_links_of(beta, solid, bc)
     rhs = rng.standard_normal(shape)
     p, it, rel = oracle.solve_gen(beta, None, bc, 0.2, rhs, tol=1e-13)
     ref = dense.solve_gen(beta, None, bc, 0.2, rhs)
     assert np.abs(p - ref).max() <= 1e-10 * np.abs(ref).max()
     assert np.all(p[solid] == 0.0)
     assert abs(p[~solid].mean()) <= 1e-13 * np.abs(p).max()
-
-
-def _close_links_of(beta, solid, bc):
-    """A link is open only if both of its cells are fluid (the product of the
-    two cell flags; a link of Sec. 3.8 sits between two cells)."""
-    for m in range(3):
-        ax = 2 - m
-        below = np.roll(solid, 1, axis=ax)        # the cell on the low side of the face
-        beta[m][solid | below] = 0.0
-
-
-def _mode(shape, bc, k):
-    """Product of 1D eigenvectors: periodic cos(2 pi k i / n), walled
-    (Neumann, cell centred) cos(pi k (i + 1/2) / n); and the 1D eigenvalues
-    -4 sin^2(.)  (times 1/h^2) of the unit-coefficient Laplacian."""
-    nz, ny, nx = shape
-    n = (nx, ny, nz)
-    out = np.ones(shape)
-    lam = 0.0
-    for m in range(3):
-        i = np.arange(n[m])
-        if bc[m] == 0:
-            v = np.cos(2 * math.pi * k[m] * i / n[m])
-            lam -= 4 * math.sin(math.pi * k[m] / n[m]) ** 2
-        else:
-            v = np.cos(math.pi * k[m] * (i + 0.5) / n[m])
-            lam -= 4 * math.sin(math.pi * k[m] / (2 * n[m])) ** 2
-        sh = [1, 1, 1]
-        sh[2 - m] = n[m]
-        out = out * v.reshape(sh)
-    return out, lam
 
 
 @pytest.mark.parametrize("bc", [(0, 1, 0), (1, 1, 1), (0, 0, 0)])
@@ -120,7 +70,7 @@ def test_helmholtz_eigenmode_closed_form(bc):
     shape = (8, 12, 16)
     h, s = 1.0 / 16, 37.0
     beta = [np.ones(shape) for _ in range(3)]
-    v, lam = _mode(shape, bc, (3, 2, 1))
+    v, lam = mode(shape, bc, (3, 2, 1))
     ev = lam / (h * h) - s
     y = oracle.apply_gen(beta, s, bc, h, v)
     assert np.abs(y - ev * v).max() <= 1e-12 * abs(ev)
@@ -135,7 +85,7 @@ def test_implicit_viscous_step_damping():
     shape, bc = (8, 8, 8), (0, 0, 0)
     h, tau, mu = 1.0 / 8, 1e-3, 2.5
     beta = [np.ones(shape) for _ in range(3)]
-    v, lam = _mode(shape, bc, (1, 2, 3))
+    v, lam = mode(shape, bc, (1, 2, 3))
     sig = 1.0 / (tau * mu)
     u, it, rel = oracle.solve_gen(beta, sig, bc, h, -v / (tau * mu), tol=1e-14)
     expect = v / (1.0 + tau * mu * abs(lam) / (h * h))
@@ -152,7 +102,7 @@ def test_solid_block_projection():
     beta = [rng.uniform(0.001, 1.0, shape) for _ in range(3)]
     solid = np.zeros(shape, dtype=bool)
     solid[3:7, 4:9, 2:6] = True
-    _close_links_of(beta, solid, bc)
+    close_links_of(beta, solid, bc)
     us = [rng.uniform(-1, 1, shape) for _ in range(3)]
     b = oracle.divergence_gen(beta, us, bc, h, 1.0 / dt)
     p, it, rel = oracle.solve_gen(beta, None, bc, h, b, tol=1e-13)
@@ -172,15 +122,6 @@ def test_solid_block_projection():
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
 
 
-def _sphere_distance(xc, s, m, centre, R):
-    """Distance t > 0 from xc along s e_m to the sphere surface."""
-    d = np.asarray(xc) - centre
-    perp = sum(d[q] ** 2 for q in range(3) if q != m)
-    root = math.sqrt(R * R - perp)
-    ts = [s * (-d[m] + root), s * (-d[m] - root)]
-    return min(t for t in ts if t > 0)
-
-
 def test_free_surface_dirichlet_branches_exact_for_linear_pressure():
     """Sec. 3.7.5, eq. mod_branches: a liquid cell next to an excluded (gas)
     cell takes the gradient (p_s - p_c) / delta to the interface.  In A_g form
@@ -188,44 +129,9 @@ def test_free_surface_dirichlet_branches_exact_for_linear_pressure():
     -beta p_s / (h delta) to the right-hand side.  For a linear pressure, with
     its wall fluxes as sources, every branch is exact, so the discrete
     solution is the linear function at every liquid cell centre."""
-    nz, ny, nx = 16, 20, 24
-    shape, bc = (nz, ny, nx), (1, 1, 1)
     h = 1.0 / 16
-    centre, R = np.array([0.71, 0.62, 0.47]), 0.27
-    g = np.array([0.3, -1.1, 0.7])
-    p0 = 2.0
-    beta0 = 1e-3                                     # 1 / rho of the liquid
-    exact = lambda x: p0 + float(g @ x)
-    idx = np.indices(shape)                          # (k, j, i)
-    X = np.stack([(idx[2] + 0.5) * h, (idx[1] + 0.5) * h, (idx[0] + 0.5) * h], axis=-1)
-    gas = np.sum((X - centre) ** 2, axis=-1) < R * R
-    beta = [np.full(shape, beta0) for _ in range(3)]
-    _close_links_of(beta, gas, bc)
-    sigma = np.zeros(shape)
-    rhs = np.zeros(shape)
-    n = (nx, ny, nz)
-    for k in range(nz):
-        for j in range(ny):
-            for i in range(nx):
-                if gas[k, j, i]:
-                    continue
-                c = [i, j, k]
-                xc = X[k, j, i]
-                for m in range(3):
-                    for s in (-1, 1):
-                        q = list(c)
-                        q[m] += s
-                        if q[m] < 0 or q[m] >= n[m]:
-                            rhs[k, j, i] -= s * beta0 * g[m] / h        # wall flux as a source
-                        elif gas[q[2], q[1], q[0]]:
-                            t = _sphere_distance(xc, s, m, centre, R)
-                            assert 0.0 < t <= h
-                            xs = xc.copy()
-                            xs[m] += s * t
-                            sigma[k, j, i] += beta0 / (h * t)
-                            rhs[k, j, i] -= beta0 * exact(xs) / (h * t)
+    bc, beta, sigma, rhs, pe, gas = bubble_dirichlet_case(h=h)
     p, it, rel = oracle.solve_gen(beta, sigma, bc, h, rhs, tol=1e-14)
-    pe = np.vectorize(lambda k, j, i: exact(X[k, j, i]))(*np.indices(shape))
     err = np.abs(p - pe)[~gas].max() / np.abs(pe).max()
     assert err <= 1e-10
     assert np.all(p[gas] == 0.0)
