@@ -805,18 +805,22 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
 template <typename T>
 int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
 {
+    using D = typename DirT<T>::type;
     hipStream_t s = c->stream;
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
     const int np = nparts(c);
     LevelBuf &v0 = H.lev[0];
     launch_scale_T<T>(c->N, c->r64, (T *)v0.r, c->scal, s);
     bool first = true;
-    double *dold = c->d64, *dnew = c->d64b;
+    D *dold = (D *)c->d64, *dnew = (D *)c->d64b;
     int since = 0;
     double window = S.rel;
+    int rc = PP_OK;
     for (;;) {
-        if (S.it >= c->opts.max_outer)
-            return fail(PP_ENOCONV, "no convergence within max_outer iterations");
+        if (S.it >= c->opts.max_outer) {
+            rc = fail(PP_ENOCONV, "no convergence within max_outer iterations");
+            break;
+        }
         vcycle_run<T>(c, H);
         if (S.st)
             S.st->vcycles++;
@@ -826,7 +830,7 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
             npd = launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
-                                      (const T *)v0.cur, dold, dnew, c->q64,
+                                      (const T *)v0.cur, dold, dnew, c->q64, x,
                                       c->sig_on ? c->sig[0] : nullptr, c->scal, first, ih2, c->part,
                                       s);
         }
@@ -834,22 +838,32 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         launch_finalize(c->part, c->pstride, npd, OP_ALPHA, 0, (double)c->N, 0, c->scal, s);
         {
             KT t(c, PP_KT_OUTER_UPDATE, true);
-            launch_pcg_update<T>(c->d, dnew, c->q64, x, c->r64, (T *)v0.r, (const T *)v0.cur, c->scal,
+            launch_pcg_update<T>(c->d, c->q64, c->r64, (T *)v0.r, (const T *)v0.cur, c->scal,
                                  c->part, c->pstride, s);
         }
         std::swap(dold, dnew);
         launch_finalize(c->part, c->pstride, np, OP_UPDATE, 0, (double)c->N, 0, c->scal, s);
-        PP_TRY(check_launch("pcg iteration"));
-        PP_TRY(read_scal(c));
+        rc = check_launch("pcg iteration");
+        if (rc == PP_OK)
+            rc = read_scal(c);
+        if (rc != PP_OK)
+            return rc;
         S.it++;
         S.rel = std::sqrt(c->hscal[S_RR]) / S.nb;
         record(S);
         if (S.rel <= tol)
-            return PP_OK;
-        int rc = check_progress(S, 8, since, window);
+            break;
+        rc = check_progress(S, 8, since, window);
         if (rc != PP_OK)
-            return rc;
+            break;
     }
+    // the last direction's update of the iterate (earlier ones were applied
+    // by the direction passes that followed them)
+    if (!first) {
+        launch_axpy_dir<D>(c->N, dold, x, c->scal, s);
+        PP_TRY(check_launch("pcg final update"));
+    }
+    return rc;
 }
 
 template <typename T>

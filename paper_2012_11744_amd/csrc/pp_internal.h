@@ -78,6 +78,7 @@ enum Slot {
     S_SBAD = 12,    // sigma entries that are not finite non-negative (validation)
     S_SPOS = 13,    // positive sigma entries
     S_NACT = 14,    // active cells of the general operator
+    S_DS = 15,      // V-cycle scale of the latest direction (outer CG)
     S_NSLOTS = 16
 };
 
@@ -192,15 +193,31 @@ template <typename T>
 void launch_axpy_T(size_t n, const T *e, double *x, const double *scal, hipStream_t s);
 template <typename T>
 void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_t s);
+// Storage of the outer search direction (in units of the V-cycle's scale):
+// FP64 with the FP64 preconditioner, FP32 with the mixed ones, whose
+// preconditioned residual is itself no more accurate than FP32.  The
+// direction only has to agree with its image q, which is formed from the
+// stored values.
+template <typename T>
+struct DirT {
+    using type = float;
+};
+template <>
+struct DirT<double> {
+    using type = double;
+};
 // returns the number of partial sums written (at most grid_blocks(red_grid(d)))
 template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const T *z, const double *dold, double *dnew, double *q, const double *sg,
-                     const double *scal, bool first, double ih2, double *part, hipStream_t s);
+                     const T *z, const typename DirT<T>::type *dold, typename DirT<T>::type *dnew,
+                     double *q, double *x, const double *sg, const double *scal, bool first,
+                     double ih2, double *part, hipStream_t s);
 template <typename T>
-void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, double *r, T *rT,
-                       const T *zold, const double *scal, double *part, size_t pstride,
-                       hipStream_t s);
+void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const T *zold,
+                       const double *scal, double *part, size_t pstride, hipStream_t s);
+// x += scal[S_ALPHA] * dv
+template <typename D>
+void launch_axpy_dir(size_t n, const D *dv, double *x, const double *scal, hipStream_t s);
 // x -= scal[slot] (slot < 0: nothing); with act, excluded cells are set to 0
 void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const unsigned char *act,
                      hipStream_t s);

@@ -1055,14 +1055,21 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
         scal[S_NEXT] = rms;
         break;
     case OP_RZ: {
+        // flexible CG: beta = (r_k . z_k - r_k . z_{k-1}) / (r_{k-1} . z_{k-1});
+        // the stored direction is in units of the V-cycle scale, so its
+        // recurrence coefficient is beta s_{k-1} / s_k
         const double rz = scal[S_USED] * s0;
-        scal[S_BETA] = first ? 0.0 : (rz - scal[S_RZOLD]) / scal[S_RZ];
+        scal[S_BETA] =
+            first ? 0.0 : (rz - scal[S_RZOLD]) / scal[S_RZ] * (scal[S_DS] / scal[S_USED]);
         scal[S_RZ] = rz;
         break;
     }
     case OP_ALPHA:
+        // s0 = D . A D with the true direction s_k D: alpha = rz / (s_k^2 s0);
+        // the slot holds alpha s_k, the coefficient of D and of q = A D
         scal[S_DQ] = s0;
-        scal[S_ALPHA] = scal[S_RZ] / s0;
+        scal[S_ALPHA] = scal[S_RZ] / (scal[S_USED] * s0);
+        scal[S_DS] = scal[S_USED];
         break;
     case OP_UPDATE:
         scal[S_RR] = s0;
@@ -1199,21 +1206,28 @@ __global__ __launch_bounds__(BLOCK) void k_dot_rz(Dims d, const double *__restri
     block_partials<1>(v, sm, part, 0);
 }
 
-// New search direction and its image in one pass:
-//   d_new = s z + beta d_old   (s = scal[S_USED]; beta = scal[S_BETA], or 0 on
-//                               the first iteration, when d_old is not read)
-//   q = A d_new,  partial d_new . q
-// d_new is recomputed at the six neighbours from z and d_old (the same
-// expression, so the same bits), which is why d_new and d_old are different
-// buffers.
-template <typename T, bool FIRST>
+// New search direction and its image in one pass.  The direction is kept in
+// units of the V-cycle's scale s_k = scal[S_USED] (the preconditioned
+// residual is s_k z), so its storage type needs no range of its own:
+//   D_new = z + gamma D_old    (gamma = scal[S_BETA] = beta_k s_{k-1} / s_k, or
+//                               0 on the first iteration, when D_old is not read)
+//   q = A D_new,  partial D_new . q
+// and the true direction is s_k D_new.  D_new is rounded to its storage type
+// before q is formed, so q is the image of exactly the stored vector; it is
+// recomputed at the six neighbours from z and D_old by the same explicit fma
+// (so the same bits), which is why D_new and D_old are different buffers.
+// The iterate's update of the previous iteration is applied here, where
+// D_old is read anyway: x += a_{k-1} D_old with a_{k-1} = scal[S_ALPHA]
+// (this launch runs before the new coefficient is finalised).
+template <typename T, typename D, bool FIRST>
 __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double *__restrict__ bx,
                                                      const double *__restrict__ by,
                                                      const double *__restrict__ bz,
                                                      const T *__restrict__ z,
-                                                     const double *__restrict__ dold,
-                                                     double *__restrict__ dnew,
+                                                     const D *__restrict__ dold,
+                                                     D *__restrict__ dnew,
                                                      double *__restrict__ q,
+                                                     double *__restrict__ x,
                                                      const double *__restrict__ sg,
                                                      const double *__restrict__ scal, double ih2,
                                                      double *part)
@@ -1223,11 +1237,12 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
     const int j = blockIdx.y * BY + threadIdx.y;
     double v[1] = {0.0};
     if (i < d.nx && j < d.ny) {
-        const double s = scal[S_USED];
-        const double beta = FIRST ? 0.0 : scal[S_BETA];
+        const double gamma = FIRST ? 0.0 : scal[S_BETA];
+        const double aold = FIRST ? 0.0 : scal[S_ALPHA];
         auto dv = [&](size_t c) -> double {
-            const double t = s * static_cast<double>(z[c]);
-            return FIRST ? t : t + beta * dold[c];
+            const double t = static_cast<double>(z[c]);
+            return static_cast<double>(
+                static_cast<D>(FIRST ? t : __builtin_fma(gamma, static_cast<double>(dold[c]), t)));
         };
         const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
         for (int k = blockIdx.z * RZ; k < ke; ++k) {
@@ -1240,7 +1255,9 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
             double qq = ih2 * f;
             if (sg)
                 qq -= sg[n.c] * dc;
-            dnew[n.c] = dc;
+            if (!FIRST)
+                x[n.c] += aold * static_cast<double>(dold[n.c]);
+            dnew[n.c] = static_cast<D>(dc);
             q[n.c] = qq;
             v[0] += dc * qq;
         }
@@ -1248,12 +1265,12 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
     block_partials<1>(v, sm, part, 0);
 }
 
-// x += alpha d; r -= alpha q; rT = r / scal[S_NEXT];
-// partials ||r||^2 and r . z_old (z_old unscaled, storage precision)
+// r -= a q (a = scal[S_ALPHA]); rT = r / scal[S_NEXT];
+// partials ||r||^2 and r . z_old (z_old unscaled, storage precision).
+// The iterate takes the matching x += a D in the next direction pass, or in
+// k_axpy_dir after the last iteration.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__restrict__ dv,
-                                                      const double *__restrict__ q,
-                                                      double *__restrict__ x,
+__global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__restrict__ q,
                                                       double *__restrict__ r, T *__restrict__ rT,
                                                       const T *__restrict__ zold,
                                                       const double *__restrict__ scal,
@@ -1269,7 +1286,6 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__re
         const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
         for (int k = blockIdx.z * RZ; k < ke; ++k) {
             const size_t c = ((size_t)k * d.ny + j) * d.nx + i;
-            x[c] += alpha * dv[c];
             const double rn = r[c] - alpha * q[c];
             r[c] = rn;
             rT[c] = static_cast<T>(rn * inv);
@@ -1278,6 +1294,17 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__re
         }
     }
     block_partials<2>(v, sm, part, pstride);
+}
+
+// x += scal[S_ALPHA] * D: the last iteration's update of the iterate
+template <typename D>
+__global__ void k_axpy_dir(size_t n, const D *__restrict__ dv, double *__restrict__ x,
+                           const double *__restrict__ scal)
+{
+    const double a = scal[S_ALPHA];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] += a * static_cast<double>(dv[i]);
 }
 
 __global__ void k_sub_mean(size_t n, double *__restrict__ x, const double *__restrict__ scal, int slot,
@@ -1555,26 +1582,36 @@ void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_
 
 template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const T *z, const double *dold, double *dnew, double *q, const double *sg,
-                     const double *scal, bool first, double ih2, double *part, hipStream_t s)
+                     const T *z, const typename DirT<T>::type *dold, typename DirT<T>::type *dnew,
+                     double *q, double *x, const double *sg, const double *scal, bool first,
+                     double ih2, double *part, hipStream_t s)
 {
+    using D = typename DirT<T>::type;
     if (first)
-        hipLaunchKernelGGL((k_dir_apply<T, true>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
-                           dold, dnew, q, sg, scal, ih2, part);
+        hipLaunchKernelGGL((k_dir_apply<T, D, true>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz,
+                           z, dold, dnew, q, x, sg, scal, ih2, part);
     else
-        hipLaunchKernelGGL((k_dir_apply<T, false>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, z,
-                           dold, dnew, q, sg, scal, ih2, part);
+        hipLaunchKernelGGL((k_dir_apply<T, D, false>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz,
+                           z, dold, dnew, q, x, sg, scal, ih2, part);
     return (int)grid_blocks(red_grid(d));
 }
 
 template <typename T>
-void launch_pcg_update(Dims d, const double *dvec, const double *q, double *x, double *r, T *rT,
-                       const T *zold, const double *scal, double *part, size_t pstride,
-                       hipStream_t s)
+void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const T *zold,
+                       const double *scal, double *part, size_t pstride, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pcg_update<T>), red_grid(d), kBlock, 0, s, d, dvec, q, x, r, rT, zold,
-                       scal, part, pstride);
+    hipLaunchKernelGGL((k_pcg_update<T>), red_grid(d), kBlock, 0, s, d, q, r, rT, zold, scal, part,
+                       pstride);
 }
+
+template <typename D>
+void launch_axpy_dir(size_t n, const D *dv, double *x, const double *scal, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_axpy_dir<D>), flat_grid(n), dim3(256), 0, s, n, dv, x, scal);
+}
+template void launch_axpy_dir<double>(size_t, const double *, double *, const double *,
+                                      hipStream_t);
+template void launch_axpy_dir<float>(size_t, const float *, double *, const double *, hipStream_t);
 
 void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const unsigned char *act,
                      hipStream_t s)
@@ -1607,12 +1644,12 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
     template void launch_axpy_T<T>(size_t, const T *, double *, const double *, hipStream_t);   \
     template void launch_dot_rz<T>(Dims, const double *, const T *, double *, hipStream_t);     \
     template int launch_dir_apply<T>(Dims, Bc, const double *, const double *, const double *,  \
-                                      const T *, const double *, double *, double *,            \
+                                      const T *, const typename DirT<T>::type *,                \
+                                      typename DirT<T>::type *, double *, double *,             \
                                       const double *, const double *, bool, double, double *,   \
                                       hipStream_t);                                             \
-    template void launch_pcg_update<T>(Dims, const double *, const double *, double *, double *, \
-                                       T *, const T *, const double *, double *, size_t,        \
-                                       hipStream_t);
+    template void launch_pcg_update<T>(Dims, const double *, double *, T *, const T *,          \
+                                       const double *, double *, size_t, hipStream_t);
 
 PP_INSTANTIATE(double)
 PP_INSTANTIATE(float)

@@ -114,7 +114,7 @@ def test_one_gauss_seidel_sweep_matches_paper_sor(S, n, bc):
 @pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0))])
 @pytest.mark.parametrize("first", [0, 1])
 def test_fused_sweep_matches_paper_sor(S, n, bc, first):
-    """One fused out-of-place sweep (tiles of 64 x 8 cells, z chunks, ring
+    """One fused out-of-place sweep (tiles of 128 x 8 cells, z chunks, ring
     recomputation) equals the oracle's sweep of eq. beta_pressure with the
     same colour order; also from a zero start (e_in not read)."""
     _say(f"fused rbgs sweep n={n} bc={bc} first={first}")
@@ -293,6 +293,26 @@ def test_deterministic_bitwise(S):
         p1 = host(sol.solve(rhs, tol=1e-9)).copy()
         p2 = host(sol.solve(rhs, tol=1e-9)).copy()
     assert np.array_equal(p1, p2)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_rhs_scale_bitwise_linear(S, precision):
+    """The mixed-precision solve keeps everything held in FP32 / FP16 (the
+    residual handed to the V-cycle, the search direction) in units of the
+    residual's RMS, and the rest in FP64, so scaling the right-hand side by
+    2^+-130 (beyond the FP32 range either way) scales the answer by exactly
+    that power of two, bit for bit, with the same iterations."""
+    w = W.config3(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision=precision) as sol:
+        p0 = host(sol.solve(dev(rhs), tol=1e-9)).copy()
+        it0 = sol.last_stats["outer_iters"]
+        for e in (130, -130):
+            _say(f"rhs scale 2^{e} {precision}")
+            pe = host(sol.solve(dev(np.ldexp(rhs, e)), tol=1e-9)).copy()
+            assert sol.last_stats["outer_iters"] == it0
+            assert np.array_equal(pe, np.ldexp(p0, e))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
