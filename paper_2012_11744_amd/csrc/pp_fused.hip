@@ -47,8 +47,8 @@ namespace pp {
 // FPD steps; the loop is unrolled by the buffer rotation period so no buffer
 // with loads in flight is copied.
 // ---------------------------------------------------------------------------
-constexpr int FTX = 64;                 // tile width in cells (32 pairs)
-constexpr int FTY = 16;                 // tile height in rows
+constexpr int FTX = 128;                // tile width in cells (64 pairs)
+constexpr int FTY = 8;                  // tile height in rows
 constexpr int FPX = FTX / 2 + 2;        // pairs per row including the ring pairs
 constexpr int FRY = FTY + 2;            // thread rows including the ring rows
 constexpr int FTHREADS = (FPX * FRY + 63) / 64 * 64;   // whole waves
@@ -113,6 +113,13 @@ __device__ __forceinline__ void st_pair(__amdgpu_buffer_rsrc_t rs, unsigned off,
 constexpr unsigned OFF_NONE = 0x80000000u;
 
 __device__ __forceinline__ int slot3(int k) { return ((k % 3) + 3) % 3; }
+
+// The Gauss-Seidel quotient.  FP32 arithmetic (FP32 and FP16 storage) takes
+// the hardware reciprocal (within 1 ulp) times the numerator: the smoother
+// only has to reduce the error, and its result is a preconditioner that the
+// FP64 outer iteration corrects; FP64 keeps the exact quotient.
+__device__ __forceinline__ float gs_quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double gs_quot(double a, double b) { return a / b; }
 
 // Block id -> (tile x, tile y, chunk), spreading contiguous ranges of tiles over
 // the 8 XCDs: consecutive workgroups are dispatched round-robin to the XCDs,
@@ -300,7 +307,7 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
         if (!ZERO)
             s = xl * SE[si][ly][ca - 1] + xh * SE[si][ly][ca + 1] + yl * SE[si][ly - 1][ca] +
                 yh * SE[si][ly + 1][ca] + zl * pick(o, pm.e) + zh * pick(o, pn.e);
-        const C val = (s - h2 * pick(o, pc.r)) / diag;
+        const C val = gs_quot(s - h2 * pick(o, pc.r), diag);
         // a missing plane (0/0) and an excluded cell (zero diagonal) get 0
         const C red = (kin && diag > C(0)) ? val : C(0);
         // in-plane faces of this plane's second-colour cell, for phase B at
@@ -324,7 +331,7 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
             C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
             if (SIG)
                 dg += pick(o, pm.sg);
-            const C blk = dg > C(0) ? (sbv - h2 * pick(o, pm.r)) / dg : C(0);
+            const C blk = dg > C(0) ? gs_quot(sbv - h2 * pick(o, pm.r), dg) : C(0);
             T2 outv;
             outv.x = static_cast<T>(o ? red_km1 : blk);
             outv.y = static_cast<T>(o ? blk : red_km1);
