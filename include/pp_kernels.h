@@ -51,6 +51,19 @@ int pp_k_smooth_fused(const pp_grid *grid, const double *beta_x, const double *b
                       const double *beta_z, const double *r, const double *e_in, double *e_out,
                       int32_t first_colour, int32_t zero_init, void *hip_stream);
 
+/* Two red-black sweeps in one pass on FP32 arrays (the kernel the FP32 V-cycle
+ * uses on large levels): e_out = sweep(sweep(e_in)), each sweep the first
+ * colour first as in pp_k_smooth_fused.  Arithmetic is FP32 with the
+ * hardware reciprocal of the diagonal (within 1 ulp), so results agree with
+ * the FP64 sweeps of the same FP32 inputs to FP32 rounding, not bit for bit.
+ * e_in and e_out must not alias; zero_init = 1 treats e_in as zero (it is not
+ * read).  Every cell count must be >= 8; nx must be even, and so must the
+ * cell count of every periodic direction; an x-y plane must stay below 2^31
+ * bytes; all arrays 16-byte aligned. */
+int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *beta_x, const float *beta_y,
+                           const float *beta_z, const float *r, const float *e_in, float *e_out,
+                           int32_t first_colour, int32_t zero_init, void *hip_stream);
+
 /* rH[C] = (1/8) sum over the 8 fine cells c of C of (r - A e)[c].
  * grid: the fine grid (all n even); rH has n/2 cells per direction; beta,
  * e and r 16-byte aligned. */

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -583,6 +584,37 @@ int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 // V-cycle
 // ---------------------------------------------------------------------------
 
+// nu out-of-place sweeps on a large level starting from the correction in
+// cur (ignored when zero_first), ping-ponging between e and e2; returns the
+// buffer holding the result.  FP32 and FP16 storage take two sweeps per pass
+// where the level allows it (the second pass of an odd nu is a single sweep).
+template <typename T>
+void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_colour,
+                   bool zero_first, hipStream_t s)
+{
+    const double h2 = v.h * v.h;
+    const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
+    for (int sw = 0; sw < nu;) {
+        void *out = (cur == v.e) ? v.e2 : v.e;
+        KT t(c, PP_KT_SMOOTH, l == 0);
+        const bool zero = zero_first && sw == 0;
+        bool two = false;
+        if constexpr (!std::is_same<T, double>::value) {
+            if (sw + 2 <= nu && fused2_fits(v.d)) {
+                launch_rbgs_fused2<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur,
+                                      (T *)out, (const T *)v.s, h2, first_colour, zero, s);
+                two = true;
+            }
+        }
+        if (!two)
+            launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
+                                 (const T *)v.s, h2, first_colour, zero, s);
+        sw += two ? 2 : 1;
+        cur = out;
+    }
+    return cur;
+}
+
 // nu_pre red-black sweeps (red first) from e = 0 on level l, then residual +
 // restriction into the right-hand side of level l + 1.  Large levels use the
 // fused out-of-place sweep (ping-pong between e and e2); smaller ones, where
@@ -595,15 +627,7 @@ void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s)
     const double h2 = v.h * v.h;
     const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
     if (cells(v.d) > FUSED_MIN_CELLS && fused_plane_fits(v.d, sizeof(T))) {
-        void *cur = v.e2;
-        for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
-            void *out = (cur == v.e) ? v.e2 : v.e;
-            KT t(c, PP_KT_SMOOTH, l == 0);
-            launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
-                                 (const T *)v.s, h2, 0, sw == 0, s);
-            cur = out;
-        }
-        v.cur = cur;
+        v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_pre, v.e2, 0, true, s);
     } else {
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
             launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2, 0,
@@ -631,15 +655,7 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
         launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
     }
     if (cells(v.d) > FUSED_MIN_CELLS && fused_plane_fits(v.d, sizeof(T))) {
-        void *cur = v.cur;
-        for (int sw = 0; sw < c->opts.nu_post; ++sw) {
-            void *out = (cur == v.e) ? v.e2 : v.e;
-            KT t(c, PP_KT_SMOOTH, l == 0);
-            launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
-                                 (const T *)v.s, h2, 1, false, s);
-            cur = out;
-        }
-        v.cur = cur;
+        v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_post, v.cur, 1, false, s);
     } else {
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
             launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2, 1,
@@ -714,6 +730,8 @@ int capture_coarse(pp_ctx *c, Hier &H)
     if (!H.present || H.tail < 2)
         return PP_OK;             // levels 1 .. L-1 are one kernel or none
     prepare_fused<T>();
+    if constexpr (!std::is_same<T, double>::value)
+        prepare_fused2<T>();
     hipStream_t cap = nullptr;
     PP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
@@ -1379,6 +1397,36 @@ int pp_k_smooth_fused(const pp_grid *grid, const double *bx, const double *by, c
                               grid->h * grid->h, first_colour, zero_init != 0,
                               (hipStream_t)hip_stream);
     return check_launch("pp_k_smooth_fused");
+}
+
+int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *bx, const float *by, const float *bz,
+                           const float *r, const float *e_in, float *e_out, int32_t first_colour,
+                           int32_t zero_init, void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!bx || !by || !bz || !r || !e_in || !e_out)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: NULL array");
+    if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)r | (uintptr_t)e_in |
+         (uintptr_t)e_out) & 15)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: arrays must be 16-byte aligned");
+    if (e_in == e_out)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: e_in and e_out must not alias");
+    if (first_colour != 0 && first_colour != 1)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: first_colour must be 0 or 1");
+    if (grid->n[0] % 2)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: nx must be even (threads own x-pairs)");
+    for (int m = 0; m < 3; ++m)
+        if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
+            return fail(PP_EINVAL,
+                        "pp_k_smooth2_fused_f32: periodic directions need an even cell count");
+    if (!fused2_fits(to_dims(grid)))
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: every cell count must be >= 8");
+    if (!fused_plane_fits(to_dims(grid), sizeof(float)))
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: an x-y plane must stay below 2^31 bytes");
+    launch_rbgs_fused2<float>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in, e_out, nullptr,
+                              grid->h * grid->h, first_colour, zero_init != 0,
+                              (hipStream_t)hip_stream);
+    return check_launch("pp_k_smooth2_fused_f32");
 }
 
 int pp_k_resid_restrict(const pp_grid *grid, const double *bx, const double *by, const double *bz,

@@ -447,6 +447,349 @@ void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
 #undef PP_FUSED_LAUNCH
 }
 
+// ---------------------------------------------------------------------------
+// Two sweeps in one pass (FP32 arithmetic: FP32 and FP16 storage).
+//
+// The plane step above, extended by two phases that lag behind it.  At step k
+//   A: first colour of plane k, sweep 1 (from e_in, as above);
+//   B: second colour of plane k-1, sweep 1;
+//   C: first colour of plane k-2, sweep 2, from the finished sweep-1 values;
+//   D: second colour of plane k-3, sweep 2, which completes that plane.
+// Every phase reads its in-plane neighbours from an LDS plane written one
+// step earlier (A from the published inputs, B from A's values, C from B's,
+// D from C's) and its z neighbours, the same pair's cells in the planes above
+// and below, from registers.  C and D update the same cells as A and B two
+// steps before, so they reuse the coefficients, reciprocal diagonal and h^2 r
+// that A and B computed, carried in registers.  One barrier per step
+// separates A (and the publication of the next plane's inputs) from B, C and
+// D.  Each phase consumes one ring cell, so the ring around the tile is two
+// pairs wide and three rows deep, and a chunk of output planes [k0, k1) is
+// marched from k0-3 to k1+2.  Per cell the pass moves the bytes of one sweep.
+// ---------------------------------------------------------------------------
+constexpr int GTX = 64;                   // tile width in cells (32 pairs)
+constexpr int GTY = 8;                    // tile height in rows
+constexpr int GPX = GTX / 2 + 4;          // pairs per row: two ring pairs on each side
+constexpr int GRY = GTY + 6;              // rows: three ring rows on each side
+constexpr int GTHREADS = (GPX * GRY + 63) / 64 * 64;
+constexpr int GLW = GTX + 12;             // LDS row: cells i0-6 .. i0+GTX+5
+constexpr int GLR = GTY + 8;              // LDS rows: j0-4 .. j0+GTY+3
+
+// what phase A (B) computed for a cell, for phase C (D) two steps later
+struct GsLag {
+    float xl, xh, yl, yh, zl, zh;   // link coefficients
+    float inv;                      // 1 / diagonal, or 0 for an excluded cell or missing plane
+    float hr;                       // h^2 r
+};
+
+template <typename T, bool ZERO, bool SIG>
+__global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T *__restrict__ bx,
+                                                          const T *__restrict__ by,
+                                                          const T *__restrict__ bz,
+                                                          const T *__restrict__ r,
+                                                          const T *__restrict__ ein,
+                                                          T *__restrict__ eout,
+                                                          const T *__restrict__ sg, float h2,
+                                                          int c0, int kz, unsigned tx_tiles,
+                                                          unsigned ty_tiles)
+{
+    using C = float;
+    using T2 = typename Vec2<T>::type;
+    constexpr int FPD = FusedDepth<T>::value;
+    constexpr int FNB = FPD + 3;
+    __shared__ C SE[2][GLR][GLW];     // e_in of planes k, k+1
+    __shared__ C SX[2][GLR][GLW];     // beta_x of planes k, k+1
+    __shared__ C SY[2][GLR][GLW];     // beta_y of planes k, k+1
+    __shared__ C RED1[3][GLR][GLW];   // phase A values (sweep 1, first colour)
+    __shared__ C BLK1[2][GLR][GLW];   // phase B values (sweep 1, second colour)
+    __shared__ C RED2[2][GLR][GLW];   // phase C values (sweep 2, first colour)
+    int bxi, byi, bzi;
+    xcd_tile(tx_tiles, ty_tiles, bxi, byi, bzi);
+    const int i0 = bxi * GTX, j0 = byi * GTY;
+    const int k0 = bzi * kz;
+    const int k1 = min(k0 + kz, d.nz);
+    const int xend = min(i0 + GTX, d.nx), yend = min(j0 + GTY, d.ny);
+
+    const int tid = threadIdx.x;
+    const bool in_layout = tid < GPX * GRY;
+    const int tl = in_layout ? tid : 0;
+    const int pl = tl % GPX - 2;      // pair within the tile; -2, -1 and those past xend are ring
+    const int rl = tl / GPX - 3;      // row within the tile; -3..-1 and those past yend are ring
+    const int xu = i0 + 2 * pl, ju = j0 + rl;
+    int x = xu, j = ju;
+    // ring pairs / rows past the grid's end wrap when periodic (at most two
+    // pairs, three rows); with walls they hold no cell
+    bool act = in_layout;
+    if (xu < 0) {
+        if (bc.x) act = false; else x = xu + d.nx;
+    } else if (xu >= d.nx) {
+        if (bc.x || xu >= d.nx + 4) act = false; else x = xu - d.nx;
+    }
+    if (ju < 0) {
+        if (bc.y) act = false; else j = ju + d.ny;
+    } else if (ju >= d.ny) {
+        if (bc.y || ju >= d.ny + 3) act = false; else j = ju - d.ny;
+    }
+    if (!act) {
+        x = 0;
+        j = 0;
+    }
+    const bool owned = act && pl >= 0 && xu < xend && rl >= 0 && ju < yend;
+    const bool dn_row = act && rl == -3;              // publishes the row below it
+    const bool up_row = act && ju == yend + 2;        // publishes the row above it
+    const int jm = (j == 0) ? d.ny - 1 : j - 1;
+    const int jp = (j == d.ny - 1) ? 0 : j + 1;
+    const bool wyl = bc.y && j == 0, wyh = bc.y && j == d.ny - 1;
+    const bool wxl = bc.x && x == 0;
+    const int jo = dn_row ? jm : (up_row ? jp : j);
+    const bool zo = up_row ? wyh : wyl;
+    const unsigned oc0 = (unsigned)(((size_t)j * d.nx + x) * sizeof(T));
+    const unsigned oo0 = (unsigned)(((size_t)jo * d.nx + x) * sizeof(T));
+    const unsigned oc = act ? oc0 : OFF_NONE;
+    const unsigned oo = act ? oo0 : OFF_NONE;
+    const unsigned ocy = (act && !wyl) ? oc0 : OFF_NONE;
+    const unsigned ooy = (act && !zo) ? oo0 : OFF_NONE;
+    const unsigned ost = owned ? oc0 : OFF_NONE;
+    const unsigned pbytes = (unsigned)((size_t)d.nx * d.ny * sizeof(T));
+    const int lx = 2 * pl + 6;        // LDS column of the pair's first cell
+    const int ly = rl + 4;            // LDS row of the pair
+    const int lyo = dn_row ? ly - 1 : (up_row ? ly + 1 : ly);
+
+    auto plane = [&](int q, int &qw) -> bool {
+        qw = q;
+        if (q < 0) {
+            if (bc.z) { qw = 0; return false; }
+            qw = q + d.nz;
+        } else if (q >= d.nz) {
+            if (bc.z) { qw = 0; return false; }
+            qw = q - d.nz;
+        }
+        return true;
+    };
+    auto load_in = [&](int q, PairIn<T> &v) __attribute__((always_inline)) {
+        int qw;
+        const unsigned nb = plane(q, qw) ? pbytes : 0u;
+        const size_t pb = (size_t)qw * pbytes;
+        auto rs = [&](const T *base, unsigned n) {
+            return plane_rsrc(reinterpret_cast<const char *>(base) + pb, n);
+        };
+        if (!ZERO) {
+            const auto re = rs(ein, nb);
+            v.e = ld_pair<T>(re, oc);
+            v.eo = ld_pair<T>(re, oo);
+        }
+        v.r = ld_pair<T>(rs(r, nb), oc);
+        v.bx = ld_pair<T>(rs(bx, nb), oc);
+        const auto ry = rs(by, nb);
+        v.by = ld_pair<T>(ry, ocy);
+        v.byo = ld_pair<T>(ry, ooy);
+        v.bz = ld_pair<T>(rs(bz, (bc.z && qw == 0) ? 0u : nb), oc);
+        if (SIG)
+            v.sg = ld_pair<T>(rs(sg, nb), oc);
+    };
+    auto pick = [](int o, T2 v) -> C { return C(o ? v.y : v.x); };
+    auto publish = [&](int slot, const PairIn<T> &v) __attribute__((always_inline)) {
+        if (!act)
+            return;
+        if (!ZERO) {
+            SE[slot][ly][lx] = C(v.e.x);
+            SE[slot][ly][lx + 1] = C(v.e.y);
+            SE[slot][lyo][lx] = C(v.eo.x);
+            SE[slot][lyo][lx + 1] = C(v.eo.y);
+        }
+        SX[slot][ly][lx] = wxl ? C(0) : C(v.bx.x);
+        SX[slot][ly][lx + 1] = C(v.bx.y);
+        SY[slot][ly][lx] = C(v.by.x);
+        SY[slot][ly][lx + 1] = C(v.by.y);
+        SY[slot][lyo][lx] = C(v.byo.x);
+        SY[slot][lyo][lx + 1] = C(v.byo.y);
+    };
+
+    for (int i = tid; i < 2 * GLR * GLW; i += GTHREADS) {
+        (&SE[0][0][0])[i] = C(0);
+        (&SX[0][0][0])[i] = C(0);
+        (&SY[0][0][0])[i] = C(0);
+        (&BLK1[0][0][0])[i] = C(0);
+        (&RED2[0][0][0])[i] = C(0);
+    }
+    for (int i = tid; i < 3 * GLR * GLW; i += GTHREADS)
+        (&RED1[0][0][0])[i] = C(0);
+
+    // own-pair values of earlier planes: A's of k-1, k-2; B's of k-2, k-3;
+    // C's of k-3, k-4
+    C red_km1 = C(0), red_km2 = C(0);
+    C blk_km1 = C(0), blk_km2 = C(0);
+    C r2_km1 = C(0), r2_km2 = C(0);
+    C sxl = C(0), sxh = C(0), syl = C(0), syh = C(0);
+    GsLag a1{}, a2{}, b1{}, b2{};
+
+    auto step = [&](int k, PairIn<T> &pm, PairIn<T> &pc, PairIn<T> &pn, PairIn<T> &pf)
+                    __attribute__((always_inline)) {
+        load_in(k + 1 + FPD, pf);
+        const int si = k & 1;
+        int kw;
+        const bool kin = act && plane(k, kw);
+        const int o = (c0 + j + k) & 1;   // first-colour cell of the pair in plane k
+        const int ca = lx + o;            // the cell every phase of this step updates
+        // phase A: first colour of plane k, sweep 1
+        const C xl = SX[si][ly][ca], xh = SX[si][ly][ca + 1];
+        const C yl = SY[si][ly][ca], yh = SY[si][ly + 1][ca];
+        const C zl = pick(o, pc.bz), zh = pick(o, pn.bz);
+        C diag = (xl + xh) + (yl + yh) + (zl + zh);
+        if (SIG)
+            diag += pick(o, pc.sg);
+        C s = C(0);
+        if (!ZERO)
+            s = xl * SE[si][ly][ca - 1] + xh * SE[si][ly][ca + 1] + yl * SE[si][ly - 1][ca] +
+                yh * SE[si][ly + 1][ca] + zl * pick(o, pm.e) + zh * pick(o, pn.e);
+        const C inva = (kin && diag > C(0)) ? __builtin_amdgcn_rcpf(diag) : C(0);
+        const C hra = h2 * pick(o, pc.r);
+        const C red = (s - hra) * inva;
+        const int cb = lx + 1 - o;
+        const C nxl = SX[si][ly][cb], nxh = SX[si][ly][cb + 1];
+        const C nyl = SY[si][ly][cb], nyh = SY[si][ly + 1][cb];
+        if (act)
+            RED1[slot3(k)][ly][ca] = red;
+        publish(si ^ 1, pn);
+        __syncthreads();
+        // phase B: second colour of plane k-1, sweep 1
+        const int sb = slot3(k - 1);
+        const C bzl = pick(o, pm.bz), bzh = pick(o, pc.bz);
+        C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
+        if (SIG)
+            dg += pick(o, pm.sg);
+        const C invb = dg > C(0) ? __builtin_amdgcn_rcpf(dg) : C(0);
+        const C hrb = h2 * pick(o, pm.r);
+        const C blk = (sxl * RED1[sb][ly][ca - 1] + sxh * RED1[sb][ly][ca + 1] +
+                       syl * RED1[sb][ly - 1][ca] + syh * RED1[sb][ly + 1][ca] + bzl * red_km2 +
+                       bzh * red - hrb) * invb;
+        if (act)
+            BLK1[(k - 1) & 1][ly][ca] = blk;
+        // phase C: first colour of plane k-2, sweep 2 (A's cell of step k-2)
+        const int sc = k & 1;
+        const C red2 = (a2.xl * BLK1[sc][ly][ca - 1] + a2.xh * BLK1[sc][ly][ca + 1] +
+                        a2.yl * BLK1[sc][ly - 1][ca] + a2.yh * BLK1[sc][ly + 1][ca] +
+                        a2.zl * blk_km2 + a2.zh * blk - a2.hr) * a2.inv;
+        if (act)
+            RED2[sc][ly][ca] = red2;
+        // phase D: second colour of plane k-3, sweep 2 (B's cell of step k-2)
+        const int sd = (k - 1) & 1;
+        const C blk2 = (b2.xl * RED2[sd][ly][ca - 1] + b2.xh * RED2[sd][ly][ca + 1] +
+                        b2.yl * RED2[sd][ly - 1][ca] + b2.yh * RED2[sd][ly + 1][ca] +
+                        b2.zl * r2_km2 + b2.zh * red2 - b2.hr) * b2.inv;
+        const int kd = k - 3;
+        if (kd >= k0) {
+            T2 outv;
+            outv.x = static_cast<T>(o ? r2_km1 : blk2);
+            outv.y = static_cast<T>(o ? blk2 : r2_km1);
+            st_pair<T>(plane_rsrc(reinterpret_cast<const char *>(eout) + (size_t)kd * pbytes, pbytes),
+                       ost, outv);
+        }
+        red_km2 = red_km1;
+        red_km1 = red;
+        blk_km2 = blk_km1;
+        blk_km1 = blk;
+        r2_km2 = r2_km1;
+        r2_km1 = red2;
+        a2 = a1;
+        a1 = GsLag{xl, xh, yl, yh, zl, zh, inva, hra};
+        b2 = b1;
+        b1 = GsLag{sxl, sxh, syl, syh, bzl, bzh, invb, hrb};
+        sxl = nxl;
+        sxh = nxh;
+        syl = nyl;
+        syh = nyh;
+    };
+
+    PairIn<T> buf[FNB];
+#pragma unroll
+    for (int u = 0; u < FNB - 1; ++u)
+        load_in(k0 - 4 + u, buf[u]);
+    __syncthreads();                  // the zero fill is complete
+    publish((k0 - 3) & 1, buf[1]);
+    __syncthreads();
+    for (int k = k0 - 3;;) {
+#pragma unroll
+        for (int u = 0; u < FNB; ++u) {
+            step(k, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB], buf[(u + FNB - 1) % FNB]);
+            if (++k > k1 + 2)
+                return;
+        }
+    }
+}
+
+template <typename T, bool ZERO, bool SIG>
+static long long fused2_slots()
+{
+    static long long cached[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64)
+        dev = 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused2<T, ZERO, SIG>,
+                                                         GTHREADS, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 256;
+        cached[dev] = (long long)per_cu * cus;
+    }
+    return cached[dev];
+}
+
+template <typename T>
+void prepare_fused2()
+{
+    (void)fused2_slots<T, true, false>();
+    (void)fused2_slots<T, false, false>();
+    (void)fused2_slots<T, true, true>();
+    (void)fused2_slots<T, false, true>();
+}
+
+template <typename T>
+void launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
+                        const T *ein, T *eout, const T *sg, double h2, int first_colour,
+                        bool zero, hipStream_t s)
+{
+    const unsigned tx = (d.nx + GTX - 1) / GTX, ty = (d.ny + GTY - 1) / GTY;
+    const long long slots =
+        sg ? (zero ? fused2_slots<T, true, true>() : fused2_slots<T, false, true>())
+           : (zero ? fused2_slots<T, true, false>() : fused2_slots<T, false, false>());
+    // the six planes a chunk marches beyond its own are recomputed: at least 8 per chunk
+    int kz = fused_kz(d, tx * ty, slots);
+    if (kz < 8)
+        kz = (d.nz < 8) ? d.nz : 8;
+    const unsigned tz = (d.nz + kz - 1) / kz;
+    const dim3 grid(tx * ty, tz);
+#define PP_FUSED2_LAUNCH(Z, S)                                                                 \
+    hipLaunchKernelGGL((k_rbgs_fused2<T, Z, S>), grid, dim3(GTHREADS), 0, s, d, bc, bx, by, bz, \
+                       r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty)
+    if (sg) {
+        if (zero)
+            PP_FUSED2_LAUNCH(true, true);
+        else
+            PP_FUSED2_LAUNCH(false, true);
+    } else {
+        if (zero)
+            PP_FUSED2_LAUNCH(true, false);
+        else
+            PP_FUSED2_LAUNCH(false, false);
+    }
+#undef PP_FUSED2_LAUNCH
+}
+
+template void prepare_fused2<float>();
+template void prepare_fused2<_Float16>();
+template void launch_rbgs_fused2<float>(Dims, Bc, const float *, const float *, const float *,
+                                        const float *, const float *, float *, const float *,
+                                        double, int, bool, hipStream_t);
+template void launch_rbgs_fused2<_Float16>(Dims, Bc, const _Float16 *, const _Float16 *,
+                                           const _Float16 *, const _Float16 *, const _Float16 *,
+                                           _Float16 *, const _Float16 *, double, int, bool,
+                                           hipStream_t);
+
 #define PP_INSTANTIATE_FUSED(T)                                                                  \
     template void prepare_fused<T>();                                                           \
     template void launch_rbgs_fused<T>(Dims, Bc, const T *, const T *, const T *, const T *,    \

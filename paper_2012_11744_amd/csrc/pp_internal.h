@@ -112,6 +112,15 @@ template <typename T>
 void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
                        const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
                        hipStream_t s);
+// Two sweeps in one pass (FP32 and FP16 storage only), out of place, ein and
+// eout distinct; needs nz >= 8 (the chunks read four planes beyond their ends).
+template <typename T>
+void prepare_fused2();
+template <typename T>
+void launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
+                        const T *ein, T *eout, const T *sg, double h2, int first_colour,
+                        bool zero, hipStream_t s);
+inline bool fused2_fits(Dims d) { return d.nz >= 8 && d.nx >= 8 && d.ny >= 8; }
 template <typename T>
 void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
                            const T *r, const T *sg, T *rH, double ih2, hipStream_t s);

@@ -298,6 +298,19 @@ def k_smooth_fused(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero_init
     return e_out
 
 
+def k_smooth2_fused_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero_init=False):
+    """Two fused sweeps on float32 device tensors (the FP32 V-cycle's kernel)."""
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    for t in (*beta, r, e_in, e_out):
+        if t.dtype != torch.float32:
+            raise TypeError("k_smooth2_fused_f32 takes float32 tensors")
+    L.check(lib.pp_k_smooth2_fused_f32(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r),
+                                       _ptr(e_in), _ptr(e_out), int(first_colour), int(zero_init),
+                                       _stream_handle(None)), "pp_k_smooth2_fused_f32")
+    return e_out
+
+
 def k_resid_restrict(shape, h, bc, beta, e, r, rH):
     lib = L.load()
     g = make_grid(shape, h, bc)

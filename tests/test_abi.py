@@ -130,6 +130,11 @@ def test_kernel_entries_validate(lib):
                                  None) == L.PP_EINVAL      # e_in aliases e_out
     assert lib.pp_k_smooth_fused(ctypes.byref(g), fake, fake, fake, fake, fake, other, 2, 0,
                                  None) == L.PP_EINVAL      # bad colour
+    for gg in (g3, _grid((10, 8, 6), 0.1, (1, 1, 1))):    # odd nx; a count below 8
+        assert lib.pp_k_smooth2_fused_f32(ctypes.byref(gg), fake, fake, fake, fake, fake, other, 0,
+                                          0, None) == L.PP_EINVAL
+    assert lib.pp_k_smooth2_fused_f32(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0, 0,
+                                      None) == L.PP_EINVAL      # e_in aliases e_out
     assert lib.pp_k_resid_restrict(ctypes.byref(g2), fake, fake, fake, fake, fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g2), fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g), fake, ctypes.c_void_p(0x1008), None) == L.PP_EINVAL   # e misaligned

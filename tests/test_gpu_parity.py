@@ -136,6 +136,40 @@ def test_fused_sweep_matches_paper_sor(S, n, bc, first):
     assert relmax(host(out), ref0) <= 1e-14
 
 
+@pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0)),
+                                  ((200, 72, 40), (0, 0, 0))])
+@pytest.mark.parametrize("first", [0, 1])
+def test_two_sweep_fused_f32_matches_paper_sor(S, n, bc, first):
+    """Two sweeps in one pass (FP32 storage and arithmetic; tiles of 64 x 8
+    cells with a ring two pairs / three rows deep, z chunks marched three
+    planes beyond their ends) against two of the oracle's sweeps of eq.
+    beta_pressure on the same FP32-rounded inputs.  Tolerance: FP32 rounding
+    of each update (a few ulps, the reciprocal within 1 ulp) carried through
+    four colour passes, relative to max|e|: 2e-6."""
+    _say(f"two-sweep fused f32 n={n} bc={bc} first={first}")
+    w = W.random_case(n, bc, seed=117)
+    beta = [b.astype(np.float32) for b in oracle.face_coeffs(w.rho, bc)]
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(w.shape).astype(np.float32)
+    e0 = rng.standard_normal(w.shape).astype(np.float32)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    bt = [f32(b) for b in beta]
+    b64 = [b.astype(np.float64) for b in beta]
+    for zero in (False, True):
+        p0 = np.zeros(w.shape) if zero else e0.astype(np.float64)
+        ref, _, _ = oracle.rbsor(b64, bc, w.h, r.astype(np.float64), p0=p0, omega=1.0, sweeps=2,
+                                 first_colour=first)
+        out = f32(np.full(w.shape, np.nan))
+        ein = f32(np.full(w.shape, np.nan)) if zero else f32(e0)
+        S.k_smooth2_fused_f32(w.shape, w.h, bc, bt, f32(r), ein, out, first_colour=first,
+                              zero_init=zero)
+        got = host(out).astype(np.float64)
+        err = relmax(got, ref)
+        _say(f"  zero={zero} err={err:.2e}")
+        assert np.isfinite(got).all()
+        assert err <= 2e-6
+
+
 def _restrict_ref(x):
     nz, ny, nx = x.shape
     return x.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(1, 3, 5))
