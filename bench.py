@@ -230,12 +230,15 @@ def main():
             "fell_back": st["fell_back"],
             "memory_bytes": sol.memory_bytes,
         }
-        # fine-level smoother, one fused red-black sweep per launch: reads e_in,
-        # r and the three face coefficients once and writes e_out: 6 words per
-        # cell; the first sweep of each cycle starts from zero and skips e_in
-        # (5 words).  With nu_pre = nu_post = 2 one launch in four is such a
-        # zero-start sweep.
+        # fine-level smoother: each launch reads e_in, r and the three face
+        # coefficients once and writes e_out: 6 words per cell; the first
+        # launch of each cycle starts from zero and skips e_in (5 words).  FP32
+        # and FP16 storage run two sweeps per launch (one launch in two starts
+        # from zero with nu_pre = nu_post = 2), FP64 one sweep per launch (one
+        # in four).
         word = {"fp64": 8, "fp32": 4, "fp16": 2}[mode]
+        dword = 8 if mode == "fp64" else 4          # outer search direction
+        zero_share = 0.25 if mode == "fp64" else 0.5
         n_sm, ms_sm = kt[L.PP_KT_SMOOTH]
         n_rr, ms_rr = kt[L.PP_KT_RESTRICT]
         n_oa, ms_oa = kt[L.PP_KT_OUTER_APPLY]
@@ -243,7 +246,7 @@ def main():
         kern = {}
         if n_sm:
             avg = ms_sm / n_sm
-            byt = (6.0 - 0.25) * word * w.cells
+            byt = (6.0 - zero_share) * word * w.cells
             kern["smoother_sweep"] = {"launches": n_sm, "avg_ms": avg, "alg_bytes": byt,
                                       "GBps": byt / (avg * 1e-3) / 1e9}
         if n_rr:
@@ -253,21 +256,24 @@ def main():
                                       "GBps": byt / (avg * 1e-3) / 1e9}
         if n_oa:
             avg = ms_oa / n_oa
-            # new direction + operator: z (V-cycle word), d_old, 3 beta in; d_new, q out
-            # (FP64); the first iteration of each solve does not read d_old
-            byt = (48 + word - 8.0 / max(1, r["outer_iters"])) * w.cells
+            # new direction + operator: z (V-cycle word), D_old, 3 beta, x in;
+            # D_new, q, x out; the first iteration of each solve reads neither
+            # D_old nor x and writes no x
+            byt = (48 + word + 2 * dword - (dword + 16.0) / max(1, r["outer_iters"])) * w.cells
             kern["outer_apply"] = {"launches": n_oa, "avg_ms": avg, "alg_bytes": byt,
                                    "GBps": byt / (avg * 1e-3) / 1e9}
         if n_ou:
             avg = ms_ou / n_ou
-            byt = (48 + 2 * word) * w.cells         # x, d, r, q in; x, r out; z in, r_T out
+            byt = (24 + 2 * word) * w.cells         # q, r in; r out; z_old in, r_T out
             kern["outer_update"] = {"launches": n_ou, "avg_ms": avg, "alg_bytes": byt,
                                     "GBps": byt / (avg * 1e-3) / 1e9}
         r["kernels"] = kern
         if mi == 0 and "smoother_sweep" in kern:
             k = kern["smoother_sweep"]
             traffic, source = counter_traffic() if mode == "fp32" and N == 256 else (None, "other shape")
-            roof = {"kernel": "fused red-black Gauss-Seidel sweep (fine level, %s)" % mode,
+            roof = {"kernel": "fused red-black Gauss-Seidel pass (fine level, %s, %s)"
+                              % (mode, "one sweep per launch" if mode == "fp64" else
+                                 "two sweeps per launch"),
                     "bound": "hbm", "achieved": round(k["GBps"], 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(k["GBps"] / HBM_PEAK_GBS, 4),
                     "traffic": traffic, "traffic_source": source,

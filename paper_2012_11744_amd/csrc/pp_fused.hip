@@ -494,8 +494,14 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
 {
     using C = float;
     using T2 = typename Vec2<T>::type;
-    constexpr int FPD = FusedDepth<T>::value;
+    // Planes of loads in flight beyond k+1: three for FP32, one for FP16
+    // (whose registers then allow two workgroups per CU).  The loop is
+    // unrolled by the buffer count FNB; with FP32's six buffers, a multiple
+    // of both slot periods (2 and 3), every LDS slot index is a compile-time
+    // constant.
+    constexpr int FPD = sizeof(T) == 4 ? 3 : 1;
     constexpr int FNB = FPD + 3;
+    constexpr bool CT_SLOTS = FNB % 6 == 0;
     __shared__ C SE[2][GLR][GLW];     // e_in of planes k, k+1
     __shared__ C SX[2][GLR][GLW];     // beta_x of planes k, k+1
     __shared__ C SY[2][GLR][GLW];     // beta_y of planes k, k+1
@@ -622,13 +628,23 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     C sxl = C(0), sxh = C(0), syl = C(0), syh = C(0);
     GsLag a1{}, a2{}, b1{}, b2{};
 
-    auto step = [&](int k, PairIn<T> &pm, PairIn<T> &pc, PairIn<T> &pn, PairIn<T> &pf)
+    // LDS slots are counted from the first plane of the march, kb = k0 - 3:
+    // plane k's inputs sit in slot (k - kb) mod 2, its phase-A values in slot
+    // (k - kb) mod 3; u is the unrolled step index, (k - kb) mod FNB
+    const int kb = k0 - 3;
+    const int p0 = (c0 + j + kb) & 1;
+    // waves that hold only outer ring rows, whose phase C and D values no
+    // thread reads, skip those phases
+    const bool cdw = __any(in_layout && rl >= -1 && rl <= GTY);
+    auto step = [&](int k, int u, PairIn<T> &pm, PairIn<T> &pc, PairIn<T> &pn, PairIn<T> &pf)
                     __attribute__((always_inline)) {
         load_in(k + 1 + FPD, pf);
-        const int si = k & 1;
+        const int st = CT_SLOTS ? u : k - kb;
+        const int si = st & 1;
+        const int s3 = CT_SLOTS ? u % 3 : slot3(st);
         int kw;
         const bool kin = act && plane(k, kw);
-        const int o = (c0 + j + k) & 1;   // first-colour cell of the pair in plane k
+        const int o = p0 ^ (st & 1);      // first-colour cell of the pair in plane k
         const int ca = lx + o;            // the cell every phase of this step updates
         // phase A: first colour of plane k, sweep 1
         const C xl = SX[si][ly][ca], xh = SX[si][ly][ca + 1];
@@ -648,11 +664,11 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
         const C nxl = SX[si][ly][cb], nxh = SX[si][ly][cb + 1];
         const C nyl = SY[si][ly][cb], nyh = SY[si][ly + 1][cb];
         if (act)
-            RED1[slot3(k)][ly][ca] = red;
+            RED1[s3][ly][ca] = red;
         publish(si ^ 1, pn);
         __syncthreads();
         // phase B: second colour of plane k-1, sweep 1
-        const int sb = slot3(k - 1);
+        const int sb = s3 == 0 ? 2 : s3 - 1;
         const C bzl = pick(o, pm.bz), bzh = pick(o, pc.bz);
         C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
         if (SIG)
@@ -663,26 +679,29 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
                        syl * RED1[sb][ly - 1][ca] + syh * RED1[sb][ly + 1][ca] + bzl * red_km2 +
                        bzh * red - hrb) * invb;
         if (act)
-            BLK1[(k - 1) & 1][ly][ca] = blk;
-        // phase C: first colour of plane k-2, sweep 2 (A's cell of step k-2)
-        const int sc = k & 1;
-        const C red2 = (a2.xl * BLK1[sc][ly][ca - 1] + a2.xh * BLK1[sc][ly][ca + 1] +
-                        a2.yl * BLK1[sc][ly - 1][ca] + a2.yh * BLK1[sc][ly + 1][ca] +
-                        a2.zl * blk_km2 + a2.zh * blk - a2.hr) * a2.inv;
-        if (act)
-            RED2[sc][ly][ca] = red2;
-        // phase D: second colour of plane k-3, sweep 2 (B's cell of step k-2)
-        const int sd = (k - 1) & 1;
-        const C blk2 = (b2.xl * RED2[sd][ly][ca - 1] + b2.xh * RED2[sd][ly][ca + 1] +
-                        b2.yl * RED2[sd][ly - 1][ca] + b2.yh * RED2[sd][ly + 1][ca] +
-                        b2.zl * r2_km2 + b2.zh * red2 - b2.hr) * b2.inv;
-        const int kd = k - 3;
-        if (kd >= k0) {
-            T2 outv;
-            outv.x = static_cast<T>(o ? r2_km1 : blk2);
-            outv.y = static_cast<T>(o ? blk2 : r2_km1);
-            st_pair<T>(plane_rsrc(reinterpret_cast<const char *>(eout) + (size_t)kd * pbytes, pbytes),
-                       ost, outv);
+            BLK1[si ^ 1][ly][ca] = blk;
+        C red2 = C(0);
+        if (cdw) {
+            // phase C: first colour of plane k-2, sweep 2 (A's cell of step k-2)
+            red2 = (a2.xl * BLK1[si][ly][ca - 1] + a2.xh * BLK1[si][ly][ca + 1] +
+                    a2.yl * BLK1[si][ly - 1][ca] + a2.yh * BLK1[si][ly + 1][ca] + a2.zl * blk_km2 +
+                    a2.zh * blk - a2.hr) * a2.inv;
+            if (act)
+                RED2[si][ly][ca] = red2;
+            // phase D: second colour of plane k-3, sweep 2 (B's cell of step k-2)
+            const int sd = si ^ 1;
+            const C blk2 = (b2.xl * RED2[sd][ly][ca - 1] + b2.xh * RED2[sd][ly][ca + 1] +
+                            b2.yl * RED2[sd][ly - 1][ca] + b2.yh * RED2[sd][ly + 1][ca] +
+                            b2.zl * r2_km2 + b2.zh * red2 - b2.hr) * b2.inv;
+            const int kd = k - 3;
+            if (kd >= k0) {
+                T2 outv;
+                outv.x = static_cast<T>(o ? r2_km1 : blk2);
+                outv.y = static_cast<T>(o ? blk2 : r2_km1);
+                st_pair<T>(
+                    plane_rsrc(reinterpret_cast<const char *>(eout) + (size_t)kd * pbytes, pbytes),
+                    ost, outv);
+            }
         }
         red_km2 = red_km1;
         red_km1 = red;
@@ -705,12 +724,13 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     for (int u = 0; u < FNB - 1; ++u)
         load_in(k0 - 4 + u, buf[u]);
     __syncthreads();                  // the zero fill is complete
-    publish((k0 - 3) & 1, buf[1]);
+    publish(0, buf[1]);
     __syncthreads();
-    for (int k = k0 - 3;;) {
+    for (int k = kb;;) {
 #pragma unroll
         for (int u = 0; u < FNB; ++u) {
-            step(k, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB], buf[(u + FNB - 1) % FNB]);
+            step(k, u, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB],
+                 buf[(u + FNB - 1) % FNB]);
             if (++k > k1 + 2)
                 return;
         }
