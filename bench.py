@@ -81,7 +81,7 @@ def summarize_db(path):
               f"{mn / 1e3:.2f} | {mx / 1e3:.2f} | {100 * tot / total:.1f} |")
 
 
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "fused_rbgs_layer256.md")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "fused2_rbgs_layer256.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2012_11744_amd", "csrc", "pp_fused.hip")
 
 
