@@ -560,16 +560,14 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     const int ly = rl + 4;            // LDS row of the pair
     const int lyo = dn_row ? ly - 1 : (up_row ? ly + 1 : ly);
 
+    // plane q: its wrapped index, and whether it exists (walls end the grid);
+    // selects rather than branches (q is within four planes of the grid)
     auto plane = [&](int q, int &qw) -> bool {
-        qw = q;
-        if (q < 0) {
-            if (bc.z) { qw = 0; return false; }
-            qw = q + d.nz;
-        } else if (q >= d.nz) {
-            if (bc.z) { qw = 0; return false; }
-            qw = q - d.nz;
-        }
-        return true;
+        const bool lo = q < 0, hi = q >= d.nz;
+        qw = lo ? q + d.nz : (hi ? q - d.nz : q);
+        const bool ok = !(bc.z && (lo || hi));
+        qw = ok ? qw : 0;
+        return ok;
     };
     auto load_in = [&](int q, PairIn<T> &v) __attribute__((always_inline)) {
         int qw;
@@ -667,32 +665,45 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
             RED1[s3][ly][ca] = red;
         publish(si ^ 1, pn);
         __syncthreads();
-        // phase B: second colour of plane k-1, sweep 1
+        // The in-plane neighbours of phases B, C and D were all written before
+        // this barrier (A's of plane k-1 in this step, B's of plane k-2 and C's
+        // of plane k-3 in the previous one), and none is overwritten below, so
+        // all twelve LDS reads are issued at once.
         const int sb = s3 == 0 ? 2 : s3 - 1;
+        const C bw = RED1[sb][ly][ca - 1], be = RED1[sb][ly][ca + 1];
+        const C bs = RED1[sb][ly - 1][ca], bn = RED1[sb][ly + 1][ca];
+        C cw = C(0), ce = C(0), cs = C(0), cn = C(0), dw = C(0), de = C(0), ds = C(0), dn = C(0);
+        if (cdw) {
+            cw = BLK1[si][ly][ca - 1];
+            ce = BLK1[si][ly][ca + 1];
+            cs = BLK1[si][ly - 1][ca];
+            cn = BLK1[si][ly + 1][ca];
+            dw = RED2[si ^ 1][ly][ca - 1];
+            de = RED2[si ^ 1][ly][ca + 1];
+            ds = RED2[si ^ 1][ly - 1][ca];
+            dn = RED2[si ^ 1][ly + 1][ca];
+        }
+        // phase B: second colour of plane k-1, sweep 1
         const C bzl = pick(o, pm.bz), bzh = pick(o, pc.bz);
         C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
         if (SIG)
             dg += pick(o, pm.sg);
         const C invb = dg > C(0) ? __builtin_amdgcn_rcpf(dg) : C(0);
         const C hrb = h2 * pick(o, pm.r);
-        const C blk = (sxl * RED1[sb][ly][ca - 1] + sxh * RED1[sb][ly][ca + 1] +
-                       syl * RED1[sb][ly - 1][ca] + syh * RED1[sb][ly + 1][ca] + bzl * red_km2 +
-                       bzh * red - hrb) * invb;
+        const C blk = (sxl * bw + sxh * be + syl * bs + syh * bn + bzl * red_km2 + bzh * red - hrb) *
+                      invb;
         if (act)
             BLK1[si ^ 1][ly][ca] = blk;
         C red2 = C(0);
         if (cdw) {
             // phase C: first colour of plane k-2, sweep 2 (A's cell of step k-2)
-            red2 = (a2.xl * BLK1[si][ly][ca - 1] + a2.xh * BLK1[si][ly][ca + 1] +
-                    a2.yl * BLK1[si][ly - 1][ca] + a2.yh * BLK1[si][ly + 1][ca] + a2.zl * blk_km2 +
+            red2 = (a2.xl * cw + a2.xh * ce + a2.yl * cs + a2.yh * cn + a2.zl * blk_km2 +
                     a2.zh * blk - a2.hr) * a2.inv;
             if (act)
                 RED2[si][ly][ca] = red2;
             // phase D: second colour of plane k-3, sweep 2 (B's cell of step k-2)
-            const int sd = si ^ 1;
-            const C blk2 = (b2.xl * RED2[sd][ly][ca - 1] + b2.xh * RED2[sd][ly][ca + 1] +
-                            b2.yl * RED2[sd][ly - 1][ca] + b2.yh * RED2[sd][ly + 1][ca] +
-                            b2.zl * r2_km2 + b2.zh * red2 - b2.hr) * b2.inv;
+            const C blk2 = (b2.xl * dw + b2.xh * de + b2.yl * ds + b2.yh * dn + b2.zl * r2_km2 +
+                            b2.zh * red2 - b2.hr) * b2.inv;
             const int kd = k - 3;
             if (kd >= k0) {
                 T2 outv;
