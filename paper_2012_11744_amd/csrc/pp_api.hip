@@ -626,7 +626,7 @@ void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s)
     LevelBuf &v = H.lev[l];
     const double h2 = v.h * v.h;
     const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
-    if (cells(v.d) > FUSED_MIN_CELLS && fused_plane_fits(v.d, sizeof(T))) {
+    if (cells(v.d) > fused_min_cells<T>() && fused_plane_fits(v.d, sizeof(T))) {
         v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_pre, v.e2, 0, true, s);
     } else {
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
@@ -654,7 +654,7 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
         KT t(c, PP_KT_PROLONG, l == 0);
         launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
     }
-    if (cells(v.d) > FUSED_MIN_CELLS && fused_plane_fits(v.d, sizeof(T))) {
+    if (cells(v.d) > fused_min_cells<T>() && fused_plane_fits(v.d, sizeof(T))) {
         v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_post, v.cur, 1, false, s);
     } else {
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
