@@ -8,8 +8,8 @@ relative residual of 1e-8.
 
 One step = one complete projection for a new density field, every row of the
 hot path on the GPU, inputs resident in HBM:
-    face coefficients beta = 1/rho_f from rho          (pp_face_coeffs)
-    hierarchy rebuild (coarse beta, FP32 copies, A^+)  (pp_update_coeffs)
+    face coefficients beta = 1/rho_f from rho and the
+    hierarchy rebuild (coarse beta, FP32 copies, A^+)  (pp_update_density)
     b = D u* / dt                                     (pp_divergence)
     A p = b - mean(b) to 1e-8                          (pp_solve)
     u = u* - dt beta G p                               (pp_project)
@@ -178,8 +178,7 @@ def main():
         sol = S.Solver(beta, w.h, w.bc, precision=mode)
 
         def step():
-            S.face_coeffs(rho, w.h, w.bc, out=beta)
-            sol.update_coeffs(beta)
+            sol.update_density(rho)
             sol.divergence(us, 1.0 / w.dt, out=b)
             sol.solve(b, tol=args.tol, p=p)
             sol.project(us, p, w.dt, out=u)
@@ -364,8 +363,7 @@ def jet512(args):
     sol = S.Solver(beta, w.h, w.bc, precision="fp32")
 
     def forward():
-        S.face_coeffs(rho, w.h, w.bc, out=beta)
-        sol.update_coeffs(beta)
+        sol.update_density(rho)
         sol.divergence(us, 1.0 / w.dt, out=b)
         sol.solve(b, tol=args.tol, p=p)
         sol.project(us, p, w.dt, out=u)

@@ -159,6 +159,18 @@ int pp_setup_general(const pp_grid *grid, const double *beta_x, const double *be
                      const double *beta_z, const double *sigma, const pp_opts *opts,
                      void *hip_stream, pp_ctx **out);
 
+/* New coefficients from the cell densities (Sec. 3.2: beta = 1/rho at the
+ * faces, the interpolation of pp_face_coeffs): beta = 2 / (rho_L + rho_R) on
+ * every non-wall face, computed on the device together with the hierarchy
+ * rebuild of pp_update_coeffs, so the coefficients are the ones
+ * pp_face_coeffs followed by pp_update_coeffs would load, bit for bit, in one
+ * pass over memory.  rho: device (nz, ny, nx) FP64 array, read only, owned by
+ * the caller (16-byte alignment selects the one-pass kernel).  For contexts
+ * made by pp_setup only.  PP_EINVAL if a cell's density or a resulting face
+ * coefficient is not a finite positive number; the context's coefficients
+ * are then undefined until a later successful update. */
+int pp_update_density(pp_ctx *ctx, const double *rho);
+
 /* New coefficients for a context made by pp_setup_general (same grid);
  * sigma must be NULL exactly when it was NULL at setup.  As pp_update_coeffs
  * otherwise. */

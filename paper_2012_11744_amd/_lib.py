@@ -64,7 +64,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = [
-    "pp_opts_default", "pp_face_coeffs", "pp_setup", "pp_setup_general", "pp_update_coeffs",
+    "pp_opts_default", "pp_face_coeffs", "pp_setup", "pp_setup_general", "pp_update_coeffs", "pp_update_density",
     "pp_update_general", "pp_divergence",
     "pp_apply", "pp_solve", "pp_project", "pp_solve_adjoint", "pp_levels", "pp_level_dims",
     "pp_memory", "pp_destroy", "pp_strerror", "pp_last_error",
@@ -97,6 +97,7 @@ def load():
         "pp_setup": (I, [GP, P, P, P, OP, P, ctypes.POINTER(P)]),
         "pp_setup_general": (I, [GP, P, P, P, P, OP, P, ctypes.POINTER(P)]),
         "pp_update_coeffs": (I, [P, P, P, P]),
+        "pp_update_density": (I, [P, P]),
         "pp_update_general": (I, [P, P, P, P, P]),
         "pp_divergence": (I, [P, P, P, P, D, P]),
         "pp_apply": (I, [P, P, P]),

@@ -528,42 +528,64 @@ int load_coeffs_general(pp_ctx *c, const double *bx, const double *by, const dou
     return PP_OK;
 }
 
-int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
+// Level-0 coefficients into the FP64 chain (and the mixed hierarchy's level
+// 0 and level 1 where the one-pass kernel applies), then the coarse levels,
+// the storage copies and the coarsest pseudo-inverse.  The coefficients come
+// from the caller's beta arrays, or (rho non-null) are computed from the
+// cell densities.
+int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
 {
-    const double *src[3] = {bx, by, bz};
     int first_coarse = 0;   // first level whose coefficients are still to be coarsened from
     bool level0_converted = false;
-    const bool aligned = !(((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz) & 15);
-    if (c->nlev > 1 && aligned) {
-        // one pass: copy, walls, validity, storage copy of level 0, level 1
+    const uintptr_t align = rho ? (uintptr_t)rho
+                                : ((uintptr_t)src[0] | (uintptr_t)src[1] | (uintptr_t)src[2]);
+    bool rho_checked = false;
+    if (c->nlev > 1 && !(align & 15)) {
+        // one pass: copy (or beta from rho), walls, validity, storage copy of
+        // level 0, level 1
         double *dst[3] = {c->chain[0][0], c->chain[0][1], c->chain[0][2]};
         double *crs[3] = {c->chain[1][0], c->chain[1][1], c->chain[1][2]};
         int np = 0;
         const Hier &H = c->hmix;
+        auto one_pass = [&](auto *t) {
+            using TT = std::remove_pointer_t<decltype(t)>;
+            TT *tt[3] = {t, t ? (TT *)H.lev[0].b[1] : nullptr, t ? (TT *)H.lev[0].b[2] : nullptr};
+            return rho ? launch_load_density<TT>(c->d, c->bc, rho, dst, tt, crs, c->part, c->stream)
+                       : launch_load_coeffs<TT>(c->d, c->bc, src, dst, tt, crs, c->part, c->stream);
+        };
         if (H.present && H.st == ST_F32) {
-            float *t[3] = {(float *)H.lev[0].b[0], (float *)H.lev[0].b[1], (float *)H.lev[0].b[2]};
-            np = launch_load_coeffs<float>(c->d, c->bc, src, dst, t, crs, c->part, c->stream);
+            np = one_pass((float *)H.lev[0].b[0]);
             level0_converted = true;
         } else if (H.present && H.st == ST_F16) {
-            _Float16 *t[3] = {(_Float16 *)H.lev[0].b[0], (_Float16 *)H.lev[0].b[1],
-                              (_Float16 *)H.lev[0].b[2]};
-            np = launch_load_coeffs<_Float16>(c->d, c->bc, src, dst, t, crs, c->part, c->stream);
+            np = one_pass((_Float16 *)H.lev[0].b[0]);
             level0_converted = true;
         } else {
-            float *t[3] = {nullptr, nullptr, nullptr};
-            np = launch_load_coeffs<float>(c->d, c->bc, src, dst, t, crs, c->part, c->stream);
+            np = one_pass((float *)nullptr);
         }
         launch_finalize(c->part, c->pstride, np, OP_STORE, S_COUNT, (double)c->N, 0, c->scal,
                         c->stream);
         first_coarse = 1;
+        rho_checked = rho != nullptr;
     } else {
-        for (int m = 0; m < 3; ++m)
-            PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N,
-                                  hipMemcpyDeviceToDevice, c->stream));
-        launch_zero_walls(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], c->stream);
+        if (rho) {
+            launch_face_coeffs(c->d, c->bc, rho, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                               c->stream);
+        } else {
+            for (int m = 0; m < 3; ++m)
+                PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N,
+                                      hipMemcpyDeviceToDevice, c->stream));
+            launch_zero_walls(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                              c->stream);
+        }
         launch_check_beta(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], false,
                           c->part, c->stream);
         launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_COUNT, (double)c->N, 0,
+                        c->scal, c->stream);
+    }
+    const bool rho_count = rho && !rho_checked;   // densities counted by their own pass
+    if (rho_count) {
+        launch_check_rho(c->d, rho, c->part, c->stream);
+        launch_finalize(c->part, c->pstride, nparts(c), OP_STORE, S_SBAD, (double)c->N, 0,
                         c->scal, c->stream);
     }
     PP_TRY(check_launch("coefficient check"));
@@ -573,11 +595,23 @@ int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
     PP_TRY(check_launch("coarsen coefficients"));
     PP_TRY(fill_hier(c, c->hmix, level0_converted ? 1 : 0));
     PP_TRY(read_scal(c));
-    if (c->hscal[S_COUNT] != 0.0)
+    const double nbad = c->hscal[S_COUNT] + (rho_count ? c->hscal[S_SBAD] : 0.0);
+    if (nbad != 0.0) {
+        if (rho)
+            return fail(PP_EINVAL, "rho: " + std::to_string((long long)nbad) +
+                                       " cells or faces are not finite positive numbers "
+                                       "(density, or the face coefficient 2 / (rho_L + rho_R))");
         return fail(PP_EINVAL, "beta: " + std::to_string((long long)c->hscal[S_COUNT]) +
                                    " non-wall faces are not finite positive numbers");
+    }
     PP_TRY(build_pinv(c));
     return PP_OK;
+}
+
+int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
+{
+    const double *src[3] = {bx, by, bz};
+    return load_coeffs_impl(c, src, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1225,6 +1259,18 @@ int pp_update_coeffs(pp_ctx *c, const double *bx, const double *by, const double
         return load_coeffs_general(c, bx, by, bz, nullptr);
     }
     return load_coeffs(c, bx, by, bz);
+}
+
+int pp_update_density(pp_ctx *c, const double *rho)
+{
+    PP_TRY(check_ctx(c));
+    if (!rho)
+        return fail(PP_EINVAL, "pp_update_density: NULL rho");
+    if (c->gen)
+        return fail(PP_EINVAL, "pp_update_density: a general context takes its coefficients "
+                               "from pp_update_general");
+    const double *src[3] = {nullptr, nullptr, nullptr};
+    return load_coeffs_impl(c, src, rho);
 }
 
 int pp_update_general(pp_ctx *c, const double *bx, const double *by, const double *bz,

@@ -159,6 +159,13 @@ void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, con
 template <typename T>
 int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
                        T *const dstT[3], double *const coarse[3], double *part, hipStream_t s);
+// as launch_load_coeffs with beta computed from the cell densities (the
+// arithmetic of launch_face_coeffs); the partials also count cells whose
+// density is not a finite positive number
+template <typename T>
+int launch_load_density(Dims fd, Bc bc, const double *rho, double *const dst[3], T *const dstT[3],
+                        double *const coarse[3], double *part, hipStream_t s);
+void launch_check_rho(Dims d, const double *rho, double *part, hipStream_t s);
 void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s);
 // partials of the count of non-wall faces that are not finite positive
 // numbers (finite non-negative with allow_zero: closed links allowed)

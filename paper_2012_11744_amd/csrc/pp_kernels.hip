@@ -734,6 +734,108 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
     block_partials<1>(v, sm, part, 0);
 }
 
+// k_load_coeffs with the face coefficients computed from the cell densities
+// on the way (beta = 2 / (rho_L + rho_R), the expression of k_face_coeffs, so
+// the bits are the same): each coarse cell's 8 children read rho at the
+// children and at their low x, y, z neighbours.  Partial: non-wall faces whose
+// beta is not a finite positive number plus cells whose rho is not.
+template <typename T, bool WT>
+__global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const double *__restrict__ rho,
+                                                        double *__restrict__ dx,
+                                                        double *__restrict__ dy,
+                                                        double *__restrict__ dz, T *__restrict__ tx,
+                                                        T *__restrict__ ty, T *__restrict__ tz,
+                                                        double *__restrict__ hx,
+                                                        double *__restrict__ hy,
+                                                        double *__restrict__ hz, double *part)
+{
+    using D2 = double __attribute__((ext_vector_type(2)));
+    using T2 = typename Vec2<T>::type;
+    __shared__ double sm[1][BLOCK / 64];
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const int I = blockIdx.x * BX + threadIdx.x;
+    const int J = blockIdx.y * BY + threadIdx.y;
+    double v[1] = {0.0};
+    if (I < cd.nx && J < cd.ny) {
+        const size_t fy = (size_t)fd.nx, fz = (size_t)fd.nx * fd.ny;
+        const int x = 2 * I;
+        const int xm = (x == 0) ? fd.nx - 1 : x - 1;
+        const int Ke = min(cd.nz, ((int)blockIdx.z + 1) * (RZ / 2));
+        for (int K = blockIdx.z * (RZ / 2); K < Ke; ++K) {
+            double ax[2][2], ay[2][2], az[2][2];   // [dk][dj] / [dk][di] / [dj][di] terms
+            for (int dk = 0; dk < 2; ++dk)
+                for (int dj = 0; dj < 2; ++dj) {
+                    const int j = 2 * J + dj, k = 2 * K + dk;
+                    const int jm = (j == 0) ? fd.ny - 1 : j - 1;
+                    const int km = (k == 0) ? fd.nz - 1 : k - 1;
+                    const size_t row = (size_t)k * fz + (size_t)j * fy;
+                    const size_t c = row + x;
+                    const D2 rc = *reinterpret_cast<const D2 *>(rho + c);
+                    const double rxm = rho[row + xm];
+                    const D2 rym = *reinterpret_cast<const D2 *>(rho + (size_t)k * fz + (size_t)jm * fy + x);
+                    const D2 rzm = *reinterpret_cast<const D2 *>(rho + (size_t)km * fz + (size_t)j * fy + x);
+                    const bool wx = bc.x && I == 0, wy = bc.y && j == 0, wz = bc.z && k == 0;
+                    D2 bxv, byv, bzv;
+                    bxv.x = wx ? 0.0 : 2.0 / (rxm + rc.x);
+                    bxv.y = 2.0 / (rc.x + rc.y);
+                    byv = wy ? D2{0.0, 0.0} : D2{2.0 / (rym.x + rc.x), 2.0 / (rym.y + rc.y)};
+                    bzv = wz ? D2{0.0, 0.0} : D2{2.0 / (rzm.x + rc.x), 2.0 / (rzm.y + rc.y)};
+                    const double f[6] = {bxv.x, bxv.y, byv.x, byv.y, bzv.x, bzv.y};
+                    const bool w[6] = {wx, false, wy, wy, wz, wz};
+                    for (int q = 0; q < 6; ++q)
+                        if (!w[q] && !(f[q] > 0.0 && f[q] < INFINITY))
+                            v[0] += 1.0;
+                    if (!(rc.x > 0.0 && rc.x < INFINITY))
+                        v[0] += 1.0;
+                    if (!(rc.y > 0.0 && rc.y < INFINITY))
+                        v[0] += 1.0;
+                    *reinterpret_cast<D2 *>(dx + c) = bxv;
+                    *reinterpret_cast<D2 *>(dy + c) = byv;
+                    *reinterpret_cast<D2 *>(dz + c) = bzv;
+                    if (WT) {
+                        *reinterpret_cast<T2 *>(tx + c) = T2{static_cast<T>(bxv.x), static_cast<T>(bxv.y)};
+                        *reinterpret_cast<T2 *>(ty + c) = T2{static_cast<T>(byv.x), static_cast<T>(byv.y)};
+                        *reinterpret_cast<T2 *>(tz + c) = T2{static_cast<T>(bzv.x), static_cast<T>(bzv.y)};
+                    }
+                    ax[dk][dj] = bxv.x;
+                    if (dj == 0) {
+                        ay[dk][0] = byv.x;
+                        ay[dk][1] = byv.y;
+                    }
+                    if (dk == 0) {
+                        az[dj][0] = bzv.x;
+                        az[dj][1] = bzv.y;
+                    }
+                }
+            const size_t C = ((size_t)K * cd.ny + J) * cd.nx + I;
+            // same grouping as k_coarsen_beta
+            hx[C] = (bc.x && I == 0) ? 0.0 : 0.25 * ((ax[0][0] + ax[0][1]) + (ax[1][0] + ax[1][1]));
+            hy[C] = (bc.y && J == 0) ? 0.0 : 0.25 * ((ay[0][0] + ay[0][1]) + (ay[1][0] + ay[1][1]));
+            hz[C] = (bc.z && K == 0) ? 0.0 : 0.25 * ((az[0][0] + az[0][1]) + (az[1][0] + az[1][1]));
+        }
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
+// counts cells whose density is not a finite positive number
+__global__ __launch_bounds__(BLOCK) void k_check_rho(Dims d, const double *__restrict__ rho,
+                                                     double *part)
+{
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny) {
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const double r = rho[((size_t)k * d.ny + j) * d.nx + i];
+            if (!(r > 0.0 && r < INFINITY))
+                v[0] += 1.0;
+        }
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
 // counts non-wall faces whose beta is not a finite positive number
 __global__ __launch_bounds__(BLOCK) void k_check_beta(Dims d, Bc bc, const double *__restrict__ bx,
                                                       const double *__restrict__ by,
@@ -1447,6 +1549,26 @@ int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const
     return (int)grid_blocks(g);
 }
 
+template <typename T>
+int launch_load_density(Dims fd, Bc bc, const double *rho, double *const dst[3], T *const dstT[3],
+                        double *const coarse[3], double *part, hipStream_t s)
+{
+    const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
+    const dim3 g((cd.nx + BX - 1) / BX, (cd.ny + BY - 1) / BY, (cd.nz + RZ / 2 - 1) / (RZ / 2));
+    if (dstT[0])
+        hipLaunchKernelGGL((k_load_density<T, true>), g, kBlock, 0, s, fd, bc, rho, dst[0], dst[1],
+                           dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2], part);
+    else
+        hipLaunchKernelGGL((k_load_density<T, false>), g, kBlock, 0, s, fd, bc, rho, dst[0], dst[1],
+                           dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2], part);
+    return (int)grid_blocks(g);
+}
+
+void launch_check_rho(Dims d, const double *rho, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_rho, red_grid(d), kBlock, 0, s, d, rho, part);
+}
+
 void launch_check_beta(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                        bool allow_zero, double *part, hipStream_t s)
 {
@@ -1628,6 +1750,8 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
     template void launch_prolong<T>(Dims, Bc, const T *, T *, hipStream_t);                     \
     template int launch_load_coeffs<T>(Dims, Bc, const double *const[3], double *const[3],      \
                                        T *const[3], double *const[3], double *, hipStream_t);   \
+    template int launch_load_density<T>(Dims, Bc, const double *, double *const[3], T *const[3], \
+                                        double *const[3], double *, hipStream_t);               \
     template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
     template void launch_tail<T>(int, const Dims *, const double *, const void *const (*)[3],   \
                                  void *const *, void *const *, const void *const *, Bc, int,    \

@@ -171,6 +171,14 @@ class Solver:
             L.check(self._lib.pp_update_coeffs(self._ctx, *(self._field(b, "beta") for b in beta)),
                     "pp_update_coeffs")
 
+    def update_density(self, rho: torch.Tensor) -> None:
+        """New face coefficients beta = 2 / (rho_L + rho_R) computed from the
+        cell densities on the device, with the hierarchy rebuild, in one pass."""
+        if self.general:
+            raise ValueError("a general context takes its coefficients from update_coeffs")
+        L.check(self._lib.pp_update_density(self._ctx, self._field(rho, "rho")),
+                "pp_update_density")
+
     def divergence(self, u: Sequence[torch.Tensor], scale: float = 1.0,
                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
