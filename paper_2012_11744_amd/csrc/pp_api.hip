@@ -119,6 +119,8 @@ struct pp_ctx {
     Hier h64;                    // FP64 hierarchy (FP64 mode, and the mixed-mode fallback)
     double *pinv;
     int ncoarse;
+    double *hcoarse;             // pinned: the coarsest level's beta (3 arrays) and sigma, read back
+    double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
     double *r64, *d64, *d64b, *q64;
     double *part;
     size_t pstride;
@@ -368,6 +370,22 @@ int cholesky(std::vector<double> &a, int n)
     return 0;
 }
 
+// Enqueue the read-back of the coarsest level's coefficients into pinned
+// host memory; build_pinv uses them after the next read_scal, which waits
+// for the stream, so the coefficient load costs one synchronisation.
+int enqueue_coarse_download(pp_ctx *c)
+{
+    const int L = c->nlev - 1;
+    const size_t n = cells(c->ld[L]);
+    for (int m = 0; m < 3; ++m)
+        PP_HIP(hipMemcpyAsync(c->hcoarse + m * n, c->chain[L][m], sizeof(double) * n,
+                              hipMemcpyDeviceToHost, c->stream));
+    if (c->sig_on)
+        PP_HIP(hipMemcpyAsync(c->hcoarse + 3 * n, c->sig[L], sizeof(double) * n,
+                              hipMemcpyDeviceToHost, c->stream));
+    return PP_OK;
+}
+
 // FP64 pseudo-inverse of the coarsest operator.  The pressure operator A is
 // singular (constants in the null space): with K = -A + (s/n) 1 1^T positive
 // definite, A^+ = (1/(s n)) 1 1^T - K^-1.  For the general operator
@@ -375,23 +393,16 @@ int cholesky(std::vector<double> &a, int n)
 // diagonal); when sigma is present the operator is definite there and
 // A^+ = -K^-1 with K = -A + diag(sigma).  Excluded cells get zero rows and
 // columns.
+// The coarsest coefficients come from the pinned read-back of
+// enqueue_coarse_download.
 int build_pinv(pp_ctx *c)
 {
     const int L = c->nlev - 1;
     const Dims d = c->ld[L];
     const int n = (int)cells(d);
     const double h = c->lh[L];
-    std::vector<double> b[3];
-    for (int m = 0; m < 3; ++m) {
-        b[m].resize(n);
-        PP_HIP(hipMemcpyAsync(b[m].data(), c->chain[L][m], sizeof(double) * n, hipMemcpyDeviceToHost,
-                              c->stream));
-    }
-    std::vector<double> sg(n, 0.0);
-    if (c->sig_on)
-        PP_HIP(hipMemcpyAsync(sg.data(), c->sig[L], sizeof(double) * n, hipMemcpyDeviceToHost,
-                              c->stream));
-    PP_HIP(hipStreamSynchronize(c->stream));
+    const double *b[3] = {c->hcoarse, c->hcoarse + n, c->hcoarse + 2 * (size_t)n};
+    const double *sg = c->sig_on ? c->hcoarse + 3 * (size_t)n : nullptr;
     std::vector<double> A((size_t)n * n, 0.0);
     const int nn[3] = {d.nx, d.ny, d.nz};
     const int wall[3] = {c->bc.x, c->bc.y, c->bc.z};
@@ -415,7 +426,8 @@ int build_pinv(pp_ctx *c)
                     A[(size_t)Lc * n + Lc] -= w;
                     A[(size_t)Lc * n + R] += w;
                 }
-                A[(size_t)R * n + R] -= sg[R];
+                if (sg)
+                    A[(size_t)R * n + R] -= sg[R];
             }
     std::vector<int> idx;
     for (int i = 0; i < n; ++i)
@@ -435,32 +447,37 @@ int build_pinv(pp_ctx *c)
     if (cholesky(K, na) != 0)
         return fail(PP_EINVAL, "coarsest operator is not definite on mean-zero fields "
                                "(disconnected domain?)");
-    std::vector<double> P((size_t)n * n, 0.0);
-    std::vector<double> y(na);
-    for (int col = 0; col < na; ++col) {
-        for (int i = 0; i < na; ++i) {
-            double t = (i == col) ? 1.0 : 0.0;
-            for (int kk = 0; kk < i; ++kk)
-                t -= K[(size_t)i * na + kk] * y[kk];
-            y[i] = t / K[(size_t)i * na + i];
+    // K^-1 = L^-T L^-1.  Row j of Mt holds column j of M = L^-1 (entries j..na-1),
+    // so both products below run over contiguous memory.
+    std::vector<double> Mt((size_t)na * na, 0.0);
+    for (int j = 0; j < na; ++j) {
+        double *mj = &Mt[(size_t)j * na];
+        mj[j] = 1.0 / K[(size_t)j * na + j];
+        for (int i = j + 1; i < na; ++i) {
+            const double *li = &K[(size_t)i * na];
+            double t = 0.0;
+            for (int kk = j; kk < i; ++kk)
+                t += li[kk] * mj[kk];
+            mj[i] = -t / li[i];
         }
-        for (int i = na - 1; i >= 0; --i) {
-            double t = y[i];
-            for (int kk = i + 1; kk < na; ++kk)
-                t -= K[(size_t)kk * na + i] * y[kk];
-            y[i] = t / K[(size_t)i * na + i];
-        }
-        for (int i = 0; i < na; ++i)
-            P[(size_t)idx[i] * n + idx[col]] = (singular ? 1.0 / (s * na) : 0.0) - y[i];
     }
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j) {
-            const double v = 0.5 * (P[(size_t)i * n + j] + P[(size_t)j * n + i]);
-            P[(size_t)i * n + j] = v;
-            P[(size_t)j * n + i] = v;
+    double *P = c->hpinv;
+    std::fill(P, P + (size_t)n * n, 0.0);
+    const double shift = singular ? 1.0 / (s * na) : 0.0;
+    for (int a = 0; a < na; ++a) {
+        const double *ma = &Mt[(size_t)a * na];
+        for (int bb = 0; bb <= a; ++bb) {
+            const double *mb = &Mt[(size_t)bb * na];
+            double t = 0.0;
+            for (int kk = a; kk < na; ++kk)
+                t += ma[kk] * mb[kk];
+            const double v = shift - t;
+            P[(size_t)idx[a] * n + idx[bb]] = v;
+            P[(size_t)idx[bb] * n + idx[a]] = v;
         }
-    PP_HIP(hipMemcpyAsync(c->pinv, P.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, c->stream));
-    PP_HIP(hipStreamSynchronize(c->stream));
+    }
+    // no wait: hpinv is next written after a later read_scal, which waits for this copy
+    PP_HIP(hipMemcpyAsync(c->pinv, P, sizeof(double) * n * n, hipMemcpyHostToDevice, c->stream));
     return PP_OK;
 }
 
@@ -519,6 +536,7 @@ int load_coeffs_general(pp_ctx *c, const double *bx, const double *by, const dou
                                    " entries are not finite non-negative numbers");
     PP_TRY(fill_hier(c, c->hmix, 0));
     PP_TRY(fill_hier(c, c->h64, 0));
+    PP_TRY(enqueue_coarse_download(c));
     PP_TRY(read_scal(c));
     c->singular = !(c->sig_on && c->hscal[S_SPOS] > 0.0);
     c->nact = c->hscal[S_NACT];
@@ -594,6 +612,7 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
                             c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2], c->stream);
     PP_TRY(check_launch("coarsen coefficients"));
     PP_TRY(fill_hier(c, c->hmix, level0_converted ? 1 : 0));
+    PP_TRY(enqueue_coarse_download(c));
     PP_TRY(read_scal(c));
     const double nbad = c->hscal[S_COUNT] + (rho_count ? c->hscal[S_SBAD] : 0.0);
     if (nbad != 0.0) {
@@ -1134,6 +1153,10 @@ void pp_destroy(pp_ctx *c)
         (void)hipFree(p);
     if (c->hscal)
         (void)hipHostFree(c->hscal);
+    if (c->hcoarse)
+        (void)hipHostFree(c->hcoarse);
+    if (c->hpinv)
+        (void)hipHostFree(c->hpinv);
     delete c;
 }
 
@@ -1218,6 +1241,16 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
     if (hipHostMalloc((void **)&c->hscal, sizeof(double) * S_NSLOTS, hipHostMallocDefault) !=
         hipSuccess) {
         c->hscal = nullptr;
+        return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
+    }
+    if (hipHostMalloc((void **)&c->hcoarse, sizeof(double) * 4 * (size_t)c->ncoarse,
+                      hipHostMallocDefault) != hipSuccess) {
+        c->hcoarse = nullptr;
+        return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
+    }
+    if (hipHostMalloc((void **)&c->hpinv, sizeof(double) * (size_t)c->ncoarse * c->ncoarse,
+                      hipHostMallocDefault) != hipSuccess) {
+        c->hpinv = nullptr;
         return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
     }
     if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
