@@ -33,6 +33,7 @@ namespace {
 constexpr int MAXLEV = 24;
 constexpr int COARSEST_MAX = 1024;
 constexpr int STAGNATED = 1;   // internal code: outer loop stopped improving
+constexpr int CONVERGED = 2;   // internal code: the residual reached the tolerance
 
 thread_local std::string g_err;
 
@@ -120,6 +121,8 @@ struct pp_ctx {
     double *pinv;
     int ncoarse;
     double *hcoarse;             // pinned: the coarsest level's beta (3 arrays) and sigma, read back
+    double *hiter;               // pinned: the scalars of the last two outer iterations, read back
+    hipEvent_t iter_ev[2];       // their copies done
     double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
     double *r64, *d64, *d64b, *q64;
     double *part;
@@ -873,6 +876,13 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
     return PP_OK;
 }
 
+// The loop launches an iteration before knowing whether the previous one
+// converged only while the last residual exceeds the tolerance by this
+// factor times the square of the last measured reduction per iteration, so
+// that the next iteration is needed unless convergence suddenly speeds up
+// more than threefold (which then costs one extra iteration).
+constexpr double SPECULATE = 10.0;
+
 template <typename T>
 int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
 {
@@ -886,12 +896,13 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
     D *dold = (D *)c->d64, *dnew = (D *)c->d64b;
     int since = 0;
     double window = S.rel;
-    int rc = PP_OK;
-    for (;;) {
-        if (S.it >= c->opts.max_outer) {
-            rc = fail(PP_ENOCONV, "no convergence within max_outer iterations");
-            break;
-        }
+    // Iterations are launched ahead of the host's convergence test while the
+    // last known residual is far above the tolerance: the scalars of each
+    // iteration are copied to a pinned slot of their own, and the host folds
+    // them in one iteration late, so the GPU does not idle during the test.
+    int launched = 0, seen = 0;
+    double rate = 0.0;   // residual reduction of the last folded iteration (0: none yet)
+    auto launch_iteration = [&]() -> int {
         vcycle_run<T>(c, H);
         if (S.st)
             S.st->vcycles++;
@@ -914,23 +925,64 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         }
         std::swap(dold, dnew);
         launch_finalize(c->part, c->pstride, np, OP_UPDATE, 0, (double)c->N, 0, c->scal, s);
-        rc = check_launch("pcg iteration");
-        if (rc == PP_OK)
-            rc = read_scal(c);
-        if (rc != PP_OK)
-            return rc;
+        const int slot = launched & 1;
+        PP_HIP(hipMemcpyAsync(c->hiter + slot * S_NSLOTS, c->scal, sizeof(double) * S_NSLOTS,
+                              hipMemcpyDeviceToHost, s));
+        PP_HIP(hipEventRecord(c->iter_ev[slot], s));
+        ++launched;
+        return check_launch("pcg iteration");
+    };
+    // fold the oldest unseen iteration into S: CONVERGED, PP_OK (go on),
+    // STAGNATED or an error
+    auto process = [&]() -> int {
+        const int slot = seen & 1;
+        PP_HIP(hipEventSynchronize(c->iter_ev[slot]));
+        ++seen;
         S.it++;
-        S.rel = std::sqrt(c->hscal[S_RR]) / S.nb;
+        const double before = S.rel;
+        S.rel = std::sqrt(c->hiter[slot * S_NSLOTS + S_RR]) / S.nb;
+        rate = (S.rel > 0.0) ? std::max(1.0, before / S.rel) : INFINITY;
         record(S);
         if (S.rel <= tol)
+            return CONVERGED;
+        return check_progress(S, 8, since, window);
+    };
+    int rc = PP_OK;
+    for (;;) {
+        if (S.it + (launched - seen) >= c->opts.max_outer) {
+            rc = (seen < launched) ? process() : PP_OK;
+            rc = (rc == CONVERGED) ? PP_OK
+                                   : (rc == PP_OK ? fail(PP_ENOCONV,
+                                                         "no convergence within max_outer iterations")
+                                                  : rc);
             break;
-        rc = check_progress(S, 8, since, window);
+        }
+        rc = launch_iteration();
         if (rc != PP_OK)
-            break;
+            return rc;
+        if (launched - seen == 2) {
+            // the previous iteration: any stop it calls for waits for the one
+            // now in flight, whose update the iterate already carries
+            rc = process();
+            if (rc != PP_OK)
+                rc = process();
+            if (rc != PP_OK)
+                break;
+        }
+        if (launched - seen == 1) {
+            if (rate > 0.0 && S.rel > SPECULATE * rate * rate * tol &&
+                S.it + 1 < c->opts.max_outer)
+                continue;   // the iteration after this one is needed either way
+            rc = process();
+            if (rc != PP_OK)
+                break;
+        }
     }
+    if (rc == CONVERGED)
+        rc = PP_OK;
     // the last direction's update of the iterate (earlier ones were applied
     // by the direction passes that followed them)
-    if (!first) {
+    if (launched > 0) {
         launch_axpy_dir<D>(c->N, dold, x, c->scal, s);
         PP_TRY(check_launch("pcg final update"));
     }
@@ -1157,6 +1209,11 @@ void pp_destroy(pp_ctx *c)
         (void)hipHostFree(c->hcoarse);
     if (c->hpinv)
         (void)hipHostFree(c->hpinv);
+    if (c->hiter)
+        (void)hipHostFree(c->hiter);
+    for (hipEvent_t e : c->iter_ev)
+        if (e)
+            (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -1253,6 +1310,16 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
         c->hpinv = nullptr;
         return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
     }
+    if (hipHostMalloc((void **)&c->hiter, sizeof(double) * 2 * S_NSLOTS, hipHostMallocDefault) !=
+        hipSuccess) {
+        c->hiter = nullptr;
+        return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
+    }
+    for (int i = 0; i < 2; ++i)
+        if (hipEventCreateWithFlags(&c->iter_ev[i], hipEventDisableTiming) != hipSuccess) {
+            c->iter_ev[i] = nullptr;
+            return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
+        }
     if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
         return bail(fail(PP_EHIP, "hipMemsetAsync failed"));
     rc = gen ? load_coeffs_general(c, bx, by, bz, sg) : load_coeffs(c, bx, by, bz);
