@@ -323,7 +323,7 @@ def main():
         "config": {"workload": f"layer+200 droplets, rho 1000/1.2, {N}^3, periodic x,y walls z, "
                                f"tol {args.tol:g}", "cells": w.cells, "parallelism": "single GPU"},
         "dof_per_s": round(head["dof_per_s"], 1),
-        "modes": {m: {k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()
+        "modes": {m: {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r.items()
                       if k != "kernels"} for m, r in results.items()},
         "kernels": {m: r["kernels"] for m, r in results.items()},
         "roofline": roof,
