@@ -109,8 +109,19 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double (*sm)[BLO
         const size_t blin =
             blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            part[(size_t)q * pstride + blin] = (sm[q][0] + sm[q][1]) + (sm[q][2] + sm[q][3]);
+        for (int q = 0; q < NQ; ++q) {
+            // pairwise over the waves, in a fixed order
+            double t[BLOCK / 64];
+#pragma unroll
+            for (int w = 0; w < BLOCK / 64; ++w)
+                t[w] = sm[q][w];
+#pragma unroll
+            for (int w = BLOCK / 64; w > 1; w /= 2)
+#pragma unroll
+                for (int i = 0; i < w / 2; ++i)
+                    t[i] = t[2 * i] + t[2 * i + 1];
+            part[(size_t)q * pstride + blin] = t[0];
+        }
     }
 }
 
@@ -1114,31 +1125,53 @@ __global__ __launch_bounds__(BLOCK) void k_sum(Dims d, const double *__restrict_
     block_partials<1>(v, sm, part, 0);
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ part, size_t pstride,
-                                                   int nparts, int op, int slot, double ncells,
-                                                   int first, double *scal)
+// Fixed-order sum of the partials (each thread a strided run, then the
+// wave's lanes by butterfly shuffles, then the waves' sums in order), and the
+// scalar update of `op`.  One barrier: the kernel is launched once or more
+// per outer iteration and sits on the iteration's critical path.
+constexpr int FIN_THREADS = 1024;
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restrict__ part,
+                                                          size_t pstride, int nparts, int op,
+                                                          int slot, double ncells, int first,
+                                                          double *scal)
 {
-    __shared__ double sm[2][1024];
-    const int nq = (op == OP_INIT || op == OP_UPDATE) ? 2 : 1;
+    __shared__ double sm[2][FIN_THREADS / 64];
+    const bool two = op == OP_INIT || op == OP_UPDATE;
     const int t = threadIdx.x;
-    for (int q = 0; q < 2; ++q) {
-        double acc = 0.0;
-        if (q < nq)
-            for (int i = t; i < nparts; i += 1024)
-                acc += part[(size_t)q * pstride + i];
-        sm[q][t] = acc;
+    // four loads in flight per accumulation step (the sum order stays fixed)
+    double a0 = 0.0, a1 = 0.0;
+    int i = t;
+    for (; i + 3 * FIN_THREADS < nparts; i += 4 * FIN_THREADS) {
+        const double *p0 = part + i;
+        a0 += (p0[0] + p0[FIN_THREADS]) + (p0[2 * FIN_THREADS] + p0[3 * FIN_THREADS]);
+        if (two) {
+            const double *p1 = part + pstride + i;
+            a1 += (p1[0] + p1[FIN_THREADS]) + (p1[2 * FIN_THREADS] + p1[3 * FIN_THREADS]);
+        }
+    }
+    for (; i < nparts; i += FIN_THREADS) {
+        a0 += part[i];
+        if (two)
+            a1 += part[pstride + i];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+    }
+    if ((t & 63) == 0) {
+        sm[0][t >> 6] = a0;
+        sm[1][t >> 6] = a1;
     }
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) {
-            sm[0][t] += sm[0][t + w];
-            sm[1][t] += sm[1][t + w];
-        }
-        __syncthreads();
-    }
     if (t != 0)
         return;
-    const double s0 = sm[0][0], s1 = sm[1][0];
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int w = 0; w < FIN_THREADS / 64; ++w) {
+        s0 += sm[0][w];
+        s1 += sm[1][w];
+    }
     double rms;
     switch (op) {
     case OP_STORE:
@@ -1657,7 +1690,7 @@ void launch_sum(Dims d, const double *x, const unsigned char *act, double *part,
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
                      double ncells, int first, double *scal, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, part, pstride, nparts, op, slot,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, part, pstride, nparts, op, slot,
                        ncells, first, scal);
 }
 
