@@ -122,6 +122,8 @@ struct pp_ctx {
     int ncoarse;
     double *hcoarse;             // pinned: the coarsest level's beta (3 arrays) and sigma, read back
     double *hiter;               // pinned: the scalars of the last two outer iterations, read back
+    const double *dot_r;         // set by the outer loop: the fine-level pass that finishes the
+    int dot_np;                  // V-cycle also forms the partials of dot_r . z (dot_np of them)
     hipEvent_t iter_ev[2];       // their copies done
     double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
     double *r64, *d64, *d64b, *q64;
@@ -646,7 +648,7 @@ int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 // where the level allows it (the second pass of an odd nu is a single sweep).
 template <typename T>
 void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_colour,
-                   bool zero_first, hipStream_t s)
+                   bool zero_first, hipStream_t s, const double *dot_r = nullptr)
 {
     const double h2 = v.h * v.h;
     const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
@@ -657,8 +659,13 @@ void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_c
         bool two = false;
         if constexpr (!std::is_same<T, double>::value) {
             if (sw + 2 <= nu && fused2_fits(v.d)) {
-                launch_rbgs_fused2<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur,
-                                      (T *)out, (const T *)v.s, h2, first_colour, zero, s);
+                // the last pass may also form the outer loop's dot product
+                const bool last = sw + 2 == nu;
+                const int np = launch_rbgs_fused2<T>(
+                    v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
+                    (const T *)v.s, h2, first_colour, zero, s, last ? dot_r : nullptr, c->part);
+                if (last && np > 0)
+                    c->dot_np = np;
                 two = true;
             }
         }
@@ -711,7 +718,8 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
         launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
     }
     if (cells(v.d) > fused_min_cells<T>() && fused_plane_fits(v.d, sizeof(T))) {
-        v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_post, v.cur, 1, false, s);
+        v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_post, v.cur, 1, false, s,
+                                l == 0 ? c->dot_r : nullptr);
     } else {
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
             launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2, 1,
@@ -903,11 +911,21 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
     int launched = 0, seen = 0;
     double rate = 0.0;   // residual reduction of the last folded iteration (0: none yet)
     auto launch_iteration = [&]() -> int {
+        // r . z comes from the V-cycle's last fine-level pass where that pass
+        // can form it, else from its own kernel
+        c->dot_r = c->r64;
+        c->dot_np = 0;
         vcycle_run<T>(c, H);
+        c->dot_r = nullptr;
         if (S.st)
             S.st->vcycles++;
-        launch_dot_rz<T>(c->d, c->r64, (const T *)v0.cur, c->part, s);
-        launch_finalize(c->part, c->pstride, np, OP_RZ, 0, (double)c->N, first ? 1 : 0, c->scal, s);
+        int nrz = c->dot_np;
+        if (nrz == 0) {
+            launch_dot_rz<T>(c->d, c->r64, (const T *)v0.cur, c->part, s);
+            nrz = np;
+        }
+        launch_finalize(c->part, c->pstride, nrz, OP_RZ, 0, (double)c->N, first ? 1 : 0, c->scal,
+                        s);
         int npd;
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
@@ -1573,6 +1591,56 @@ int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *bx, const float *by
                               grid->h * grid->h, first_colour, zero_init != 0,
                               (hipStream_t)hip_stream);
     return check_launch("pp_k_smooth2_fused_f32");
+}
+
+int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *bx, const float *by,
+                               const float *bz, const float *r, const float *e_in, float *e_out,
+                               int32_t first_colour, const double *rdot, double *dot,
+                               void *hip_stream)
+{
+    if (!rdot || !dot)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: NULL array");
+    if (((uintptr_t)rdot | (uintptr_t)dot) & 15)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: arrays must be 16-byte aligned");
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!fused_plane_fits(to_dims(grid), sizeof(double)))
+        return fail(PP_EINVAL,
+                    "pp_k_smooth2_fused_dot_f32: an x-y plane of rdot must stay below 2^31 bytes");
+    // the checks of pp_k_smooth2_fused_f32, without launching anything yet
+    if (!bx || !by || !bz || !r || !e_in || !e_out)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: NULL array");
+    if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)r | (uintptr_t)e_in |
+         (uintptr_t)e_out) & 15)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: arrays must be 16-byte aligned");
+    if (e_in == e_out)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: e_in and e_out must not alias");
+    if (first_colour != 0 && first_colour != 1)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: first_colour must be 0 or 1");
+    if (grid->n[0] % 2)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: nx must be even");
+    for (int m = 0; m < 3; ++m)
+        if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
+            return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: periodic directions need an even "
+                                   "cell count");
+    const Dims d = to_dims(grid);
+    if (!fused2_fits(d))
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: every cell count must be >= 8");
+    // partial sums: at most one per workgroup (tiles x chunks of >= 8 planes)
+    const size_t nparts_max = (size_t)((d.nx + 63) / 64) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
+    double *part = nullptr;
+    PP_HIP(hipMalloc((void **)&part, sizeof(double) * nparts_max));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int np = launch_rbgs_fused2<float>(d, to_bc(grid), bx, by, bz, r, e_in, e_out, nullptr,
+                                             grid->h * grid->h, first_colour, false, s, rdot, part);
+    int rc = PP_OK;
+    if (np <= 0 || (size_t)np > nparts_max)
+        rc = fail(PP_EHIP, "pp_k_smooth2_fused_dot_f32: unexpected workgroup count");
+    else
+        launch_finalize(part, (size_t)np, np, OP_STORE, 0, 1.0, 0, dot, s);
+    const int rl = check_launch("pp_k_smooth2_fused_dot_f32");
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(part);
+    return rc != PP_OK ? rc : rl;
 }
 
 int pp_k_resid_restrict(const pp_grid *grid, const double *bx, const double *by, const double *bz,

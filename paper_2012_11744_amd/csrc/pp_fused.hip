@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "pp_device.h"
 #include "pp_internal.h"
@@ -481,7 +482,10 @@ struct GsLag {
     float hr;                       // h^2 r
 };
 
-template <typename T, bool ZERO, bool SIG>
+// DOT (FP32, regular pass): also the partial sums of r . e_out over each
+// workgroup's output cells, r an FP64 array of the fine grid (the outer
+// iteration's residual against the preconditioned one); part[workgroup].
+template <typename T, bool ZERO, bool SIG, bool DOT>
 __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T *__restrict__ bx,
                                                           const T *__restrict__ by,
                                                           const T *__restrict__ bz,
@@ -490,7 +494,9 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
                                                           T *__restrict__ eout,
                                                           const T *__restrict__ sg, float h2,
                                                           int c0, int kz, unsigned tx_tiles,
-                                                          unsigned ty_tiles)
+                                                          unsigned ty_tiles,
+                                                          const double *__restrict__ rdot,
+                                                          double *__restrict__ part)
 {
     using C = float;
     using T2 = typename Vec2<T>::type;
@@ -502,6 +508,7 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     constexpr int FPD = sizeof(T) == 4 ? 3 : 1;
     constexpr int FNB = FPD + 3;
     constexpr bool CT_SLOTS = FNB % 6 == 0;
+    static_assert(!DOT || (CT_SLOTS && !ZERO), "the dot product rides on FP32 regular passes");
     __shared__ C SE[2][GLR][GLW];     // e_in of planes k, k+1
     __shared__ C SX[2][GLR][GLW];     // beta_x of planes k, k+1
     __shared__ C SY[2][GLR][GLW];     // beta_y of planes k, k+1
@@ -625,6 +632,13 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     C r2_km1 = C(0), r2_km2 = C(0);
     C sxl = C(0), sxh = C(0), syl = C(0), syh = C(0);
     GsLag a1{}, a2{}, b1{}, b2{};
+    // DOT: r of the own pair for the planes k-2, k-1, k (slot (k - kb) mod 3),
+    // loaded three steps before phase D stores that plane
+    using D2 = double __attribute__((ext_vector_type(2)));
+    D2 rq[3] = {D2{0.0, 0.0}, D2{0.0, 0.0}, D2{0.0, 0.0}};
+    double dacc = 0.0;
+    const unsigned ostd = owned ? (unsigned)(((size_t)j * d.nx + x) * sizeof(double)) : OFF_NONE;
+    const unsigned pbytes_d = (unsigned)((size_t)d.nx * d.ny * sizeof(double));
 
     // LDS slots are counted from the first plane of the march, kb = k0 - 3:
     // plane k's inputs sit in slot (k - kb) mod 2, its phase-A values in slot
@@ -712,7 +726,21 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
                 st_pair<T>(
                     plane_rsrc(reinterpret_cast<const char *>(eout) + (size_t)kd * pbytes, pbytes),
                     ost, outv);
+                if (DOT)   // r is zero past the grid and for cells outside the tile
+                    dacc += rq[s3].x * static_cast<double>(outv.x) +
+                            rq[s3].y * static_cast<double>(outv.y);
             }
+        }
+        if (DOT) {
+            // r of plane k (an output plane of this chunk, else zeros), for phase D
+            // three steps on; the slot just read held plane k-3
+            const bool out = k >= k0 && k < k1;
+            rq[s3] = __builtin_bit_cast(
+                D2, __builtin_amdgcn_raw_buffer_load_b128(
+                        plane_rsrc(reinterpret_cast<const char *>(rdot) +
+                                       (size_t)(out ? k : 0) * pbytes_d,
+                                   out ? pbytes_d : 0u),
+                        ostd, 0, 0));
         }
         red_km2 = red_km1;
         red_km1 = red;
@@ -737,18 +765,36 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     __syncthreads();                  // the zero fill is complete
     publish(0, buf[1]);
     __syncthreads();
-    for (int k = kb;;) {
+    for (int k = kb, more = 1; more;) {
 #pragma unroll
         for (int u = 0; u < FNB; ++u) {
             step(k, u, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB],
                  buf[(u + FNB - 1) % FNB]);
-            if (++k > k1 + 2)
-                return;
+            if (++k > k1 + 2) {
+                more = 0;
+                break;
+            }
+        }
+    }
+    if (DOT) {
+        __shared__ double wsum[GTHREADS / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            dacc += __shfl_xor(dacc, o, 64);
+        if ((tid & 63) == 0)
+            wsum[tid >> 6] = dacc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < GTHREADS / 64; ++w)
+                t += wsum[w];
+            part[blockIdx.x + gridDim.x * blockIdx.y] = t;
         }
     }
 }
 
-template <typename T, bool ZERO, bool SIG>
+template <typename T, bool ZERO, bool SIG, bool DOT>
 static long long fused2_slots()
 {
     static long long cached[64] = {0};
@@ -758,7 +804,7 @@ static long long fused2_slots()
         dev = 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused2<T, ZERO, SIG>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused2<T, ZERO, SIG, DOT>,
                                                          GTHREADS, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
@@ -773,53 +819,69 @@ static long long fused2_slots()
 template <typename T>
 void prepare_fused2()
 {
-    (void)fused2_slots<T, true, false>();
-    (void)fused2_slots<T, false, false>();
-    (void)fused2_slots<T, true, true>();
-    (void)fused2_slots<T, false, true>();
+    (void)fused2_slots<T, true, false, false>();
+    (void)fused2_slots<T, false, false, false>();
+    (void)fused2_slots<T, true, true, false>();
+    (void)fused2_slots<T, false, true, false>();
+    if constexpr (std::is_same<T, float>::value)
+        (void)fused2_slots<T, false, false, true>();
 }
 
 template <typename T>
-void launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
-                        const T *ein, T *eout, const T *sg, double h2, int first_colour,
-                        bool zero, hipStream_t s)
+int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
+                       const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
+                       hipStream_t s, const double *rdot, double *part)
 {
     const unsigned tx = (d.nx + GTX - 1) / GTX, ty = (d.ny + GTY - 1) / GTY;
-    const long long slots =
-        sg ? (zero ? fused2_slots<T, true, true>() : fused2_slots<T, false, true>())
-           : (zero ? fused2_slots<T, true, false>() : fused2_slots<T, false, false>());
+    // the fused dot product: FP32 regular passes without a diagonal term
+    const bool dot = rdot && part && std::is_same<T, float>::value && !zero && !sg &&
+                     fused_plane_fits(d, sizeof(double));
+    long long slots;
+    if (dot)
+        slots = fused2_slots<T, false, false, std::is_same<T, float>::value>();
+    else
+        slots = sg ? (zero ? fused2_slots<T, true, true, false>()
+                           : fused2_slots<T, false, true, false>())
+                   : (zero ? fused2_slots<T, true, false, false>()
+                           : fused2_slots<T, false, false, false>());
     // the six planes a chunk marches beyond its own are recomputed: at least 8 per chunk
     int kz = fused_kz(d, tx * ty, slots);
     if (kz < 8)
         kz = (d.nz < 8) ? d.nz : 8;
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty, tz);
-#define PP_FUSED2_LAUNCH(Z, S)                                                                 \
-    hipLaunchKernelGGL((k_rbgs_fused2<T, Z, S>), grid, dim3(GTHREADS), 0, s, d, bc, bx, by, bz, \
-                       r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty)
+#define PP_FUSED2_LAUNCH(Z, S, D)                                                                \
+    hipLaunchKernelGGL((k_rbgs_fused2<T, Z, S, D>), grid, dim3(GTHREADS), 0, s, d, bc, bx, by,   \
+                       bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty, rdot, part)
+    if (dot) {
+        if constexpr (std::is_same<T, float>::value)
+            PP_FUSED2_LAUNCH(false, false, true);
+        return (int)(grid.x * grid.y);
+    }
     if (sg) {
         if (zero)
-            PP_FUSED2_LAUNCH(true, true);
+            PP_FUSED2_LAUNCH(true, true, false);
         else
-            PP_FUSED2_LAUNCH(false, true);
+            PP_FUSED2_LAUNCH(false, true, false);
     } else {
         if (zero)
-            PP_FUSED2_LAUNCH(true, false);
+            PP_FUSED2_LAUNCH(true, false, false);
         else
-            PP_FUSED2_LAUNCH(false, false);
+            PP_FUSED2_LAUNCH(false, false, false);
     }
 #undef PP_FUSED2_LAUNCH
+    return 0;
 }
 
 template void prepare_fused2<float>();
 template void prepare_fused2<_Float16>();
-template void launch_rbgs_fused2<float>(Dims, Bc, const float *, const float *, const float *,
-                                        const float *, const float *, float *, const float *,
-                                        double, int, bool, hipStream_t);
-template void launch_rbgs_fused2<_Float16>(Dims, Bc, const _Float16 *, const _Float16 *,
-                                           const _Float16 *, const _Float16 *, const _Float16 *,
-                                           _Float16 *, const _Float16 *, double, int, bool,
-                                           hipStream_t);
+template int launch_rbgs_fused2<float>(Dims, Bc, const float *, const float *, const float *,
+                                       const float *, const float *, float *, const float *, double,
+                                       int, bool, hipStream_t, const double *, double *);
+template int launch_rbgs_fused2<_Float16>(Dims, Bc, const _Float16 *, const _Float16 *,
+                                          const _Float16 *, const _Float16 *, const _Float16 *,
+                                          _Float16 *, const _Float16 *, double, int, bool,
+                                          hipStream_t, const double *, double *);
 
 #define PP_INSTANTIATE_FUSED(T)                                                                  \
     template void prepare_fused<T>();                                                           \
