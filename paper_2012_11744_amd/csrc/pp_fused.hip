@@ -65,10 +65,10 @@ struct FusedDepth {
 };
 
 // Inputs of one thread's pair at one plane, as loaded (storage precision).
-// eo / byo: e_in and beta_y of the row beyond a ring row (a copy of the own
-// row for the other threads).  Values a thread must treat as zero (inactive
-// thread, missing plane, wall faces of y and z) arrive as zero from the
-// buffer range check.
+// eo / byo: e_in and beta_y of the row beyond an outermost ring row (zero
+// for the other threads, which read no such row).  Values a thread must
+// treat as zero (inactive thread, missing plane, wall faces of y and z)
+// arrive as zero from the buffer range check.
 template <typename T>
 struct PairIn {
     using T2 = typename Vec2<T>::type;
@@ -206,13 +206,15 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
     const bool wxl = bc.x && x == 0;
     const int jo = dn_row ? jm : (up_row ? jp : j);
     const bool zo = up_row ? wyh : wyl;   // the y faces published in row lyo are walls
-    // byte offsets of the pair within a plane; OFF_NONE reads zero
+    const bool beyond = dn_row || up_row;   // only these threads read the row beyond
+    // byte offsets of the pair within a plane; OFF_NONE reads zero (and, for
+    // the row beyond, spares the other threads a load of their own row)
     const unsigned oc0 = (unsigned)(((size_t)j * d.nx + x) * sizeof(T));
     const unsigned oo0 = (unsigned)(((size_t)jo * d.nx + x) * sizeof(T));
     const unsigned oc = act ? oc0 : OFF_NONE;
-    const unsigned oo = act ? oo0 : OFF_NONE;
+    const unsigned oo = (act && beyond) ? oo0 : OFF_NONE;
     const unsigned ocy = (act && !wyl) ? oc0 : OFF_NONE;
-    const unsigned ooy = (act && !zo) ? oo0 : OFF_NONE;
+    const unsigned ooy = (act && beyond && !zo) ? oo0 : OFF_NONE;
     const unsigned ost = owned ? oc0 : OFF_NONE;
     const unsigned pbytes = (unsigned)((size_t)d.nx * d.ny * sizeof(T));
     const int lx = 2 * pl + 4;        // LDS column of the pair's first cell
@@ -263,15 +265,19 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
         if (!ZERO) {
             SE[slot][ly][lx] = C(v.e.x);
             SE[slot][ly][lx + 1] = C(v.e.y);
-            SE[slot][lyo][lx] = C(v.eo.x);
-            SE[slot][lyo][lx + 1] = C(v.eo.y);
         }
         SX[slot][ly][lx] = wxl ? C(0) : C(v.bx.x);
         SX[slot][ly][lx + 1] = C(v.bx.y);
         SY[slot][ly][lx] = C(v.by.x);
         SY[slot][ly][lx + 1] = C(v.by.y);
-        SY[slot][lyo][lx] = C(v.byo.x);
-        SY[slot][lyo][lx + 1] = C(v.byo.y);
+        if (beyond) {
+            if (!ZERO) {
+                SE[slot][lyo][lx] = C(v.eo.x);
+                SE[slot][lyo][lx + 1] = C(v.eo.y);
+            }
+            SY[slot][lyo][lx] = C(v.byo.x);
+            SY[slot][lyo][lx + 1] = C(v.byo.y);
+        }
     };
 
     // padding columns and rows read as zero
@@ -555,12 +561,13 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     const bool wxl = bc.x && x == 0;
     const int jo = dn_row ? jm : (up_row ? jp : j);
     const bool zo = up_row ? wyh : wyl;
+    const bool beyond = dn_row || up_row;   // only these threads read the row beyond
     const unsigned oc0 = (unsigned)(((size_t)j * d.nx + x) * sizeof(T));
     const unsigned oo0 = (unsigned)(((size_t)jo * d.nx + x) * sizeof(T));
     const unsigned oc = act ? oc0 : OFF_NONE;
-    const unsigned oo = act ? oo0 : OFF_NONE;
+    const unsigned oo = (act && beyond) ? oo0 : OFF_NONE;
     const unsigned ocy = (act && !wyl) ? oc0 : OFF_NONE;
-    const unsigned ooy = (act && !zo) ? oo0 : OFF_NONE;
+    const unsigned ooy = (act && beyond && !zo) ? oo0 : OFF_NONE;
     const unsigned ost = owned ? oc0 : OFF_NONE;
     const unsigned pbytes = (unsigned)((size_t)d.nx * d.ny * sizeof(T));
     const int lx = 2 * pl + 6;        // LDS column of the pair's first cell
@@ -604,15 +611,19 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
         if (!ZERO) {
             SE[slot][ly][lx] = C(v.e.x);
             SE[slot][ly][lx + 1] = C(v.e.y);
-            SE[slot][lyo][lx] = C(v.eo.x);
-            SE[slot][lyo][lx + 1] = C(v.eo.y);
         }
         SX[slot][ly][lx] = wxl ? C(0) : C(v.bx.x);
         SX[slot][ly][lx + 1] = C(v.bx.y);
         SY[slot][ly][lx] = C(v.by.x);
         SY[slot][ly][lx + 1] = C(v.by.y);
-        SY[slot][lyo][lx] = C(v.byo.x);
-        SY[slot][lyo][lx + 1] = C(v.byo.y);
+        if (beyond) {
+            if (!ZERO) {
+                SE[slot][lyo][lx] = C(v.eo.x);
+                SE[slot][lyo][lx + 1] = C(v.eo.y);
+            }
+            SY[slot][lyo][lx] = C(v.byo.x);
+            SY[slot][lyo][lx + 1] = C(v.byo.y);
+        }
     };
 
     for (int i = tid; i < 2 * GLR * GLW; i += GTHREADS) {
