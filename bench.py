@@ -257,10 +257,11 @@ def main():
                                       "GBps": byt / (avg * 1e-3) / 1e9}
         if n_oa:
             avg = ms_oa / n_oa
-            # new direction + operator: z (V-cycle word), D_old, 3 beta, x in;
-            # D_new, q, x out; the first iteration of each solve reads neither
-            # D_old nor x and writes no x
-            byt = (48 + word + 2 * dword - (dword + 16.0) / max(1, r["outer_iters"])) * w.cells
+            # new direction + operator: z (V-cycle word), D_old, rho (the step
+            # loads the coefficients from the densities, so the kernel forms
+            # beta from them), x in; D_new, q, x out; the first iteration of
+            # each solve reads neither D_old nor x and writes no x
+            byt = (32 + word + 2 * dword - (dword + 16.0) / max(1, r["outer_iters"])) * w.cells
             kern["outer_apply"] = {"launches": n_oa, "avg_ms": avg, "alg_bytes": byt,
                                    "GBps": byt / (avg * 1e-3) / 1e9}
         if n_ou:

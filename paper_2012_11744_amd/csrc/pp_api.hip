@@ -116,6 +116,12 @@ struct pp_ctx {
     double *sig[MAXLEV];
     unsigned char *act;
     double nact;
+    // the cell densities of the last pp_update_density (allocated by its first
+    // call); rho_ok while the fine coefficients are the ones formed from them,
+    // so the outer operator kernels may form them again instead of reading
+    // the three coefficient arrays
+    double *rho;
+    bool rho_ok;
     Hier hmix;                   // FP32 / FP16 hierarchy (mixed precision)
     Hier h64;                    // FP64 hierarchy (FP64 mode, and the mixed-mode fallback)
     double *pinv;
@@ -558,6 +564,9 @@ int load_coeffs_general(pp_ctx *c, const double *bx, const double *by, const dou
 // cell densities.
 int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
 {
+    c->rho_ok = false;
+    if (rho && !c->rho)
+        PP_TRY(dev_alloc_t(c, &c->rho, sizeof(double) * c->N));
     int first_coarse = 0;   // first level whose coefficients are still to be coarsened from
     bool level0_converted = false;
     const uintptr_t align = rho ? (uintptr_t)rho
@@ -573,7 +582,8 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
         auto one_pass = [&](auto *t) {
             using TT = std::remove_pointer_t<decltype(t)>;
             TT *tt[3] = {t, t ? (TT *)H.lev[0].b[1] : nullptr, t ? (TT *)H.lev[0].b[2] : nullptr};
-            return rho ? launch_load_density<TT>(c->d, c->bc, rho, dst, tt, crs, c->part, c->stream)
+            return rho ? launch_load_density<TT>(c->d, c->bc, rho, dst, tt, crs, c->rho, c->part,
+                                                 c->stream)
                        : launch_load_coeffs<TT>(c->d, c->bc, src, dst, tt, crs, c->part, c->stream);
         };
         if (H.present && H.st == ST_F32) {
@@ -593,6 +603,8 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
         if (rho) {
             launch_face_coeffs(c->d, c->bc, rho, c->chain[0][0], c->chain[0][1], c->chain[0][2],
                                c->stream);
+            PP_HIP(hipMemcpyAsync(c->rho, rho, sizeof(double) * c->N, hipMemcpyDeviceToDevice,
+                                  c->stream));
         } else {
             for (int m = 0; m < 3; ++m)
                 PP_HIP(hipMemcpyAsync(c->chain[0][m], src[m], sizeof(double) * c->N,
@@ -629,6 +641,7 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
                                    " non-wall faces are not finite positive numbers");
     }
     PP_TRY(build_pinv(c));
+    c->rho_ok = rho != nullptr;
     return PP_OK;
 }
 
@@ -869,13 +882,17 @@ int check_progress(SolveState &S, int since_best_limit, int &since, double &best
     return PP_OK;
 }
 
+// the densities the fine coefficients were formed from, or null: the outer
+// operator kernels then read the coefficient arrays
+const double *op_rho(const pp_ctx *c) { return (c->rho_ok && !c->gen) ? c->rho : nullptr; }
+
 // residual of the current iterate into r64 (+ RR, BB, scales); returns rel
 int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveState &S)
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
-    launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs, c->scal, x,
-                    zero_x, c->sig_on ? c->sig[0] : nullptr, c->gen ? c->act : nullptr, c->r64, ih2,
-                    c->part, c->pstride, c->stream);
+    launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], op_rho(c), rhs,
+                    c->scal, x, zero_x, c->sig_on ? c->sig[0] : nullptr, c->gen ? c->act : nullptr,
+                    c->r64, ih2, c->part, c->pstride, c->stream);
     launch_finalize(c->part, c->pstride, nparts(c), OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
     PP_TRY(check_launch("residual"));
     PP_TRY(read_scal(c));
@@ -930,7 +947,7 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
             npd = launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
-                                      (const T *)v0.cur, dold, dnew, c->q64, x,
+                                      op_rho(c), (const T *)v0.cur, dold, dnew, c->q64, x,
                                       c->sig_on ? c->sig[0] : nullptr, c->scal, first, ih2, c->part,
                                       s);
         }

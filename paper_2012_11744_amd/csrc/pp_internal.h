@@ -163,11 +163,11 @@ template <typename T>
 int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
                        T *const dstT[3], double *const coarse[3], double *part, hipStream_t s);
 // as launch_load_coeffs with beta computed from the cell densities (the
-// arithmetic of launch_face_coeffs); the partials also count cells whose
-// density is not a finite positive number
+// arithmetic of launch_face_coeffs), also copying the densities to rcopy; the
+// partials also count cells whose density is not a finite positive number
 template <typename T>
 int launch_load_density(Dims fd, Bc bc, const double *rho, double *const dst[3], T *const dstT[3],
-                        double *const coarse[3], double *part, hipStream_t s);
+                        double *const coarse[3], double *rcopy, double *part, hipStream_t s);
 void launch_check_rho(Dims d, const double *rho, double *part, hipStream_t s);
 void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s);
 // partials of the count of non-wall faces that are not finite positive
@@ -205,10 +205,11 @@ void launch_fill(double *x, size_t n, double v, hipStream_t s);
 void launch_sum(Dims d, const double *x, const unsigned char *act, double *part, hipStream_t s);
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
                      double ncells, int first, double *scal, hipStream_t s);
+// rho as for launch_dir_apply
 void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,
-                     const unsigned char *act, double *r64, double ih2, double *part,
-                     size_t pstride, hipStream_t s);
+                     const double *rho, const double *b, const double *scal, double *x,
+                     bool zero_x, const double *sg, const unsigned char *act, double *r64,
+                     double ih2, double *part, size_t pstride, hipStream_t s);
 template <typename T>
 void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                        const double *b, const double *scal, const double *x, const double *sg,
@@ -234,10 +235,12 @@ struct DirT<double> {
 };
 // returns the number of partial sums written (at most grid_blocks(red_grid(d)))
 template <typename T>
+// rho non-null: the link coefficients are formed from the cell densities
+// (the plain operator whose coefficients came from them), not read from bx..bz
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const T *z, const typename DirT<T>::type *dold, typename DirT<T>::type *dnew,
-                     double *q, double *x, const double *sg, const double *scal, bool first,
-                     double ih2, double *part, hipStream_t s);
+                     const double *rho, const T *z, const typename DirT<T>::type *dold,
+                     typename DirT<T>::type *dnew, double *q, double *x, const double *sg,
+                     const double *scal, bool first, double ih2, double *part, hipStream_t s);
 template <typename T>
 void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const T *zold,
                        const double *scal, double *part, size_t pstride, hipStream_t s);

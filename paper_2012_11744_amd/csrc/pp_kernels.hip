@@ -78,6 +78,21 @@ __device__ __forceinline__ Links<T> links(const Nb &n, const T *bx, const T *by,
     return L;
 }
 
+// the six link coefficients from the cell densities: beta = 2 / (rho_low +
+// rho_high), the expression the density load stores (0 across walls)
+__device__ __forceinline__ Links<double> links_rho(const Nb &n, const double *rho)
+{
+    Links<double> L;
+    const double rc = rho[n.c];
+    L.xl = n.wxl ? 0.0 : 2.0 / (rho[n.xm] + rc);
+    L.xh = n.wxh ? 0.0 : 2.0 / (rc + rho[n.xp]);
+    L.yl = n.wyl ? 0.0 : 2.0 / (rho[n.ym] + rc);
+    L.yh = n.wyh ? 0.0 : 2.0 / (rc + rho[n.yp]);
+    L.zl = n.wzl ? 0.0 : 2.0 / (rho[n.zm] + rc);
+    L.zh = n.wzh ? 0.0 : 2.0 / (rc + rho[n.zp]);
+    return L;
+}
+
 // h^2 (A x)_c
 template <typename T, typename X>
 __device__ __forceinline__ typename Acc<T>::type flux_sum(const Nb &n, const Links<T> &L, const X *x)
@@ -748,8 +763,10 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
 // k_load_coeffs with the face coefficients computed from the cell densities
 // on the way (beta = 2 / (rho_L + rho_R), the expression of k_face_coeffs, so
 // the bits are the same): each coarse cell's 8 children read rho at the
-// children and at their low x, y, z neighbours.  Partial: non-wall faces whose
-// beta is not a finite positive number plus cells whose rho is not.
+// children and at their low x, y, z neighbours, and copy it to rcopy, which
+// the outer operator kernels read in place of the three coefficient arrays.
+// Partial: non-wall faces whose beta is not a finite positive number plus
+// cells whose rho is not.
 template <typename T, bool WT>
 __global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const double *__restrict__ rho,
                                                         double *__restrict__ dx,
@@ -758,7 +775,8 @@ __global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const do
                                                         T *__restrict__ ty, T *__restrict__ tz,
                                                         double *__restrict__ hx,
                                                         double *__restrict__ hy,
-                                                        double *__restrict__ hz, double *part)
+                                                        double *__restrict__ hz,
+                                                        double *__restrict__ rcopy, double *part)
 {
     using D2 = double __attribute__((ext_vector_type(2)));
     using T2 = typename Vec2<T>::type;
@@ -803,6 +821,7 @@ __global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const do
                     *reinterpret_cast<D2 *>(dx + c) = bxv;
                     *reinterpret_cast<D2 *>(dy + c) = byv;
                     *reinterpret_cast<D2 *>(dz + c) = bzv;
+                    *reinterpret_cast<D2 *>(rcopy + c) = rc;
                     if (WT) {
                         *reinterpret_cast<T2 *>(tx + c) = T2{static_cast<T>(bxv.x), static_cast<T>(bxv.y)};
                         *reinterpret_cast<T2 *>(ty + c) = T2{static_cast<T>(byv.x), static_cast<T>(byv.y)};
@@ -1225,11 +1244,13 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restri
 }
 
 // r = (b - mean b) - A x; partials ||r||^2 and ||b - mean b||^2.
-// ZEROX: x is set to zero (cold start) and A x is skipped.
-template <bool ZEROX>
+// ZEROX: x is set to zero (cold start) and A x is skipped.  RHO: the link
+// coefficients are formed from the cell densities (as in k_dir_apply).
+template <bool ZEROX, bool RHO>
 __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double *__restrict__ bx,
                                                     const double *__restrict__ by,
                                                     const double *__restrict__ bz,
+                                                    const double *__restrict__ rho,
                                                     const double *__restrict__ b,
                                                     const double *__restrict__ scal, double *x,
                                                     const double *__restrict__ sg,
@@ -1252,7 +1273,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
             if (ZEROX) {
                 x[n.c] = 0.0;
             } else {
-                const Links<double> L = links(n, bx, by, bz);
+                const Links<double> L = RHO ? links_rho(n, rho) : links(n, bx, by, bz);
                 ax = ih2 * flux_sum(n, L, x);
                 if (sg)
                     ax -= sg[n.c] * x[n.c];
@@ -1349,15 +1370,22 @@ __global__ __launch_bounds__(BLOCK) void k_dot_rz(Dims d, const double *__restri
 //   q = A D_new,  partial D_new . q
 // and the true direction is s_k D_new.  D_new is rounded to its storage type
 // before q is formed, so q is the image of exactly the stored vector; it is
-// recomputed at the six neighbours from z and D_old by the same explicit fma
-// (so the same bits), which is why D_new and D_old are different buffers.
-// The iterate's update of the previous iteration is applied here, where
-// D_old is read anyway: x += a_{k-1} D_old with a_{k-1} = scal[S_ALPHA]
+// recomputed at the in-plane neighbours from z and D_old by the same explicit
+// fma (so the same bits), which is why D_new and D_old are different buffers.
+// Each thread walks a column of RZ planes and carries the column's values of
+// the planes below and above (D_new, and the low z-face coefficient) in
+// registers.  The iterate's update of the previous iteration is applied here,
+// where D_old is read anyway: x += a_{k-1} D_old with a_{k-1} = scal[S_ALPHA]
 // (this launch runs before the new coefficient is finalised).
-template <typename T, typename D, bool FIRST>
+// RHO: the link coefficients are formed from the cell densities,
+// beta = 2 / (rho_low + rho_high), the expression the density load stores, so
+// q has the same bits as with the stored coefficients while 8 bytes per cell
+// are read instead of 24.
+template <typename T, typename D, bool FIRST, bool RHO>
 __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double *__restrict__ bx,
                                                      const double *__restrict__ by,
                                                      const double *__restrict__ bz,
+                                                     const double *__restrict__ rho,
                                                      const T *__restrict__ z,
                                                      const D *__restrict__ dold,
                                                      D *__restrict__ dnew,
@@ -1379,22 +1407,64 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
             return static_cast<double>(
                 static_cast<D>(FIRST ? t : __builtin_fma(gamma, static_cast<double>(dold[c]), t)));
         };
-        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
-        for (int k = blockIdx.z * RZ; k < ke; ++k) {
-            const Nb n = neighbours(d, bc, i, j, k);
-            const Links<double> L = links(n, bx, by, bz);
-            const double dc = dv(n.c);
-            const double f = L.xh * (dv(n.xp) - dc) - L.xl * (dc - dv(n.xm)) +
-                             L.yh * (dv(n.yp) - dc) - L.yl * (dc - dv(n.ym)) +
-                             L.zh * (dv(n.zp) - dc) - L.zl * (dc - dv(n.zm));
+        const size_t sz = (size_t)d.nx * d.ny;
+        const size_t col = (size_t)j * d.nx + i;
+        // in-plane neighbour offsets (periodic wrap; wall links are masked below)
+        const ptrdiff_t oxm = (i == 0) ? d.nx - 1 : -1;
+        const ptrdiff_t oxp = (i == d.nx - 1) ? -(ptrdiff_t)(d.nx - 1) : 1;
+        const ptrdiff_t oym = (j == 0) ? (ptrdiff_t)(d.ny - 1) * d.nx : -(ptrdiff_t)d.nx;
+        const ptrdiff_t oyp = (j == d.ny - 1) ? -(ptrdiff_t)(d.ny - 1) * d.nx : (ptrdiff_t)d.nx;
+        const bool wxl = bc.x && i == 0, wxh = bc.x && i == d.nx - 1;
+        const bool wyl = bc.y && j == 0, wyh = bc.y && j == d.ny - 1;
+        const int k0 = blockIdx.z * RZ;
+        const int ke = min(d.nz, k0 + RZ);
+        const size_t cm0 = col + (size_t)(k0 == 0 ? d.nz - 1 : k0 - 1) * sz;
+        double dm = dv(cm0), dc = dv(col + (size_t)k0 * sz);
+        double rc = 0.0, zl;
+        if (RHO) {
+            rc = rho[col + (size_t)k0 * sz];
+            zl = 2.0 / (rho[cm0] + rc);
+        } else {
+            zl = bz[col + (size_t)k0 * sz];
+        }
+        for (int k = k0; k < ke; ++k) {
+            const size_t c = col + (size_t)k * sz;
+            const size_t cp = col + (size_t)(k == d.nz - 1 ? 0 : k + 1) * sz;
+            const double dp = dv(cp);
+            double lxl, lxh, lyl, lyh, lzh;
+            if (RHO) {
+                const double rp = rho[cp];
+                lxl = 2.0 / (rho[c + oxm] + rc);
+                lxh = 2.0 / (rc + rho[c + oxp]);
+                lyl = 2.0 / (rho[c + oym] + rc);
+                lyh = 2.0 / (rc + rho[c + oyp]);
+                lzh = 2.0 / (rc + rp);
+                rc = rp;
+            } else {
+                lxl = bx[c];
+                lxh = bx[c + oxp];
+                lyl = by[c];
+                lyh = by[c + oyp];
+                lzh = bz[cp];
+            }
+            const double Lxl = wxl ? 0.0 : lxl, Lxh = wxh ? 0.0 : lxh;
+            const double Lyl = wyl ? 0.0 : lyl, Lyh = wyh ? 0.0 : lyh;
+            const double Lzl = (bc.z && k == 0) ? 0.0 : zl;
+            const double Lzh = (bc.z && k == d.nz - 1) ? 0.0 : lzh;
+            const double f = Lxh * (dv(c + oxp) - dc) - Lxl * (dc - dv(c + oxm)) +
+                             Lyh * (dv(c + oyp) - dc) - Lyl * (dc - dv(c + oym)) +
+                             Lzh * (dp - dc) - Lzl * (dc - dm);
             double qq = ih2 * f;
             if (sg)
-                qq -= sg[n.c] * dc;
+                qq -= sg[c] * dc;
             if (!FIRST)
-                x[n.c] += aold * static_cast<double>(dold[n.c]);
-            dnew[n.c] = static_cast<D>(dc);
-            q[n.c] = qq;
+                x[c] += aold * static_cast<double>(dold[c]);
+            dnew[c] = static_cast<D>(dc);
+            q[c] = qq;
             v[0] += dc * qq;
+            zl = lzh;
+            dm = dc;
+            dc = dp;
         }
     }
     block_partials<1>(v, sm, part, 0);
@@ -1584,16 +1654,18 @@ int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const
 
 template <typename T>
 int launch_load_density(Dims fd, Bc bc, const double *rho, double *const dst[3], T *const dstT[3],
-                        double *const coarse[3], double *part, hipStream_t s)
+                        double *const coarse[3], double *rcopy, double *part, hipStream_t s)
 {
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     const dim3 g((cd.nx + BX - 1) / BX, (cd.ny + BY - 1) / BY, (cd.nz + RZ / 2 - 1) / (RZ / 2));
     if (dstT[0])
         hipLaunchKernelGGL((k_load_density<T, true>), g, kBlock, 0, s, fd, bc, rho, dst[0], dst[1],
-                           dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2], part);
+                           dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2],
+                           rcopy, part);
     else
         hipLaunchKernelGGL((k_load_density<T, false>), g, kBlock, 0, s, fd, bc, rho, dst[0], dst[1],
-                           dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2], part);
+                           dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2],
+                           rcopy, part);
     return (int)grid_blocks(g);
 }
 
@@ -1695,16 +1767,20 @@ void launch_finalize(const double *part, size_t pstride, int nparts, int op, int
 }
 
 void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,
-                     const unsigned char *act, double *r64, double ih2, double *part,
-                     size_t pstride, hipStream_t s)
+                     const double *rho, const double *b, const double *scal, double *x,
+                     bool zero_x, const double *sg, const unsigned char *act, double *r64,
+                     double ih2, double *part, size_t pstride, hipStream_t s)
 {
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, rho, b, scal, x, sg,
+                           act, r64, ih2, part, pstride);
+    };
     if (zero_x)
-        hipLaunchKernelGGL(k_residual<true>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal,
-                           x, sg, act, r64, ih2, part, pstride);
+        go(k_residual<true, false>);
+    else if (rho)
+        go(k_residual<false, true>);
     else
-        hipLaunchKernelGGL(k_residual<false>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b,
-                           scal, x, sg, act, r64, ih2, part, pstride);
+        go(k_residual<false, false>);
 }
 
 template <typename T>
@@ -1737,17 +1813,19 @@ void launch_dot_rz(Dims d, const double *r, const T *z, double *part, hipStream_
 
 template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const T *z, const typename DirT<T>::type *dold, typename DirT<T>::type *dnew,
-                     double *q, double *x, const double *sg, const double *scal, bool first,
-                     double ih2, double *part, hipStream_t s)
+                     const double *rho, const T *z, const typename DirT<T>::type *dold,
+                     typename DirT<T>::type *dnew, double *q, double *x, const double *sg,
+                     const double *scal, bool first, double ih2, double *part, hipStream_t s)
 {
     using D = typename DirT<T>::type;
-    if (first)
-        hipLaunchKernelGGL((k_dir_apply<T, D, true>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz,
-                           z, dold, dnew, q, x, sg, scal, ih2, part);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, rho, z, dold, dnew,
+                           q, x, sg, scal, ih2, part);
+    };
+    if (rho)
+        first ? go(k_dir_apply<T, D, true, true>) : go(k_dir_apply<T, D, false, true>);
     else
-        hipLaunchKernelGGL((k_dir_apply<T, D, false>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz,
-                           z, dold, dnew, q, x, sg, scal, ih2, part);
+        first ? go(k_dir_apply<T, D, true, false>) : go(k_dir_apply<T, D, false, false>);
     return (int)grid_blocks(red_grid(d));
 }
 
@@ -1784,7 +1862,7 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
     template int launch_load_coeffs<T>(Dims, Bc, const double *const[3], double *const[3],      \
                                        T *const[3], double *const[3], double *, hipStream_t);   \
     template int launch_load_density<T>(Dims, Bc, const double *, double *const[3], T *const[3], \
-                                        double *const[3], double *, hipStream_t);               \
+                                        double *const[3], double *, double *, hipStream_t);     \
     template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
     template void launch_tail<T>(int, const Dims *, const double *, const void *const (*)[3],   \
                                  void *const *, void *const *, const void *const *, Bc, int,    \
@@ -1801,7 +1879,8 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
     template void launch_axpy_T<T>(size_t, const T *, double *, const double *, hipStream_t);   \
     template void launch_dot_rz<T>(Dims, const double *, const T *, double *, hipStream_t);     \
     template int launch_dir_apply<T>(Dims, Bc, const double *, const double *, const double *,  \
-                                      const T *, const typename DirT<T>::type *,                \
+                                      const double *, const T *,                                \
+                                      const typename DirT<T>::type *,                           \
                                       typename DirT<T>::type *, double *, double *,             \
                                       const double *, const double *, bool, double, double *,   \
                                       hipStream_t);                                             \

@@ -7,7 +7,12 @@ path must load the same coefficients bit for bit: the tests compare whole
 solves and projections with those of pp_face_coeffs + pp_update_coeffs
 bitwise, on the one-pass kernel (aligned rho, several levels) and on the
 fallback path (a single-level grid; a misaligned rho), and check that bad
-densities are rejected.
+densities are rejected.  After a density update the outer operator kernels
+(search direction image, residual) form beta from a copy of rho instead of
+reading the three coefficient arrays; the bitwise comparisons cover them, and
+further tests check that the copy is the library's own (the caller may
+overwrite rho), that a later coefficient update stops its use, that z
+chunks which do not divide the grid wrap correctly, and the adjoint.
 """
 import sys
 
@@ -131,3 +136,73 @@ def test_density_update_refused_for_general_context(S):
     with S.Solver(beta, w.h, w.bc, general=True) as sol:
         with pytest.raises((L.PPError, ValueError)):
             sol.update_density(dev(w.rho))
+
+
+@pytest.mark.parametrize("n,bc", [((36, 28, 20), (0, 0, 0)), ((40, 24, 28), (0, 1, 1)),
+                                  ((10, 10, 9), (0, 1, 0))])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_density_update_partial_z_chunks(S, n, bc, precision):
+    """nz not a multiple of the 8-plane column walk of the outer kernels, with
+    periodic z (the carried plane below wraps) and walls; nz = 9 takes the
+    fallback load (one level) and its copy of rho."""
+    w = W.random_case(n, bc, seed=133, ratio=500.0)
+    _say(f"density update partial z chunks n={n} bc={bc} {precision}")
+    (p1, u1, i1), (p2, u2, i2) = _two_ways(S, w, precision, dev(w.rho))
+    assert i1 == i2
+    assert np.array_equal(p1, p2)
+    for a, b in zip(u1, u2):
+        assert np.array_equal(a, b)
+
+
+def test_density_copy_is_owned_and_dropped_by_coefficient_update(S):
+    """The library keeps its own copy of rho: overwriting the caller's tensor
+    after the update changes nothing.  A later pp_update_coeffs makes the
+    stored coefficients the operator again (the copy of rho is stale)."""
+    w = W.config3(32)
+    us = [dev(u) for u in w.us]
+    beta_a = S.face_coeffs(dev(w.rho), w.h, w.bc)
+    rho_b = np.where(w.rho > 500.0, 2.0, 700.0)
+    beta_b = S.face_coeffs(dev(rho_b), w.h, w.bc)
+
+    def solve_with(setup):
+        with S.Solver(beta_a, w.h, w.bc, precision="fp32") as sol:
+            setup(sol)
+            b = sol.divergence(us, 1.0 / w.dt)
+            return host(sol.solve(b, tol=1e-10)).copy()
+
+    p_a = solve_with(lambda sol: sol.update_coeffs(beta_a))
+    p_b = solve_with(lambda sol: sol.update_coeffs(beta_b))
+
+    def overwrite(sol):
+        r = dev(w.rho)
+        sol.update_density(r)
+        r.fill_(5.0)
+        torch.cuda.synchronize()
+
+    assert np.array_equal(solve_with(overwrite), p_a)
+    assert np.array_equal(
+        solve_with(lambda sol: (sol.update_density(dev(w.rho)), sol.update_coeffs(beta_b))), p_b)
+    assert np.array_equal(
+        solve_with(lambda sol: (sol.update_coeffs(beta_b), sol.update_density(dev(w.rho)))), p_a)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_density_update_adjoint_bitwise(S, precision):
+    """The adjoint solve runs the same outer kernels: g_rhs and g_beta agree
+    bit for bit between the two ways of loading the coefficients."""
+    w = W.random_case((40, 24, 32), (1, 0, 1), seed=134, ratio=1000.0)
+    us = [dev(u) for u in w.us]
+    g = dev(np.random.default_rng(135).standard_normal(w.shape))
+    beta0 = S.face_coeffs(dev(np.full(w.shape, 3.0)), w.h, w.bc)
+    outs = []
+    for mode in ("beta", "rho"):
+        with S.Solver(beta0, w.h, w.bc, precision=precision) as sol:
+            if mode == "beta":
+                sol.update_coeffs(S.face_coeffs(dev(w.rho), w.h, w.bc))
+            else:
+                sol.update_density(dev(w.rho))
+            p = sol.solve(sol.divergence(us, 1.0 / w.dt), tol=1e-10)
+            g_rhs, g_b = sol.adjoint(p, g, tol=1e-10)
+            outs.append([host(g_rhs).copy()] + [host(t).copy() for t in g_b])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
