@@ -65,17 +65,18 @@ int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *beta_x, const float
                            int32_t first_colour, int32_t zero_init, void *hip_stream);
 
 /* pp_k_smooth2_fused_f32 (regular pass: e_in is read) that also forms
- * *dot = sum over all cells of rdot[c] * e_out[c], the product the FP32
- * V-cycle's last fine-level pass hands to the outer conjugate-gradient
- * iteration.  rdot: FP64 cell array, read only; dot: one FP64 device value.
- * Both 16-byte aligned; an x-y plane of rdot must stay below 2^31 bytes.
- * e_out is the same as from pp_k_smooth2_fused_f32, bit for bit; the sum is
- * formed in FP64 from per-workgroup partials in a fixed order.  Allocates
- * its partial-sum scratch and waits for the stream (a component-test entry). */
+ * *dot = sum over all cells of r[c] * e_out[c], with r the pass's own
+ * right-hand side: the product (in units of the V-cycle's scale) that the
+ * FP32 V-cycle's last fine-level pass hands to the outer conjugate-gradient
+ * iteration.  dot: one FP64 device value, 8-byte aligned.  e_out is the same
+ * as from pp_k_smooth2_fused_f32, bit for bit; each product r[c] e_out[c] is
+ * formed in FP64 from the h^2 r[c] the sweep carries (FP32), the sum in FP64
+ * from per-workgroup partials in a fixed order.  Allocates its partial-sum
+ * scratch and waits for the stream (a component-test entry). */
 int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *beta_x, const float *beta_y,
                                const float *beta_z, const float *r, const float *e_in,
-                               float *e_out, int32_t first_colour, const double *rdot,
-                               double *dot, void *hip_stream);
+                               float *e_out, int32_t first_colour, double *dot,
+                               void *hip_stream);
 
 /* rH[C] = (1/8) sum over the 8 fine cells c of C of (r - A e)[c].
  * grid: the fine grid (all n even); rH has n/2 cells per direction; beta,

@@ -113,7 +113,7 @@ def load():
         "pp_k_smooth": (I, [GP, P, P, P, P, P, I32, I32, P]),
         "pp_k_smooth_fused": (I, [GP, P, P, P, P, P, P, I32, I32, P]),
         "pp_k_smooth2_fused_f32": (I, [GP, P, P, P, P, P, P, I32, I32, P]),
-        "pp_k_smooth2_fused_dot_f32": (I, [GP, P, P, P, P, P, P, I32, P, P, P]),
+        "pp_k_smooth2_fused_dot_f32": (I, [GP, P, P, P, P, P, P, I32, P, P]),
         "pp_k_resid_restrict": (I, [GP, P, P, P, P, P, P, P]),
         "pp_k_prolong_add": (I, [GP, P, P, P]),
         "pp_k_coarsen_beta": (I, [GP, P, P, P, P, P, P, P]),

@@ -128,8 +128,9 @@ struct pp_ctx {
     int ncoarse;
     double *hcoarse;             // pinned: the coarsest level's beta (3 arrays) and sigma, read back
     double *hiter;               // pinned: the scalars of the last two outer iterations, read back
-    const double *dot_r;         // set by the outer loop: the fine-level pass that finishes the
-    int dot_np;                  // V-cycle also forms the partials of dot_r . z (dot_np of them)
+    bool dot_on;                 // set by the outer loop: the fine-level pass that finishes the
+    int dot_np;                  // V-cycle also forms the partials of r . z (dot_np of them,
+                                 // r the V-cycle's scaled right-hand side)
     hipEvent_t iter_ev[2];       // their copies done
     double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
     double *r64, *d64, *d64b, *q64;
@@ -661,7 +662,7 @@ int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
 // where the level allows it (the second pass of an odd nu is a single sweep).
 template <typename T>
 void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_colour,
-                   bool zero_first, hipStream_t s, const double *dot_r = nullptr)
+                   bool zero_first, hipStream_t s, bool dot = false)
 {
     const double h2 = v.h * v.h;
     const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
@@ -676,7 +677,7 @@ void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_c
                 const bool last = sw + 2 == nu;
                 const int np = launch_rbgs_fused2<T>(
                     v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
-                    (const T *)v.s, h2, first_colour, zero, s, last ? dot_r : nullptr, c->part);
+                    (const T *)v.s, h2, first_colour, zero, s, (last && dot) ? c->part : nullptr);
                 if (last && np > 0)
                     c->dot_np = np;
                 two = true;
@@ -732,7 +733,7 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
     }
     if (cells(v.d) > fused_min_cells<T>() && fused_plane_fits(v.d, sizeof(T))) {
         v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_post, v.cur, 1, false, s,
-                                l == 0 ? c->dot_r : nullptr);
+                                l == 0 && c->dot_on);
     } else {
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
             launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2, 1,
@@ -930,19 +931,19 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
     auto launch_iteration = [&]() -> int {
         // r . z comes from the V-cycle's last fine-level pass where that pass
         // can form it, else from its own kernel
-        c->dot_r = c->r64;
+        c->dot_on = true;
         c->dot_np = 0;
         vcycle_run<T>(c, H);
-        c->dot_r = nullptr;
+        c->dot_on = false;
         if (S.st)
             S.st->vcycles++;
-        int nrz = c->dot_np;
+        int nrz = c->dot_np, op = OP_RZ_T;
         if (nrz == 0) {
             launch_dot_rz<T>(c->d, c->r64, (const T *)v0.cur, c->part, s);
             nrz = np;
+            op = OP_RZ;
         }
-        launch_finalize(c->part, c->pstride, nrz, OP_RZ, 0, (double)c->N, first ? 1 : 0, c->scal,
-                        s);
+        launch_finalize(c->part, c->pstride, nrz, op, 0, (double)c->N, first ? 1 : 0, c->scal, s);
         int npd;
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
@@ -1612,17 +1613,16 @@ int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *bx, const float *by
 
 int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *bx, const float *by,
                                const float *bz, const float *r, const float *e_in, float *e_out,
-                               int32_t first_colour, const double *rdot, double *dot,
-                               void *hip_stream)
+                               int32_t first_colour, double *dot, void *hip_stream)
 {
-    if (!rdot || !dot)
+    if (!dot)
         return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: NULL array");
-    if (((uintptr_t)rdot | (uintptr_t)dot) & 15)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: arrays must be 16-byte aligned");
+    if ((uintptr_t)dot & 7)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: dot must be 8-byte aligned");
     PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
-    if (!fused_plane_fits(to_dims(grid), sizeof(double)))
+    if (!fused_plane_fits(to_dims(grid), sizeof(float)))
         return fail(PP_EINVAL,
-                    "pp_k_smooth2_fused_dot_f32: an x-y plane of rdot must stay below 2^31 bytes");
+                    "pp_k_smooth2_fused_dot_f32: an x-y plane must stay below 2^31 bytes");
     // the checks of pp_k_smooth2_fused_f32, without launching anything yet
     if (!bx || !by || !bz || !r || !e_in || !e_out)
         return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: NULL array");
@@ -1648,7 +1648,7 @@ int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *bx, const float
     PP_HIP(hipMalloc((void **)&part, sizeof(double) * nparts_max));
     hipStream_t s = (hipStream_t)hip_stream;
     const int np = launch_rbgs_fused2<float>(d, to_bc(grid), bx, by, bz, r, e_in, e_out, nullptr,
-                                             grid->h * grid->h, first_colour, false, s, rdot, part);
+                                             grid->h * grid->h, first_colour, false, s, part);
     int rc = PP_OK;
     if (np <= 0 || (size_t)np > nparts_max)
         rc = fail(PP_EHIP, "pp_k_smooth2_fused_dot_f32: unexpected workgroup count");

@@ -489,8 +489,10 @@ struct GsLag {
 };
 
 // DOT (FP32, regular pass): also the partial sums of r . e_out over each
-// workgroup's output cells, r an FP64 array of the fine grid (the outer
-// iteration's residual against the preconditioned one); part[workgroup].
+// workgroup's output cells, r the pass's own right-hand side, products summed
+// in FP64 (the outer iteration's residual against the preconditioned one,
+// both in units of the V-cycle's scale); part[workgroup].  The h^2 r values
+// that phases C and D already carry supply r, so nothing more is loaded.
 template <typename T, bool ZERO, bool SIG, bool DOT>
 __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T *__restrict__ bx,
                                                           const T *__restrict__ by,
@@ -501,7 +503,6 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
                                                           const T *__restrict__ sg, float h2,
                                                           int c0, int kz, unsigned tx_tiles,
                                                           unsigned ty_tiles,
-                                                          const double *__restrict__ rdot,
                                                           double *__restrict__ part)
 {
     using C = float;
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     constexpr int FPD = sizeof(T) == 4 ? 3 : 1;
     constexpr int FNB = FPD + 3;
     constexpr bool CT_SLOTS = FNB % 6 == 0;
-    static_assert(!DOT || (CT_SLOTS && !ZERO), "the dot product rides on FP32 regular passes");
+    static_assert(!DOT || (!ZERO && !SIG), "the dot product rides on regular passes");
     __shared__ C SE[2][GLR][GLW];     // e_in of planes k, k+1
     __shared__ C SX[2][GLR][GLW];     // beta_x of planes k, k+1
     __shared__ C SY[2][GLR][GLW];     // beta_y of planes k, k+1
@@ -643,13 +644,10 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     C r2_km1 = C(0), r2_km2 = C(0);
     C sxl = C(0), sxh = C(0), syl = C(0), syh = C(0);
     GsLag a1{}, a2{}, b1{}, b2{};
-    // DOT: r of the own pair for the planes k-2, k-1, k (slot (k - kb) mod 3),
-    // loaded three steps before phase D stores that plane
-    using D2 = double __attribute__((ext_vector_type(2)));
-    D2 rq[3] = {D2{0.0, 0.0}, D2{0.0, 0.0}, D2{0.0, 0.0}};
+    // DOT: h^2 r of C's cell of the previous step (the first-colour cell of
+    // the plane phase D completes), and the sum of h^2 r e_out
+    C hrc = C(0);
     double dacc = 0.0;
-    const unsigned ostd = owned ? (unsigned)(((size_t)j * d.nx + x) * sizeof(double)) : OFF_NONE;
-    const unsigned pbytes_d = (unsigned)((size_t)d.nx * d.ny * sizeof(double));
 
     // LDS slots are counted from the first plane of the march, kb = k0 - 3:
     // plane k's inputs sit in slot (k - kb) mod 2, its phase-A values in slot
@@ -737,21 +735,10 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
                 st_pair<T>(
                     plane_rsrc(reinterpret_cast<const char *>(eout) + (size_t)kd * pbytes, pbytes),
                     ost, outv);
-                if (DOT)   // r is zero past the grid and for cells outside the tile
-                    dacc += rq[s3].x * static_cast<double>(outv.x) +
-                            rq[s3].y * static_cast<double>(outv.y);
+                if (DOT && owned)
+                    dacc += static_cast<double>(hrc) * static_cast<double>(r2_km1) +
+                            static_cast<double>(b2.hr) * static_cast<double>(blk2);
             }
-        }
-        if (DOT) {
-            // r of plane k (an output plane of this chunk, else zeros), for phase D
-            // three steps on; the slot just read held plane k-3
-            const bool out = k >= k0 && k < k1;
-            rq[s3] = __builtin_bit_cast(
-                D2, __builtin_amdgcn_raw_buffer_load_b128(
-                        plane_rsrc(reinterpret_cast<const char *>(rdot) +
-                                       (size_t)(out ? k : 0) * pbytes_d,
-                                   out ? pbytes_d : 0u),
-                        ostd, 0, 0));
         }
         red_km2 = red_km1;
         red_km1 = red;
@@ -759,6 +746,8 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
         blk_km1 = blk;
         r2_km2 = r2_km1;
         r2_km1 = red2;
+        if (DOT)
+            hrc = a2.hr;
         a2 = a1;
         a1 = GsLag{xl, xh, yl, yh, zl, zh, inva, hra};
         b2 = b1;
@@ -800,7 +789,7 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
 #pragma unroll
             for (int w = 0; w < GTHREADS / 64; ++w)
                 t += wsum[w];
-            part[blockIdx.x + gridDim.x * blockIdx.y] = t;
+            part[blockIdx.x + gridDim.x * blockIdx.y] = t / static_cast<double>(h2);
         }
     }
 }
@@ -841,12 +830,11 @@ void prepare_fused2()
 template <typename T>
 int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
                        const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
-                       hipStream_t s, const double *rdot, double *part)
+                       hipStream_t s, double *part)
 {
     const unsigned tx = (d.nx + GTX - 1) / GTX, ty = (d.ny + GTY - 1) / GTY;
     // the fused dot product: FP32 regular passes without a diagonal term
-    const bool dot = rdot && part && std::is_same<T, float>::value && !zero && !sg &&
-                     fused_plane_fits(d, sizeof(double));
+    const bool dot = part && std::is_same<T, float>::value && !zero && !sg;
     long long slots;
     if (dot)
         slots = fused2_slots<T, false, false, std::is_same<T, float>::value>();
@@ -863,7 +851,7 @@ int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
     const dim3 grid(tx * ty, tz);
 #define PP_FUSED2_LAUNCH(Z, S, D)                                                                \
     hipLaunchKernelGGL((k_rbgs_fused2<T, Z, S, D>), grid, dim3(GTHREADS), 0, s, d, bc, bx, by,   \
-                       bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty, rdot, part)
+                       bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty, part)
     if (dot) {
         if constexpr (std::is_same<T, float>::value)
             PP_FUSED2_LAUNCH(false, false, true);
@@ -888,11 +876,11 @@ template void prepare_fused2<float>();
 template void prepare_fused2<_Float16>();
 template int launch_rbgs_fused2<float>(Dims, Bc, const float *, const float *, const float *,
                                        const float *, const float *, float *, const float *, double,
-                                       int, bool, hipStream_t, const double *, double *);
+                                       int, bool, hipStream_t, double *);
 template int launch_rbgs_fused2<_Float16>(Dims, Bc, const _Float16 *, const _Float16 *,
                                           const _Float16 *, const _Float16 *, const _Float16 *,
                                           _Float16 *, const _Float16 *, double, int, bool,
-                                          hipStream_t, const double *, double *);
+                                          hipStream_t, double *);
 
 #define PP_INSTANTIATE_FUSED(T)                                                                  \
     template void prepare_fused<T>();                                                           \

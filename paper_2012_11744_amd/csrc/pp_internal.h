@@ -96,7 +96,8 @@ enum FinalizeOp {
     OP_RZ = 3,      // RZ, BETA (flexible Polak-Ribiere)
     OP_ALPHA = 4,   // ALPHA = RZ / DQ
     OP_UPDATE = 5,  // RR, RZOLD, rotate scales
-    OP_DC = 6       // RR, rotate scales
+    OP_DC = 6,      // RR, rotate scales
+    OP_RZ_T = 7     // as OP_RZ, the partials formed with the V-cycle's scaled right-hand side
 };
 
 // ---------------------------------------------------------------------------
@@ -123,13 +124,13 @@ void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
 // eout distinct; needs nz >= 8 (the chunks read four planes beyond their ends).
 template <typename T>
 void prepare_fused2();
-// With rdot and part given, an FP32 regular pass without sigma also writes the
-// partial sums of rdot . e_out (rdot: FP64 cell array), one per workgroup, and
-// returns their number; otherwise returns 0.
+// With part given, an FP32 regular pass without sigma also writes the partial
+// sums of r . e_out (its own right-hand side against its output, products in
+// FP64), one per workgroup, and returns their number; otherwise returns 0.
 template <typename T>
 int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
                        const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
-                       hipStream_t s, const double *rdot = nullptr, double *part = nullptr);
+                       hipStream_t s, double *part = nullptr);
 inline bool fused2_fits(Dims d) { return d.nz >= 8 && d.nx >= 8 && d.ny >= 8; }
 template <typename T>
 void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,

@@ -1208,11 +1208,13 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restri
         scal[S_USED] = rms;
         scal[S_NEXT] = rms;
         break;
-    case OP_RZ: {
+    case OP_RZ:
+    case OP_RZ_T: {
         // flexible CG: beta = (r_k . z_k - r_k . z_{k-1}) / (r_{k-1} . z_{k-1});
         // the stored direction is in units of the V-cycle scale, so its
-        // recurrence coefficient is beta s_{k-1} / s_k
-        const double rz = scal[S_USED] * s0;
+        // recurrence coefficient is beta s_{k-1} / s_k.  OP_RZ_T: the partials
+        // are of r / s_k, the right-hand side the V-cycle was given
+        const double rz = (op == OP_RZ_T ? scal[S_USED] * scal[S_USED] : scal[S_USED]) * s0;
         scal[S_BETA] =
             first ? 0.0 : (rz - scal[S_RZOLD]) / scal[S_RZ] * (scal[S_DS] / scal[S_USED]);
         scal[S_RZ] = rz;

@@ -319,19 +319,18 @@ def k_smooth2_fused_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero
     return e_out
 
 
-def k_smooth2_fused_dot_f32(shape, h, bc, beta, r, e_in, e_out, rdot, first_colour=0):
-    """k_smooth2_fused_f32 that also returns sum(rdot * e_out) (rdot float64)."""
+def k_smooth2_fused_dot_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0):
+    """k_smooth2_fused_f32 that also returns sum(r * e_out), r the pass's own
+    right-hand side (products and sum in FP64)."""
     lib = L.load()
     g = make_grid(shape, h, bc)
     for t in (*beta, r, e_in, e_out):
         if t.dtype != torch.float32:
             raise TypeError("k_smooth2_fused_dot_f32 takes float32 fields")
-    if rdot.dtype != torch.float64:
-        raise TypeError("rdot must be float64")
-    dot = torch.empty(2, dtype=torch.float64, device=rdot.device)
+    dot = torch.empty(1, dtype=torch.float64, device=r.device)
     L.check(lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r),
-                                           _ptr(e_in), _ptr(e_out), int(first_colour), _ptr(rdot),
-                                           _ptr(dot), _stream_handle(None)),
+                                           _ptr(e_in), _ptr(e_out), int(first_colour), _ptr(dot),
+                                           _stream_handle(None)),
             "pp_k_smooth2_fused_dot_f32")
     return float(dot[0].item())
 

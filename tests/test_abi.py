@@ -137,9 +137,11 @@ def test_kernel_entries_validate(lib):
     assert lib.pp_k_smooth2_fused_f32(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0, 0,
                                       None) == L.PP_EINVAL      # e_in aliases e_out
     assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, other, 0,
-                                          None, fake, None) == L.PP_EINVAL      # no rdot
+                                          None, None) == L.PP_EINVAL      # no dot
+    assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, other, 0,
+                                          ctypes.c_void_p(0x1004), None) == L.PP_EINVAL   # dot misaligned
     assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0,
-                                          fake, other, None) == L.PP_EINVAL     # aliasing
+                                          other, None) == L.PP_EINVAL     # aliasing
     assert lib.pp_k_resid_restrict(ctypes.byref(g2), fake, fake, fake, fake, fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g2), fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g), fake, ctypes.c_void_p(0x1008), None) == L.PP_EINVAL   # e misaligned

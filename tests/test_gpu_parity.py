@@ -174,30 +174,35 @@ def test_two_sweep_fused_f32_matches_paper_sor(S, n, bc, first):
                                   ((200, 72, 40), (0, 0, 0))])
 def test_two_sweep_fused_dot_product(S, n, bc):
     """The FP32 V-cycle's last fine pass also forms r . e_out for the outer
-    iteration: e_out equals the plain pass bit for bit, and the dot product
-    equals the FP64 sum of r * e_out up to summation order (relative 1e-12
-    of the sum of |r * e_out|)."""
+    iteration, r its own right-hand side: e_out equals the plain pass bit for
+    bit.  Each product is formed from the FP32 h^2 r the sweep carries, so the
+    dot product equals sum(fl32(h^2 r) e_out) / h^2 in FP64 up to summation
+    order (relative 1e-12 of the sum of absolute terms), and sum(r e_out)
+    within the FP32 rounding of h^2 r (2^-24 per term)."""
     _say(f"two-sweep fused dot n={n} bc={bc}")
     w = W.random_case(n, bc, seed=118)
     beta = [b.astype(np.float32) for b in oracle.face_coeffs(w.rho, bc)]
     rng = np.random.default_rng(6)
     r = rng.standard_normal(w.shape).astype(np.float32)
     e0 = rng.standard_normal(w.shape).astype(np.float32)
-    rd = rng.standard_normal(w.shape)
+    h2f = np.float32(w.h * w.h)
+    hr = (h2f * r).astype(np.float64)            # FP32 product, as the sweep forms it
     f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     bt = [f32(b) for b in beta]
     for first in (0, 1):
         plain = f32(np.full(w.shape, np.nan))
         S.k_smooth2_fused_f32(w.shape, w.h, bc, bt, f32(r), f32(e0), plain, first_colour=first)
         out = f32(np.full(w.shape, np.nan))
-        dot = S.k_smooth2_fused_dot_f32(w.shape, w.h, bc, bt, f32(r), f32(e0), out, dev(rd),
+        dot = S.k_smooth2_fused_dot_f32(w.shape, w.h, bc, bt, f32(r), f32(e0), out,
                                         first_colour=first)
         eo = host(out).astype(np.float64)
         assert np.array_equal(host(plain), host(out))
-        ref = float(np.sum(rd * eo))
-        scale = float(np.sum(np.abs(rd * eo)))
-        _say(f"  first={first} dot={dot:.15e} ref={ref:.15e}")
+        ref = float(np.sum(hr * eo)) / float(h2f)
+        scale = float(np.sum(np.abs(hr * eo))) / float(h2f)
+        plain_ref = float(np.sum(r.astype(np.float64) * eo))
+        _say(f"  first={first} dot={dot:.15e} ref={ref:.15e} sum(r e)={plain_ref:.15e}")
         assert abs(dot - ref) <= 1e-12 * scale
+        assert abs(dot - plain_ref) <= 2.0 ** -23 * scale
 
 
 def _restrict_ref(x):
