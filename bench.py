@@ -266,7 +266,7 @@ def main():
                                    "GBps": byt / (avg * 1e-3) / 1e9}
         if n_ou:
             avg = ms_ou / n_ou
-            byt = (24 + 2 * word) * w.cells         # q, r in; r out; z_old in, r_T out
+            byt = (24 + word) * w.cells             # q, r in; r out; r_T out
             kern["outer_update"] = {"launches": n_ou, "avg_ms": avg, "alg_bytes": byt,
                                     "GBps": byt / (avg * 1e-3) / 1e9}
         r["kernels"] = kern

@@ -950,14 +950,13 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
             npd = launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
                                       op_rho(c), (const T *)v0.cur, dold, dnew, c->q64, x,
                                       c->sig_on ? c->sig[0] : nullptr, c->scal, first, ih2, c->part,
-                                      s);
+                                      c->pstride, s);
         }
         first = false;
         launch_finalize(c->part, c->pstride, npd, OP_ALPHA, 0, (double)c->N, 0, c->scal, s);
         {
             KT t(c, PP_KT_OUTER_UPDATE, true);
-            launch_pcg_update<T>(c->d, c->q64, c->r64, (T *)v0.r, (const T *)v0.cur, c->scal,
-                                 c->part, c->pstride, s);
+            launch_pcg_update<T>(c->d, c->q64, c->r64, (T *)v0.r, c->scal, c->part, s);
         }
         std::swap(dold, dnew);
         launch_finalize(c->part, c->pstride, np, OP_UPDATE, 0, (double)c->N, 0, c->scal, s);

@@ -241,10 +241,11 @@ template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                      const double *rho, const T *z, const typename DirT<T>::type *dold,
                      typename DirT<T>::type *dnew, double *q, double *x, const double *sg,
-                     const double *scal, bool first, double ih2, double *part, hipStream_t s);
+                     const double *scal, bool first, double ih2, double *part, size_t pstride,
+                     hipStream_t s);
 template <typename T>
-void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const T *zold,
-                       const double *scal, double *part, size_t pstride, hipStream_t s);
+void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const double *scal, double *part,
+                       hipStream_t s);
 // x += scal[S_ALPHA] * dv
 template <typename D>
 void launch_axpy_dir(size_t n, const D *dv, double *x, const double *scal, hipStream_t s);

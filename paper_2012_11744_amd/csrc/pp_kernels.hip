@@ -1155,7 +1155,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restri
                                                           double *scal)
 {
     __shared__ double sm[2][FIN_THREADS / 64];
-    const bool two = op == OP_INIT || op == OP_UPDATE;
+    const bool two = op == OP_INIT || op == OP_ALPHA;
     const int t = threadIdx.x;
     // four loads in flight per accumulation step (the sum order stays fixed)
     double a0 = 0.0, a1 = 0.0;
@@ -1222,14 +1222,19 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restri
     }
     case OP_ALPHA:
         // s0 = D . A D with the true direction s_k D: alpha = rz / (s_k^2 s0);
-        // the slot holds alpha s_k, the coefficient of D and of q = A D
+        // the slot holds alpha s_k, the coefficient of D and of q = A D.
+        // s1 = D_old . A D: since alpha_k (D_k . A D_k) = r_k . z_k and
+        // D_k - z_k = beta_k D_{k-1}, the next residual against this z is
+        // r_{k+1} . z_k = alpha_k beta_k (D_{k-1} . A D_k), in stored units
+        // alpha s_k * gamma * s_k s1 / s_k (zero on the first iteration, whose
+        // gamma is 0 and whose direction pass sums no s1)
         scal[S_DQ] = s0;
         scal[S_ALPHA] = scal[S_RZ] / (scal[S_USED] * s0);
         scal[S_DS] = scal[S_USED];
+        scal[S_RZOLD] = scal[S_ALPHA] * scal[S_BETA] * scal[S_USED] * s1;
         break;
     case OP_UPDATE:
         scal[S_RR] = s0;
-        scal[S_RZOLD] = scal[S_USED] * s1;
         scal[S_USED] = scal[S_NEXT];
         rms = sqrt(s0 / ncells);
         scal[S_NEXT] = (rms > 0.0 && rms < INFINITY) ? rms : 1.0;
@@ -1374,6 +1379,8 @@ __global__ __launch_bounds__(BLOCK) void k_dot_rz(Dims d, const double *__restri
 // before q is formed, so q is the image of exactly the stored vector; it is
 // recomputed at the in-plane neighbours from z and D_old by the same explicit
 // fma (so the same bits), which is why D_new and D_old are different buffers.
+// The second partial is D_old . q, from which the flexible coefficient's
+// r_{k+1} . z_k follows without a pass over z_k (see OP_ALPHA).
 // Each thread walks a column of RZ planes and carries the column's values of
 // the planes below and above (D_new, and the low z-face coefficient) in
 // registers.  The iterate's update of the previous iteration is applied here,
@@ -1395,12 +1402,12 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
                                                      double *__restrict__ x,
                                                      const double *__restrict__ sg,
                                                      const double *__restrict__ scal, double ih2,
-                                                     double *part)
+                                                     double *part, size_t pstride)
 {
-    __shared__ double sm[1][BLOCK / 64];
+    __shared__ double sm[2][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    double v[1] = {0.0};
+    double v[2] = {0.0, 0.0};
     if (i < d.nx && j < d.ny) {
         const double gamma = FIRST ? 0.0 : scal[S_BETA];
         const double aold = FIRST ? 0.0 : scal[S_ALPHA];
@@ -1459,8 +1466,11 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
             double qq = ih2 * f;
             if (sg)
                 qq -= sg[c] * dc;
-            if (!FIRST)
-                x[c] += aold * static_cast<double>(dold[c]);
+            if (!FIRST) {
+                const double dold_c = static_cast<double>(dold[c]);
+                x[c] += aold * dold_c;
+                v[1] += dold_c * qq;
+            }
             dnew[c] = static_cast<D>(dc);
             q[c] = qq;
             v[0] += dc * qq;
@@ -1469,24 +1479,22 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
             dc = dp;
         }
     }
-    block_partials<1>(v, sm, part, 0);
+    block_partials<2>(v, sm, part, pstride);
 }
 
-// r -= a q (a = scal[S_ALPHA]); rT = r / scal[S_NEXT];
-// partials ||r||^2 and r . z_old (z_old unscaled, storage precision).
+// r -= a q (a = scal[S_ALPHA]); rT = r / scal[S_NEXT]; partial ||r||^2.
 // The iterate takes the matching x += a D in the next direction pass, or in
 // k_axpy_dir after the last iteration.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__restrict__ q,
                                                       double *__restrict__ r, T *__restrict__ rT,
-                                                      const T *__restrict__ zold,
                                                       const double *__restrict__ scal,
-                                                      double *part, size_t pstride)
+                                                      double *part)
 {
-    __shared__ double sm[2][BLOCK / 64];
+    __shared__ double sm[1][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    double v[2] = {0.0, 0.0};
+    double v[1] = {0.0};
     if (i < d.nx && j < d.ny) {
         const double alpha = scal[S_ALPHA];
         const double inv = 1.0 / scal[S_NEXT];
@@ -1497,10 +1505,9 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__re
             r[c] = rn;
             rT[c] = static_cast<T>(rn * inv);
             v[0] += rn * rn;
-            v[1] += rn * static_cast<double>(zold[c]);
         }
     }
-    block_partials<2>(v, sm, part, pstride);
+    block_partials<1>(v, sm, part, 0);
 }
 
 // x += scal[S_ALPHA] * D: the last iteration's update of the iterate
@@ -1817,12 +1824,13 @@ template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                      const double *rho, const T *z, const typename DirT<T>::type *dold,
                      typename DirT<T>::type *dnew, double *q, double *x, const double *sg,
-                     const double *scal, bool first, double ih2, double *part, hipStream_t s)
+                     const double *scal, bool first, double ih2, double *part, size_t pstride,
+                     hipStream_t s)
 {
     using D = typename DirT<T>::type;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, rho, z, dold, dnew,
-                           q, x, sg, scal, ih2, part);
+                           q, x, sg, scal, ih2, part, pstride);
     };
     if (rho)
         first ? go(k_dir_apply<T, D, true, true>) : go(k_dir_apply<T, D, false, true>);
@@ -1832,11 +1840,10 @@ int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const do
 }
 
 template <typename T>
-void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const T *zold,
-                       const double *scal, double *part, size_t pstride, hipStream_t s)
+void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const double *scal, double *part,
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pcg_update<T>), red_grid(d), kBlock, 0, s, d, q, r, rT, zold, scal, part,
-                       pstride);
+    hipLaunchKernelGGL((k_pcg_update<T>), red_grid(d), kBlock, 0, s, d, q, r, rT, scal, part);
 }
 
 template <typename D>
@@ -1885,9 +1892,9 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
                                       const typename DirT<T>::type *,                           \
                                       typename DirT<T>::type *, double *, double *,             \
                                       const double *, const double *, bool, double, double *,   \
-                                      hipStream_t);                                             \
-    template void launch_pcg_update<T>(Dims, const double *, double *, T *, const T *,          \
-                                       const double *, double *, size_t, hipStream_t);
+                                      size_t, hipStream_t);                                     \
+    template void launch_pcg_update<T>(Dims, const double *, double *, T *, const double *,     \
+                                       double *, hipStream_t);
 
 PP_INSTANTIATE(double)
 PP_INSTANTIATE(float)
