@@ -1472,8 +1472,8 @@ int pp_project(pp_ctx *c, const double *usx, const double *usy, const double *us
         return fail(PP_EINVAL, "pp_project: p must not alias the output");
     if (!std::isfinite(dt))
         return fail(PP_EINVAL, "pp_project: dt must be finite");
-    launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], usx, usy, usz, p,
-                   dt / c->grid.h, ux, uy, uz, c->stream);
+    launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], op_rho(c), usx, usy,
+                   usz, p, dt / c->grid.h, ux, uy, uz, c->stream);
     return check_launch("pp_project");
 }
 

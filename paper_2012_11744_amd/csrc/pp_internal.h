@@ -191,9 +191,11 @@ void launch_divergence(Dims d, Bc bc, const double *ux, const double *uy, const 
                        double *out, hipStream_t s);
 void launch_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                   const double *x, const double *sg, double *y, double ih2, hipStream_t s);
+// rho non-null: beta from the cell densities (as for launch_dir_apply)
 void launch_project(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                    const double *usx, const double *usy, const double *usz, const double *p,
-                    double dt_over_h, double *ux, double *uy, double *uz, hipStream_t s);
+                    const double *rho, const double *usx, const double *usy, const double *usz,
+                    const double *p, double dt_over_h, double *ux, double *uy, double *uz,
+                    hipStream_t s);
 void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, double ih2,
                           const double *bx, const double *by, const double *bz, double *gx,
                           double *gy, double *gz, hipStream_t s);

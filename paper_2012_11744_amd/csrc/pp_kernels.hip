@@ -177,9 +177,13 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restri
     e[n.c] = static_cast<T>(diag > C(0) ? (s - h2 * ld(r, n.c)) / diag : C(0));
 }
 
-// rH = mean over the 8 children of (r - A e).  One thread per coarse cell;
-// the two x-children of each of its four (y, z) child rows are handled as a
-// pair with two-element vector loads.
+// rH = mean over the 8 children of (r - A e).  One thread per coarse column
+// (I, J) walks kz coarse planes along z; the two x-children of each of its two
+// child rows are handled as a pair with two-element vector loads.  The fine
+// planes below and at the current one (e) and the low z-face coefficient are
+// carried in registers, and the two child rows are each other's y-neighbours,
+// so only the rows 2J-1 and 2J+2 and the next plane are loaded beside the
+// children themselves.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const T *__restrict__ bx,
                                                           const T *__restrict__ by,
@@ -188,14 +192,15 @@ __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const 
                                                           const T *__restrict__ r,
                                                           const T *__restrict__ sg,
                                                           T *__restrict__ rH,
-                                                          typename Acc<T>::type ih2)
+                                                          typename Acc<T>::type ih2, int kz)
 {
     using C = typename Acc<T>::type;
     using T2 = typename Vec2<T>::type;
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     const int I = blockIdx.x * BX + threadIdx.x;
     const int J = blockIdx.y * BY + threadIdx.y;
-    const int K = blockIdx.z;
+    const int K0 = blockIdx.z * kz;
+    const int K1 = min(K0 + kz, cd.nz);
     if (I >= cd.nx || J >= cd.ny)
         return;
     const size_t sy = (size_t)fd.nx, sz = (size_t)fd.nx * fd.ny;
@@ -203,52 +208,77 @@ __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const 
     const int xm1 = (x == 0) ? fd.nx - 1 : x - 1;
     const int xp2 = (x + 2 == fd.nx) ? 0 : x + 2;
     const bool wxl = bc.x && x == 0, wxh = bc.x && x + 2 == fd.nx;
+    // child rows j0 = 2J, j1 = 2J + 1 (ny is even, so j0 never touches the
+    // high wall and j1 never the low one); the rows outside them
+    const int j0 = 2 * J, j1 = j0 + 1;
+    const int jm = (j0 == 0) ? fd.ny - 1 : j0 - 1, jp = (j1 == fd.ny - 1) ? 0 : j1 + 1;
+    const bool wyl = bc.y && j0 == 0, wyh = bc.y && j1 == fd.ny - 1;
+    const size_t r0 = (size_t)j0 * sy + x, r1 = (size_t)j1 * sy + x;
     auto ld2 = [](const T *p, size_t i) -> T2 { return *reinterpret_cast<const T2 *>(p + i); };
-    C acc = C(0);
-#pragma unroll 1
-    for (int dk = 0; dk < 2; ++dk) {
-        const int k = 2 * K + dk;
-        const int km = (k == 0) ? fd.nz - 1 : k - 1, kp = (k == fd.nz - 1) ? 0 : k + 1;
-        const bool wzl = bc.z && k == 0, wzh = bc.z && k == fd.nz - 1;
+    // one fine cell pair of a child row: h^2 (A e) of both cells
+    auto pair_flux = [&](T2 ec, T2 xx, C exm, C exp, C bxn, T2 ylo, T2 yhi, T2 eym, T2 eyp,
+                         T2 zlo, T2 zhi, T2 ezm, T2 ezp, bool wyl_, bool wyh_, bool wzl, bool wzh,
+                         C &f0, C &f1) {
+        const C e0 = C(ec.x), e1 = C(ec.y);
+        f0 = C(xx.y) * (e1 - e0) - (wxl ? C(0) : C(xx.x)) * (e0 - exm) +
+             (wyh_ ? C(0) : C(yhi.x)) * (C(eyp.x) - e0) - (wyl_ ? C(0) : C(ylo.x)) * (e0 - C(eym.x)) +
+             (wzh ? C(0) : C(zhi.x)) * (C(ezp.x) - e0) - (wzl ? C(0) : C(zlo.x)) * (e0 - C(ezm.x));
+        f1 = (wxh ? C(0) : bxn) * (exp - e1) - C(xx.y) * (e1 - e0) +
+             (wyh_ ? C(0) : C(yhi.y)) * (C(eyp.y) - e1) - (wyl_ ? C(0) : C(ylo.y)) * (e1 - C(eym.y)) +
+             (wzh ? C(0) : C(zhi.y)) * (C(ezp.y) - e1) - (wzl ? C(0) : C(zlo.y)) * (e1 - C(ezm.y));
+    };
+    // the fine plane below the first one, the first one, its low z faces
+    int k = 2 * K0;
+    size_t pl = (size_t)k * sz;
+    const size_t pm = (size_t)(k == 0 ? fd.nz - 1 : k - 1) * sz;
+    T2 em0 = ld2(e, pm + r0), em1 = ld2(e, pm + r1);
+    T2 ec0 = ld2(e, pl + r0), ec1 = ld2(e, pl + r1);
+    T2 zl0 = ld2(bz, pl + r0), zl1 = ld2(bz, pl + r1);
+    for (int K = K0; K < K1; ++K) {
+        C acc = C(0);
 #pragma unroll
-        for (int dj = 0; dj < 2; ++dj) {
-            const int j = 2 * J + dj;
-            const int jm = (j == 0) ? fd.ny - 1 : j - 1, jp = (j == fd.ny - 1) ? 0 : j + 1;
-            const bool wyl = bc.y && j == 0, wyh = bc.y && j == fd.ny - 1;
-            const size_t plane = (size_t)k * sz, rowj = (size_t)j * sy;
-            const size_t c = plane + rowj + x;
-            const T2 ec = ld2(e, c), rr = ld2(r, c), xx = ld2(bx, c), ylo = ld2(by, c), zlo = ld2(bz, c);
-            const T2 yhi = ld2(by, plane + (size_t)jp * sy + x);
-            const T2 zhi = ld2(bz, (size_t)kp * sz + rowj + x);
-            const T2 eym = ld2(e, plane + (size_t)jm * sy + x), eyp = ld2(e, plane + (size_t)jp * sy + x);
-            const T2 ezm = ld2(e, (size_t)km * sz + rowj + x), ezp = ld2(e, (size_t)kp * sz + rowj + x);
-            const C exm = ld(e, plane + rowj + xm1), exp = ld(e, plane + rowj + xp2);
-            const C bxn = ld(bx, plane + rowj + xp2);
-            const C e0 = C(ec.x), e1 = C(ec.y);
-            // cell x
-            const C f0 = C(xx.y) * (e1 - e0) - (wxl ? C(0) : C(xx.x)) * (e0 - exm) +
-                         (wyh ? C(0) : C(yhi.x)) * (C(eyp.x) - e0) -
-                         (wyl ? C(0) : C(ylo.x)) * (e0 - C(eym.x)) +
-                         (wzh ? C(0) : C(zhi.x)) * (C(ezp.x) - e0) -
-                         (wzl ? C(0) : C(zlo.x)) * (e0 - C(ezm.x));
-            // cell x + 1
-            const C f1 = (wxh ? C(0) : bxn) * (exp - e1) - C(xx.y) * (e1 - e0) +
-                         (wyh ? C(0) : C(yhi.y)) * (C(eyp.y) - e1) -
-                         (wyl ? C(0) : C(ylo.y)) * (e1 - C(eym.y)) +
-                         (wzh ? C(0) : C(zhi.y)) * (C(ezp.y) - e1) -
-                         (wzl ? C(0) : C(zlo.y)) * (e1 - C(ezm.y));
+        for (int dk = 0; dk < 2; ++dk, ++k) {
+            pl = (size_t)k * sz;
+            const size_t pp = (size_t)(k == fd.nz - 1 ? 0 : k + 1) * sz;
+            const bool wzl = bc.z && k == 0, wzh = bc.z && k == fd.nz - 1;
+            const T2 ep0 = ld2(e, pp + r0), ep1 = ld2(e, pp + r1);
+            const T2 zh0 = ld2(bz, pp + r0), zh1 = ld2(bz, pp + r1);
+            const T2 rr0 = ld2(r, pl + r0), rr1 = ld2(r, pl + r1);
+            const T2 xx0 = ld2(bx, pl + r0), xx1 = ld2(bx, pl + r1);
+            const T2 yl0 = ld2(by, pl + r0), yl1 = ld2(by, pl + r1);
+            const T2 yh1 = ld2(by, pl + (size_t)jp * sy + x);
+            const T2 eym = ld2(e, pl + (size_t)jm * sy + x), eyp = ld2(e, pl + (size_t)jp * sy + x);
+            const size_t rw0 = pl + (size_t)j0 * sy, rw1 = pl + (size_t)j1 * sy;
+            const C exm0 = ld(e, rw0 + xm1), exp0 = ld(e, rw0 + xp2);
+            const C exm1 = ld(e, rw1 + xm1), exp1 = ld(e, rw1 + xp2);
+            const C bxn0 = ld(bx, rw0 + xp2), bxn1 = ld(bx, rw1 + xp2);
+            C f00, f01, f10, f11;
+            // row j0: its high y neighbour is row j1; row j1: its low one is j0
+            pair_flux(ec0, xx0, exm0, exp0, bxn0, yl0, yl1, eym, ec1, zl0, zh0, em0, ep0, wyl,
+                      false, wzl, wzh, f00, f01);
+            pair_flux(ec1, xx1, exm1, exp1, bxn1, yl1, yh1, ec0, eyp, zl1, zh1, em1, ep1, false,
+                      wyh, wzl, wzh, f10, f11);
             // r - A e; the general operator's diagonal term sg = h^2 sigma
             // adds + sigma e = ih2 sg e
-            C s0 = C(0), s1 = C(0);
+            C s00 = C(0), s01 = C(0), s10 = C(0), s11 = C(0);
             if (sg) {
-                const T2 sv = ld2(sg, c);
-                s0 = ih2 * (C(sv.x) * e0);
-                s1 = ih2 * (C(sv.y) * e1);
+                const T2 sv0 = ld2(sg, pl + r0), sv1 = ld2(sg, pl + r1);
+                s00 = ih2 * (C(sv0.x) * C(ec0.x));
+                s01 = ih2 * (C(sv0.y) * C(ec0.y));
+                s10 = ih2 * (C(sv1.x) * C(ec1.x));
+                s11 = ih2 * (C(sv1.y) * C(ec1.y));
             }
-            acc += (C(rr.x) - ih2 * f0 + s0) + (C(rr.y) - ih2 * f1 + s1);
+            acc += (C(rr0.x) - ih2 * f00 + s00) + (C(rr0.y) - ih2 * f01 + s01);
+            acc += (C(rr1.x) - ih2 * f10 + s10) + (C(rr1.y) - ih2 * f11 + s11);
+            em0 = ec0;
+            em1 = ec1;
+            ec0 = ep0;
+            ec1 = ep1;
+            zl0 = zh0;
+            zl1 = zh1;
         }
+        rH[((size_t)K * cd.ny + J) * cd.nx + I] = static_cast<T>(acc * C(0.125));
     }
-    rH[((size_t)K * cd.ny + J) * cd.nx + I] = static_cast<T>(acc * C(0.125));
 }
 
 __device__ __forceinline__ int other_parent(int i, int nH, int wall)
@@ -1037,10 +1067,13 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, Bc bc, const double *__
 
 // u_m = us_m - dt beta_m G_m p on open faces, 0 on wall faces and on closed
 // links (beta = 0: the link flags multiply the velocity) (eq. fotm).
-// u may alias us: each thread reads and writes only its own entries.
+// u may alias us: each thread reads and writes only its own entries.  RHO:
+// beta formed from the cell densities (as in k_dir_apply).
+template <bool RHO>
 __global__ __launch_bounds__(BLOCK) void k_project(Dims d, Bc bc, const double *__restrict__ bx,
                                                    const double *__restrict__ by,
                                                    const double *__restrict__ bz,
+                                                   const double *__restrict__ rho,
                                                    const double *usx, const double *usy,
                                                    const double *usz, const double *__restrict__ p,
                                                    double dt_h, double *ux, double *uy, double *uz)
@@ -1052,7 +1085,17 @@ __global__ __launch_bounds__(BLOCK) void k_project(Dims d, Bc bc, const double *
         return;
     const Nb n = neighbours(d, bc, i, j, k);
     const double pc = p[n.c];
-    const double fx = bx[n.c], fy = by[n.c], fz = bz[n.c];
+    double fx, fy, fz;
+    if (RHO) {   // beta from the densities, as the density load stores it
+        const double rc = rho[n.c];
+        fx = 2.0 / (rho[n.xm] + rc);
+        fy = 2.0 / (rho[n.ym] + rc);
+        fz = 2.0 / (rho[n.zm] + rc);
+    } else {
+        fx = bx[n.c];
+        fy = by[n.c];
+        fz = bz[n.c];
+    }
     const double vx = (n.wxl || fx == 0.0) ? 0.0 : usx[n.c] - dt_h * fx * (pc - p[n.xm]);
     const double vy = (n.wyl || fy == 0.0) ? 0.0 : usy[n.c] - dt_h * fy * (pc - p[n.ym]);
     const double vz = (n.wzl || fz == 0.0) ? 0.0 : usz[n.c] - dt_h * fz * (pc - p[n.zm]);
@@ -1565,8 +1608,15 @@ void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz
 {
     using C = typename Acc<T>::type;
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    hipLaunchKernelGGL((k_resid_restrict<T>), cell_grid(cd), kBlock, 0, s, fd, bc, bx, by, bz, e, r,
-                       sg, rH, (C)ih2);
+    // coarse planes per thread: the longest walk (up to 4) that still leaves
+    // at least 1024 workgroups, so the machine stays full
+    dim3 g = cell_grid(cd);
+    int kz = 1;
+    while (kz < 4 && (size_t)g.x * g.y * ((cd.nz + 2 * kz - 1) / (2 * kz)) >= 1024)
+        kz *= 2;
+    g.z = (cd.nz + kz - 1) / kz;
+    hipLaunchKernelGGL((k_resid_restrict<T>), g, kBlock, 0, s, fd, bc, bx, by, bz, e, r, sg, rH,
+                       (C)ih2, kz);
 }
 
 template <typename T>
@@ -1733,11 +1783,16 @@ void launch_apply(Dims d, Bc bc, const double *bx, const double *by, const doubl
 }
 
 void launch_project(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                    const double *usx, const double *usy, const double *usz, const double *p,
-                    double dt_over_h, double *ux, double *uy, double *uz, hipStream_t s)
+                    const double *rho, const double *usx, const double *usy, const double *usz,
+                    const double *p, double dt_over_h, double *ux, double *uy, double *uz,
+                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_project, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, usx, usy, usz, p,
-                       dt_over_h, ux, uy, uz);
+    if (rho)
+        hipLaunchKernelGGL(k_project<true>, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, rho, usx,
+                           usy, usz, p, dt_over_h, ux, uy, uz);
+    else
+        hipLaunchKernelGGL(k_project<false>, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, rho,
+                           usx, usy, usz, p, dt_over_h, ux, uy, uz);
 }
 
 void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, double ih2,
