@@ -234,12 +234,11 @@ def main():
         # launch of each cycle starts from zero and skips e_in (5 words).  FP32
         # and FP16 storage run two sweeps per launch (one launch in two starts
         # from zero with nu_pre = nu_post = 2), FP64 one sweep per launch (one
-        # in four).  In FP32 the post-smoothing launch also reads the FP64
-        # outer residual (8 B per cell) to form r . z.
+        # in four).  In FP32 the post-smoothing launch also forms r . z, from
+        # values it holds already (no bytes of its own).
         word = {"fp64": 8, "fp32": 4, "fp16": 2}[mode]
         dword = 8 if mode == "fp64" else 4          # outer search direction
         zero_share = 0.25 if mode == "fp64" else 0.5
-        dot_bytes = 4.0 if mode == "fp32" else 0.0  # mean over the two launches
         n_sm, ms_sm = kt[L.PP_KT_SMOOTH]
         n_rr, ms_rr = kt[L.PP_KT_RESTRICT]
         n_oa, ms_oa = kt[L.PP_KT_OUTER_APPLY]
@@ -247,7 +246,7 @@ def main():
         kern = {}
         if n_sm:
             avg = ms_sm / n_sm
-            byt = ((6.0 - zero_share) * word + dot_bytes) * w.cells
+            byt = (6.0 - zero_share) * word * w.cells
             kern["smoother_sweep"] = {"launches": n_sm, "avg_ms": avg, "alg_bytes": byt,
                                       "GBps": byt / (avg * 1e-3) / 1e9}
         if n_rr:

@@ -208,11 +208,10 @@ void launch_fill(double *x, size_t n, double v, hipStream_t s);
 void launch_sum(Dims d, const double *x, const unsigned char *act, double *part, hipStream_t s);
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
                      double ncells, int first, double *scal, hipStream_t s);
-// rho as for launch_dir_apply
 void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const double *rho, const double *b, const double *scal, double *x,
-                     bool zero_x, const double *sg, const unsigned char *act, double *r64,
-                     double ih2, double *part, size_t pstride, hipStream_t s);
+                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,
+                     const unsigned char *act, double *r64, double ih2, double *part,
+                     size_t pstride, hipStream_t s);
 template <typename T>
 void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                        const double *b, const double *scal, const double *x, const double *sg,

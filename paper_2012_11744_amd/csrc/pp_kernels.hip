@@ -78,21 +78,6 @@ __device__ __forceinline__ Links<T> links(const Nb &n, const T *bx, const T *by,
     return L;
 }
 
-// the six link coefficients from the cell densities: beta = 2 / (rho_low +
-// rho_high), the expression the density load stores (0 across walls)
-__device__ __forceinline__ Links<double> links_rho(const Nb &n, const double *rho)
-{
-    Links<double> L;
-    const double rc = rho[n.c];
-    L.xl = n.wxl ? 0.0 : 2.0 / (rho[n.xm] + rc);
-    L.xh = n.wxh ? 0.0 : 2.0 / (rc + rho[n.xp]);
-    L.yl = n.wyl ? 0.0 : 2.0 / (rho[n.ym] + rc);
-    L.yh = n.wyh ? 0.0 : 2.0 / (rc + rho[n.yp]);
-    L.zl = n.wzl ? 0.0 : 2.0 / (rho[n.zm] + rc);
-    L.zh = n.wzh ? 0.0 : 2.0 / (rc + rho[n.zp]);
-    return L;
-}
-
 // h^2 (A x)_c
 template <typename T, typename X>
 __device__ __forceinline__ typename Acc<T>::type flux_sum(const Nb &n, const Links<T> &L, const X *x)
@@ -1294,13 +1279,11 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restri
 }
 
 // r = (b - mean b) - A x; partials ||r||^2 and ||b - mean b||^2.
-// ZEROX: x is set to zero (cold start) and A x is skipped.  RHO: the link
-// coefficients are formed from the cell densities (as in k_dir_apply).
-template <bool ZEROX, bool RHO>
+// ZEROX: x is set to zero (cold start) and A x is skipped.
+template <bool ZEROX>
 __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double *__restrict__ bx,
                                                     const double *__restrict__ by,
                                                     const double *__restrict__ bz,
-                                                    const double *__restrict__ rho,
                                                     const double *__restrict__ b,
                                                     const double *__restrict__ scal, double *x,
                                                     const double *__restrict__ sg,
@@ -1323,7 +1306,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
             if (ZEROX) {
                 x[n.c] = 0.0;
             } else {
-                const Links<double> L = RHO ? links_rho(n, rho) : links(n, bx, by, bz);
+                const Links<double> L = links(n, bx, by, bz);
                 ax = ih2 * flux_sum(n, L, x);
                 if (sg)
                     ax -= sg[n.c] * x[n.c];
@@ -1831,20 +1814,16 @@ void launch_finalize(const double *part, size_t pstride, int nparts, int op, int
 }
 
 void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const double *rho, const double *b, const double *scal, double *x,
-                     bool zero_x, const double *sg, const unsigned char *act, double *r64,
-                     double ih2, double *part, size_t pstride, hipStream_t s)
+                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,
+                     const unsigned char *act, double *r64, double ih2, double *part,
+                     size_t pstride, hipStream_t s)
 {
-    auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, rho, b, scal, x, sg,
-                           act, r64, ih2, part, pstride);
-    };
     if (zero_x)
-        go(k_residual<true, false>);
-    else if (rho)
-        go(k_residual<false, true>);
+        hipLaunchKernelGGL(k_residual<true>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal,
+                           x, sg, act, r64, ih2, part, pstride);
     else
-        go(k_residual<false, false>);
+        hipLaunchKernelGGL(k_residual<false>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b,
+                           scal, x, sg, act, r64, ih2, part, pstride);
 }
 
 template <typename T>

@@ -7,9 +7,9 @@ path must load the same coefficients bit for bit: the tests compare whole
 solves and projections with those of pp_face_coeffs + pp_update_coeffs
 bitwise, on the one-pass kernel (aligned rho, several levels) and on the
 fallback path (a single-level grid; a misaligned rho), and check that bad
-densities are rejected.  After a density update the outer operator kernels
-(search direction image, residual) form beta from a copy of rho instead of
-reading the three coefficient arrays; the bitwise comparisons cover them, and
+densities are rejected.  After a density update the search direction's
+image and the projection form beta from a copy of rho instead of reading the
+three coefficient arrays; the bitwise comparisons cover them, and
 further tests check that the copy is the library's own (the caller may
 overwrite rho), that a later coefficient update stops its use, that z
 chunks which do not divide the grid wrap correctly, and the adjoint.
