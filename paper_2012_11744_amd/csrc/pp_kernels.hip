@@ -1508,6 +1508,218 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
     block_partials<2>(v, sm, part, pstride);
 }
 
+// k_dir_apply for grids with even nx and ny (and a 16-byte aligned iterate):
+// each thread owns a 2 x 2 block of cells, an x-pair in two rows, so a
+// workgroup covers 128 x 8 cells of each plane.  Workgroups are dispatched to
+// the XCDs in turn, so the halo rows and lines a workgroup shares with its
+// neighbours are fetched again by another XCD's L2; per cell there are half as
+// many of them here.  The faces between the block's cells are formed once.
+// Same arithmetic per cell as k_dir_apply (same order of terms).
+template <typename T, typename D, bool FIRST, bool RHO>
+__global__ __launch_bounds__(BLOCK) void k_dir_apply2(Dims d, Bc bc, const double *__restrict__ bx,
+                                                      const double *__restrict__ by,
+                                                      const double *__restrict__ bz,
+                                                      const double *__restrict__ rho,
+                                                      const T *__restrict__ z,
+                                                      const D *__restrict__ dold,
+                                                      D *__restrict__ dnew,
+                                                      double *__restrict__ q,
+                                                      double *__restrict__ x,
+                                                      const double *__restrict__ sg,
+                                                      const double *__restrict__ scal, double ih2,
+                                                      double *part, size_t pstride)
+{
+    using T2 = typename Vec2<T>::type;
+    using D2 = typename Vec2<D>::type;
+    using F2 = double __attribute__((ext_vector_type(2)));
+    __shared__ double sm[2][BLOCK / 64];
+    const int x0 = 2 * (int)(blockIdx.x * BX + threadIdx.x);
+    const int j0 = 2 * (int)(blockIdx.y * BY + threadIdx.y), j1 = j0 + 1;
+    double v[2] = {0.0, 0.0};
+    if (x0 < d.nx && j0 < d.ny) {
+        const double gamma = FIRST ? 0.0 : scal[S_BETA];
+        const double aold = FIRST ? 0.0 : scal[S_ALPHA];
+        const size_t sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
+        const int xm = (x0 == 0) ? d.nx - 1 : x0 - 1;
+        const int xp = (x0 + 2 == d.nx) ? 0 : x0 + 2;
+        const int jm = (j0 == 0) ? d.ny - 1 : j0 - 1;
+        const int jp = (j1 + 1 == d.ny) ? 0 : j1 + 1;
+        const bool wxl = bc.x && x0 == 0, wxh = bc.x && x0 + 2 == d.nx;
+        const bool wyl = bc.y && j0 == 0, wyh = bc.y && j1 == d.ny - 1;
+        // in-plane offsets: the pair in rows j0 and j1, the pair in the rows
+        // beyond them, the cells beyond the pair in rows j0 and j1
+        const size_t o0 = (size_t)j0 * sy + x0, o1 = (size_t)j1 * sy + x0;
+        const size_t om = (size_t)jm * sy + x0, op = (size_t)jp * sy + x0;
+        const size_t m0 = (size_t)j0 * sy + xm, m1 = (size_t)j1 * sy + xm;
+        const size_t p0 = (size_t)j0 * sy + xp, p1 = (size_t)j1 * sy + xp;
+        auto dcast = [&](double t, double o) -> double {
+            return static_cast<double>(static_cast<D>(FIRST ? t : __builtin_fma(gamma, o, t)));
+        };
+        auto dv1 = [&](size_t c) -> double {
+            return dcast(static_cast<double>(z[c]), FIRST ? 0.0 : static_cast<double>(dold[c]));
+        };
+        // the direction at a pair, and D_old there
+        auto dv2 = [&](size_t c, double &a, double &b, double &oa, double &ob) {
+            const T2 t = *reinterpret_cast<const T2 *>(z + c);
+            oa = ob = 0.0;
+            if (!FIRST) {
+                const D2 o = *reinterpret_cast<const D2 *>(dold + c);
+                oa = static_cast<double>(o.x);
+                ob = static_cast<double>(o.y);
+            }
+            a = dcast(static_cast<double>(t.x), oa);
+            b = dcast(static_cast<double>(t.y), ob);
+        };
+        auto ld2d = [](const double *p, size_t c) -> F2 {
+            return *reinterpret_cast<const F2 *>(p + c);
+        };
+        // cells 0: (x0, j0), 1: (x0 + 1, j0), 2: (x0, j1), 3: (x0 + 1, j1)
+        const int k0 = blockIdx.z * RZ;
+        const int ke = min(d.nz, k0 + RZ);
+        const size_t pm = (size_t)(k0 == 0 ? d.nz - 1 : k0 - 1) * sz, pc0 = (size_t)k0 * sz;
+        double Dm[4], Dc[4], Oc[4], ZL[4], Rc[4], t0, t1;
+        dv2(pm + o0, Dm[0], Dm[1], t0, t1);
+        dv2(pm + o1, Dm[2], Dm[3], t0, t1);
+        dv2(pc0 + o0, Dc[0], Dc[1], Oc[0], Oc[1]);
+        dv2(pc0 + o1, Dc[2], Dc[3], Oc[2], Oc[3]);
+        if (RHO) {
+            const F2 a0 = ld2d(rho, pm + o0), a1 = ld2d(rho, pm + o1);
+            const F2 c0 = ld2d(rho, pc0 + o0), c1 = ld2d(rho, pc0 + o1);
+            Rc[0] = c0.x;
+            Rc[1] = c0.y;
+            Rc[2] = c1.x;
+            Rc[3] = c1.y;
+            ZL[0] = 2.0 / (a0.x + Rc[0]);
+            ZL[1] = 2.0 / (a0.y + Rc[1]);
+            ZL[2] = 2.0 / (a1.x + Rc[2]);
+            ZL[3] = 2.0 / (a1.y + Rc[3]);
+        } else {
+            const F2 c0 = ld2d(bz, pc0 + o0), c1 = ld2d(bz, pc0 + o1);
+            ZL[0] = c0.x;
+            ZL[1] = c0.y;
+            ZL[2] = c1.x;
+            ZL[3] = c1.y;
+        }
+        for (int k = k0; k < ke; ++k) {
+            const size_t pl = (size_t)k * sz;
+            const size_t pp = (size_t)(k == d.nz - 1 ? 0 : k + 1) * sz;
+            double Dp[4], Op[4];
+            dv2(pp + o0, Dp[0], Dp[1], Op[0], Op[1]);
+            dv2(pp + o1, Dp[2], Dp[3], Op[2], Op[3]);
+            // the direction beyond the block in this plane
+            const double dxm0 = dv1(pl + m0), dxp0 = dv1(pl + p0);
+            const double dxm1 = dv1(pl + m1), dxp1 = dv1(pl + p1);
+            double dym0, dym1, dyp0, dyp1;
+            dv2(pl + om, dym0, dym1, t0, t1);
+            dv2(pl + op, dyp0, dyp1, t0, t1);
+            // link coefficients: x faces per row (low, middle, high), y faces
+            // per column (low, middle, high), the high z faces
+            double fx[2][3], fy[2][3], zh[4], Rp[4];
+            if (RHO) {
+                const F2 a0 = ld2d(rho, pp + o0), a1 = ld2d(rho, pp + o1);
+                Rp[0] = a0.x;
+                Rp[1] = a0.y;
+                Rp[2] = a1.x;
+                Rp[3] = a1.y;
+                const double rxm0 = rho[pl + m0], rxp0 = rho[pl + p0];
+                const double rxm1 = rho[pl + m1], rxp1 = rho[pl + p1];
+                const F2 rym = ld2d(rho, pl + om), ryp = ld2d(rho, pl + op);
+                fx[0][0] = 2.0 / (rxm0 + Rc[0]);
+                fx[0][1] = 2.0 / (Rc[0] + Rc[1]);
+                fx[0][2] = 2.0 / (Rc[1] + rxp0);
+                fx[1][0] = 2.0 / (rxm1 + Rc[2]);
+                fx[1][1] = 2.0 / (Rc[2] + Rc[3]);
+                fx[1][2] = 2.0 / (Rc[3] + rxp1);
+                fy[0][0] = 2.0 / (rym.x + Rc[0]);
+                fy[0][1] = 2.0 / (Rc[0] + Rc[2]);
+                fy[0][2] = 2.0 / (Rc[2] + ryp.x);
+                fy[1][0] = 2.0 / (rym.y + Rc[1]);
+                fy[1][1] = 2.0 / (Rc[1] + Rc[3]);
+                fy[1][2] = 2.0 / (Rc[3] + ryp.y);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    zh[c] = 2.0 / (Rc[c] + Rp[c]);
+            } else {
+                const F2 bx0 = ld2d(bx, pl + o0), bx1 = ld2d(bx, pl + o1);
+                const F2 by0 = ld2d(by, pl + o0), by1 = ld2d(by, pl + o1);
+                const F2 byp = ld2d(by, pl + op);
+                const F2 bz0 = ld2d(bz, pp + o0), bz1 = ld2d(bz, pp + o1);
+                fx[0][0] = bx0.x;
+                fx[0][1] = bx0.y;
+                fx[0][2] = bx[pl + p0];
+                fx[1][0] = bx1.x;
+                fx[1][1] = bx1.y;
+                fx[1][2] = bx[pl + p1];
+                fy[0][0] = by0.x;
+                fy[0][1] = by1.x;
+                fy[0][2] = byp.x;
+                fy[1][0] = by0.y;
+                fy[1][1] = by1.y;
+                fy[1][2] = byp.y;
+                zh[0] = bz0.x;
+                zh[1] = bz0.y;
+                zh[2] = bz1.x;
+                zh[3] = bz1.y;
+            }
+            const bool wzl = bc.z && k == 0, wzh = bc.z && k == d.nz - 1;
+            // per cell: x column cx, row ry; neighbours in x and y
+            const double nxm[4] = {dxm0, Dc[0], dxm1, Dc[2]};
+            const double nxp[4] = {Dc[1], dxp0, Dc[3], dxp1};
+            const double nym[4] = {dym0, dym1, Dc[0], Dc[1]};
+            const double nyp[4] = {Dc[2], Dc[3], dyp0, dyp1};
+            double qq[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int cx = c & 1, ry = c >> 1;
+                const double Lxl = (cx == 0 && wxl) ? 0.0 : fx[ry][cx];
+                const double Lxh = (cx == 1 && wxh) ? 0.0 : fx[ry][cx + 1];
+                const double Lyl = (ry == 0 && wyl) ? 0.0 : fy[cx][ry];
+                const double Lyh = (ry == 1 && wyh) ? 0.0 : fy[cx][ry + 1];
+                const double Lzl = wzl ? 0.0 : ZL[c];
+                const double Lzh = wzh ? 0.0 : zh[c];
+                const double dc = Dc[c];
+                const double f = Lxh * (nxp[c] - dc) - Lxl * (dc - nxm[c]) +
+                                 Lyh * (nyp[c] - dc) - Lyl * (dc - nym[c]) +
+                                 Lzh * (Dp[c] - dc) - Lzl * (dc - Dm[c]);
+                qq[c] = ih2 * f;
+                if (sg)
+                    qq[c] -= sg[pl + (ry ? o1 : o0) + cx] * dc;
+            }
+            if (!FIRST) {
+                F2 *xa = reinterpret_cast<F2 *>(x + pl + o0);
+                F2 *xb = reinterpret_cast<F2 *>(x + pl + o1);
+                F2 va = *xa, vb = *xb;
+                va.x += aold * Oc[0];
+                va.y += aold * Oc[1];
+                vb.x += aold * Oc[2];
+                vb.y += aold * Oc[3];
+                *xa = va;
+                *xb = vb;
+            }
+            *reinterpret_cast<D2 *>(dnew + pl + o0) = D2{static_cast<D>(Dc[0]), static_cast<D>(Dc[1])};
+            *reinterpret_cast<D2 *>(dnew + pl + o1) = D2{static_cast<D>(Dc[2]), static_cast<D>(Dc[3])};
+            *reinterpret_cast<F2 *>(q + pl + o0) = F2{qq[0], qq[1]};
+            *reinterpret_cast<F2 *>(q + pl + o1) = F2{qq[2], qq[3]};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                v[0] += Dc[c] * qq[c];
+                if (!FIRST)
+                    v[1] += Oc[c] * qq[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ZL[c] = zh[c];
+                Dm[c] = Dc[c];
+                Dc[c] = Dp[c];
+                Oc[c] = Op[c];
+                if (RHO)
+                    Rc[c] = Rp[c];
+            }
+        }
+    }
+    block_partials<2>(v, sm, part, pstride);
+}
+
 // r -= a q (a = scal[S_ALPHA]); rT = r / scal[S_NEXT]; partial ||r||^2.
 // The iterate takes the matching x += a D in the next direction pass, or in
 // k_axpy_dir after the last iteration.
@@ -1862,15 +2074,27 @@ int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const do
                      hipStream_t s)
 {
     using D = typename DirT<T>::type;
+    // 2 x 2 cells per thread where the grid and the iterate allow pairs
+    const bool quad = d.nx % 2 == 0 && d.ny % 2 == 0 && ((uintptr_t)x & 15) == 0;
+    const dim3 g = quad ? dim3((d.nx / 2 + BX - 1) / BX, (d.ny / 2 + BY - 1) / BY,
+                               (d.nz + RZ - 1) / RZ)
+                        : red_grid(d);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, rho, z, dold, dnew,
-                           q, x, sg, scal, ih2, part, pstride);
+        hipLaunchKernelGGL(kern, g, kBlock, 0, s, d, bc, bx, by, bz, rho, z, dold, dnew, q, x, sg,
+                           scal, ih2, part, pstride);
     };
-    if (rho)
-        first ? go(k_dir_apply<T, D, true, true>) : go(k_dir_apply<T, D, false, true>);
-    else
-        first ? go(k_dir_apply<T, D, true, false>) : go(k_dir_apply<T, D, false, false>);
-    return (int)grid_blocks(red_grid(d));
+    if (quad) {
+        if (rho)
+            first ? go(k_dir_apply2<T, D, true, true>) : go(k_dir_apply2<T, D, false, true>);
+        else
+            first ? go(k_dir_apply2<T, D, true, false>) : go(k_dir_apply2<T, D, false, false>);
+    } else {
+        if (rho)
+            first ? go(k_dir_apply<T, D, true, true>) : go(k_dir_apply<T, D, false, true>);
+        else
+            first ? go(k_dir_apply<T, D, true, false>) : go(k_dir_apply<T, D, false, false>);
+    }
+    return (int)grid_blocks(g);
 }
 
 template <typename T>
