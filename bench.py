@@ -256,11 +256,16 @@ def main():
                                       "GBps": byt / (avg * 1e-3) / 1e9}
         if n_oa:
             avg = ms_oa / n_oa
-            # new direction + operator: z (V-cycle word), D_old, rho (the step
+            # new direction + operator: z (V-cycle word) and rho in (the step
             # loads the coefficients from the densities, so the kernel forms
-            # beta from them), x in; D_new, q, x out; the first iteration of
-            # each solve reads neither D_old nor x and writes no x
-            byt = (32 + word + 2 * dword - (dword + 16.0) / max(1, r["outer_iters"])) * w.cells
+            # beta from them), D_new and q out; from the second iteration D_old
+            # in; the iterate takes two directions at a time, in the passes of
+            # even iterations from the second: x in and out and D_{k-2} in
+            n_it = max(1, r["outer_iters"])
+            n_hold = n_it // 2
+            n_two = n_it - 1 - n_hold
+            byt = ((16 + word + dword) + n_hold * (16 + word + 2 * dword)
+                   + n_two * (32 + word + 3 * dword)) / n_it * w.cells
             kern["outer_apply"] = {"launches": n_oa, "avg_ms": avg, "alg_bytes": byt,
                                    "GBps": byt / (avg * 1e-3) / 1e9}
         if n_ou:

@@ -947,9 +947,13 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         int npd;
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
+            // the iterate takes the pending directions two at a time: the
+            // passes of odd iterations hold theirs, those of even ones apply
+            // the last two
+            const int mode = first ? DIR_FIRST : ((launched & 1) ? DIR_HOLD : DIR_TWO);
             npd = launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
                                       op_rho(c), (const T *)v0.cur, dold, dnew, c->q64, x,
-                                      c->sig_on ? c->sig[0] : nullptr, c->scal, first, ih2, c->part,
+                                      c->sig_on ? c->sig[0] : nullptr, c->scal, mode, ih2, c->part,
                                       c->pstride, s);
         }
         first = false;
@@ -1015,10 +1019,12 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
     }
     if (rc == CONVERGED)
         rc = PP_OK;
-    // the last direction's update of the iterate (earlier ones were applied
-    // by the direction passes that followed them)
+    // the updates of the iterate still pending: the last direction (in dold
+    // after the swap), and after an odd last iteration also the one before it
+    // (in dnew), whose pass held it
     if (launched > 0) {
-        launch_axpy_dir<D>(c->N, dold, x, c->scal, s);
+        const bool two = ((launched - 1) & 1) != 0;
+        launch_axpy_dir<D>(c->N, dold, two ? dnew : nullptr, x, c->scal, s);
         PP_TRY(check_launch("pcg final update"));
     }
     return rc;

@@ -86,7 +86,8 @@ enum Slot {
     S_SPOS = 13,    // positive sigma entries
     S_NACT = 14,    // active cells of the general operator
     S_DS = 15,      // V-cycle scale of the latest direction (outer CG)
-    S_NSLOTS = 16
+    S_APREV = 16,   // the previous outer iteration's ALPHA
+    S_NSLOTS = 17
 };
 
 enum FinalizeOp {
@@ -236,20 +237,26 @@ struct DirT<double> {
     using type = double;
 };
 // returns the number of partial sums written (at most grid_blocks(red_grid(d)))
-template <typename T>
 // rho non-null: the link coefficients are formed from the cell densities
-// (the plain operator whose coefficients came from them), not read from bx..bz
+// (the plain operator whose coefficients came from them), not read from bx..bz.
+// The iterate's update (mode): DIR_FIRST none (first iteration: no D_old),
+// DIR_HOLD none (its direction waits a pass), DIR_TWO x += APREV * (dnew as
+// it was, D_{k-2}) + ALPHA * D_old, the two pending directions.
+enum DirMode { DIR_FIRST = 0, DIR_HOLD = 1, DIR_TWO = 2 };
+template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                      const double *rho, const T *z, const typename DirT<T>::type *dold,
                      typename DirT<T>::type *dnew, double *q, double *x, const double *sg,
-                     const double *scal, bool first, double ih2, double *part, size_t pstride,
+                     const double *scal, int mode, double ih2, double *part, size_t pstride,
                      hipStream_t s);
 template <typename T>
 void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const double *scal, double *part,
                        hipStream_t s);
-// x += scal[S_ALPHA] * dv
+// x += scal[S_ALPHA] * dv, after x += scal[S_APREV] * dv_prev when dv_prev
+// is given (the two directions still pending after the last iteration)
 template <typename D>
-void launch_axpy_dir(size_t n, const D *dv, double *x, const double *scal, hipStream_t s);
+void launch_axpy_dir(size_t n, const D *dv, const D *dv_prev, double *x, const double *scal,
+                     hipStream_t s);
 // x -= scal[slot] (slot < 0: nothing); with act, excluded cells are set to 0
 void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const unsigned char *act,
                      hipStream_t s);

@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "pp_device.h"
 #include "pp_internal.h"
@@ -1257,6 +1258,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restri
         // alpha s_k * gamma * s_k s1 / s_k (zero on the first iteration, whose
         // gamma is 0 and whose direction pass sums no s1)
         scal[S_DQ] = s0;
+        scal[S_APREV] = scal[S_ALPHA];
         scal[S_ALPHA] = scal[S_RZ] / (scal[S_USED] * s0);
         scal[S_DS] = scal[S_USED];
         scal[S_RZOLD] = scal[S_ALPHA] * scal[S_BETA] * scal[S_USED] * s1;
@@ -1409,14 +1411,17 @@ __global__ __launch_bounds__(BLOCK) void k_dot_rz(Dims d, const double *__restri
 // r_{k+1} . z_k follows without a pass over z_k (see OP_ALPHA).
 // Each thread walks a column of RZ planes and carries the column's values of
 // the planes below and above (D_new, and the low z-face coefficient) in
-// registers.  The iterate's update of the previous iteration is applied here,
-// where D_old is read anyway: x += a_{k-1} D_old with a_{k-1} = scal[S_ALPHA]
-// (this launch runs before the new coefficient is finalised).
+// registers.  The iterate's updates are applied here, where D_old is read
+// anyway, two directions at a time: MODE == DIR_TWO adds a_{k-2} D_{k-2}
+// (D_{k-2} is what dnew holds until this pass overwrites it, a_{k-2} =
+// scal[S_APREV]) and then a_{k-1} D_old (a_{k-1} = scal[S_ALPHA]; this launch
+// runs before the new coefficient is finalised); DIR_HOLD leaves x alone, so
+// its direction waits for the next pass, and DIR_FIRST has no D_old.
 // RHO: the link coefficients are formed from the cell densities,
 // beta = 2 / (rho_low + rho_high), the expression the density load stores, so
 // q has the same bits as with the stored coefficients while 8 bytes per cell
 // are read instead of 24.
-template <typename T, typename D, bool FIRST, bool RHO>
+template <typename T, typename D, int MODE, bool RHO>
 __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double *__restrict__ bx,
                                                      const double *__restrict__ by,
                                                      const double *__restrict__ bz,
@@ -1434,9 +1439,11 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
     double v[2] = {0.0, 0.0};
+    constexpr bool FIRST = MODE == DIR_FIRST;
     if (i < d.nx && j < d.ny) {
         const double gamma = FIRST ? 0.0 : scal[S_BETA];
         const double aold = FIRST ? 0.0 : scal[S_ALPHA];
+        const double aprev = MODE == DIR_TWO ? scal[S_APREV] : 0.0;
         auto dv = [&](size_t c) -> double {
             const double t = static_cast<double>(z[c]);
             return static_cast<double>(
@@ -1494,7 +1501,8 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
                 qq -= sg[c] * dc;
             if (!FIRST) {
                 const double dold_c = static_cast<double>(dold[c]);
-                x[c] += aold * dold_c;
+                if (MODE == DIR_TWO)
+                    x[c] = (x[c] + aprev * static_cast<double>(dnew[c])) + aold * dold_c;
                 v[1] += dold_c * qq;
             }
             dnew[c] = static_cast<D>(dc);
@@ -1514,8 +1522,9 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply(Dims d, Bc bc, const double
 // the XCDs in turn, so the halo rows and lines a workgroup shares with its
 // neighbours are fetched again by another XCD's L2; per cell there are half as
 // many of them here.  The faces between the block's cells are formed once.
-// Same arithmetic per cell as k_dir_apply (same order of terms).
-template <typename T, typename D, bool FIRST, bool RHO>
+// Same arithmetic per cell as k_dir_apply (same order of terms), and the same
+// iterate updates (MODE).
+template <typename T, typename D, int MODE, bool RHO>
 __global__ __launch_bounds__(BLOCK) void k_dir_apply2(Dims d, Bc bc, const double *__restrict__ bx,
                                                       const double *__restrict__ by,
                                                       const double *__restrict__ bz,
@@ -1536,9 +1545,11 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply2(Dims d, Bc bc, const doubl
     const int x0 = 2 * (int)(blockIdx.x * BX + threadIdx.x);
     const int j0 = 2 * (int)(blockIdx.y * BY + threadIdx.y), j1 = j0 + 1;
     double v[2] = {0.0, 0.0};
+    constexpr bool FIRST = MODE == DIR_FIRST;
     if (x0 < d.nx && j0 < d.ny) {
         const double gamma = FIRST ? 0.0 : scal[S_BETA];
         const double aold = FIRST ? 0.0 : scal[S_ALPHA];
+        const double aprev = MODE == DIR_TWO ? scal[S_APREV] : 0.0;
         const size_t sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
         const int xm = (x0 == 0) ? d.nx - 1 : x0 - 1;
         const int xp = (x0 + 2 == d.nx) ? 0 : x0 + 2;
@@ -1685,14 +1696,17 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply2(Dims d, Bc bc, const doubl
                 if (sg)
                     qq[c] -= sg[pl + (ry ? o1 : o0) + cx] * dc;
             }
-            if (!FIRST) {
+            if (MODE == DIR_TWO) {
+                // D_{k-2} is what dnew holds until the stores below
+                const D2 ea = *reinterpret_cast<const D2 *>(dnew + pl + o0);
+                const D2 eb = *reinterpret_cast<const D2 *>(dnew + pl + o1);
                 F2 *xa = reinterpret_cast<F2 *>(x + pl + o0);
                 F2 *xb = reinterpret_cast<F2 *>(x + pl + o1);
                 F2 va = *xa, vb = *xb;
-                va.x += aold * Oc[0];
-                va.y += aold * Oc[1];
-                vb.x += aold * Oc[2];
-                vb.y += aold * Oc[3];
+                va.x = (va.x + aprev * static_cast<double>(ea.x)) + aold * Oc[0];
+                va.y = (va.y + aprev * static_cast<double>(ea.y)) + aold * Oc[1];
+                vb.x = (vb.x + aprev * static_cast<double>(eb.x)) + aold * Oc[2];
+                vb.y = (vb.y + aprev * static_cast<double>(eb.y)) + aold * Oc[3];
                 *xa = va;
                 *xb = vb;
             }
@@ -1721,8 +1735,8 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply2(Dims d, Bc bc, const doubl
 }
 
 // r -= a q (a = scal[S_ALPHA]); rT = r / scal[S_NEXT]; partial ||r||^2.
-// The iterate takes the matching x += a D in the next direction pass, or in
-// k_axpy_dir after the last iteration.
+// The iterate takes the matching x += a D in a later direction pass (two
+// directions at a time), or in k_axpy_dir after the last iteration.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__restrict__ q,
                                                       double *__restrict__ r, T *__restrict__ rT,
@@ -1748,15 +1762,21 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(Dims d, const double *__re
     block_partials<1>(v, sm, part, 0);
 }
 
-// x += scal[S_ALPHA] * D: the last iteration's update of the iterate
+// x += scal[S_ALPHA] * D (after x += scal[S_APREV] * D_prev when given): the
+// updates of the iterate still pending after the last iteration
 template <typename D>
-__global__ void k_axpy_dir(size_t n, const D *__restrict__ dv, double *__restrict__ x,
-                           const double *__restrict__ scal)
+__global__ void k_axpy_dir(size_t n, const D *__restrict__ dv, const D *__restrict__ dv_prev,
+                           double *__restrict__ x, const double *__restrict__ scal)
 {
     const double a = scal[S_ALPHA];
+    const double ap = dv_prev ? scal[S_APREV] : 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        x[i] += a * static_cast<double>(dv[i]);
+         i += (size_t)gridDim.x * blockDim.x) {
+        double v = x[i];
+        if (dv_prev)
+            v += ap * static_cast<double>(dv_prev[i]);
+        x[i] = v + a * static_cast<double>(dv[i]);
+    }
 }
 
 __global__ void k_sub_mean(size_t n, double *__restrict__ x, const double *__restrict__ scal, int slot,
@@ -2070,7 +2090,7 @@ template <typename T>
 int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                      const double *rho, const T *z, const typename DirT<T>::type *dold,
                      typename DirT<T>::type *dnew, double *q, double *x, const double *sg,
-                     const double *scal, bool first, double ih2, double *part, size_t pstride,
+                     const double *scal, int mode, double ih2, double *part, size_t pstride,
                      hipStream_t s)
 {
     using D = typename DirT<T>::type;
@@ -2083,17 +2103,28 @@ int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const do
         hipLaunchKernelGGL(kern, g, kBlock, 0, s, d, bc, bx, by, bz, rho, z, dold, dnew, q, x, sg,
                            scal, ih2, part, pstride);
     };
-    if (quad) {
-        if (rho)
-            first ? go(k_dir_apply2<T, D, true, true>) : go(k_dir_apply2<T, D, false, true>);
-        else
-            first ? go(k_dir_apply2<T, D, true, false>) : go(k_dir_apply2<T, D, false, false>);
-    } else {
-        if (rho)
-            first ? go(k_dir_apply<T, D, true, true>) : go(k_dir_apply<T, D, false, true>);
-        else
-            first ? go(k_dir_apply<T, D, true, false>) : go(k_dir_apply<T, D, false, false>);
-    }
+    auto by_mode = [&](auto r) {
+        constexpr bool RH = decltype(r)::value;
+        if (quad) {
+            if (mode == DIR_FIRST)
+                go(k_dir_apply2<T, D, DIR_FIRST, RH>);
+            else if (mode == DIR_HOLD)
+                go(k_dir_apply2<T, D, DIR_HOLD, RH>);
+            else
+                go(k_dir_apply2<T, D, DIR_TWO, RH>);
+        } else {
+            if (mode == DIR_FIRST)
+                go(k_dir_apply<T, D, DIR_FIRST, RH>);
+            else if (mode == DIR_HOLD)
+                go(k_dir_apply<T, D, DIR_HOLD, RH>);
+            else
+                go(k_dir_apply<T, D, DIR_TWO, RH>);
+        }
+    };
+    if (rho)
+        by_mode(std::true_type{});
+    else
+        by_mode(std::false_type{});
     return (int)grid_blocks(g);
 }
 
@@ -2105,13 +2136,15 @@ void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const double *
 }
 
 template <typename D>
-void launch_axpy_dir(size_t n, const D *dv, double *x, const double *scal, hipStream_t s)
+void launch_axpy_dir(size_t n, const D *dv, const D *dv_prev, double *x, const double *scal,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL((k_axpy_dir<D>), flat_grid(n), dim3(256), 0, s, n, dv, x, scal);
+    hipLaunchKernelGGL((k_axpy_dir<D>), flat_grid(n), dim3(256), 0, s, n, dv, dv_prev, x, scal);
 }
-template void launch_axpy_dir<double>(size_t, const double *, double *, const double *,
-                                      hipStream_t);
-template void launch_axpy_dir<float>(size_t, const float *, double *, const double *, hipStream_t);
+template void launch_axpy_dir<double>(size_t, const double *, const double *, double *,
+                                      const double *, hipStream_t);
+template void launch_axpy_dir<float>(size_t, const float *, const float *, double *,
+                                     const double *, hipStream_t);
 
 void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const unsigned char *act,
                      hipStream_t s)
@@ -2149,7 +2182,7 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
                                       const double *, const T *,                                \
                                       const typename DirT<T>::type *,                           \
                                       typename DirT<T>::type *, double *, double *,             \
-                                      const double *, const double *, bool, double, double *,   \
+                                      const double *, const double *, int, double, double *,    \
                                       size_t, hipStream_t);                                     \
     template void launch_pcg_update<T>(Dims, const double *, double *, T *, const double *,     \
                                        double *, hipStream_t);

@@ -324,6 +324,52 @@ def test_random_ratio1000_ragged(S, n, bc, precision):
     _parity_solve(S, w, precision, tol=1e-11, ptol=1e-8)
 
 
+@pytest.mark.parametrize("n,bc", [((9, 10, 10), (1, 0, 1)), ((10, 9, 8), (0, 1, 0)),
+                                  ((7, 11, 12), (0, 0, 1))])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_odd_grid_one_cell_direction_pass(S, n, bc, precision):
+    """Odd nx or ny: the direction pass takes its one-cell form (pairs of
+    cells need both counts even); single-level grids of at most 1024 cells."""
+    _say(f"odd grid n={n} bc={bc} {precision}")
+    w = W.random_case(n, bc, seed=136, ratio=1000.0)
+    _parity_solve(S, w, precision, tol=1e-11, ptol=1e-8)
+
+
+@pytest.mark.parametrize("load", ["beta", "rho"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_unaligned_iterate_one_cell_direction_pass(S, precision, load):
+    """p handed as a view one element into a larger buffer (8-byte aligned):
+    the direction pass updates the iterate one cell at a time, with the
+    stored coefficients or (after a density update) beta formed from rho.
+    Parity with the oracle as for an aligned p."""
+    w = W.config3(64)
+    _say(f"unaligned p config3 64^3 {precision} {load}")
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    p_o = _oracle_p(w, beta, rhs, 1e-13)
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision=precision) as sol:
+        if load == "rho":
+            sol.update_density(dev(w.rho))
+        b = sol.divergence([dev(u) for u in w.us], 1.0 / w.dt)
+        big = torch.zeros(w.rho.size + 1, dtype=torch.float64, device="cuda")
+        p = big[1:].view(w.shape)
+        assert p.data_ptr() % 16 == 8
+        sol.solve(b, tol=1e-11, p=p)
+        it_u = sol.last_stats["outer_iters"]
+        p_a = sol.solve(b, tol=1e-11)
+        it_a = sol.last_stats["outer_iters"]
+        p_h, pa_h = host(p), host(p_a)
+    res = oracle.apply(beta, w.bc, w.h, p_h)
+    bm = rhs - rhs.mean()
+    rel_true = np.linalg.norm(bm - res) / np.linalg.norm(bm)
+    _say(f"  iters unaligned={it_u} aligned={it_a} true={rel_true:.2e} "
+         f"err_p={relmax(p_h, p_o):.2e} vs aligned={relmax(p_h, pa_h):.2e}")
+    assert rel_true <= 1.05e-11
+    assert relmax(p_h, p_o) <= 1e-8
+    assert relmax(p_h, pa_h) <= 1e-9
+    assert abs(it_u - it_a) <= 1
+
+
 @pytest.mark.parametrize("outer", ["pcg", "dc"])
 def test_config3_layer_droplets_64(S, outer):
     _say(f"config3 geometry at 64^3, fp32, {outer}")
