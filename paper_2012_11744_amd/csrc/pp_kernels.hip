@@ -1322,6 +1322,114 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
     block_partials<2>(v, sm, part, pstride);
 }
 
+// k_residual (x given) for grids with even nx and ny and 16-byte aligned
+// arrays: each thread owns a 2 x 2 block of cells and walks RZ planes with the
+// column's planes below and at the current one carried in registers, as in
+// k_dir_apply2; the same per-cell arithmetic as the one-cell kernel.
+__global__ __launch_bounds__(BLOCK) void k_residual2(Dims d, Bc bc, const double *__restrict__ bx,
+                                                     const double *__restrict__ by,
+                                                     const double *__restrict__ bz,
+                                                     const double *__restrict__ b,
+                                                     const double *__restrict__ scal,
+                                                     const double *__restrict__ x,
+                                                     const double *__restrict__ sg,
+                                                     const unsigned char *__restrict__ act,
+                                                     double *__restrict__ r64, double ih2,
+                                                     double *part, size_t pstride)
+{
+    using F2 = double __attribute__((ext_vector_type(2)));
+    __shared__ double sm[2][BLOCK / 64];
+    const int x0 = 2 * (int)(blockIdx.x * BX + threadIdx.x);
+    const int j0 = 2 * (int)(blockIdx.y * BY + threadIdx.y), j1 = j0 + 1;
+    double v[2] = {0.0, 0.0};
+    if (x0 < d.nx && j0 < d.ny) {
+        const double mean = scal[S_MEAN];
+        const size_t sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
+        const int xm = (x0 == 0) ? d.nx - 1 : x0 - 1;
+        const int xp = (x0 + 2 == d.nx) ? 0 : x0 + 2;
+        const int jm = (j0 == 0) ? d.ny - 1 : j0 - 1;
+        const int jp = (j1 + 1 == d.ny) ? 0 : j1 + 1;
+        const bool wxl = bc.x && x0 == 0, wxh = bc.x && x0 + 2 == d.nx;
+        const bool wyl = bc.y && j0 == 0, wyh = bc.y && j1 == d.ny - 1;
+        const size_t o0 = (size_t)j0 * sy + x0, o1 = (size_t)j1 * sy + x0;
+        const size_t om = (size_t)jm * sy + x0, op = (size_t)jp * sy + x0;
+        const size_t m0 = (size_t)j0 * sy + xm, m1 = (size_t)j1 * sy + xm;
+        const size_t p0 = (size_t)j0 * sy + xp, p1 = (size_t)j1 * sy + xp;
+        auto ld2d = [](const double *p, size_t c) -> F2 {
+            return *reinterpret_cast<const F2 *>(p + c);
+        };
+        auto quad = [&](const double *p, size_t pl, double (&o)[4]) {
+            const F2 a = ld2d(p, pl + o0), c = ld2d(p, pl + o1);
+            o[0] = a.x;
+            o[1] = a.y;
+            o[2] = c.x;
+            o[3] = c.y;
+        };
+        // cells 0: (x0, j0), 1: (x0 + 1, j0), 2: (x0, j1), 3: (x0 + 1, j1)
+        const int k0 = blockIdx.z * RZ;
+        const int ke = min(d.nz, k0 + RZ);
+        double Xm[4], Xc[4], ZL[4];
+        quad(x, (size_t)(k0 == 0 ? d.nz - 1 : k0 - 1) * sz, Xm);
+        quad(x, (size_t)k0 * sz, Xc);
+        quad(bz, (size_t)k0 * sz, ZL);
+        for (int k = k0; k < ke; ++k) {
+            const size_t pl = (size_t)k * sz;
+            const size_t pp = (size_t)(k == d.nz - 1 ? 0 : k + 1) * sz;
+            double Xp[4], zh[4], bb[4];
+            quad(x, pp, Xp);
+            quad(bz, pp, zh);
+            quad(b, pl, bb);
+            const double xm0 = x[pl + m0], xp0 = x[pl + p0];
+            const double xm1 = x[pl + m1], xp1 = x[pl + p1];
+            const F2 xym = ld2d(x, pl + om), xyp = ld2d(x, pl + op);
+            const F2 bx0 = ld2d(bx, pl + o0), bx1 = ld2d(bx, pl + o1);
+            const F2 by0 = ld2d(by, pl + o0), by1 = ld2d(by, pl + o1);
+            const F2 byp = ld2d(by, pl + op);
+            // x faces per row (low, middle, high), y faces per column
+            const double fx[2][3] = {{bx0.x, bx0.y, bx[pl + p0]}, {bx1.x, bx1.y, bx[pl + p1]}};
+            const double fy[2][3] = {{by0.x, by1.x, byp.x}, {by0.y, by1.y, byp.y}};
+            const bool wzl = bc.z && k == 0, wzh = bc.z && k == d.nz - 1;
+            const double nxm[4] = {xm0, Xc[0], xm1, Xc[2]};
+            const double nxp[4] = {Xc[1], xp0, Xc[3], xp1};
+            const double nym[4] = {xym.x, xym.y, Xc[0], Xc[1]};
+            const double nyp[4] = {Xc[2], Xc[3], xyp.x, xyp.y};
+            double rr[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int cx = c & 1, ry = c >> 1;
+                const size_t cell = pl + (ry ? o1 : o0) + cx;
+                const double Lxl = (cx == 0 && wxl) ? 0.0 : fx[ry][cx];
+                const double Lxh = (cx == 1 && wxh) ? 0.0 : fx[ry][cx + 1];
+                const double Lyl = (ry == 0 && wyl) ? 0.0 : fy[cx][ry];
+                const double Lyh = (ry == 1 && wyh) ? 0.0 : fy[cx][ry + 1];
+                const double Lzl = wzl ? 0.0 : ZL[c];
+                const double Lzh = wzh ? 0.0 : zh[c];
+                const double xc = Xc[c];
+                // the right-hand side of an excluded cell is not part of the system
+                const double bm = (act && !act[cell]) ? 0.0 : bb[c] - mean;
+                const double f = Lxh * (nxp[c] - xc) - Lxl * (xc - nxm[c]) +
+                                 Lyh * (nyp[c] - xc) - Lyl * (xc - nym[c]) +
+                                 Lzh * (Xp[c] - xc) - Lzl * (xc - Xm[c]);
+                double ax = ih2 * f;
+                if (sg)
+                    ax -= sg[cell] * xc;
+                rr[c] = bm - ax;
+                v[0] += rr[c] * rr[c];
+                v[1] += bm * bm;
+            }
+            *reinterpret_cast<F2 *>(r64 + pl + o0) = F2{rr[0], rr[1]};
+            *reinterpret_cast<F2 *>(r64 + pl + o1) = F2{rr[2], rr[3]};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                Xm[c] = Xc[c];
+                Xc[c] = Xp[c];
+                ZL[c] = zh[c];
+            }
+        }
+    }
+    block_partials<2>(v, sm, part, pstride);
+}
+
 // defect-correction residual: rT = ((b - mean b) - A x) / scal[S_NEXT]; partial ||r||^2
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_residual_T(Dims d, Bc bc, const double *__restrict__ bx,
@@ -2045,17 +2153,26 @@ void launch_finalize(const double *part, size_t pstride, int nparts, int op, int
                        ncells, first, scal);
 }
 
-void launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,
-                     const unsigned char *act, double *r64, double ih2, double *part,
-                     size_t pstride, hipStream_t s)
+int launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                    const double *b, const double *scal, double *x, bool zero_x, const double *sg,
+                    const unsigned char *act, double *r64, double ih2, double *part,
+                    size_t pstride, hipStream_t s)
 {
+    const bool quad = !zero_x && d.nx % 2 == 0 && d.ny % 2 == 0 &&
+                      (((uintptr_t)x | (uintptr_t)b | (uintptr_t)r64) & 15) == 0;
+    if (quad) {
+        const dim3 g((d.nx / 2 + BX - 1) / BX, (d.ny / 2 + BY - 1) / BY, (d.nz + RZ - 1) / RZ);
+        hipLaunchKernelGGL(k_residual2, g, kBlock, 0, s, d, bc, bx, by, bz, b, scal, x, sg, act,
+                           r64, ih2, part, pstride);
+        return (int)grid_blocks(g);
+    }
     if (zero_x)
         hipLaunchKernelGGL(k_residual<true>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal,
                            x, sg, act, r64, ih2, part, pstride);
     else
         hipLaunchKernelGGL(k_residual<false>, red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b,
                            scal, x, sg, act, r64, ih2, part, pstride);
+    return (int)grid_blocks(red_grid(d));
 }
 
 template <typename T>
