@@ -168,7 +168,11 @@ int pp_setup_general(const pp_grid *grid, const double *beta_x, const double *be
  * the caller (16-byte alignment selects the one-pass kernel).  For contexts
  * made by pp_setup only.  PP_EINVAL if a cell's density or a resulting face
  * coefficient is not a finite positive number; the context's coefficients
- * are then undefined until a later successful update. */
+ * are then undefined until a later successful update.  The context keeps its
+ * own copy of rho (N doubles, allocated by the first call; the caller may
+ * overwrite rho afterwards): until the next coefficient update, pp_solve's
+ * search-direction pass and pp_project form beta from it with the same
+ * expression (same bits) instead of reading the three coefficient arrays. */
 int pp_update_density(pp_ctx *ctx, const double *rho);
 
 /* New coefficients for a context made by pp_setup_general (same grid);
