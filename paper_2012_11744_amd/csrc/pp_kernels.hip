@@ -126,6 +126,30 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double (*sm)[BLO
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn and each XCD has its own L2.
+// The stencil kernels with 2 x 2 cells per thread (and the restriction, whose
+// threads own 2 x 2 x 2 fine cells) take their blocks in groups
+// of all x-blocks of two block rows, one group per XCD in turn: the halo lines
+// and rows the blocks of a group share (and the periodic wrap in x) then sit
+// in one L2, while the XCDs still work through neighbouring groups, so their
+// accesses stay spread over the address space.  Identity where the grid does
+// not divide into such groups.
+__device__ __forceinline__ void xcd_groups(unsigned &bx, unsigned &by, unsigned &bz)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    bz = blockIdx.z;
+    if (gy % 2 != 0 || (gx * gy * gz) % 8 != 0 || ((gy / 2) * gz) % 8 != 0)
+        return;
+    const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned xcd = p & 7u, slot = p >> 3;
+    const unsigned member = slot % (2 * gx), group = (slot / (2 * gx)) * 8 + xcd;
+    bz = group / (gy / 2);
+    by = 2 * (group % (gy / 2)) + member / gx;
+    bx = member % gx;
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle kernels (templated on the storage type)
 // ---------------------------------------------------------------------------
@@ -183,9 +207,11 @@ __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const 
     using C = typename Acc<T>::type;
     using T2 = typename Vec2<T>::type;
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    const int I = blockIdx.x * BX + threadIdx.x;
-    const int J = blockIdx.y * BY + threadIdx.y;
-    const int K0 = blockIdx.z * kz;
+    unsigned gbx, gby, gbz;
+    xcd_groups(gbx, gby, gbz);
+    const int I = (int)gbx * BX + threadIdx.x;
+    const int J = (int)gby * BY + threadIdx.y;
+    const int K0 = (int)gbz * kz;
     const int K1 = min(K0 + kz, cd.nz);
     if (I >= cd.nx || J >= cd.ny)
         return;
@@ -1339,8 +1365,10 @@ __global__ __launch_bounds__(BLOCK) void k_residual2(Dims d, Bc bc, const double
 {
     using F2 = double __attribute__((ext_vector_type(2)));
     __shared__ double sm[2][BLOCK / 64];
-    const int x0 = 2 * (int)(blockIdx.x * BX + threadIdx.x);
-    const int j0 = 2 * (int)(blockIdx.y * BY + threadIdx.y), j1 = j0 + 1;
+    unsigned gbx, gby, gbz;
+    xcd_groups(gbx, gby, gbz);
+    const int x0 = 2 * (int)(gbx * BX + threadIdx.x);
+    const int j0 = 2 * (int)(gby * BY + threadIdx.y), j1 = j0 + 1;
     double v[2] = {0.0, 0.0};
     if (x0 < d.nx && j0 < d.ny) {
         const double mean = scal[S_MEAN];
@@ -1366,7 +1394,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual2(Dims d, Bc bc, const double
             o[3] = c.y;
         };
         // cells 0: (x0, j0), 1: (x0 + 1, j0), 2: (x0, j1), 3: (x0 + 1, j1)
-        const int k0 = blockIdx.z * RZ;
+        const int k0 = (int)gbz * RZ;
         const int ke = min(d.nz, k0 + RZ);
         double Xm[4], Xc[4], ZL[4];
         quad(x, (size_t)(k0 == 0 ? d.nz - 1 : k0 - 1) * sz, Xm);
@@ -1650,8 +1678,10 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply2(Dims d, Bc bc, const doubl
     using D2 = typename Vec2<D>::type;
     using F2 = double __attribute__((ext_vector_type(2)));
     __shared__ double sm[2][BLOCK / 64];
-    const int x0 = 2 * (int)(blockIdx.x * BX + threadIdx.x);
-    const int j0 = 2 * (int)(blockIdx.y * BY + threadIdx.y), j1 = j0 + 1;
+    unsigned gbx, gby, gbz;
+    xcd_groups(gbx, gby, gbz);
+    const int x0 = 2 * (int)(gbx * BX + threadIdx.x);
+    const int j0 = 2 * (int)(gby * BY + threadIdx.y), j1 = j0 + 1;
     double v[2] = {0.0, 0.0};
     constexpr bool FIRST = MODE == DIR_FIRST;
     if (x0 < d.nx && j0 < d.ny) {
@@ -1693,7 +1723,7 @@ __global__ __launch_bounds__(BLOCK) void k_dir_apply2(Dims d, Bc bc, const doubl
             return *reinterpret_cast<const F2 *>(p + c);
         };
         // cells 0: (x0, j0), 1: (x0 + 1, j0), 2: (x0, j1), 3: (x0 + 1, j1)
-        const int k0 = blockIdx.z * RZ;
+        const int k0 = (int)gbz * RZ;
         const int ke = min(d.nz, k0 + RZ);
         const size_t pm = (size_t)(k0 == 0 ? d.nz - 1 : k0 - 1) * sz, pc0 = (size_t)k0 * sz;
         double Dm[4], Dc[4], Oc[4], ZL[4], Rc[4], t0, t1;
