@@ -1001,10 +1001,11 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         if (rc != PP_OK)
             return rc;
         if (launched - seen == 2) {
-            // the previous iteration: any stop it calls for waits for the one
-            // now in flight, whose update the iterate already carries
+            // the previous iteration: a convergence or stagnation stop it
+            // calls for waits for the one now in flight, whose update the
+            // iterate already carries; an error ends the loop at once
             rc = process();
-            if (rc != PP_OK)
+            if (rc == CONVERGED || rc == STAGNATED)
                 rc = process();
             if (rc != PP_OK)
                 break;

@@ -89,10 +89,49 @@ def test_layer256_parity(S, layer256, precision):
     _say(f"  tol 1e-8: {it8} iterations, oracle residual {r8:.2e}, p error {err8:.2e}; "
          f"tol 1e-11: p error {err11:.2e}, div(u) error {err_div:.2e}, u error {err_u:.2e}")
     assert r8 <= 1.05e-8
-    assert err8 <= 1e-5
+    # measured 1.4e-9 (FP32) and 5.5e-10; the residual tolerance does not
+    # bound the p error by itself (condition number ~1e8), so the bound
+    # leaves a margin of about 70 over the measured values
+    assert err8 <= 1e-7
+    # iteration counts of the timed configuration (measured 8, 8 and 9): a
+    # mistake in a preconditioner kernel shows up here first
+    assert it8 <= (10 if precision == "fp16" else 9)
     assert err11 <= 1e-8
     assert err_div <= 1e-8
     assert err_u <= 1e-8
+
+
+def test_layer256_low_ratio_fp16(S):
+    """The same layer and droplets with liquid density 10 (ratio 8.3), where
+    FP16 storage of the V-cycle is meant to hold: element-wise parity at tol
+    1e-11 and the oracle's FP64 residual of the answer at the timing
+    tolerance."""
+    _say("generating the 256^3 layer+droplets workload at density ratio 8.3")
+    w = W.config3(256, rho_l=10.0)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    _say("oracle solve at 256^3, ratio 8.3 (tol 1e-13)")
+    p_o, it_o, rel_o = oracle.solve(beta, w.bc, w.h, rhs, tol=1e-13)
+    _say(f"  oracle: {it_o} iterations, rel {rel_o:.2e}")
+    rho = dev(w.rho)
+    bt = S.face_coeffs(rho, w.h, w.bc)
+    with S.Solver(bt, w.h, w.bc, precision="fp16") as sol:
+        sol.update_density(rho)
+        us = [dev(u) for u in w.us]
+        b = sol.divergence(us, 1.0 / w.dt)
+        p8 = host(sol.solve(b, tol=1e-8)).copy()
+        st8 = dict(sol.last_stats)
+        p11 = host(sol.solve(b, tol=1e-11)).copy()
+        st11 = dict(sol.last_stats)
+    r8 = rel_res(beta, w.bc, w.h, rhs, p8)
+    err8 = np.abs(p8 - p_o).max() / np.abs(p_o).max()
+    err11 = np.abs(p11 - p_o).max() / np.abs(p_o).max()
+    _say(f"  fp16 tol 1e-8: {st8['outer_iters']} iterations (fell back: {st8['fell_back']}), "
+         f"oracle residual {r8:.2e}, p error {err8:.2e}; tol 1e-11: {st11['outer_iters']} "
+         f"iterations, p error {err11:.2e}")
+    assert not st8["fell_back"] and not st11["fell_back"]
+    assert r8 <= 1.05e-8
+    assert err11 <= 1e-8
 
 
 @pytest.fixture(scope="module")

@@ -226,7 +226,13 @@ def _prolong_ref(eH, bc):
     return out
 
 
-@pytest.mark.parametrize("n,bc", RAGGED)
+# grids whose coarse level takes the restriction's grouped block order: two
+# x-blocks of 64 coarse columns with a partial last one, two block rows (the
+# second partial in the first case) and a multiple of 8 block planes
+XCD_GROUPED = [((144, 12, 16), (0, 1, 1)), ((144, 16, 32), (1, 0, 0))]
+
+
+@pytest.mark.parametrize("n,bc", RAGGED + XCD_GROUPED)
 def test_transfers(S, n, bc):
     _say(f"transfers n={n} bc={bc}")
     w = W.random_case(n, bc, seed=104)
@@ -538,6 +544,67 @@ def test_adjoint_matches_oracle(S, precision):
         assert relmax(host(g), g_o) <= 1e-8
         for m in range(3):
             assert relmax(host(gb[m]), gb_o[m]) <= 1e-8
+
+
+def test_adjoint_finite_differences_64(S):
+    """Config 4 at its own size (64^3, drop of density ratio 100): the
+    hand-written backward (mixed FP32 V-cycle, tol 1e-12) against central
+    differences of L = sum(w p) in 50 right-hand-side entries and 50 face
+    coefficients spread over the three directions.  The perturbed solves are
+    FP64, warm-started from the unperturbed p, to 1e-13; the coefficient
+    perturbations go through update_coeffs on one context.  Steps: 1e-6 of
+    the RMS of the right-hand side, 1e-6 absolute for beta."""
+    _say("adjoint FD config4 64^3")
+    w = W.config4(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    wt = dev(w.w)
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision="fp32") as sol:
+        p = sol.solve(dev(rhs), tol=1e-12)
+        g, gb = sol.adjoint(p, wt, tol=1e-12)
+        g_rhs = host(g)
+        g_b = [host(x) for x in gb]
+    rng = np.random.default_rng(3)
+    n = 64
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision="fp64", warm_start=True) as s64:
+        p0 = dev(np.zeros(w.shape))
+        s64.solve(dev(rhs), tol=1e-13, p=p0)
+
+        def L_of(rhs_):
+            pp = p0.clone()
+            s64.solve(rhs_, tol=1e-13, p=pp)
+            return float((wt * pp).sum())
+
+        d = 1e-6 * np.sqrt(np.mean(rhs ** 2))
+        rt = dev(rhs)
+        worst = 0.0
+        for _ in range(50):
+            c = tuple(int(v) for v in rng.integers(0, n, 3))
+            rt[c] += d
+            lp = L_of(rt)
+            rt[c] -= 2 * d
+            lm = L_of(rt)
+            rt[c] += d
+            fd = (lp - lm) / (2 * d)
+            worst = max(worst, abs(fd - g_rhs[c]) / np.abs(g_rhs).max())
+        _say(f"  rhs entries: worst |fd - adjoint| / max|g_rhs| = {worst:.2e}")
+        assert worst <= 1e-5
+        bdev = [dev(b) for b in beta]
+        worst = 0.0
+        for _ in range(50):
+            m = int(rng.integers(0, 3))
+            c = tuple(int(v) for v in rng.integers(0, n, 3))
+            bdev[m][c] += 1e-6
+            s64.update_coeffs(bdev)
+            lp = L_of(rt)
+            bdev[m][c] -= 2e-6
+            s64.update_coeffs(bdev)
+            lm = L_of(rt)
+            bdev[m][c] += 1e-6
+            fd = (lp - lm) / 2e-6
+            worst = max(worst, abs(fd - g_b[m][c]) / np.abs(g_b[m]).max())
+        _say(f"  face coefficients: worst |fd - adjoint| / max|g_beta| = {worst:.2e}")
+        assert worst <= 1e-4
 
 
 def test_autograd_finite_differences(S):
