@@ -78,6 +78,25 @@ int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *beta_x, const f
                                float *e_out, int32_t first_colour, double *dot,
                                void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same pass as
+ * pp_k_smooth2_fused_dot_f32, with the same arguments and the same results
+ * bit for bit (e_out and *dot), that allocates nothing and does not wait for
+ * the stream.  Its workgroup partial sums go to a static device array of
+ * 65,536 FP64 values (512 KiB) that each GPU the library runs on holds until
+ * the process ends; grids needing more partials than that,
+ * ceil(nx/64) * ceil(ny/8) * ceil(nz/8) > 65,536 (512^3 needs 32,768), are
+ * rejected with PP_EINVAL.  Every partial the sum reads is written by the
+ * same call, so nothing carries over between calls.  All calls on one GPU
+ * share the array: calls that overlap in time on one GPU (different streams
+ * or threads) race and must be serialised by the caller.  hip_stream must
+ * belong to the calling thread's current device (NULL = its default
+ * stream).  *dot is ready when the stream reaches the end of the call. */
+int pp_k_smooth2_fused_dot_f32_noalloc(const pp_grid *grid, const float *beta_x,
+                                       const float *beta_y, const float *beta_z, const float *r,
+                                       const float *e_in, float *e_out, int32_t first_colour,
+                                       double *dot, void *hip_stream);
+
 /* rH[C] = (1/8) sum over the 8 fine cells c of C of (r - A e)[c].
  * grid: the fine grid (all n even); rH has n/2 cells per direction; beta,
  * e and r 16-byte aligned. */

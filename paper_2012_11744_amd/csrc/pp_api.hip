@@ -17,6 +17,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <utility>
@@ -1374,6 +1375,85 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
     return PP_OK;
 }
 
+// Arguments of the two-sweep pass that forms r . e_out (both entry points):
+// every check of pp_k_smooth2_fused_f32 plus the output pointer.  On success
+// *nparts_max bounds the number of workgroup partial sums the launch writes.
+int check_smooth2_dot(const char *who, const pp_grid *grid, const float *bx, const float *by,
+                      const float *bz, const float *r, const float *e_in, const float *e_out,
+                      int32_t first_colour, const double *dot, size_t *nparts_max)
+{
+    const std::string w(who);
+    if (!dot)
+        return fail(PP_EINVAL, w + ": NULL array");
+    if ((uintptr_t)dot & 7)
+        return fail(PP_EINVAL, w + ": dot must be 8-byte aligned");
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!fused_plane_fits(to_dims(grid), sizeof(float)))
+        return fail(PP_EINVAL, w + ": an x-y plane must stay below 2^31 bytes");
+    if (!bx || !by || !bz || !r || !e_in || !e_out)
+        return fail(PP_EINVAL, w + ": NULL array");
+    if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)r | (uintptr_t)e_in |
+         (uintptr_t)e_out) & 15)
+        return fail(PP_EINVAL, w + ": arrays must be 16-byte aligned");
+    if (e_in == e_out)
+        return fail(PP_EINVAL, w + ": e_in and e_out must not alias");
+    if (first_colour != 0 && first_colour != 1)
+        return fail(PP_EINVAL, w + ": first_colour must be 0 or 1");
+    if (grid->n[0] % 2)
+        return fail(PP_EINVAL, w + ": nx must be even");
+    for (int m = 0; m < 3; ++m)
+        if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
+            return fail(PP_EINVAL, w + ": periodic directions need an even cell count");
+    const Dims d = to_dims(grid);
+    if (!fused2_fits(d))
+        return fail(PP_EINVAL, w + ": every cell count must be >= 8");
+    // at most one partial per workgroup: tiles x z chunks of >= 8 planes
+    *nparts_max = (size_t)((d.nx + 63) / 64) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
+    return PP_OK;
+}
+
+// Workgroup partial sums of pp_k_smooth2_fused_dot_f32_noalloc live in this
+// fixed device array (512 KiB; each GPU the library runs on holds its own
+// copy until the process ends) instead of a buffer allocated per call.  Host
+// code must not pass `scratch` itself to a kernel: its device address comes
+// from hipGetSymbolAddress, taken once per device.
+constexpr size_t NOALLOC_PARTS = 65536;
+static __device__ __align__(256) double scratch[NOALLOC_PARTS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the device that owns stream s (which must be
+// the calling thread's current device), looked up on the first call there.
+int noalloc_scratch(hipStream_t s, double **out)
+{
+    int dev = 0;
+    PP_HIP(hipGetDevice(&dev));
+    if (s) {
+        int sdev = -1;
+        PP_HIP(hipStreamGetDevice(s, &sdev));
+        if (sdev != dev)
+            return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32_noalloc: the stream belongs to "
+                                   "device " + std::to_string(sdev) + ", the current device is " +
+                                   std::to_string(dev));
+    }
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32_noalloc: device index beyond " +
+                                   std::to_string(MAX_DEVICES - 1));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        PP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            return fail(PP_EHIP, "pp_k_smooth2_fused_dot_f32_noalloc: no device address for the "
+                                 "scratch array");
+        g_scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return PP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1622,35 +1702,10 @@ int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *bx, const float
                                const float *bz, const float *r, const float *e_in, float *e_out,
                                int32_t first_colour, double *dot, void *hip_stream)
 {
-    if (!dot)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: NULL array");
-    if ((uintptr_t)dot & 7)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: dot must be 8-byte aligned");
-    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
-    if (!fused_plane_fits(to_dims(grid), sizeof(float)))
-        return fail(PP_EINVAL,
-                    "pp_k_smooth2_fused_dot_f32: an x-y plane must stay below 2^31 bytes");
-    // the checks of pp_k_smooth2_fused_f32, without launching anything yet
-    if (!bx || !by || !bz || !r || !e_in || !e_out)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: NULL array");
-    if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)r | (uintptr_t)e_in |
-         (uintptr_t)e_out) & 15)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: arrays must be 16-byte aligned");
-    if (e_in == e_out)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: e_in and e_out must not alias");
-    if (first_colour != 0 && first_colour != 1)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: first_colour must be 0 or 1");
-    if (grid->n[0] % 2)
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: nx must be even");
-    for (int m = 0; m < 3; ++m)
-        if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
-            return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: periodic directions need an even "
-                                   "cell count");
+    size_t nparts_max = 0;
+    PP_TRY(check_smooth2_dot("pp_k_smooth2_fused_dot_f32", grid, bx, by, bz, r, e_in, e_out,
+                             first_colour, dot, &nparts_max));
     const Dims d = to_dims(grid);
-    if (!fused2_fits(d))
-        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32: every cell count must be >= 8");
-    // partial sums: at most one per workgroup (tiles x chunks of >= 8 planes)
-    const size_t nparts_max = (size_t)((d.nx + 63) / 64) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
     double *part = nullptr;
     PP_HIP(hipMalloc((void **)&part, sizeof(double) * nparts_max));
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1665,6 +1720,36 @@ int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *bx, const float
     (void)hipStreamSynchronize(s);
     (void)hipFree(part);
     return rc != PP_OK ? rc : rl;
+}
+
+int pp_k_smooth2_fused_dot_f32_noalloc(const pp_grid *grid, const float *bx, const float *by,
+                                       const float *bz, const float *r, const float *e_in,
+                                       float *e_out, int32_t first_colour, double *dot,
+                                       void *hip_stream)
+{
+    size_t nparts_max = 0;
+    PP_TRY(check_smooth2_dot("pp_k_smooth2_fused_dot_f32_noalloc", grid, bx, by, bz, r, e_in,
+                             e_out, first_colour, dot, &nparts_max));
+    if (nparts_max > NOALLOC_PARTS)
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32_noalloc: the grid needs up to " +
+                                   std::to_string(nparts_max) +
+                                   " workgroup partial sums (ceil(nx/64) ceil(ny/8) ceil(nz/8)); "
+                                   "the static scratch holds " +
+                                   std::to_string(NOALLOC_PARTS));
+    hipStream_t s = (hipStream_t)hip_stream;
+    double *part = nullptr;
+    PP_TRY(noalloc_scratch(s, &part));
+    // the launch takes z chunks of at least 8 planes, so it never uses more
+    // than nparts_max partial sums (checked above against the array size)
+    const int np = launch_rbgs_fused2<float>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in,
+                                             e_out, nullptr, grid->h * grid->h, first_colour,
+                                             false, s, part);
+    PP_TRY(check_launch("pp_k_smooth2_fused_dot_f32_noalloc"));
+    if (np <= 0 || (size_t)np > nparts_max)
+        return fail(PP_EHIP, "pp_k_smooth2_fused_dot_f32_noalloc: unexpected workgroup count");
+    // every partial the finalising sum reads was written by this launch
+    launch_finalize(part, (size_t)np, np, OP_STORE, 0, 1.0, 0, dot, s);
+    return check_launch("pp_k_smooth2_fused_dot_f32_noalloc");
 }
 
 int pp_k_resid_restrict(const pp_grid *grid, const double *bx, const double *by, const double *bz,

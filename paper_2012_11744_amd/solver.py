@@ -335,6 +335,26 @@ def k_smooth2_fused_dot_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0):
     return float(dot[0].item())
 
 
+def k_smooth2_fused_dot_f32_noalloc(shape, h, bc, beta, r, e_in, e_out, dot, first_colour=0):
+    """The pass of k_smooth2_fused_dot_f32 through the entry point that
+    allocates nothing: its partial sums use the library's static device
+    array, and the result goes to `dot` (a float64 device tensor of at least
+    one element) on the current stream, without waiting."""
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    for t in (*beta, r, e_in, e_out):
+        if t.dtype != torch.float32:
+            raise TypeError("k_smooth2_fused_dot_f32_noalloc takes float32 fields")
+    if dot.dtype != torch.float64 or dot.numel() < 1:
+        raise TypeError("dot must be a float64 tensor of at least one element")
+    L.check(lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(g), *(_ptr(b) for b in beta),
+                                                   _ptr(r), _ptr(e_in), _ptr(e_out),
+                                                   int(first_colour), _ptr(dot),
+                                                   _stream_handle(None)),
+            "pp_k_smooth2_fused_dot_f32_noalloc")
+    return dot
+
+
 def k_resid_restrict(shape, h, bc, beta, e, r, rH):
     lib = L.load()
     g = make_grid(shape, h, bc)

@@ -142,6 +142,17 @@ def test_kernel_entries_validate(lib):
                                           ctypes.c_void_p(0x1004), None) == L.PP_EINVAL   # dot misaligned
     assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0,
                                           other, None) == L.PP_EINVAL     # aliasing
+    # the entry point that allocates nothing checks the same arguments, and
+    # rejects grids whose partial sums would not fit its static array
+    assert lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(g), fake, fake, fake, fake, fake,
+                                                  other, 0, None, None) == L.PP_EINVAL
+    assert lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(g), fake, fake, fake, fake, fake,
+                                                  fake, 0, other, None) == L.PP_EINVAL
+    big = _grid((1024, 1024, 1024), 1.0 / 1024, (0, 0, 0))   # 16 * 128 * 128 partial sums
+    assert lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(big), fake, fake, fake, fake, fake,
+                                                  other, 0, ctypes.c_void_p(0x3000),
+                                                  None) == L.PP_EINVAL
+    assert b"65536" in lib.pp_last_error()
     assert lib.pp_k_resid_restrict(ctypes.byref(g2), fake, fake, fake, fake, fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g2), fake, fake, None) == L.PP_EINVAL
     assert lib.pp_k_prolong_add(ctypes.byref(g), fake, ctypes.c_void_p(0x1008), None) == L.PP_EINVAL   # e misaligned
