@@ -18,7 +18,16 @@ its own and reported beside the forward figure.
 
 Prints one JSON line: the headline `value` is mixed-precision (FP32 V-cycle,
 FP64 outer) solves/s; FP64 and FP16-storage runs of the same steps are
-reported under "modes".
+reported under "modes", each with its max relative error of p, div(u) and u
+against the FP64 CPU oracle's solution of the same system (solved to 1e-13),
+computed after the timed region.  The same line carries, under "configs",
+the 128^3 bubbles at density ratio 1000 (walls; FP64 and mixed FP32:
+solves/s, iterations, errors against the oracle) and the 512^3 jet (walls;
+mixed FP32 forward and backward: ms, iterations, device memory).  The CPU
+baseline is the oracle's full projection step (face coefficients,
+divergence, MG-PCG to the same tolerance, projection) on the same 256^3
+system, median of 3 runs on all host threads, plus one run on one thread at
+128^3.
 """
 import argparse
 import json
@@ -45,8 +54,17 @@ def parse():
                     help="comma list; the first is the headline mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=12,
-                    help="oracle PCG iterations in the CPU-baseline sample")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the error metrics against the oracle")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 128^3 bubbles and 512^3 jet blocks")
+    ap.add_argument("--quick", action="store_true",
+                    help="timed steps only (no CPU baseline, errors, configs or adjoint): "
+                         "for profiling runs")
+    ap.add_argument("--cpu-repeats", type=int, default=3,
+                    help="oracle projection steps timed on all threads (median reported)")
+    ap.add_argument("--cpu-1thread-n", type=int, default=128,
+                    help="grid of the one-thread oracle run (same geometry; 0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time the plain copy kernel on 2 x 1 GiB buffers and exit (reference "
                          "for achievable HBM bandwidth and for scaling FETCH/WRITE counters)")
@@ -146,162 +164,21 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2012_11744_amd import _lib as L
-    from paper_2012_11744_amd import solver as S
     from paper_2012_11744_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.quick:
+        args.no_cpu_baseline = args.no_adjoint = args.no_errors = args.no_configs = True
     if args.workload == "jet512":
-        jet512(args)
+        print(json.dumps(bench_jet512(args)), flush=True)
         return
     N = args.n
     t0 = time.time()
     w = W.config3(N)
     log(f"[bench] workload {w.name} {N}^3 generated in {time.time() - t0:.1f}s")
-
-    def dev(a):
-        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
-
-    rho = dev(w.rho)
-    us = [dev(u) for u in w.us]
-    beta = tuple(torch.empty_like(rho) for _ in range(3))
-    b = torch.empty_like(rho)
-    p = torch.empty_like(rho)
-    u = tuple(torch.empty_like(rho) for _ in range(3))
-    S.face_coeffs(rho, w.h, w.bc, out=beta)
-
     modes = args.modes.split(",")
-    results = {}
-    roof = None
-    for mi, mode in enumerate(modes):
-        sol = S.Solver(beta, w.h, w.bc, precision=mode)
-
-        def step():
-            sol.update_density(rho)
-            sol.divergence(us, 1.0 / w.dt, out=b)
-            sol.solve(b, tol=args.tol, p=p)
-            sol.project(us, p, w.dt, out=u)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        iters = []
-        # timed region: exactly `steps` steps; HIP-event timers bracket the
-        # launches of the roofline kernel (fine-level smoother) only
-        sol.timing(True, kinds=[L.PP_KT_SMOOTH])
-        sol.timing_reset()
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-            iters.append(sol.last_stats["outer_iters"])
-        torch.cuda.synchronize()
-        t_end = time.perf_counter()
-        kt = {L.PP_KT_SMOOTH: sol.timing_get(L.PP_KT_SMOOTH)}
-        sol.timing(False)
-        ms = (t_end - t_start) * 1e3 / args.steps
-        # diagnostic pass (not the headline): the same steps without any timer,
-        # then with every fine-level kernel kind timed
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
-        sol.timing(True)
-        sol.timing_reset()
-        for _ in range(max(2, args.steps // 4)):
-            step()
-        torch.cuda.synchronize()
-        for k in range(L.PP_KT_COUNT):
-            if k != L.PP_KT_SMOOTH:
-                kt[k] = sol.timing_get(k)
-        sol.timing(False)
-        st = sol.last_stats
-        r = {
-            "solves_per_s": 1e3 / ms,
-            "ms_per_step": ms,
-            "ms_per_step_no_timers": ms_plain,
-            "dof_per_s": w.cells * 1e3 / ms,
-            "outer_iters": int(np.median(iters)),
-            "rel_res": st["rel_res"],
-            "fell_back": st["fell_back"],
-            "memory_bytes": sol.memory_bytes,
-        }
-        # fine-level smoother: each launch reads e_in, r and the three face
-        # coefficients once and writes e_out: 6 words per cell; the first
-        # launch of each cycle starts from zero and skips e_in (5 words).  FP32
-        # and FP16 storage run two sweeps per launch (one launch in two starts
-        # from zero with nu_pre = nu_post = 2), FP64 one sweep per launch (one
-        # in four).  In FP32 the post-smoothing launch also forms r . z, from
-        # values it holds already (no bytes of its own).
-        word = {"fp64": 8, "fp32": 4, "fp16": 2}[mode]
-        dword = 8 if mode == "fp64" else 4          # outer search direction
-        zero_share = 0.25 if mode == "fp64" else 0.5
-        n_sm, ms_sm = kt[L.PP_KT_SMOOTH]
-        n_rr, ms_rr = kt[L.PP_KT_RESTRICT]
-        n_oa, ms_oa = kt[L.PP_KT_OUTER_APPLY]
-        n_ou, ms_ou = kt[L.PP_KT_OUTER_UPDATE]
-        kern = {}
-        if n_sm:
-            avg = ms_sm / n_sm
-            byt = (6.0 - zero_share) * word * w.cells
-            kern["smoother_sweep"] = {"launches": n_sm, "avg_ms": avg, "alg_bytes": byt,
-                                      "GBps": byt / (avg * 1e-3) / 1e9}
-        if n_rr:
-            avg = ms_rr / n_rr
-            byt = (5 * word + word / 8) * w.cells   # e, r, 3 beta in; r_H out
-            kern["resid_restrict"] = {"launches": n_rr, "avg_ms": avg, "alg_bytes": byt,
-                                      "GBps": byt / (avg * 1e-3) / 1e9}
-        if n_oa:
-            avg = ms_oa / n_oa
-            # new direction + operator: z (V-cycle word) and rho in (the step
-            # loads the coefficients from the densities, so the kernel forms
-            # beta from them), D_new and q out; from the second iteration D_old
-            # in; the iterate takes two directions at a time, in the passes of
-            # even iterations from the second: x in and out and D_{k-2} in
-            n_it = max(1, r["outer_iters"])
-            n_hold = n_it // 2
-            n_two = n_it - 1 - n_hold
-            byt = ((16 + word + dword) + n_hold * (16 + word + 2 * dword)
-                   + n_two * (32 + word + 3 * dword)) / n_it * w.cells
-            kern["outer_apply"] = {"launches": n_oa, "avg_ms": avg, "alg_bytes": byt,
-                                   "GBps": byt / (avg * 1e-3) / 1e9}
-        if n_ou:
-            avg = ms_ou / n_ou
-            byt = (24 + word) * w.cells             # q, r in; r out; r_T out
-            kern["outer_update"] = {"launches": n_ou, "avg_ms": avg, "alg_bytes": byt,
-                                    "GBps": byt / (avg * 1e-3) / 1e9}
-        r["kernels"] = kern
-        if mi == 0 and "smoother_sweep" in kern:
-            k = kern["smoother_sweep"]
-            traffic, source = counter_traffic() if mode == "fp32" and N == 256 else (None, "other shape")
-            roof = {"kernel": "fused red-black Gauss-Seidel pass (fine level, %s, %s)"
-                              % (mode, "one sweep per launch" if mode == "fp64" else
-                                 "two sweeps per launch"),
-                    "bound": "hbm", "achieved": round(k["GBps"], 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(k["GBps"] / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "traffic_source": source,
-                    "alg_bytes_per_launch": k["alg_bytes"], "avg_launch_ms": k["avg_ms"]}
-        if not args.no_adjoint and mi == 0:
-            g_p = dev(w.us[0])
-            gr = torch.empty_like(rho)
-            for _ in range(2):
-                sol.adjoint(p, g_p, tol=args.tol)
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            for _ in range(max(3, args.steps // 4)):
-                sol.adjoint(p, g_p, tol=args.tol)
-            torch.cuda.synchronize()
-            r["adjoint_ms"] = (time.perf_counter() - ta) * 1e3 / max(3, args.steps // 4)
-            r["adjoint_iters"] = sol.last_stats["outer_iters"]
-            del gr
-        results[mode] = r
-        log(f"[bench] {mode}: {r['solves_per_s']:.1f} solves/s, {ms:.3f} ms/step "
-            f"(no timers {ms_plain:.3f}), iters={r['outer_iters']}, kernels="
-            + ", ".join(f"{k}={v['GBps']:.0f}GB/s" for k, v in kern.items()))
-        sol.close()
+    results, roof, fields = run_modes(w, modes, args, keep=not args.no_errors)
 
     copy = copy_bandwidth()
     log(f"[bench] copy kernel: {copy['GBps']:.0f} GB/s")
@@ -309,9 +186,20 @@ def main():
         roof["copy_kernel_GBps"] = round(copy["GBps"], 1)
         roof["frac_of_copy"] = round(roof["achieved"] / copy["GBps"], 4)
 
-    cpu = None
+    configs = {}
+    if not args.no_configs:
+        configs["bubbles128"] = bench_bubbles128(args)
+        configs["jet512"] = bench_jet512(args)
+
+    # host-side work from here on: nothing below is timed on the GPU
+    cpu, ref = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args)
+        cpu, ref = cpu_baseline(w, args)
+    if not args.no_errors:
+        errs = oracle_errors(w, fields, ref, args.tol)
+        for m, e in errs.items():
+            results[m].update(e)
+        del fields
 
     head = results[modes[0]]
     line = {
@@ -330,115 +218,464 @@ def main():
         "config": {"workload": f"layer+200 droplets, rho 1000/1.2, {N}^3, periodic x,y walls z, "
                                f"tol {args.tol:g}", "cells": w.cells, "parallelism": "single GPU"},
         "dof_per_s": round(head["dof_per_s"], 1),
-        "modes": {m: {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r.items()
-                      if k != "kernels"} for m, r in results.items()},
+        "modes": {m: {k: _fmt(v) for k, v in r.items() if k != "kernels"}
+                  for m, r in results.items()},
         "kernels": {m: r["kernels"] for m, r in results.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     if "fp64" in results and modes[0] != "fp64":
         line["mixed_over_fp64"] = round(head["solves_per_s"] / results["fp64"]["solves_per_s"], 3)
+    if configs:
+        line["configs"] = configs
     print(json.dumps(line), flush=True)
 
 
-def jet512(args):
-    """Forward (setup + divergence + mixed solve to 1e-8 + projection) and
-    backward (adjoint solve re-running the V-cycles + face products) at 512^3
-    with walls on all sides: ms and device memory per solve."""
+def _fmt(v):
+    if isinstance(v, float):
+        return float(f"{v:.6g}")
+    if isinstance(v, dict):
+        return {k: _fmt(x) for k, x in v.items()}
+    return v
+
+
+def _dev(a):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _step_fn(sol, rho, us, b, p, u, w, tol):
+    """One projection step for the density field rho: coefficients and
+    hierarchy, right-hand side, solve, projection."""
+    def step():
+        sol.update_density(rho)
+        sol.divergence(us, 1.0 / w.dt, out=b)
+        sol.solve(b, tol=tol, p=p)
+        sol.project(us, p, w.dt, out=u)
+    return step
+
+
+def run_modes(w, modes, args, keep):
+    """Times `steps` projection steps per V-cycle precision on the workload;
+    returns per-mode results, the roofline object of the first mode and (when
+    keep) host copies of p and u of each mode's last step."""
     import numpy as np
     import torch
 
+    from paper_2012_11744_amd import _lib as L
     from paper_2012_11744_amd import solver as S
-    from paper_2012_11744_amd import workloads as W
-    t0 = time.time()
-    w = W.config5(512)
-    log(f"[bench] jet 512^3 generated in {time.time() - t0:.1f}s")
 
-    def dev(a):
-        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
-
-    rho = dev(w.rho)
-    us = [dev(u) for u in w.us]
-    wt = dev(w.w)
+    rho = _dev(w.rho)
+    us = [_dev(u) for u in w.us]
     beta = tuple(torch.empty_like(rho) for _ in range(3))
     b = torch.empty_like(rho)
     p = torch.empty_like(rho)
     u = tuple(torch.empty_like(rho) for _ in range(3))
     S.face_coeffs(rho, w.h, w.bc, out=beta)
-    torch.cuda.synchronize()
-    fields = torch.cuda.memory_allocated()
-    sol = S.Solver(beta, w.h, w.bc, precision="fp32")
+    results, fields = {}, {}
+    roof = None
+    for mi, mode in enumerate(modes):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        sol = S.Solver(beta, w.h, w.bc, precision=mode)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - ts) * 1e3
+        step = _step_fn(sol, rho, us, b, p, u, w, args.tol)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        iters = []
+        # timed region: exactly `steps` steps; HIP-event timers bracket the
+        # launches of the roofline kernel (fine-level smoother) only
+        sol.timing(True, kinds=[L.PP_KT_SMOOTH])
+        sol.timing_reset()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+            iters.append(sol.last_stats["outer_iters"])
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+        kt = {L.PP_KT_SMOOTH: sol.timing_get(L.PP_KT_SMOOTH)}
+        sol.timing(False)
+        ms = (t_end - t_start) * 1e3 / args.steps
+        st = sol.last_stats
+        if keep:
+            fields[mode] = (p.cpu().numpy(), [c.cpu().numpy() for c in u], st["rel_res"])
+        # diagnostic passes (not the headline): the same steps without any
+        # timer; every fine-level kernel kind timed; the parts of a step
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
+        sol.timing(True)
+        sol.timing_reset()
+        for _ in range(max(2, args.steps // 4)):
+            step()
+        torch.cuda.synchronize()
+        for k in range(L.PP_KT_COUNT):
+            if k != L.PP_KT_SMOOTH:
+                kt[k] = sol.timing_get(k)
+        sol.timing(False)
+        parts = step_parts(sol, rho, us, b, p, u, w, args.tol, reps=max(2, args.steps // 4))
+        r = {
+            "solves_per_s": 1e3 / ms,
+            "ms_per_step": ms,
+            "ms_per_step_no_timers": ms_plain,
+            "dof_per_s": w.cells * 1e3 / ms,
+            "outer_iters": int(np.median(iters)),
+            "rel_res": st["rel_res"],
+            "fell_back": st["fell_back"],
+            "memory_bytes": sol.memory_bytes,
+            "setup_ms": setup_ms,
+            "step_parts_ms": parts,
+        }
+        r["kernels"] = kernel_rates(mode, kt, r["outer_iters"], w.cells)
+        kern = r["kernels"]
+        if mi == 0 and "smoother_sweep" in kern:
+            k = kern["smoother_sweep"]
+            traffic, source = (counter_traffic() if mode == "fp32" and w.n[0] == 256
+                               else (None, "other shape"))
+            roof = {"kernel": "fused red-black Gauss-Seidel pass (fine level, %s, %s)"
+                              % (mode, "one sweep per launch" if mode == "fp64" else
+                                 "two sweeps per launch"),
+                    "bound": "hbm", "achieved": round(k["GBps"], 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(k["GBps"] / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "traffic_source": source,
+                    "alg_bytes_per_launch": k["alg_bytes"], "avg_launch_ms": k["avg_ms"]}
+        if not args.no_adjoint and mi == 0:
+            g_p = _dev(w.us[0])
+            for _ in range(2):
+                sol.adjoint(p, g_p, tol=args.tol)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            na = max(3, args.steps // 4)
+            for _ in range(na):
+                sol.adjoint(p, g_p, tol=args.tol)
+            torch.cuda.synchronize()
+            r["adjoint_ms"] = (time.perf_counter() - ta) * 1e3 / na
+            r["adjoint_iters"] = sol.last_stats["outer_iters"]
+            del g_p
+        results[mode] = r
+        log(f"[bench] {mode}: {r['solves_per_s']:.1f} solves/s, {ms:.3f} ms/step "
+            f"(no timers {ms_plain:.3f}), iters={r['outer_iters']}, setup {setup_ms:.1f} ms, "
+            f"parts {parts}, kernels="
+            + ", ".join(f"{k}={v['GBps']:.0f}GB/s" for k, v in kern.items()))
+        sol.close()
+    del rho, us, beta, b, p, u
+    torch.cuda.empty_cache()
+    return results, roof, fields
 
-    def forward():
+
+def step_parts(sol, rho, us, b, p, u, w, tol, reps):
+    """Mean device time of each part of a step (HIP events on the stream),
+    measured in a loop of its own after the timed region."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    acc = [0.0] * 4
+    for _ in range(reps):
+        ev[0].record()
         sol.update_density(rho)
+        ev[1].record()
         sol.divergence(us, 1.0 / w.dt, out=b)
-        sol.solve(b, tol=args.tol, p=p)
+        ev[2].record()
+        sol.solve(b, tol=tol, p=p)
+        ev[3].record()
         sol.project(us, p, w.dt, out=u)
-
-    reps = max(2, args.steps // 4)
-    forward()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(reps):
-        forward()
-    torch.cuda.synchronize()
-    fwd_ms = (time.perf_counter() - t1) * 1e3 / reps
-    fwd_it = sol.last_stats["outer_iters"]
-    sol.adjoint(p, wt, tol=args.tol)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(reps):
-        g = sol.adjoint(p, wt, tol=args.tol)
-        del g
-    torch.cuda.synchronize()
-    bwd_ms = (time.perf_counter() - t2) * 1e3 / reps
-    bwd_it = sol.last_stats["outer_iters"]
-    peak = torch.cuda.max_memory_allocated()
-    line = {
-        "metric": "pressure projection forward + backward at 512^3, ms and device memory per solve",
-        "workload": "jet along x, rho 800 / 1, 512^3, walls, mixed FP32 V-cycle in FP64 PCG, tol %g"
-                    % args.tol,
-        "forward_ms": round(fwd_ms, 3), "forward_iters": fwd_it,
-        "backward_ms": round(bwd_ms, 3), "backward_iters": bwd_it,
-        "solver_context_bytes": sol.memory_bytes,
-        "torch_fields_bytes": int(fields),
-        "torch_peak_bytes_with_backward_outputs": int(peak),
-        "cells": w.cells, "reps": reps,
-    }
-    sol.close()
-    print(json.dumps(line), flush=True)
+        ev[4].record()
+        torch.cuda.synchronize()
+        for i in range(4):
+            acc[i] += ev[i].elapsed_time(ev[i + 1])
+    names = ("update_density", "divergence", "solve", "project")
+    return {n: round(a / reps, 4) for n, a in zip(names, acc)}
 
 
-def cpu_baseline(w, args):
-    """The FP64 CPU oracle on a bounded sample of the same solve: its MG-PCG
-    on the full-size system, capped at a few iterations; solves/s is scaled
-    by the iteration count needed for tol, extrapolated from the observed
-    residual reduction per iteration."""
+def kernel_rates(mode, kt, n_it, cells):
+    """Algorithmic GB/s of the fine-level kernel kinds timed by the library."""
+    from paper_2012_11744_amd import _lib as L
+    # fine-level smoother: each launch reads e_in, r and the three face
+    # coefficients once and writes e_out: 6 words per cell; the first
+    # launch of each cycle starts from zero and skips e_in (5 words).  FP32
+    # and FP16 storage run two sweeps per launch (one launch in two starts
+    # from zero with nu_pre = nu_post = 2), FP64 one sweep per launch (one
+    # in four).  In FP32 the post-smoothing launch also forms r . z, from
+    # values it holds already (no bytes of its own).
+    word = {"fp64": 8, "fp32": 4, "fp16": 2}[mode]
+    dword = 8 if mode == "fp64" else 4          # outer search direction
+    zero_share = 0.25 if mode == "fp64" else 0.5
+    n_sm, ms_sm = kt[L.PP_KT_SMOOTH]
+    n_rr, ms_rr = kt[L.PP_KT_RESTRICT]
+    n_oa, ms_oa = kt[L.PP_KT_OUTER_APPLY]
+    n_ou, ms_ou = kt[L.PP_KT_OUTER_UPDATE]
+    kern = {}
+
+    def put(name, n, ms, byt):
+        avg = ms / n
+        kern[name] = {"launches": n, "avg_ms": avg, "alg_bytes": byt,
+                      "GBps": byt / (avg * 1e-3) / 1e9}
+
+    if n_sm:
+        put("smoother_sweep", n_sm, ms_sm, (6.0 - zero_share) * word * cells)
+    if n_rr:
+        put("resid_restrict", n_rr, ms_rr, (5 * word + word / 8) * cells)  # e, r, 3 beta; r_H
+    if n_oa:
+        # new direction + operator: z (V-cycle word) and rho in (the step
+        # loads the coefficients from the densities, so the kernel forms
+        # beta from them), D_new and q out; from the second iteration D_old
+        # in; the iterate takes two directions at a time, in the passes of
+        # even iterations from the second: x in and out and D_{k-2} in
+        n_it = max(1, n_it)
+        n_hold = n_it // 2
+        n_two = n_it - 1 - n_hold
+        put("outer_apply", n_oa, ms_oa,
+            ((16 + word + dword) + n_hold * (16 + word + 2 * dword)
+             + n_two * (32 + word + 3 * dword)) / n_it * cells)
+    if n_ou:
+        put("outer_update", n_ou, ms_ou, (24 + word) * cells)   # q, r in; r, r_T out
+    return kern
+
+
+def errors_vs(w, beta, p_ref, p, u):
+    """Max relative errors of a GPU answer against the oracle's: p, D u (at
+    the scale of D u*) and u (at the scale of u*); plus the oracle's FP64
+    relative residual of the GPU p."""
     import numpy as np
 
+    import oracle
+    u_ref = oracle.project(beta, w.bc, w.h, w.dt, w.us, p_ref)
+    du = oracle.divergence(u, w.bc, w.h)
+    du_ref = oracle.divergence(u_ref, w.bc, w.h)
+    dus = np.abs(oracle.divergence(w.us, w.bc, w.h)).max()
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    bm = rhs - rhs.mean()
+    res = np.linalg.norm(bm - oracle.apply(beta, w.bc, w.h, p)) / np.linalg.norm(bm)
+    return {
+        "err_p": float(np.abs(p - p_ref).max() / np.abs(p_ref).max()),
+        "err_div": float(np.abs(du - du_ref).max() / dus),
+        "err_u": float(max(np.abs(u[m] - u_ref[m]).max() for m in range(3))
+                       / max(np.abs(c).max() for c in w.us)),
+        "rel_res_oracle": float(res),
+    }
+
+
+def oracle_reference(w, p0=None):
+    """The oracle's solution of the workload's system to 1e-13 (warm-started
+    from p0 when given)."""
+    import oracle
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    t0 = time.perf_counter()
+    p_ref, it, rel = oracle.solve(beta, w.bc, w.h, rhs, tol=1e-13, p0=p0)
+    log(f"[bench] oracle reference {w.name} {w.n}: {it} iterations to rel {rel:.2e} "
+        f"in {time.perf_counter() - t0:.1f}s")
+    return beta, p_ref
+
+
+def oracle_errors(w, fields, ref, tol):
+    """Errors of each mode's last step against the oracle (solved to 1e-13)."""
+    _beta, p_ref = oracle_reference(w, p0=None if ref is None else ref)
+    out = {}
+    for mode, (p, u, _rel) in fields.items():
+        out[mode] = errors_vs(w, _beta, p_ref, p, u)
+        log(f"[bench] {mode} vs oracle: " + ", ".join(f"{k}={v:.2e}" for k, v in out[mode].items()))
+    return out
+
+
+def bench_bubbles128(args):
+    """128^3, walls, 20 gas bubbles in liquid at density ratio 1000 (seed 1),
+    gravity term in u*: FP64 and mixed FP32 projection steps to args.tol
+    (solves/s, iterations), with errors against the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2012_11744_amd import solver as S
+    from paper_2012_11744_amd import workloads as W
+    w = W.config2(128)
+    rho = _dev(w.rho)
+    us = [_dev(u) for u in w.us]
+    beta = S.face_coeffs(rho, w.h, w.bc)
+    b, p = torch.empty_like(rho), torch.empty_like(rho)
+    u = tuple(torch.empty_like(rho) for _ in range(3))
+    out, fields = {}, {}
+    steps = max(5, args.steps // 2)
+    for mode in ("fp64", "fp32"):
+        with S.Solver(beta, w.h, w.bc, precision=mode) as sol:
+            step = _step_fn(sol, rho, us, b, p, u, w, args.tol)
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iters = []
+            for _ in range(steps):
+                step()
+                iters.append(sol.last_stats["outer_iters"])
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            st = sol.last_stats
+            out[mode] = {"solves_per_s": 1e3 / ms, "ms_per_step": ms,
+                         "outer_iters": int(np.median(iters)), "rel_res": st["rel_res"],
+                         "fell_back": st["fell_back"]}
+            fields[mode] = (p.cpu().numpy(), [c.cpu().numpy() for c in u])
+        log(f"[bench] bubbles 128^3 {mode}: {1e3 / ms:.1f} solves/s, {ms:.3f} ms/step, "
+            f"iters={out[mode]['outer_iters']}")
+    del rho, us, beta, b, p, u
+    torch.cuda.empty_cache()
+    if not args.no_errors:
+        beta_o, p_ref = oracle_reference(w)
+        for mode, (ph, uh) in fields.items():
+            out[mode].update(errors_vs(w, beta_o, p_ref, ph, uh))
+    res = {"workload": "20 gas bubbles in liquid, rho 1000/1, 128^3, walls, gravity in u*, "
+                       f"tol {args.tol:g}", "steps": steps}
+    res.update({m: _fmt(v) for m, v in out.items()})
+    if "fp64" in out and "fp32" in out:
+        res["mixed_over_fp64"] = round(out["fp32"]["solves_per_s"] / out["fp64"]["solves_per_s"], 3)
+    return res
+
+
+def bench_jet512(args):
+    """Forward (coefficients and hierarchy from rho, divergence, mixed solve
+    to tol, projection) and backward (adjoint solve re-running the V-cycles,
+    face products) at 512^3 with walls on all sides: ms and iterations per
+    solve, device memory, and the oracle's FP64 residuals of the answers."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2012_11744_amd import solver as S
+    from paper_2012_11744_amd import workloads as W
+    t0 = time.time()
+    w = W.config5(512)
+    log(f"[bench] jet 512^3 generated in {time.time() - t0:.1f}s")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, total = torch.cuda.mem_get_info()
+    rho = _dev(w.rho)
+    us = [_dev(u) for u in w.us]
+    wt = _dev(w.w)
+    beta = S.face_coeffs(rho, w.h, w.bc)
+    b, p = torch.empty_like(rho), torch.empty_like(rho)
+    u = tuple(torch.empty_like(rho) for _ in range(3))
+    sol = S.Solver(beta, w.h, w.bc, precision="fp32")
+    fwd = _step_fn(sol, rho, us, b, p, u, w, args.tol)
+    reps = 3
+    fwd()
+    torch.cuda.synchronize()
+    tf = []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        fwd()
+        torch.cuda.synchronize()
+        tf.append((time.perf_counter() - t1) * 1e3)
+    fwd_it = sol.last_stats["outer_iters"]
+    g = sol.adjoint(p, wt, tol=args.tol)
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(reps):
+        del g
+        t2 = time.perf_counter()
+        g = sol.adjoint(p, wt, tol=args.tol)
+        torch.cuda.synchronize()
+        tb.append((time.perf_counter() - t2) * 1e3)
+    bwd_it = sol.last_stats["outer_iters"]
+    free1, _ = torch.cuda.mem_get_info()
+    res = {
+        "workload": "jet along x, rho 800/1, 512^3, walls, mixed FP32 V-cycle in FP64 PCG, "
+                    f"tol {args.tol:g}",
+        "forward_ms": round(float(np.median(tf)), 3), "forward_iters": fwd_it,
+        "backward_ms": round(float(np.median(tb)), 3), "backward_iters": bwd_it,
+        "solver_context_bytes": sol.memory_bytes,
+        "device_bytes_in_use": int(free0 - free1),
+        "device_bytes_note": "fields (rho, u*, w, beta, b, p, u), solver context and adjoint "
+                             "outputs (lambda, 3 face products), all resident at once",
+        "cells": w.cells, "reps": reps,
+    }
+    if not args.no_errors:
+        ph, lh = p.cpu().numpy(), g[0].cpu().numpy()
+        uh = [c.cpu().numpy() for c in u]
+        betah = [x.cpu().numpy() for x in beta]
+        rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+        bm = rhs - rhs.mean()
+        res["rel_res_oracle"] = float(np.linalg.norm(bm - oracle.apply(betah, w.bc, w.h, ph))
+                                      / np.linalg.norm(bm))
+        du = oracle.divergence(uh, w.bc, w.h)
+        res["rel_div_u"] = float(np.linalg.norm(du) / np.linalg.norm(
+            oracle.divergence(w.us, w.bc, w.h)))
+        wm = w.w - w.w.mean()
+        res["adjoint_rel_res_oracle"] = float(
+            np.linalg.norm(wm - oracle.apply(betah, w.bc, w.h, lh)) / np.linalg.norm(wm))
+    sol.close()
+    del rho, us, wt, beta, b, p, u, g
+    torch.cuda.empty_cache()
+    log(f"[bench] jet 512^3: forward {res['forward_ms']} ms ({fwd_it} iterations), backward "
+        f"{res['backward_ms']} ms ({bwd_it} iterations), device bytes {res['device_bytes_in_use']}")
+    return res
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_projection_step(w, tol):
+    """The oracle's projection step (face coefficients, divergence, solve to
+    tol, projection); returns (seconds, p, iterations, rel_res)."""
     import oracle
     t0 = time.perf_counter()
     beta = oracle.face_coeffs(w.rho, w.bc)
     rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
-    t_setup = time.perf_counter() - t0
-    k = args.cpu_sample_iters
-    t1 = time.perf_counter()
-    _, it, rel = oracle.solve(beta, w.bc, w.h, rhs, tol=args.tol, maxit=k, check=False)
-    t_solve = time.perf_counter() - t1
-    if rel <= args.tol:
-        need = it
-    else:
-        rate = rel ** (1.0 / max(it, 1))
-        need = it * math.log(args.tol) / math.log(rel) if rate < 1 else float("inf")
-    per_iter = t_solve / max(it, 1)
-    est = t_setup + per_iter * need
-    log(f"[bench] cpu oracle: {it} iterations in {t_solve:.1f}s (rel {rel:.2e}), "
-        f"~{need:.1f} needed -> {est:.1f}s per solve on {oracle.threads()} threads")
-    return {"value": round(1.0 / est, 6), "unit": "solves/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"oracle FP64 MG-PCG on the same {w.n[0]}^3 system, {it} iterations "
-                      f"({t_solve:.1f}s, rel res {rel:.2e}); per-solve time = setup + "
-                      f"per-iteration time x {need:.1f} iterations extrapolated to tol {args.tol:g}"}
+    p, it, rel = oracle.solve(beta, w.bc, w.h, rhs, tol=tol)
+    oracle.project(beta, w.bc, w.h, w.dt, w.us, p)
+    return time.perf_counter() - t0, p, it, rel
+
+
+def cpu_baseline(w, args):
+    """The FP64 CPU oracle's full projection step on the same system and
+    tolerance, timed: median of args.cpu_repeats runs on all host threads,
+    then one run on one thread of the same geometry at args.cpu_1thread_n^3.
+    Returns the baseline object and the last p (a warm start for the error
+    reference)."""
+    import numpy as np
+
+    import oracle
+    from paper_2012_11744_amd import workloads as W
+    threads = oracle.threads()
+    runs = []
+    p = None
+    for _ in range(max(1, args.cpu_repeats)):
+        t, p, it, rel = cpu_projection_step(w, args.tol)
+        runs.append(t)
+        log(f"[bench] cpu oracle step: {t:.2f}s ({it} iterations, rel {rel:.2e}, "
+            f"{threads} threads)")
+    med = float(np.median(runs))
+    one = None
+    if args.cpu_1thread_n > 0:
+        w1 = W.config3(args.cpu_1thread_n)
+        oracle.set_threads(1)
+        try:
+            t1, _, it1, rel1 = cpu_projection_step(w1, args.tol)
+        finally:
+            oracle.set_threads(threads)
+        one = {"value": round(1.0 / t1, 6), "unit": "solves/s", "cores": 1,
+               "workload": f"the same geometry at {args.cpu_1thread_n}^3", "seconds": round(t1, 3),
+               "iterations": it1, "rel_res": rel1}
+        log(f"[bench] cpu oracle step, 1 thread, {args.cpu_1thread_n}^3: {t1:.2f}s "
+            f"({it1} iterations)")
+    out = {"value": round(1.0 / med, 6), "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"measured: the oracle's full projection step (face coefficients, "
+                     f"divergence, FP64 MG-PCG to rel. residual {args.tol:g}, projection) on "
+                     f"the same {w.n[0]}^3 system, {it} iterations (rel {rel:.2e}), median of "
+                     f"{len(runs)} runs on {threads} threads",
+           "runs_s": [round(x, 3) for x in runs], "iterations": it, "cpu_model": cpu_model(),
+           "one_thread": one}
+    return out, p
 
 
 if __name__ == "__main__":

@@ -104,6 +104,14 @@ def threads() -> int:
     return int(_load().ppo_threads())
 
 
+def set_threads(n: int) -> None:
+    """Run later oracle calls (from this Python thread) on n OpenMP threads."""
+    lib = _load()
+    lib.ppo_set_threads.argtypes = [ctypes.c_int]
+    lib.ppo_set_threads.restype = None
+    lib.ppo_set_threads(int(n))
+
+
 def _grid(shape, bc):
     nz, ny, nx = shape
     n = (ctypes.c_int64 * 3)(nx, ny, nz)

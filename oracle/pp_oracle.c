@@ -128,6 +128,18 @@ EXPORT int ppo_threads(void)
 #endif
 }
 
+/* number of threads later parallel loops of the calling thread use (n >= 1);
+   for timing only: sums over cells may then group their terms differently */
+EXPORT void ppo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* face coefficients, divergence, operator, projection                       */
 /* ------------------------------------------------------------------------ */
