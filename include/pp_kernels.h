@@ -11,9 +11,14 @@
  * Gauss-Seidel of Sec. 3.7.1 (eq. beta_pressure) with over-relaxation 1.
  * Transfer operators are not given in the paper; the readings used:
  *   restriction   r_H = mean of the 8 fine residuals of a coarse cell,
- *   prolongation  trilinear in cell centres (weights 3/4, 1/4 per axis; at a
- *                 wall the missing coarse neighbour is the cell itself),
- *   coarse beta   mean of the 4 fine faces that make up a coarse face.
+ *   prolongation  cell-centred, per axis between the parent (weight 1 - w)
+ *                 and the next coarse cell on the fine cell's side (w), the
+ *                 axes composed as a product; w follows the face
+ *                 coefficients (pp_k_prolong_weights; 1/4 for equal ones,
+ *                 i.e. trilinear interpolation); at a wall the missing coarse
+ *                 neighbour is the parent itself,
+ *   coarse beta   the mean of two estimates of the conductance between two
+ *                 coarse cell centres (pp_k_coarsen_beta).
  * Each call validates its arguments, enqueues on `hip_stream` (NULL = default
  * stream) and returns a pp_status.
  */
@@ -105,12 +110,48 @@ int pp_k_resid_restrict(const pp_grid *grid, const double *beta_x, const double 
                         void *hip_stream);
 
 /* e += P eH, trilinear cell-centred prolongation (3/4 parent, 1/4 the next
- * coarse cell per axis; at a wall the parent itself).  grid: the fine grid
- * (all n even); eH has n/2 cells per direction; e 16-byte aligned. */
+ * coarse cell per axis; at a wall the parent itself): the weighted
+ * prolongation below with every weight 1/4.  grid: the fine grid (all n
+ * even); eH has n/2 cells per direction; e 16-byte aligned. */
 int pp_k_prolong_add(const pp_grid *grid, const double *eH, double *e, void *hip_stream);
 
-/* Coarse face coefficients: mean of the 4 fine faces of each coarse face
- * (wall faces stay 0).  grid: the fine grid; outputs have n/2 cells each. */
+/* Prolongation weights of every cell of a level (the multigrid V-cycle's
+ * interpolation follows the coefficients; the paper gives no transfer
+ * operators).  Along an axis a fine cell lies between its parent's centre
+ * and the next coarse centre on its side; over that interval the links are
+ * half the link between the two children (coefficient gn), the cell's outer
+ * face (gm) and half the link beyond it (gf), and the weight of the next
+ * coarse cell is the near half link's share of their series resistance:
+ *   w = gm gf / (gm gf + gn (2 gf + gm))      (0 when the denominator is 0)
+ * i.e. 1/4 for equal coefficients, near 0 for a cell tied to its parent by a
+ * strong link and to the next cell through weak ones, 0 at a wall.  For an
+ * even index i along the axis gn, gm, gf are the faces i+1, i, i-1, for an
+ * odd one i, i+1, i+2 (wrapped; in a wall direction the face of wrapped
+ * index 0 counts as 0).  beta_*: FP64 n cells each.  w: n 32-bit words,
+ * written: the x, y and z weights as 8-bit fractions q/256 in bits 0-7,
+ * 8-15 and 16-23, q = min(255, floor(256 w + 1/2)); bits 24-31 zero. */
+int pp_k_prolong_weights(const pp_grid *grid, const double *beta_x, const double *beta_y,
+                         const double *beta_z, uint32_t *w, void *hip_stream);
+
+/* e += P eH with the weights of pp_k_prolong_weights (fine-grid cells): per
+ * axis (1 - w) times the parent plus w times the next coarse cell on the
+ * fine cell's side (the parent itself at a wall), the three axes composed
+ * as a product.  grid: the fine grid (all n even); eH has n/2 cells per
+ * direction; e 16-byte and w 8-byte aligned. */
+int pp_k_prolong_add_weighted(const pp_grid *grid, const double *eH, const uint32_t *w,
+                              double *e, void *hip_stream);
+
+/* Coarse face coefficients (wall faces stay 0).  Each of the 4 fine rows
+ * that cross a coarse face I contributes its faces lo = 2I-1, mid = 2I and
+ * hi = 2I+1 along the normal; the coarse coefficient is the mean of
+ *   (a) the mean of the 4 mid faces (the rows in parallel, each taken at the
+ *       coarse face: exact when the coefficients vary only across the face)
+ *   (b) the mean of the 4 series coefficients 2 / (1/(2 lo) + 1/mid + 1/(2 hi))
+ *       (each row's links in series between the two coarse centres: exact
+ *       when they vary only along the normal; 0 if a link is closed).
+ * (a) overrates a face that cuts through a small inclusion of large
+ * coefficient, (b) ignores flow between the rows.  grid: the fine grid;
+ * outputs have n/2 cells each. */
 int pp_k_coarsen_beta(const pp_grid *grid, const double *beta_x, const double *beta_y,
                       const double *beta_z, double *bH_x, double *bH_y, double *bH_z,
                       void *hip_stream);

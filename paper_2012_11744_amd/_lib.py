@@ -69,7 +69,8 @@ EXPORTS = [
     "pp_apply", "pp_solve", "pp_project", "pp_solve_adjoint", "pp_levels", "pp_level_dims",
     "pp_memory", "pp_destroy", "pp_strerror", "pp_last_error",
     "pp_k_smooth", "pp_k_smooth_fused", "pp_k_smooth2_fused_f32", "pp_k_smooth2_fused_dot_f32",
-    "pp_k_smooth2_fused_dot_f32_noalloc", "pp_k_resid_restrict", "pp_k_prolong_add", "pp_k_coarsen_beta", "pp_vcycle",
+    "pp_k_smooth2_fused_dot_f32_noalloc", "pp_k_resid_restrict", "pp_k_prolong_add",
+    "pp_k_prolong_weights", "pp_k_prolong_add_weighted", "pp_k_coarsen_beta", "pp_vcycle",
     "pp_k_copy", "pp_timing_enable", "pp_timing_reset", "pp_timing_get",
 ]
 
@@ -118,6 +119,8 @@ def load():
         "pp_k_smooth2_fused_dot_f32_noalloc": (I, [GP, P, P, P, P, P, P, I32, P, P]),
         "pp_k_resid_restrict": (I, [GP, P, P, P, P, P, P, P]),
         "pp_k_prolong_add": (I, [GP, P, P, P]),
+        "pp_k_prolong_weights": (I, [GP, P, P, P, P, P]),
+        "pp_k_prolong_add_weighted": (I, [GP, P, P, P, P]),
         "pp_k_coarsen_beta": (I, [GP, P, P, P, P, P, P, P]),
         "pp_vcycle": (I, [P, P, P]),
         "pp_k_copy": (I, [P, P, ctypes.c_int64, P]),

@@ -108,6 +108,9 @@ struct pp_ctx {
     Dims ld[MAXLEV];
     double lh[MAXLEV];
     double *chain[MAXLEV][3];   // FP64 face coefficients per level; chain[0] = the fine copy
+    // prolongation weights (one packed word per cell) of every level but the
+    // coarsest, formed from the chain: shared by both hierarchies
+    unsigned *pw[MAXLEV];
     // general operator A - diag(sigma) (pp_setup_general): closed links
     // allowed; sigma per level in FP64 (coarse sigma = mean of the 8
     // children); the active cells of level 0 and their count
@@ -504,6 +507,16 @@ int read_scal(pp_ctx *c)
 
 int nparts(pp_ctx *c) { return (int)grid_blocks(red_grid(c->d)); }
 
+// the prolongation weights of the levels from `from` on (all but the
+// coarsest), from the FP64 chain
+int build_weights(pp_ctx *c, int from)
+{
+    for (int l = from; l + 1 < c->nlev; ++l)
+        launch_prolong_weights(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
+                               c->pw[l], c->stream);
+    return check_launch("prolongation weights");
+}
+
 // General operator: copy and check beta (closed links allowed) and sigma,
 // mark the active cells, coarsen both through the levels, fill the storage
 // hierarchies and build the coarsest pseudo-inverse.
@@ -540,6 +553,7 @@ int load_coeffs_general(pp_ctx *c, const double *bx, const double *by, const dou
             launch_coarsen_sigma(c->ld[l], c->sig[l], c->sig[l + 1], c->stream);
     }
     PP_TRY(check_launch("coarsen coefficients"));
+    PP_TRY(build_weights(c, 0));
     PP_TRY(read_scal(c));
     if (c->hscal[S_COUNT] != 0.0)
         return fail(PP_EINVAL, "beta: " + std::to_string((long long)c->hscal[S_COUNT]) +
@@ -584,9 +598,10 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
         auto one_pass = [&](auto *t) {
             using TT = std::remove_pointer_t<decltype(t)>;
             TT *tt[3] = {t, t ? (TT *)H.lev[0].b[1] : nullptr, t ? (TT *)H.lev[0].b[2] : nullptr};
-            return rho ? launch_load_density<TT>(c->d, c->bc, rho, dst, tt, crs, c->rho, c->part,
-                                                 c->stream)
-                       : launch_load_coeffs<TT>(c->d, c->bc, src, dst, tt, crs, c->part, c->stream);
+            return rho ? launch_load_density<TT>(c->d, c->bc, rho, dst, tt, crs, c->rho, c->pw[0],
+                                                 c->part, c->stream)
+                       : launch_load_coeffs<TT>(c->d, c->bc, src, dst, tt, crs, c->pw[0], c->part,
+                                                c->stream);
         };
         if (H.present && H.st == ST_F32) {
             np = one_pass((float *)H.lev[0].b[0]);
@@ -630,6 +645,7 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
         launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
                             c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2], c->stream);
     PP_TRY(check_launch("coarsen coefficients"));
+    PP_TRY(build_weights(c, first_coarse));   // the one-pass kernel formed level 0's
     PP_TRY(fill_hier(c, c->hmix, level0_converted ? 1 : 0));
     PP_TRY(enqueue_coarse_download(c));
     PP_TRY(read_scal(c));
@@ -730,7 +746,7 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
     const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
     {
         KT t(c, PP_KT_PROLONG, l == 0);
-        launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, s);
+        launch_prolong<T>(v.d, c->bc, (const T *)H.lev[l + 1].cur, (T *)v.cur, c->pw[l], s);
     }
     if (cells(v.d) > fused_min_cells<T>() && fused_plane_fits(v.d, sizeof(T))) {
         v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_post, v.cur, 1, false, s,
@@ -756,8 +772,10 @@ void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
     void *e[TAIL_MAX];
     void *r[TAIL_MAX];
     const void *sg[TAIL_MAX];
+    const unsigned *w[TAIL_MAX];
     for (int q = 0; q < n; ++q) {
         LevelBuf &v = H.lev[t + q];
+        w[q] = c->pw[t + q];
         d[q] = v.d;
         h2[q] = v.h * v.h;
         for (int m = 0; m < 3; ++m)
@@ -767,7 +785,7 @@ void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
         sg[q] = v.s;
         v.cur = v.e;
     }
-    launch_tail<T>(n, d, h2, b, e, r, sg, c->bc, c->opts.nu_coarse, c->opts.nu_coarse, c->pinv,
+    launch_tail<T>(n, d, h2, b, e, r, sg, w, c->bc, c->opts.nu_coarse, c->opts.nu_coarse, c->pinv,
                    c->ncoarse, s);
 }
 
@@ -1314,6 +1332,10 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
     for (int l = 0; l < nlev && rc == PP_OK; ++l)
         for (int m = 0; m < 3 && rc == PP_OK; ++m)
             rc = dev_alloc_t(c, &c->chain[l][m], sizeof(double) * cells(ld[l]));
+    for (int l = 0; l < MAXLEV; ++l)
+        c->pw[l] = nullptr;
+    for (int l = 0; l + 1 < nlev && rc == PP_OK; ++l)
+        rc = dev_alloc_t(c, &c->pw[l], sizeof(unsigned) * cells(ld[l]));
     for (int l = 0; l < nlev && rc == PP_OK && c->sig_on; ++l)
         rc = dev_alloc_t(c, &c->sig[l], sizeof(double) * cells(ld[l]));
     if (rc == PP_OK && gen)
@@ -1778,8 +1800,34 @@ int pp_k_prolong_add(const pp_grid *grid, const double *eH, double *e, void *hip
             return fail(PP_EINVAL, "pp_k_prolong_add: the fine grid needs even cell counts");
     if ((uintptr_t)e & 15)
         return fail(PP_EINVAL, "pp_k_prolong_add: e must be 16-byte aligned (x-pairs are vectors)");
-    launch_prolong<double>(to_dims(grid), to_bc(grid), eH, e, (hipStream_t)hip_stream);
+    launch_prolong<double>(to_dims(grid), to_bc(grid), eH, e, nullptr, (hipStream_t)hip_stream);
     return check_launch("pp_k_prolong_add");
+}
+
+int pp_k_prolong_weights(const pp_grid *grid, const double *bx, const double *by,
+                         const double *bz, uint32_t *w, void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!bx || !by || !bz || !w)
+        return fail(PP_EINVAL, "pp_k_prolong_weights: NULL array");
+    launch_prolong_weights(to_dims(grid), to_bc(grid), bx, by, bz, w, (hipStream_t)hip_stream);
+    return check_launch("pp_k_prolong_weights");
+}
+
+int pp_k_prolong_add_weighted(const pp_grid *grid, const double *eH, const uint32_t *w, double *e,
+                              void *hip_stream)
+{
+    PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
+    if (!eH || !e || !w)
+        return fail(PP_EINVAL, "pp_k_prolong_add_weighted: NULL array");
+    for (int m = 0; m < 3; ++m)
+        if (grid->n[m] % 2)
+            return fail(PP_EINVAL, "pp_k_prolong_add_weighted: the fine grid needs even cell counts");
+    if (((uintptr_t)e & 15) || ((uintptr_t)w & 7))
+        return fail(PP_EINVAL, "pp_k_prolong_add_weighted: e must be 16-byte aligned and w "
+                               "8-byte aligned (x-pairs are vectors)");
+    launch_prolong<double>(to_dims(grid), to_bc(grid), eH, e, w, (hipStream_t)hip_stream);
+    return check_launch("pp_k_prolong_add_weighted");
 }
 
 int pp_k_coarsen_beta(const pp_grid *grid, const double *bx, const double *by, const double *bz,

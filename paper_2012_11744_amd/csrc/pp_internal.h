@@ -136,16 +136,22 @@ inline bool fused2_fits(Dims d) { return d.nz >= 8 && d.nx >= 8 && d.ny >= 8; }
 template <typename T>
 void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
                            const T *r, const T *sg, T *rH, double ih2, hipStream_t s);
+// e += P eH with the prolongation weights w of the fine level (one 32-bit
+// word per fine cell: the x, y and z weights as 8-bit fractions of 256 in
+// bits 0-7, 8-15, 16-23; null: 1/4 everywhere, trilinear)
 template <typename T>
-void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s);
+void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, const unsigned *w, hipStream_t s);
+// the prolongation weights of a level from its FP64 face coefficients
+void launch_prolong_weights(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                            unsigned *w, hipStream_t s);
 template <typename T>
 void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s);
 // the V-cycle on nlev levels (the last one the coarsest) in one workgroup;
 // input r[0], output e[0] (in place; every level's e is overwritten)
 template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
-                 void *const *r, const void *const *sg, Bc bc, int nu_pre, int nu_post,
-                 const double *pinv, int ncoarse, hipStream_t s);
+                 void *const *r, const void *const *sg, const unsigned *const *w, Bc bc,
+                 int nu_pre, int nu_post, const double *pinv, int ncoarse, hipStream_t s);
 template <typename T>
 void launch_convert(size_t n, const double *src, T *dst, hipStream_t s);
 template <typename T>
@@ -163,13 +169,15 @@ void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, con
 // even; returns the number of partial sums written
 template <typename T>
 int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
-                       T *const dstT[3], double *const coarse[3], double *part, hipStream_t s);
+                       T *const dstT[3], double *const coarse[3], unsigned *w0, double *part,
+                       hipStream_t s);
 // as launch_load_coeffs with beta computed from the cell densities (the
 // arithmetic of launch_face_coeffs), also copying the densities to rcopy; the
 // partials also count cells whose density is not a finite positive number
 template <typename T>
 int launch_load_density(Dims fd, Bc bc, const double *rho, double *const dst[3], T *const dstT[3],
-                        double *const coarse[3], double *rcopy, double *part, hipStream_t s);
+                        double *const coarse[3], double *rcopy, unsigned *w0, double *part,
+                        hipStream_t s);
 void launch_check_rho(Dims d, const double *rho, double *part, hipStream_t s);
 void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStream_t s);
 // partials of the count of non-wall faces that are not finite positive

@@ -302,17 +302,126 @@ __device__ __forceinline__ int other_parent(int i, int nH, int wall)
     return o;
 }
 
-// e += P eH: cell-centred trilinear interpolation (3/4 parent, 1/4 the next
-// coarse cell on the fine cell's side, per axis; at a wall the parent itself).
-// One thread per coarse cell updates its 2 x 2 x 2 children: it reads the
-// 3 x 3 x 3 coarse neighbourhood once, interpolates along x, then y, then z,
+// Weight of the far coarse cell in the prolongation of one fine cell along
+// one axis.  The fine cell lies between its parent's centre (at the face
+// between the two children) and the far coarse neighbour's centre (at the
+// face beyond the cell's other side); along a row of links this interval is
+// half a link to the parent's centre (coefficient gn: the face between the
+// children), the cell's outer face (gm) and half of the link beyond it (gf).
+// The weight is the near half-link's share of the series resistance,
+//   w = (1/2 gn) / (1/2 gn + 1/gm + 1/2 gf) = gm gf / (gm gf + gn (2 gf + gm)),
+// 1/4 for equal coefficients (trilinear interpolation), near 0 for a fine cell
+// tied to its parent by a strong link and to the far cell through weak ones,
+// 0 at a wall (gm = 0), and 0 for a cell closed on both sides.
+__device__ __forceinline__ double far_weight(double gn, double gm, double gf)
+{
+    // the same bits at every call site: no contraction into fused multiply-adds
+#pragma clang fp contract(off)
+    const double den = gm * gf + gn * (2.0 * gf + gm);
+    return den > 0.0 ? (gm * gf) / den : 0.0;
+}
+
+// The three weights of a cell are stored as 8-bit fractions of 256 in one
+// 32-bit word (x in bits 0-7, y in 8-15, z in 16-23): q = round(256 w),
+// at most 255, so 1/4 is exact.
+__device__ __forceinline__ unsigned weight_q(double w)
+{
+    const int q = (int)(w * 256.0 + 0.5);
+    return (unsigned)(q > 255 ? 255 : q);
+}
+
+__device__ __forceinline__ unsigned pack_weights(double wx, double wy, double wz)
+{
+    return weight_q(wx) | (weight_q(wy) << 8) | (weight_q(wz) << 16);
+}
+
+// The prolongation weights of the 8 fine cells of a coarse cell (x = 2I,
+// y = 2J, z = 2K), stored as four x-pairs of packed words.  For each of the
+// 4 rows of each axis (x: rows (dk, dj); y: columns (dk, di); z: columns
+// (dj, di)) the faces x-1 .. x+3 along it: lo, mid, hi (as for
+// coarse_face) and f2, f3 (the faces beyond the high child).
+__device__ __forceinline__ void children_weights(const double xlo[4], const double xmid[4],
+                                                 const double xhi[4], const double x2[4],
+                                                 const double x3[4], const double ylo[4],
+                                                 const double ymid[4], const double yhi[4],
+                                                 const double y2[4], const double y3[4],
+                                                 const double zlo[4], const double zmid[4],
+                                                 const double zhi[4], const double z2[4],
+                                                 const double z3[4], unsigned *w, size_t c00,
+                                                 size_t fy, size_t fz)
+{
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj) {
+            unsigned q[2];
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+                const int rx = 2 * dk + dj, ry = 2 * dk + di, rz = 2 * dj + di;
+                const double wx = di ? far_weight(xhi[rx], x2[rx], x3[rx])
+                                     : far_weight(xhi[rx], xmid[rx], xlo[rx]);
+                const double wy = dj ? far_weight(yhi[ry], y2[ry], y3[ry])
+                                     : far_weight(yhi[ry], ymid[ry], ylo[ry]);
+                const double wz = dk ? far_weight(zhi[rz], z2[rz], z3[rz])
+                                     : far_weight(zhi[rz], zmid[rz], zlo[rz]);
+                q[di] = pack_weights(wx, wy, wz);
+            }
+            *reinterpret_cast<U2 *>(w + c00 + dk * fz + dj * fy) = U2{q[0], q[1]};
+        }
+}
+
+// Prolongation weights of every cell of a level, from its FP64 face
+// coefficients: along each axis, an even index i (low child) has
+// gn = beta[i+1], gm = beta[i], gf = beta[i-1]; an odd one gn = beta[i],
+// gm = beta[i+1], gf = beta[i+2] (indices wrapped; in a wall direction the
+// face of wrapped index 0, the lower wall or the implicit upper one, is 0
+// whatever is stored).
+__global__ __launch_bounds__(BLOCK) void k_prolong_weights(Dims d, Bc bc, const double *__restrict__ bx,
+                                                           const double *__restrict__ by,
+                                                           const double *__restrict__ bz,
+                                                           unsigned *__restrict__ w)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny)
+        return;
+    const size_t sy = d.nx, sz = (size_t)d.nx * d.ny;
+    const size_t c = (size_t)k * sz + (size_t)j * sy + i;
+    // coefficient of face v (wrapped) along one axis
+    auto face = [](const double *b, int v, int n, size_t stride, size_t base, int wall) {
+        v = v < 0 ? v + n : (v >= n ? v - n : v);
+        return (wall && v == 0) ? 0.0 : b[base + (size_t)v * stride];
+    };
+    // the weight from the faces idx-1 .. idx+2 along one axis
+    auto axis = [&](const double *b, int idx, int n, size_t stride, size_t base, int wall) {
+        const double f0 = face(b, idx - 1, n, stride, base, wall);
+        const double f1 = face(b, idx, n, stride, base, wall);
+        const double f2 = face(b, idx + 1, n, stride, base, wall);
+        const double f3 = face(b, idx + 2, n, stride, base, wall);
+        return (idx & 1) ? far_weight(f1, f2, f3) : far_weight(f2, f1, f0);
+    };
+    w[c] = pack_weights(axis(bx, i, d.nx, 1, c - i, bc.x),
+                        axis(by, j, d.ny, sy, c - (size_t)j * sy, bc.y),
+                        axis(bz, k, d.nz, sz, c - (size_t)k * sz, bc.z));
+}
+
+// e += P eH: cell-centred interpolation per axis between the parent and the
+// next coarse cell on the fine cell's side (at a wall: the parent itself),
+// the next cell weighted by the fine cell's weight w along that axis and the
+// parent by 1 - w; the axes compose as a product (trilinear when every
+// weight is 1/4; w null: 1/4 everywhere).  One thread per coarse cell updates
+// its 2 x 2 x 2 children: it reads the 3 x 3 x 3 coarse neighbourhood once
 // and adds to the children as four x-pairs (vector read-modify-write).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_prolong(Dims fd, Bc bc, const T *__restrict__ eH,
-                                                   T *__restrict__ e)
+                                                   T *__restrict__ e,
+                                                   const unsigned *__restrict__ w)
 {
     using C = typename Acc<T>::type;
     using T2 = typename Vec2<T>::type;
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     const int I = blockIdx.x * BX + threadIdx.x;
     const int J = blockIdx.y * BY + threadIdx.y;
@@ -320,38 +429,51 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(Dims fd, Bc bc, const T *__re
     if (I >= cd.nx || J >= cd.ny)
         return;
     // the other parent of the low (0) and high (1) child along each axis
-    const int Im = other_parent(2 * I, cd.nx, bc.x), Ip = other_parent(2 * I + 1, cd.nx, bc.x);
+    const int In[2] = {other_parent(2 * I, cd.nx, bc.x), other_parent(2 * I + 1, cd.nx, bc.x)};
     const int Jn[2] = {other_parent(2 * J, cd.ny, bc.y), other_parent(2 * J + 1, cd.ny, bc.y)};
     const int Kn[2] = {other_parent(2 * K, cd.nz, bc.z), other_parent(2 * K + 1, cd.nz, bc.z)};
     const size_t sy = cd.nx, sz = (size_t)cd.nx * cd.ny;
-    const C a = C(0.75), b = C(0.25);
-    // x-interpolated values of the coarse rows (k, j): [0] for child 2I, [1] for 2I+1
-    auto xrow = [&](int kk, int jj, C (&out)[2]) {
-        const size_t r0 = (size_t)kk * sz + (size_t)jj * sy;
-        const C c0 = ld(eH, r0 + I);
-        out[0] = a * c0 + b * ld(eH, r0 + Im);
-        out[1] = a * c0 + b * ld(eH, r0 + Ip);
-    };
-    C X[3][3][2];                      // [z: K, Kn0, Kn1][y: J, Jn0, Jn1][x child]
-    const int ks[3] = {K, Kn[0], Kn[1]}, js[3] = {J, Jn[0], Jn[1]};
+    // coarse values: [z: K, Kn0, Kn1][y: J, Jn0, Jn1][x: I, In0, In1]
+    C V[3][3][3];
+    const int ks[3] = {K, Kn[0], Kn[1]}, js[3] = {J, Jn[0], Jn[1]}, is[3] = {I, In[0], In[1]};
 #pragma unroll
     for (int u = 0; u < 3; ++u)
 #pragma unroll
-        for (int v = 0; v < 3; ++v)
-            xrow(ks[u], js[v], X[u][v]);
+        for (int v = 0; v < 3; ++v) {
+            const size_t r0 = (size_t)ks[u] * sz + (size_t)js[v] * sy;
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+                V[u][v][t] = ld(eH, r0 + is[t]);
+        }
+    const C q = C(0.25);
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz) {
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
             const size_t c = ((size_t)(2 * K + cz) * fd.ny + (2 * J + cy)) * fd.nx + 2 * I;
+            C ax[2] = {q, q}, ay[2] = {q, q}, az[2] = {q, q};
+            if (w) {
+                const U2 pw = *reinterpret_cast<const U2 *>(w + c);
+                const unsigned wv[2] = {pw.x, pw.y};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    ax[h] = C(wv[h] & 255u) * C(1.0 / 256.0);
+                    ay[h] = C((wv[h] >> 8) & 255u) * C(1.0 / 256.0);
+                    az[h] = C((wv[h] >> 16) & 255u) * C(1.0 / 256.0);
+                }
+            }
             T2 *ep = reinterpret_cast<T2 *>(e + c);
             T2 ev = *ep;
             C v[2];
 #pragma unroll
             for (int cx = 0; cx < 2; ++cx) {
-                const C y0 = a * X[0][0][cx] + b * X[0][1 + cy][cx];
-                const C y1 = a * X[1 + cz][0][cx] + b * X[1 + cz][1 + cy][cx];
-                v[cx] = a * y0 + b * y1;
+                // along x in the four coarse rows (z: parent / next, y: parent / next)
+                auto xl = [&](int u, int w_) {
+                    return V[u][w_][0] + ax[cx] * (V[u][w_][1 + cx] - V[u][w_][0]);
+                };
+                const C y0 = xl(0, 0) + ay[cx] * (xl(0, 1 + cy) - xl(0, 0));
+                const C y1 = xl(1 + cz, 0) + ay[cx] * (xl(1 + cz, 1 + cy) - xl(1 + cz, 0));
+                v[cx] = y0 + az[cx] * (y1 - y0);
             }
             ev.x = static_cast<T>(C(ev.x) + v[0]);
             ev.y = static_cast<T>(C(ev.y) + v[1]);
@@ -393,6 +515,7 @@ struct TailArgs {
     T *e[TAIL_MAX];
     T *r[TAIL_MAX];
     const T *s[TAIL_MAX];      // diagonal term of the general operator, or null
+    const unsigned *w[TAIL_MAX];   // prolongation weights of each level but the last, or null
     Bc bc;
     int nu_pre, nu_post;
     const double *pinv;        // pseudo-inverse of the coarsest operator
@@ -508,9 +631,11 @@ __device__ __forceinline__ C tp_residual_sum(const TPair<C> &P, const C *E, C ih
     return acc;
 }
 
-// e += P eH on the pair's two cells (cell-centred trilinear, as k_prolong)
+// e += P eH on the pair's two cells (the interpolation of k_prolong, with the
+// level's weights; w null: 1/4)
 template <typename C>
-__device__ __forceinline__ void tp_prolong(const TPair<C> &P, Dims fd, Bc bc, const C *EH, C *E)
+__device__ __forceinline__ void tp_prolong(const TPair<C> &P, Dims fd, Bc bc, const C *EH, C *E,
+                                           const unsigned *w)
 {
     if (!P.on)
         return;
@@ -518,21 +643,28 @@ __device__ __forceinline__ void tp_prolong(const TPair<C> &P, Dims fd, Bc bc, co
     const int nxy = fd.nx * fd.ny;
     const int k = P.c / nxy, rem = P.c - k * nxy;
     const int j = rem / fd.nx, i0 = rem - j * fd.nx;
-    const int I = i0 >> 1, Im = other_parent(i0, cd.nx, bc.x), Ip = other_parent(i0 + 1, cd.nx, bc.x);
+    const int I = i0 >> 1;
+    const int In[2] = {other_parent(i0, cd.nx, bc.x), other_parent(i0 + 1, cd.nx, bc.x)};
     const int J0 = j >> 1, J1 = other_parent(j, cd.ny, bc.y);
     const int K0 = k >> 1, K1 = other_parent(k, cd.nz, bc.z);
     const int sy = cd.nx, sz = cd.nx * cd.ny;
-    const C a = C(0.75), b = C(0.25);
     const int rows[4] = {K0 * sz + J0 * sy, K0 * sz + J1 * sy, K1 * sz + J0 * sy, K1 * sz + J1 * sy};
-    C x0[4], x1[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const C cI = EH[rows[u] + I];
-        x0[u] = a * cI + b * EH[rows[u] + Im];
-        x1[u] = a * cI + b * EH[rows[u] + Ip];
+    for (int q = 0; q < 2; ++q) {
+        const unsigned pw = w ? w[P.c + q] : 0x404040u;   // 64/256 = 1/4 on each axis
+        const C ax = C(pw & 255u) * C(1.0 / 256.0);
+        const C ay = C((pw >> 8) & 255u) * C(1.0 / 256.0);
+        const C az = C((pw >> 16) & 255u) * C(1.0 / 256.0);
+        C xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const C cI = EH[rows[u] + I];
+            xv[u] = cI + ax * (EH[rows[u] + In[q]] - cI);
+        }
+        const C y0 = xv[0] + ay * (xv[1] - xv[0]);
+        const C y1 = xv[2] + ay * (xv[3] - xv[2]);
+        E[P.c + q] += y0 + az * (y1 - y0);
     }
-    E[P.c] += a * (a * x0[0] + b * x0[1]) + b * (a * x0[2] + b * x0[3]);
-    E[P.c + 1] += a * (a * x1[0] + b * x1[1]) + b * (a * x1[2] + b * x1[3]);
 }
 
 template <typename T>
@@ -631,7 +763,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
         visit(l);
 #pragma unroll
         for (int u = 0; u < TAIL_PAIRS; ++u)
-            tp_prolong(P[u], a.d[l], a.bc, E + off[l + 1], El);
+            tp_prolong(P[u], a.d[l], a.bc, E + off[l + 1], El, a.w[l]);
         __syncthreads();
         for (int sw = 0; sw < a.nu_post; ++sw)
             for (int colour = 1; colour >= 0; --colour) {
@@ -691,7 +823,36 @@ __global__ void k_to_double(size_t n, const T *__restrict__ src, double *__restr
 // setup kernels (FP64)
 // ---------------------------------------------------------------------------
 
-// coarse beta = mean of the 4 fine faces of a coarse face; wall faces stay 0
+// Coarse face coefficient from the 4 fine rows that cross a coarse face, each
+// row given by its faces lo = 2I-1, mid = 2I and hi = 2I+1 along the normal
+// (mid lies on the coarse face, lo and hi at the centres of the two coarse
+// cells).  It is the mean of two estimates of the conductance between the
+// two coarse centres, with the rows in parallel: each row's conductance taken
+// at the coarse face alone (exact when the coefficients vary only across the
+// face; the mean of the 4 faces), and each row's links in series over the
+// distance 2h (half a link, a link, half a link: exact when they vary only
+// along the normal).  The first estimate overrates a face that cuts through
+// a small inclusion of large coefficient, the second ignores flow between
+// the rows; a closed link (0) gives a series term of 0.  Rows are summed in
+// the order 0 + 1, 2 + 3 of the callers' (outer, inner) row indices.
+__device__ __forceinline__ double coarse_face(const double lo[4], const double mid[4],
+                                              const double hi[4])
+{
+    // the same bits at every call site: no contraction into fused multiply-adds
+#pragma clang fp contract(off)
+    double ser[4];
+    // 2 / (1/(2 lo) + 1/mid + 1/(2 hi)) with one division
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double den = (mid[q] * hi[q] + 2.0 * (lo[q] * hi[q])) + lo[q] * mid[q];
+        ser[q] = den > 0.0 ? (4.0 * lo[q]) * (mid[q] * hi[q]) / den : 0.0;
+    }
+    const double par = 0.25 * ((mid[0] + mid[1]) + (mid[2] + mid[3]));
+    const double srs = 0.25 * ((ser[0] + ser[1]) + (ser[2] + ser[3]));
+    return 0.5 * (par + srs);
+}
+
+// coarse face coefficients (coarse_face) of every coarse face; wall faces stay 0
 __global__ __launch_bounds__(BLOCK) void k_coarsen_beta(Dims fd, Bc bc, const double *__restrict__ bx,
                                                         const double *__restrict__ by,
                                                         const double *__restrict__ bz,
@@ -706,12 +867,41 @@ __global__ __launch_bounds__(BLOCK) void k_coarsen_beta(Dims fd, Bc bc, const do
     if (I >= cd.nx || J >= cd.ny)
         return;
     const size_t sy = fd.nx, sz = (size_t)fd.nx * fd.ny;
-    const size_t f = (size_t)(2 * K) * sz + (size_t)(2 * J) * sy + (size_t)(2 * I);
+    const int x = 2 * I, y = 2 * J, z = 2 * K;
+    // the face below each coarse cell's low face, wrapped (only used where
+    // the coarse face is not a wall)
+    const int xl = (x == 0) ? fd.nx - 1 : x - 1;
+    const int yl = (y == 0) ? fd.ny - 1 : y - 1;
+    const int zl = (z == 0) ? fd.nz - 1 : z - 1;
     const size_t C = ((size_t)K * cd.ny + J) * cd.nx + I;
-    // x faces: fine i = 2I, (j, k) in {2J, 2J+1} x {2K, 2K+1}
-    hx[C] = (bc.x && I == 0) ? 0.0 : 0.25 * ((bx[f] + bx[f + sy]) + (bx[f + sz] + bx[f + sz + sy]));
-    hy[C] = (bc.y && J == 0) ? 0.0 : 0.25 * ((by[f] + by[f + 1]) + (by[f + sz] + by[f + sz + 1]));
-    hz[C] = (bc.z && K == 0) ? 0.0 : 0.25 * ((bz[f] + bz[f + 1]) + (bz[f + sy] + bz[f + sy + 1]));
+    double lo[4], mid[4], hi[4];
+    // x faces: rows (k, j) in {2K, 2K+1} x {2J, 2J+1}
+    for (int dk = 0; dk < 2; ++dk)
+        for (int dj = 0; dj < 2; ++dj) {
+            const size_t row = (size_t)(z + dk) * sz + (size_t)(y + dj) * sy;
+            lo[2 * dk + dj] = bx[row + xl];
+            mid[2 * dk + dj] = bx[row + x];
+            hi[2 * dk + dj] = bx[row + x + 1];
+        }
+    hx[C] = (bc.x && I == 0) ? 0.0 : coarse_face(lo, mid, hi);
+    // y faces: columns (k, i) in {2K, 2K+1} x {2I, 2I+1}
+    for (int dk = 0; dk < 2; ++dk)
+        for (int di = 0; di < 2; ++di) {
+            const size_t col = (size_t)(z + dk) * sz + (size_t)(x + di);
+            lo[2 * dk + di] = by[col + (size_t)yl * sy];
+            mid[2 * dk + di] = by[col + (size_t)y * sy];
+            hi[2 * dk + di] = by[col + (size_t)(y + 1) * sy];
+        }
+    hy[C] = (bc.y && J == 0) ? 0.0 : coarse_face(lo, mid, hi);
+    // z faces: columns (j, i) in {2J, 2J+1} x {2I, 2I+1}
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+            const size_t col = (size_t)(y + dj) * sy + (size_t)(x + di);
+            lo[2 * dj + di] = bz[col + (size_t)zl * sz];
+            mid[2 * dj + di] = bz[col + (size_t)z * sz];
+            hi[2 * dj + di] = bz[col + (size_t)(z + 1) * sz];
+        }
+    hz[C] = (bc.z && K == 0) ? 0.0 : coarse_face(lo, mid, hi);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz)
@@ -744,7 +934,8 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
                                                        double *__restrict__ dz, T *__restrict__ tx,
                                                        T *__restrict__ ty, T *__restrict__ tz,
                                                        double *__restrict__ hx, double *__restrict__ hy,
-                                                       double *__restrict__ hz, double *part)
+                                                       double *__restrict__ hz,
+                                                       unsigned *__restrict__ w0, double *part)
 {
     using D2 = double __attribute__((ext_vector_type(2)));
     using T2 = typename Vec2<T>::type;
@@ -755,9 +946,25 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
     double v[1] = {0.0};
     if (I < cd.nx && J < cd.ny) {
         const size_t fy = (size_t)fd.nx, fz = (size_t)fd.nx * fd.ny;
+        const int x = 2 * I, y = 2 * J;
+        // the faces 2I-1, 2J-1, 2K-1 below the coarse cell and the pairs of
+        // faces from 2I+2, 2J+2, 2K+2 above it (wrapped)
+        const int xl = (x == 0) ? fd.nx - 1 : x - 1;
+        const int yl = (y == 0) ? fd.ny - 1 : y - 1;
+        const int xu = (x + 2 == fd.nx) ? 0 : x + 2;
+        const int yu = (y + 2 == fd.ny) ? 0 : y + 2, yu3 = (yu + 1 == fd.ny) ? 0 : yu + 1;
+        // a face of wrapped index 0 in a wall direction is the wall (the
+        // implicit upper one when reached from above): 0 whatever is stored
+        const bool wxu = bc.x && xu == 0, wyu = bc.y && yu == 0;
         const int Ke = min(cd.nz, ((int)blockIdx.z + 1) * (RZ / 2));
         for (int K = blockIdx.z * (RZ / 2); K < Ke; ++K) {
-            double ax[2][2], ay[2][2], az[2][2];   // [dk][dj] / [dk][di] / [dj][di] terms
+            const int zl = (K == 0) ? fd.nz - 1 : 2 * K - 1;
+            const int zu = (2 * K + 2 == fd.nz) ? 0 : 2 * K + 2, zu3 = (zu + 1 == fd.nz) ? 0 : zu + 1;
+            const bool wzu = bc.z && zu == 0;
+            // rows of the coarse faces, in coarse_face's order: lo, mid, hi;
+            // and the two faces beyond each row's high child (weights)
+            double xlo[4], xmid[4], xhi[4], ylo[4], ymid[4], yhi[4], zlo[4], zmid[4], zhi[4];
+            double x2[4], x3[4], y2[4], y3[4], z2[4], z3[4];
             for (int dk = 0; dk < 2; ++dk)
                 for (int dj = 0; dj < 2; ++dj) {
                     const int j = 2 * J + dj, k = 2 * K + dk;
@@ -782,21 +989,60 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
                         *reinterpret_cast<T2 *>(ty + c) = T2{static_cast<T>(byv.x), static_cast<T>(byv.y)};
                         *reinterpret_cast<T2 *>(tz + c) = T2{static_cast<T>(bzv.x), static_cast<T>(bzv.y)};
                     }
-                    ax[dk][dj] = bxv.x;
+                    const size_t row = (size_t)k * fz + (size_t)j * fy;
+                    xlo[2 * dk + dj] = sx[row + xl];
+                    xmid[2 * dk + dj] = bxv.x;
+                    xhi[2 * dk + dj] = bxv.y;
+                    const D2 xb = *reinterpret_cast<const D2 *>(sx + row + xu);
+                    x2[2 * dk + dj] = wxu ? 0.0 : xb.x;
+                    x3[2 * dk + dj] = xb.y;
                     if (dj == 0) {
-                        ay[dk][0] = byv.x;
-                        ay[dk][1] = byv.y;
+                        const D2 l = *reinterpret_cast<const D2 *>(sy_ + (size_t)k * fz +
+                                                                   (size_t)yl * fy + x);
+                        ylo[2 * dk] = l.x;
+                        ylo[2 * dk + 1] = l.y;
+                        ymid[2 * dk] = byv.x;
+                        ymid[2 * dk + 1] = byv.y;
+                    } else {
+                        yhi[2 * dk] = byv.x;
+                        yhi[2 * dk + 1] = byv.y;
+                        const D2 a = *reinterpret_cast<const D2 *>(sy_ + (size_t)k * fz +
+                                                                   (size_t)yu * fy + x);
+                        const D2 b = *reinterpret_cast<const D2 *>(sy_ + (size_t)k * fz +
+                                                                   (size_t)yu3 * fy + x);
+                        y2[2 * dk] = wyu ? 0.0 : a.x;
+                        y2[2 * dk + 1] = wyu ? 0.0 : a.y;
+                        y3[2 * dk] = b.x;
+                        y3[2 * dk + 1] = b.y;
                     }
                     if (dk == 0) {
-                        az[dj][0] = bzv.x;
-                        az[dj][1] = bzv.y;
+                        const D2 l = *reinterpret_cast<const D2 *>(sz_ + (size_t)zl * fz +
+                                                                   (size_t)j * fy + x);
+                        zlo[2 * dj] = l.x;
+                        zlo[2 * dj + 1] = l.y;
+                        zmid[2 * dj] = bzv.x;
+                        zmid[2 * dj + 1] = bzv.y;
+                    } else {
+                        zhi[2 * dj] = bzv.x;
+                        zhi[2 * dj + 1] = bzv.y;
+                        const D2 a = *reinterpret_cast<const D2 *>(sz_ + (size_t)zu * fz +
+                                                                   (size_t)j * fy + x);
+                        const D2 b = *reinterpret_cast<const D2 *>(sz_ + (size_t)zu3 * fz +
+                                                                   (size_t)j * fy + x);
+                        z2[2 * dj] = wzu ? 0.0 : a.x;
+                        z2[2 * dj + 1] = wzu ? 0.0 : a.y;
+                        z3[2 * dj] = b.x;
+                        z3[2 * dj + 1] = b.y;
                     }
                 }
             const size_t C = ((size_t)K * cd.ny + J) * cd.nx + I;
-            // same grouping as k_coarsen_beta
-            hx[C] = (bc.x && I == 0) ? 0.0 : 0.25 * ((ax[0][0] + ax[0][1]) + (ax[1][0] + ax[1][1]));
-            hy[C] = (bc.y && J == 0) ? 0.0 : 0.25 * ((ay[0][0] + ay[0][1]) + (ay[1][0] + ay[1][1]));
-            hz[C] = (bc.z && K == 0) ? 0.0 : 0.25 * ((az[0][0] + az[0][1]) + (az[1][0] + az[1][1]));
+            // the same values in the same order as k_coarsen_beta
+            hx[C] = (bc.x && I == 0) ? 0.0 : coarse_face(xlo, xmid, xhi);
+            hy[C] = (bc.y && J == 0) ? 0.0 : coarse_face(ylo, ymid, yhi);
+            hz[C] = (bc.z && K == 0) ? 0.0 : coarse_face(zlo, zmid, zhi);
+            // the level's prolongation weights, as k_prolong_weights forms them
+            children_weights(xlo, xmid, xhi, x2, x3, ylo, ymid, yhi, y2, y3, zlo, zmid, zhi, z2, z3,
+                             w0, (size_t)(2 * K) * fz + (size_t)y * fy + x, fy, fz);
         }
     }
     block_partials<1>(v, sm, part, 0);
@@ -818,7 +1064,8 @@ __global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const do
                                                         double *__restrict__ hx,
                                                         double *__restrict__ hy,
                                                         double *__restrict__ hz,
-                                                        double *__restrict__ rcopy, double *part)
+                                                        double *__restrict__ rcopy,
+                                                        unsigned *__restrict__ w0, double *part)
 {
     using D2 = double __attribute__((ext_vector_type(2)));
     using T2 = typename Vec2<T>::type;
@@ -829,11 +1076,29 @@ __global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const do
     double v[1] = {0.0};
     if (I < cd.nx && J < cd.ny) {
         const size_t fy = (size_t)fd.nx, fz = (size_t)fd.nx * fd.ny;
-        const int x = 2 * I;
+        const int x = 2 * I, y = 2 * J;
         const int xm = (x == 0) ? fd.nx - 1 : x - 1;
+        // the cells below the faces 2I-1, 2J-1 (wrapped): those faces are
+        // 2 / (rho[2I-2] + rho[2I-1]) and 2 / (rho[2J-2] + rho[2J-1])
+        const int xm2 = (x < 2) ? x - 2 + fd.nx : x - 2;
+        const int ym2 = (y < 2) ? y - 2 + fd.ny : y - 2;
+        // the cells x+2, x+3 (and rows, planes) above the coarse cell
+        // (wrapped): the faces x+2 and x+3 are 2 / (rho[x+1] + rho[x+2]) and
+        // 2 / (rho[x+2] + rho[x+3]); in a wall direction the face x+2 of
+        // wrapped index 0 is the implicit upper wall
+        const int xu = (x + 2 == fd.nx) ? 0 : x + 2;
+        const int yu = (y + 2 == fd.ny) ? 0 : y + 2, yu3 = (yu + 1 == fd.ny) ? 0 : yu + 1;
+        const bool wxu = bc.x && xu == 0, wyu = bc.y && yu == 0;
         const int Ke = min(cd.nz, ((int)blockIdx.z + 1) * (RZ / 2));
         for (int K = blockIdx.z * (RZ / 2); K < Ke; ++K) {
-            double ax[2][2], ay[2][2], az[2][2];   // [dk][dj] / [dk][di] / [dj][di] terms
+            const int z = 2 * K;
+            const int zm2 = (z < 2) ? z - 2 + fd.nz : z - 2;
+            const int zu = (z + 2 == fd.nz) ? 0 : z + 2, zu3 = (zu + 1 == fd.nz) ? 0 : zu + 1;
+            const bool wzu = bc.z && zu == 0;
+            // rows of the coarse faces, in coarse_face's order: lo, mid, hi;
+            // and the two faces beyond each row's high child (weights)
+            double xlo[4], xmid[4], xhi[4], ylo[4], ymid[4], yhi[4], zlo[4], zmid[4], zhi[4];
+            double x2[4], x3[4], y2[4], y3[4], z2[4], z3[4];
             for (int dk = 0; dk < 2; ++dk)
                 for (int dj = 0; dj < 2; ++dj) {
                     const int j = 2 * J + dj, k = 2 * K + dk;
@@ -869,21 +1134,62 @@ __global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const do
                         *reinterpret_cast<T2 *>(ty + c) = T2{static_cast<T>(byv.x), static_cast<T>(byv.y)};
                         *reinterpret_cast<T2 *>(tz + c) = T2{static_cast<T>(bzv.x), static_cast<T>(bzv.y)};
                     }
-                    ax[dk][dj] = bxv.x;
+                    // the faces 2I-1, 2I+2 and 2I+3 of the row, as k_face_coeffs forms them
+                    xlo[2 * dk + dj] = 2.0 / (rho[row + xm2] + rxm);
+                    xmid[2 * dk + dj] = bxv.x;
+                    xhi[2 * dk + dj] = bxv.y;
+                    const D2 ru = *reinterpret_cast<const D2 *>(rho + row + xu);
+                    x2[2 * dk + dj] = wxu ? 0.0 : 2.0 / (rc.y + ru.x);
+                    x3[2 * dk + dj] = 2.0 / (ru.x + ru.y);
                     if (dj == 0) {
-                        ay[dk][0] = byv.x;
-                        ay[dk][1] = byv.y;
+                        const D2 r2 = *reinterpret_cast<const D2 *>(rho + (size_t)k * fz +
+                                                                    (size_t)ym2 * fy + x);
+                        ylo[2 * dk] = 2.0 / (r2.x + rym.x);
+                        ylo[2 * dk + 1] = 2.0 / (r2.y + rym.y);
+                        ymid[2 * dk] = byv.x;
+                        ymid[2 * dk + 1] = byv.y;
+                    } else {
+                        yhi[2 * dk] = byv.x;
+                        yhi[2 * dk + 1] = byv.y;
+                        // rc is the row y+1 here
+                        const D2 a = *reinterpret_cast<const D2 *>(rho + (size_t)k * fz +
+                                                                   (size_t)yu * fy + x);
+                        const D2 b = *reinterpret_cast<const D2 *>(rho + (size_t)k * fz +
+                                                                   (size_t)yu3 * fy + x);
+                        y2[2 * dk] = wyu ? 0.0 : 2.0 / (rc.x + a.x);
+                        y2[2 * dk + 1] = wyu ? 0.0 : 2.0 / (rc.y + a.y);
+                        y3[2 * dk] = 2.0 / (a.x + b.x);
+                        y3[2 * dk + 1] = 2.0 / (a.y + b.y);
                     }
                     if (dk == 0) {
-                        az[dj][0] = bzv.x;
-                        az[dj][1] = bzv.y;
+                        const D2 r2 = *reinterpret_cast<const D2 *>(rho + (size_t)zm2 * fz +
+                                                                    (size_t)j * fy + x);
+                        zlo[2 * dj] = 2.0 / (r2.x + rzm.x);
+                        zlo[2 * dj + 1] = 2.0 / (r2.y + rzm.y);
+                        zmid[2 * dj] = bzv.x;
+                        zmid[2 * dj + 1] = bzv.y;
+                    } else {
+                        zhi[2 * dj] = bzv.x;
+                        zhi[2 * dj + 1] = bzv.y;
+                        // rc is the plane z+1 here
+                        const D2 a = *reinterpret_cast<const D2 *>(rho + (size_t)zu * fz +
+                                                                   (size_t)j * fy + x);
+                        const D2 b = *reinterpret_cast<const D2 *>(rho + (size_t)zu3 * fz +
+                                                                   (size_t)j * fy + x);
+                        z2[2 * dj] = wzu ? 0.0 : 2.0 / (rc.x + a.x);
+                        z2[2 * dj + 1] = wzu ? 0.0 : 2.0 / (rc.y + a.y);
+                        z3[2 * dj] = 2.0 / (a.x + b.x);
+                        z3[2 * dj + 1] = 2.0 / (a.y + b.y);
                     }
                 }
             const size_t C = ((size_t)K * cd.ny + J) * cd.nx + I;
-            // same grouping as k_coarsen_beta
-            hx[C] = (bc.x && I == 0) ? 0.0 : 0.25 * ((ax[0][0] + ax[0][1]) + (ax[1][0] + ax[1][1]));
-            hy[C] = (bc.y && J == 0) ? 0.0 : 0.25 * ((ay[0][0] + ay[0][1]) + (ay[1][0] + ay[1][1]));
-            hz[C] = (bc.z && K == 0) ? 0.0 : 0.25 * ((az[0][0] + az[0][1]) + (az[1][0] + az[1][1]));
+            // the same values in the same order as k_coarsen_beta
+            hx[C] = (bc.x && I == 0) ? 0.0 : coarse_face(xlo, xmid, xhi);
+            hy[C] = (bc.y && J == 0) ? 0.0 : coarse_face(ylo, ymid, yhi);
+            hz[C] = (bc.z && K == 0) ? 0.0 : coarse_face(zlo, zmid, zhi);
+            // the level's prolongation weights, as k_prolong_weights forms them
+            children_weights(xlo, xmid, xhi, x2, x3, ylo, ymid, yhi, y2, y3, zlo, zmid, zhi, z2, z3,
+                             w0, (size_t)z * fz + (size_t)y * fy + x, fy, fz);
         }
     }
     block_partials<1>(v, sm, part, 0);
@@ -1139,27 +1445,23 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(Dims d, Bc bc, const do
     gz[n.c] = (n.wzl || cz) ? 0.0 : ih2 * (lc - lam[n.zm]) * (pc - p[n.zm]);
 }
 
-// Streaming copy: 16-byte accesses, four independent loads per thread in
-// flight, a grid that fills every CU several times over.
+// Streaming copy, the reference for achievable HBM bandwidth: one 16-byte
+// vector per thread (a grid of n/512 workgroups), loaded and stored with the
+// non-temporal hint, since nothing copied is read again soon.  Measured
+// against a grid-stride loop with four vectors per thread in flight, and
+// against workgroups that each copy a contiguous run of 2, 4 or 8 vectors
+// per thread, this form is the fastest on MI355X (6.6 TB/s read + write on
+// 1 GiB buffers).
 __global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src,
                                               double *__restrict__ dst, size_t n)
 {
     using D2 = double __attribute__((ext_vector_type(2)));
-    const size_t n2 = n / 2;
-    const D2 *s2 = reinterpret_cast<const D2 *>(src);
-    D2 *d2 = reinterpret_cast<D2 *>(dst);
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n2; i += 4 * stride) {
-        const D2 a = s2[i], b = s2[i + stride], c = s2[i + 2 * stride], e = s2[i + 3 * stride];
-        d2[i] = a;
-        d2[i + stride] = b;
-        d2[i + 2 * stride] = c;
-        d2[i + 3 * stride] = e;
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n / 2) {
+        const D2 v = __builtin_nontemporal_load(reinterpret_cast<const D2 *>(src) + i);
+        __builtin_nontemporal_store(v, reinterpret_cast<D2 *>(dst) + i);
     }
-    for (; i < n2; i += stride)
-        d2[i] = s2[i];
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+    if ((n & 1) && i == 0)
         dst[n - 1] = src[n - 1];
 }
 
@@ -1973,16 +2275,22 @@ void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz
 }
 
 template <typename T>
-void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, hipStream_t s)
+void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, const unsigned *w, hipStream_t s)
 {
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    hipLaunchKernelGGL((k_prolong<T>), cell_grid(cd), kBlock, 0, s, fd, bc, eH, e);
+    hipLaunchKernelGGL((k_prolong<T>), cell_grid(cd), kBlock, 0, s, fd, bc, eH, e, w);
+}
+
+void launch_prolong_weights(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
+                            unsigned *w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prolong_weights, cell_grid(d), kBlock, 0, s, d, bc, bx, by, bz, w);
 }
 
 template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
-                 void *const *r, const void *const *sg, Bc bc, int nu_pre, int nu_post,
-                 const double *pinv, int ncoarse, hipStream_t s)
+                 void *const *r, const void *const *sg, const unsigned *const *w, Bc bc,
+                 int nu_pre, int nu_post, const double *pinv, int ncoarse, hipStream_t s)
 {
     TailArgs<T> a;
     a.n = nlev;
@@ -1991,6 +2299,7 @@ void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*
         a.h2[l] = h2[l];
         for (int m = 0; m < 3; ++m)
             a.b[l][m] = (const T *)b[l][m];
+        a.w[l] = w ? w[l] : nullptr;
         a.e[l] = (T *)e[l];
         a.r[l] = (T *)r[l];
         a.s[l] = (const T *)sg[l];
@@ -2049,35 +2358,37 @@ void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStr
 
 template <typename T>
 int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
-                       T *const dstT[3], double *const coarse[3], double *part, hipStream_t s)
+                       T *const dstT[3], double *const coarse[3], unsigned *w0, double *part,
+                       hipStream_t s)
 {
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     const dim3 g((cd.nx + BX - 1) / BX, (cd.ny + BY - 1) / BY, (cd.nz + RZ / 2 - 1) / (RZ / 2));
     if (dstT[0])
         hipLaunchKernelGGL((k_load_coeffs<T, true>), g, kBlock, 0, s, fd, bc, src[0], src[1], src[2],
                            dst[0], dst[1], dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1],
-                           coarse[2], part);
+                           coarse[2], w0, part);
     else
         hipLaunchKernelGGL((k_load_coeffs<T, false>), g, kBlock, 0, s, fd, bc, src[0], src[1],
                            src[2], dst[0], dst[1], dst[2], dstT[0], dstT[1], dstT[2], coarse[0],
-                           coarse[1], coarse[2], part);
+                           coarse[1], coarse[2], w0, part);
     return (int)grid_blocks(g);
 }
 
 template <typename T>
 int launch_load_density(Dims fd, Bc bc, const double *rho, double *const dst[3], T *const dstT[3],
-                        double *const coarse[3], double *rcopy, double *part, hipStream_t s)
+                        double *const coarse[3], double *rcopy, unsigned *w0, double *part,
+                        hipStream_t s)
 {
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     const dim3 g((cd.nx + BX - 1) / BX, (cd.ny + BY - 1) / BY, (cd.nz + RZ / 2 - 1) / (RZ / 2));
     if (dstT[0])
         hipLaunchKernelGGL((k_load_density<T, true>), g, kBlock, 0, s, fd, bc, rho, dst[0], dst[1],
                            dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2],
-                           rcopy, part);
+                           rcopy, w0, part);
     else
         hipLaunchKernelGGL((k_load_density<T, false>), g, kBlock, 0, s, fd, bc, rho, dst[0], dst[1],
                            dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1], coarse[2],
-                           rcopy, part);
+                           rcopy, w0, part);
     return (int)grid_blocks(g);
 }
 
@@ -2158,12 +2469,12 @@ void launch_adjoint_faces(Dims d, Bc bc, const double *lam, const double *p, dou
 
 void launch_copy(const double *src, double *dst, size_t n, hipStream_t s)
 {
-    // 2048 x 256 threads: 8 workgroups per CU; 16-byte accesses need
-    // 16-byte aligned pointers, otherwise fall back to the plain loop
+    // 16-byte accesses need 16-byte aligned pointers, otherwise the plain loop
     if (((uintptr_t)src | (uintptr_t)dst) & 15)
         hipLaunchKernelGGL(k_copy_unaligned, flat_grid(n), dim3(256), 0, s, src, dst, n);
     else
-        hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, src, dst, n);
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)((n / 2 + 255) / 256) + 1), dim3(256), 0, s,
+                           src, dst, n);
 }
 
 void launch_fill(double *x, size_t n, double v, hipStream_t s)
@@ -2305,15 +2616,18 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
                                  const T *, double, int, bool, hipStream_t);                    \
     template void launch_resid_restrict<T>(Dims, Bc, const T *, const T *, const T *, const T *, \
                                            const T *, const T *, T *, double, hipStream_t);     \
-    template void launch_prolong<T>(Dims, Bc, const T *, T *, hipStream_t);                     \
+    template void launch_prolong<T>(Dims, Bc, const T *, T *, const unsigned *, hipStream_t);    \
     template int launch_load_coeffs<T>(Dims, Bc, const double *const[3], double *const[3],      \
-                                       T *const[3], double *const[3], double *, hipStream_t);   \
+                                       T *const[3], double *const[3], unsigned *, double *,     \
+                                       hipStream_t);                                            \
     template int launch_load_density<T>(Dims, Bc, const double *, double *const[3], T *const[3], \
-                                        double *const[3], double *, double *, hipStream_t);     \
+                                        double *const[3], double *, unsigned *, double *,       \
+                                        hipStream_t);                                           \
     template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
     template void launch_tail<T>(int, const Dims *, const double *, const void *const (*)[3],   \
-                                 void *const *, void *const *, const void *const *, Bc, int,    \
-                                 int, const double *, int, hipStream_t);                        \
+                                 void *const *, void *const *, const void *const *,             \
+                                 const unsigned *const *, Bc, int, int, const double *, int,    \
+                                 hipStream_t);                                                  \
     template void launch_convert<T>(size_t, const double *, T *, hipStream_t);                  \
     template int launch_convert_scaled<T>(size_t, const double *, double, double, T *, double *, \
                                           int, hipStream_t);                                    \

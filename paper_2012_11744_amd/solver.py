@@ -371,6 +371,26 @@ def k_prolong_add(shape, h, bc, eH, e):
     return e
 
 
+def k_prolong_weights(shape, h, bc, beta):
+    """Prolongation weights of every cell (int32 tensor: the x, y and z
+    weights as 8-bit fractions of 256 in bits 0-7, 8-15, 16-23), from the
+    FP64 face coefficients."""
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    w = torch.empty(tuple(shape), dtype=torch.int32, device=beta[0].device)
+    L.check(lib.pp_k_prolong_weights(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(w),
+                                     _stream_handle(None)), "pp_k_prolong_weights")
+    return w
+
+
+def k_prolong_add_weighted(shape, h, bc, eH, w, e):
+    lib = L.load()
+    g = make_grid(shape, h, bc)
+    L.check(lib.pp_k_prolong_add_weighted(ctypes.byref(g), _ptr(eH), _ptr(w), _ptr(e),
+                                          _stream_handle(None)), "pp_k_prolong_add_weighted")
+    return e
+
+
 def k_coarsen_beta(shape, h, bc, beta, out):
     lib = L.load()
     g = make_grid(shape, h, bc)
