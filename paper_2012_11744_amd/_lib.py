@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpp.so")
+# PP_LIB names another build of the same library (a sanitizer build of the
+# host code, for example); by default the in-tree libpp.so
+LIB_PATH = os.environ.get("PP_LIB") or os.path.join(HERE, "libpp.so")
 
 PP_OK = 0
 PP_EINVAL = -1
