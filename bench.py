@@ -246,13 +246,10 @@ def _dev(a):
 
 
 def _step_fn(sol, rho, us, b, p, u, w, tol):
-    """One projection step for the density field rho: coefficients and
-    hierarchy, right-hand side, solve, projection."""
+    """One projection step for the density field rho in one call (pp_step):
+    coefficients and hierarchy, right-hand side, solve, projection."""
     def step():
-        sol.update_density(rho)
-        sol.divergence(us, 1.0 / w.dt, out=b)
-        sol.solve(b, tol=tol, p=p)
-        sol.project(us, p, w.dt, out=u)
+        sol.step(rho, us, w.dt, tol=tol, p=p, rhs=b, out=u)
     return step
 
 

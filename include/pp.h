@@ -26,9 +26,12 @@
  *  - Direction m is periodic (PP_PERIODIC: c - e_m wraps) or walled
  *    (PP_WALL: the entry with c_m == 0 is the wall face; its value is
  *    ignored on input and treated as zero; the upper wall face is implicit).
- *  - Work is enqueued on the HIP stream given to pp_setup.  Calls that report
- *    a convergence result (pp_solve, pp_solve_adjoint) block the host until
- *    the solve ends; the others only enqueue work.
+ *  - Work is enqueued on the HIP stream given to pp_setup, and outputs are
+ *    ready in stream order.  Calls that report a convergence result
+ *    (pp_solve, pp_solve_adjoint) block the host until that result is known;
+ *    the work after it (a solve's gauge, the adjoint's face products) may
+ *    still be queued when they return.  Calls that load coefficients wait
+ *    for their validity check; the others only enqueue work.
  *  - The operator is singular (constants span its null space): solves remove
  *    the mean of the right-hand side and return the mean-zero solution.
  *  - A context is used by one host thread at a time.
@@ -211,6 +214,29 @@ int pp_solve(pp_ctx *ctx, const double *rhs, double *p, double tol, pp_stats *st
  * u may alias us (in-place update); p must not alias u. */
 int pp_project(pp_ctx *ctx, const double *us_x, const double *us_y, const double *us_z,
                const double *p, double dt, double *u_x, double *u_y, double *u_z);
+
+/* One whole projection step of the fractional-step method (Sec. 3: the
+ * density-weighted pressure equation, eq. poisson, and the velocity update,
+ * eq. fotm), in one call: pp_update_density(rho), rhs = pp_divergence(us,
+ * 1/dt), pp_solve(rhs, p, tol, stats) and pp_project(us, p, dt, u), with the
+ * same kernels in the same order and so the same results, bit for bit.  The
+ * host waits only where the solve needs its results: the density check is
+ * read back with the solve's initial residual instead of on its own, and the
+ * projection is queued before the host waits for the confirming final
+ * residual (queued again should the iteration go on; after that wait when a
+ * u_m aliases us_m, as a projection in place cannot be redone).  For contexts
+ * made by pp_setup.
+ * rho, us_x/y/z: read only; rhs (scratch that receives D us / dt), p (initial
+ * guess when opts.warm_start is set) and u_x/y/z: written; all n cells, owned
+ * by the caller.  u_m may alias us_m; no other two arrays may alias.  dt
+ * finite and nonzero, tol in (0, 1); stats as pp_solve's (may be NULL).
+ * Returns PP_OK; PP_ENOCONV (p the best iterate, u projected with it);
+ * PP_EINVAL for bad arguments (nothing done) or a rejected density (as
+ * pp_update_density: the coefficients are then undefined until a later
+ * successful update, and rhs, p and u are undefined); PP_EDIVERGED. */
+int pp_step(pp_ctx *ctx, const double *rho, const double *us_x, const double *us_y,
+            const double *us_z, double dt, double tol, double *rhs, double *p, double *u_x,
+            double *u_y, double *u_z, pp_stats *stats);
 
 /* Adjoint of p = pp_solve(rhs) for a loss L with dL/dp = g_p: solves
  * A lambda = g_p - mean(g_p) with the same hierarchy (A is symmetric) and

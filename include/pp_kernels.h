@@ -164,10 +164,12 @@ int pp_vcycle(pp_ctx *ctx, const double *r, double *e);
 int pp_k_copy(const double *src, double *dst, int64_t count, void *hip_stream);
 
 /* Kernel timing on the context's stream: every launch of a fine-level kernel
- * whose kind bit is set in `mask` (bit k = 1 << PP_KT_*) is bracketed by HIP
- * events and its duration accumulated per kind; mask 0 turns timing off.
- * pp_timing_get reports launches and total ms since the last reset (events
- * are resolved when a solve ends or when queried). */
+ * whose kind bit is set in `mask` (bit k = 1 << PP_KT_*) carries a pair of
+ * HIP events that its dispatch stamps with its own start and end
+ * (hipExtLaunchKernel), and its duration is accumulated per kind; mask 0
+ * turns timing off.  pp_timing_get reports launches and total ms since the
+ * last reset.  Events are read (after waiting for the stream) when queried,
+ * reset, turned off, or when the pool of 8192 pairs runs out. */
 enum {
     PP_KT_SMOOTH = 0,          /* fine-level red-black half sweep */
     PP_KT_RESTRICT = 1,        /* fine-level residual + restriction */

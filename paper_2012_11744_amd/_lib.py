@@ -68,7 +68,7 @@ class Stats(ctypes.Structure):
 EXPORTS = [
     "pp_opts_default", "pp_face_coeffs", "pp_setup", "pp_setup_general", "pp_update_coeffs", "pp_update_density",
     "pp_update_general", "pp_divergence",
-    "pp_apply", "pp_solve", "pp_project", "pp_solve_adjoint", "pp_levels", "pp_level_dims",
+    "pp_apply", "pp_solve", "pp_project", "pp_step", "pp_solve_adjoint", "pp_levels", "pp_level_dims",
     "pp_memory", "pp_destroy", "pp_strerror", "pp_last_error",
     "pp_k_smooth", "pp_k_smooth_fused", "pp_k_smooth2_fused_f32", "pp_k_smooth2_fused_dot_f32",
     "pp_k_smooth2_fused_dot_f32_noalloc", "pp_k_resid_restrict", "pp_k_prolong_add",
@@ -107,6 +107,7 @@ def load():
         "pp_apply": (I, [P, P, P]),
         "pp_solve": (I, [P, P, P, D, SP]),
         "pp_project": (I, [P, P, P, P, P, D, P, P, P]),
+        "pp_step": (I, [P, P, P, P, P, D, D, P, P, P, P, P, SP]),
         "pp_solve_adjoint": (I, [P, P, P, D, P, P, P, P, SP]),
         "pp_levels": (I, [P, ctypes.POINTER(I32)]),
         "pp_level_dims": (I, [P, I32, ctypes.POINTER(I32)]),

@@ -11,12 +11,16 @@
 // read back once per outer iteration.
 #include <hip/hip_runtime.h>
 
+#include <immintrin.h>
+
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -97,6 +101,10 @@ struct EventPair {
 
 }  // namespace
 
+// host copies of the scalar array: the S_NSLOTS values, then the ticket the
+// publishing kernel writes after them
+constexpr int HSLOT = S_NSLOTS + 1;
+
 struct pp_ctx {
     pp_grid grid;
     pp_opts opts;
@@ -132,11 +140,22 @@ struct pp_ctx {
     int ncoarse;
     double *hcoarse;             // pinned: the coarsest level's beta (3 arrays) and sigma, read back
     double *hiter;               // pinned: the scalars of the last two outer iterations, read back
+                                 // (HSLOT doubles each: the S_NSLOTS values, then a ticket)
+    double ticket;               // the last ticket handed to a publishing kernel
+    double iter_ticket[2];       // the ticket of each hiter slot's pending publication
+    double scal_ticket;          // ... and of hscal's
     bool dot_on;                 // set by the outer loop: the fine-level pass that finishes the
     int dot_np;                  // V-cycle also forms the partials of r . z (dot_np of them,
                                  // r the V-cycle's scaled right-hand side)
     hipEvent_t iter_ev[2];       // their copies done
+    hipEvent_t scal_ev;          // the scalar block's read-back (hscal) done
+    hipEvent_t coarse_ev;        // the coarsest coefficients' read-back (hcoarse) done
     double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
+    bool pinv_dirty;             // the coefficients changed since pinv was built: the next
+                                 // V-cycle's caller builds it first (from hcoarse)
+    bool check_pending;          // a density load's validity counts still to be read back
+                                 // (by the next solve's first wait): pp_step
+    bool check_rho_count;        // ... including the separate density count (S_SBAD)
     double *r64, *d64, *d64b, *q64;
     double *part;
     size_t pstride;
@@ -249,24 +268,34 @@ int validate_opts(const pp_opts *o)
 // kernel timing
 // ---------------------------------------------------------------------------
 
+void resolve_timing(pp_ctx *c);
+
+// Times the one kernel launched in its scope: the event pair goes to that
+// launch (PP_LAUNCH), which takes the kernel's own start and end; a scope whose
+// launch did not take them leaves its slot unused.
 struct KT {
     pp_ctx *c;
-    int kind;
     size_t slot;
-    KT(pp_ctx *ctx, int k, bool fine) : c(ctx), kind(k), slot((size_t)-1)
+    KT(pp_ctx *ctx, int k, bool fine) : c(ctx), slot((size_t)-1)
     {
         if (!c->timing || !fine || !((c->timing_mask >> k) & 1u))
             return;
         if (c->ev_used >= c->ev.size())
+            resolve_timing(c);   // waits for the stream, then reuses the pool
+        if (c->ev_used >= c->ev.size())
             return;
         slot = c->ev_used++;
         c->ev[slot].kind = k;
-        (void)hipEventRecord(c->ev[slot].a, c->stream);
+        g_launch_timer = LaunchTimer{c->ev[slot].a, c->ev[slot].b};
     }
     ~KT()
     {
-        if (slot != (size_t)-1)
-            (void)hipEventRecord(c->ev[slot].b, c->stream);
+        if (slot == (size_t)-1)
+            return;
+        if (g_launch_timer.start == c->ev[slot].a) {
+            g_launch_timer = LaunchTimer{};
+            c->ev[slot].kind = -1;
+        }
     }
 };
 
@@ -277,7 +306,8 @@ void resolve_timing(pp_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (size_t i = 0; i < c->ev_used; ++i) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, c->ev[i].a, c->ev[i].b) == hipSuccess) {
+        if (c->ev[i].kind >= 0 &&
+            hipEventElapsedTime(&ms, c->ev[i].a, c->ev[i].b) == hipSuccess) {
             c->kt_ms[c->ev[i].kind] += ms;
             c->kt_count[c->ev[i].kind] += 1;
         }
@@ -387,18 +417,17 @@ int cholesky(std::vector<double> &a, int n)
 }
 
 // Enqueue the read-back of the coarsest level's coefficients into pinned
-// host memory; build_pinv uses them after the next read_scal, which waits
-// for the stream, so the coefficient load costs one synchronisation.
+// host memory; build_pinv waits for it (coarse_ev) before reading them.
 int enqueue_coarse_download(pp_ctx *c)
 {
     const int L = c->nlev - 1;
     const size_t n = cells(c->ld[L]);
     for (int m = 0; m < 3; ++m)
-        PP_HIP(hipMemcpyAsync(c->hcoarse + m * n, c->chain[L][m], sizeof(double) * n,
-                              hipMemcpyDeviceToHost, c->stream));
+        launch_publish(c->chain[L][m], c->hcoarse + m * n, (int)n, c->stream);
     if (c->sig_on)
-        PP_HIP(hipMemcpyAsync(c->hcoarse + 3 * n, c->sig[L], sizeof(double) * n,
-                              hipMemcpyDeviceToHost, c->stream));
+        launch_publish(c->sig[L], c->hcoarse + 3 * n, (int)n, c->stream);
+    PP_TRY(check_launch("coarsest coefficients read-back"));
+    PP_HIP(hipEventRecord(c->coarse_ev, c->stream));
     return PP_OK;
 }
 
@@ -497,15 +526,68 @@ int build_pinv(pp_ctx *c)
     return PP_OK;
 }
 
-int read_scal(pp_ctx *c)
+// Wait until the kernel queued before `ev` has written `ticket` to *flag, in
+// pinned, coherent host memory, after the values it publishes.  Polling the
+// flag sees them as soon as the kernel has written them, before the end of the
+// kernel reaches the host as an event.  The event bounds the wait: once it has
+// completed, the flag holds the ticket (the kernel fences its writes first).
+int wait_ticket(const double *flag, double ticket, hipEvent_t ev)
 {
-    PP_HIP(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
-                          c->stream));
-    PP_HIP(hipStreamSynchronize(c->stream));
+    const volatile double *f = flag;
+    for (unsigned n = 1; *f != ticket; ++n) {
+        if ((n & 255u) == 0) {
+            const hipError_t q = hipEventQuery(ev);
+            if (q == hipSuccess) {
+                if (*f == ticket)
+                    break;
+                return fail(PP_EHIP, "scalar read-back: the kernel ended without its ticket");
+            }
+            if (q != hipErrorNotReady)
+                return fail(PP_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+        }
+        _mm_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     return PP_OK;
 }
 
+// the scalar block into hscal: post_scal queues the copy, wait_scal waits
+// for it (host work in between overlaps the GPU's queue)
+int post_scal(pp_ctx *c)
+{
+    c->scal_ticket = ++c->ticket;
+    launch_publish(c->scal, c->hscal, S_NSLOTS, c->stream, c->scal_ticket);
+    PP_TRY(check_launch("scalar read-back"));
+    PP_HIP(hipEventRecord(c->scal_ev, c->stream));
+    return PP_OK;
+}
+
+int wait_scal(pp_ctx *c)
+{
+    return wait_ticket(c->hscal + S_NSLOTS, c->scal_ticket, c->scal_ev);
+}
+
+int read_scal(pp_ctx *c)
+{
+    PP_TRY(post_scal(c));
+    return wait_scal(c);
+}
+
 int nparts(pp_ctx *c) { return (int)grid_blocks(red_grid(c->d)); }
+
+// the coarsest level's pseudo-inverse for the current coefficients, built on
+// the host from the read-back coarsest coefficients and queued for upload
+int ensure_pinv(pp_ctx *c)
+{
+    if (!c->pinv_dirty)
+        return PP_OK;
+    // the read-back of the coarsest coefficients (a load that does not wait
+    // for its validity counts has not waited for it either)
+    PP_HIP(hipEventSynchronize(c->coarse_ev));
+    PP_TRY(build_pinv(c));
+    c->pinv_dirty = false;
+    return PP_OK;
+}
 
 // the prolongation weights of the levels from `from` on (all but the
 // coarsest), from the FP64 chain
@@ -569,7 +651,7 @@ int load_coeffs_general(pp_ctx *c, const double *bx, const double *by, const dou
     c->nact = c->hscal[S_NACT];
     if (!(c->nact > 0.0))
         return fail(PP_EINVAL, "no cell has an open face or a diagonal term");
-    PP_TRY(build_pinv(c));
+    c->pinv_dirty = true;
     return PP_OK;
 }
 
@@ -578,9 +660,29 @@ int load_coeffs_general(pp_ctx *c, const double *bx, const double *by, const dou
 // the storage copies and the coarsest pseudo-inverse.  The coefficients come
 // from the caller's beta arrays, or (rho non-null) are computed from the
 // cell densities.
-int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
+// the verdict on a coefficient load from its validity counts, read back in
+// hscal (rho: the coefficients came from densities; rho_count: the densities
+// were counted by their own pass, into S_SBAD)
+int coeff_verdict(pp_ctx *c, bool rho, bool rho_count)
+{
+    const double nbad = c->hscal[S_COUNT] + (rho_count ? c->hscal[S_SBAD] : 0.0);
+    if (nbad == 0.0)
+        return PP_OK;
+    c->rho_ok = false;
+    if (rho)
+        return fail(PP_EINVAL, "rho: " + std::to_string((long long)nbad) +
+                                   " cells or faces are not finite positive numbers "
+                                   "(density, or the face coefficient 2 / (rho_L + rho_R))");
+    return fail(PP_EINVAL, "beta: " + std::to_string((long long)c->hscal[S_COUNT]) +
+                               " non-wall faces are not finite positive numbers");
+}
+
+// defer: leave the validity counts for the next solve's first wait (which
+// reports a rejection) instead of waiting for them here
+int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho, bool defer = false)
 {
     c->rho_ok = false;
+    c->check_pending = false;
     if (rho && !c->rho)
         PP_TRY(dev_alloc_t(c, &c->rho, sizeof(double) * c->N));
     int first_coarse = 0;   // first level whose coefficients are still to be coarsened from
@@ -641,26 +743,52 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho)
                         c->scal, c->stream);
     }
     PP_TRY(check_launch("coefficient check"));
-    for (int l = first_coarse; l + 1 < c->nlev; ++l)
-        launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
-                            c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2], c->stream);
-    PP_TRY(check_launch("coarsen coefficients"));
-    PP_TRY(build_weights(c, first_coarse));   // the one-pass kernel formed level 0's
-    PP_TRY(fill_hier(c, c->hmix, level0_converted ? 1 : 0));
-    PP_TRY(enqueue_coarse_download(c));
-    PP_TRY(read_scal(c));
-    const double nbad = c->hscal[S_COUNT] + (rho_count ? c->hscal[S_SBAD] : 0.0);
-    if (nbad != 0.0) {
-        if (rho)
-            return fail(PP_EINVAL, "rho: " + std::to_string((long long)nbad) +
-                                       " cells or faces are not finite positive numbers "
-                                       "(density, or the face coefficient 2 / (rho_L + rho_R))");
-        return fail(PP_EINVAL, "beta: " + std::to_string((long long)c->hscal[S_COUNT]) +
-                                   " non-wall faces are not finite positive numbers");
+    int conv_from = level0_converted ? 1 : 0;
+    if (first_coarse == 1 && level0_converted) {
+        // every further level but the coarsest in one pass each, with the
+        // kernel of level 0 reading the chain in place: the storage copy,
+        // the prolongation weights and the next level's coefficients (their
+        // validity count is not needed: coarse coefficients are positive
+        // means of valid fine ones)
+        const Hier &H = c->hmix;
+        for (int l = 1; l + 1 < c->nlev; ++l) {
+            double *lev[3] = {c->chain[l][0], c->chain[l][1], c->chain[l][2]};
+            const double *src[3] = {lev[0], lev[1], lev[2]};
+            double *crs[3] = {c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2]};
+            if (H.st == ST_F32) {
+                float *tt[3] = {(float *)H.lev[l].b[0], (float *)H.lev[l].b[1],
+                                (float *)H.lev[l].b[2]};
+                launch_load_coeffs<float>(c->ld[l], c->bc, src, lev, tt, crs, c->pw[l], c->part,
+                                          c->stream);
+            } else {
+                _Float16 *tt[3] = {(_Float16 *)H.lev[l].b[0], (_Float16 *)H.lev[l].b[1],
+                                   (_Float16 *)H.lev[l].b[2]};
+                launch_load_coeffs<_Float16>(c->ld[l], c->bc, src, lev, tt, crs, c->pw[l],
+                                             c->part, c->stream);
+            }
+        }
+        conv_from = std::max(1, c->nlev - 1);
+    } else {
+        for (int l = first_coarse; l + 1 < c->nlev; ++l)
+            launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],
+                                c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2],
+                                c->stream);
+        PP_TRY(build_weights(c, first_coarse));   // the one-pass kernel formed level 0's
     }
-    PP_TRY(build_pinv(c));
+    PP_TRY(check_launch("coarsen coefficients"));
+    PP_TRY(fill_hier(c, c->hmix, conv_from));
+    PP_TRY(enqueue_coarse_download(c));
+    // the coarsest pseudo-inverse is built on the host by the next solve,
+    // while the GPU works through what is queued before it
+    c->pinv_dirty = true;
     c->rho_ok = rho != nullptr;
-    return PP_OK;
+    if (defer) {
+        c->check_pending = true;
+        c->check_rho_count = rho_count;
+        return PP_OK;
+    }
+    PP_TRY(read_scal(c));
+    return coeff_verdict(c, rho != nullptr, rho_count);
 }
 
 int load_coeffs(pp_ctx *c, const double *bx, const double *by, const double *bz)
@@ -906,8 +1034,20 @@ int check_progress(SolveState &S, int since_best_limit, int &since, double &best
 // operator kernels then read the coefficient arrays
 const double *op_rho(const pp_ctx *c) { return (c->rho_ok && !c->gen) ? c->rho : nullptr; }
 
-// residual of the current iterate into r64 (+ RR, BB, scales); returns rel
-int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveState &S)
+int gauge(pp_ctx *c, double *x);
+
+// work a caller queues behind a solve's result (the projection of pp_step)
+using Tail = std::function<int()>;
+
+// residual of the current iterate into r64 (+ RR, BB, scales); returns rel.
+// gauge_x: the gauge of x is queued behind the residual, before the host
+// waits for it; it changes neither A x nor the residual (it removes a
+// constant of the null space, or clears excluded cells, which no link
+// reaches), so the iterate may go on from there.  tail (with gauge_x): queued
+// behind the read-back, so the GPU has it to work on while the host waits; if
+// the iterate goes on, it is queued again at the next confirmation.
+int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveState &S,
+                  bool gauge_x = false, const Tail *tail = nullptr)
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
     const int np = launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs,
@@ -916,7 +1056,24 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
                                    c->stream);
     launch_finalize(c->part, c->pstride, np, OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
     PP_TRY(check_launch("residual"));
-    PP_TRY(read_scal(c));
+    if (gauge_x)
+        PP_TRY(gauge(c, x));
+    PP_TRY(post_scal(c));
+    if (gauge_x && tail)
+        PP_TRY((*tail)());
+    // a pseudo-inverse still to be built is built here, on the host, while
+    // the GPU works through the residual and whatever was queued before it;
+    // its upload follows the read-back in the queue, unwaited
+    const int prc = ensure_pinv(c);
+    PP_TRY(wait_scal(c));
+    if (c->check_pending) {
+        // a deferred density check: its rejection takes precedence over a
+        // pseudo-inverse that failed on the rejected coefficients
+        c->check_pending = false;
+        PP_TRY(coeff_verdict(c, true, c->check_rho_count));
+    }
+    if (prc != PP_OK)
+        return prc;
     S.nb = std::sqrt(c->hscal[S_BB]);
     S.rel = (S.nb > 0.0) ? std::sqrt(c->hscal[S_RR]) / S.nb : 0.0;
     return PP_OK;
@@ -983,10 +1140,12 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
             launch_pcg_update<T>(c->d, c->q64, c->r64, (T *)v0.r, c->scal, c->part, s);
         }
         std::swap(dold, dnew);
-        launch_finalize(c->part, c->pstride, np, OP_UPDATE, 0, (double)c->N, 0, c->scal, s);
+        // the finalising kernel also writes the iteration's scalars to their
+        // pinned slot (no copy of its own on the stream)
         const int slot = launched & 1;
-        PP_HIP(hipMemcpyAsync(c->hiter + slot * S_NSLOTS, c->scal, sizeof(double) * S_NSLOTS,
-                              hipMemcpyDeviceToHost, s));
+        c->iter_ticket[slot] = ++c->ticket;
+        launch_finalize(c->part, c->pstride, np, OP_UPDATE, 0, (double)c->N, 0, c->scal, s,
+                        c->hiter + slot * HSLOT, c->iter_ticket[slot]);
         PP_HIP(hipEventRecord(c->iter_ev[slot], s));
         ++launched;
         return check_launch("pcg iteration");
@@ -995,11 +1154,12 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
     // STAGNATED or an error
     auto process = [&]() -> int {
         const int slot = seen & 1;
-        PP_HIP(hipEventSynchronize(c->iter_ev[slot]));
+        PP_TRY(wait_ticket(c->hiter + slot * HSLOT + S_NSLOTS, c->iter_ticket[slot],
+                           c->iter_ev[slot]));
         ++seen;
         S.it++;
         const double before = S.rel;
-        S.rel = std::sqrt(c->hiter[slot * S_NSLOTS + S_RR]) / S.nb;
+        S.rel = std::sqrt(c->hiter[slot * HSLOT + S_RR]) / S.nb;
         rate = (S.rel > 0.0) ? std::max(1.0, before / S.rel) : INFINITY;
         record(S);
         if (S.rel <= tol)
@@ -1120,8 +1280,13 @@ int gauge(pp_ctx *c, double *x)
     return check_launch("gauge");
 }
 
-int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st, bool warm)
+// tail (may be null): work to queue behind the result; *tail_queued tells
+// whether it was queued behind the final iterate (else the caller queues it)
+int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st, bool warm,
+               const Tail *tail = nullptr, bool *tail_queued = nullptr)
 {
+    if (tail_queued)
+        *tail_queued = false;
     const auto t0 = std::chrono::steady_clock::now();
     if (st) {
         std::memset(st, 0, sizeof(*st));
@@ -1140,6 +1305,7 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
         launch_mask(c->N, x, c->act, c->stream);   // excluded cells of a warm start are not read
     PP_TRY(true_residual(c, rhs, x, !warm, S));
     int rc = PP_OK;
+    bool gauged = false;   // x is gauged and unchanged since
     if (!(S.nb > 0.0)) {
         // b = 0 after mean removal: the mean-zero solution is 0
         launch_fill(x, c->N, 0.0, c->stream);
@@ -1149,12 +1315,15 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
         Hier *H = (c->opts.precision == PP_FP64) ? &c->h64 : &c->hmix;
         S.best = S.rel;
         for (int restart = 0;; ++restart) {
+            gauged = false;
             rc = run_loop(c, *H, rhs, x, tol, S);
             if (rc == PP_OK) {
                 if (c->opts.outer == PP_OUTER_DC)
                     break;   // DC residuals are true residuals already
-                // recurrences drift from the true residual: confirm it
-                PP_TRY(true_residual(c, rhs, x, false, S));
+                // recurrences drift from the true residual: confirm it (the
+                // gauge goes in the same queue)
+                PP_TRY(true_residual(c, rhs, x, false, S, true, tail));
+                gauged = true;
                 if (S.rel <= tol)
                     break;
                 if (restart >= 4) {
@@ -1180,12 +1349,12 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
             break;
         }
     }
-    if (rc == PP_OK || rc == PP_ENOCONV)
+    if ((rc == PP_OK || rc == PP_ENOCONV) && !gauged)
         PP_TRY(gauge(c, x));
-    if (c->timing)
-        resolve_timing(c);
-    else
-        PP_HIP(hipStreamSynchronize(c->stream));
+    if (tail_queued)
+        *tail_queued = gauged && tail;   // queued at the last confirmation, x unchanged since
+    // the result is known; the gauge may still be queued (stream order).
+    // Timer events are read when queried, or when their pool runs out.
     if (st) {
         st->outer_iters = S.it;
         st->rel_res = S.rel;
@@ -1276,6 +1445,10 @@ void pp_destroy(pp_ctx *c)
     for (hipEvent_t e : c->iter_ev)
         if (e)
             (void)hipEventDestroy(e);
+    if (c->scal_ev)
+        (void)hipEventDestroy(c->scal_ev);
+    if (c->coarse_ev)
+        (void)hipEventDestroy(c->coarse_ev);
     delete c;
 }
 
@@ -1361,13 +1534,13 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
         rc = dev_alloc_t(c, &c->scal, sizeof(double) * S_NSLOTS);
     if (rc != PP_OK)
         return bail(rc);
-    if (hipHostMalloc((void **)&c->hscal, sizeof(double) * S_NSLOTS, hipHostMallocDefault) !=
+    if (hipHostMalloc((void **)&c->hscal, sizeof(double) * HSLOT, hipHostMallocCoherent) !=
         hipSuccess) {
         c->hscal = nullptr;
         return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
     }
     if (hipHostMalloc((void **)&c->hcoarse, sizeof(double) * 4 * (size_t)c->ncoarse,
-                      hipHostMallocDefault) != hipSuccess) {
+                      hipHostMallocCoherent) != hipSuccess) {
         c->hcoarse = nullptr;
         return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
     }
@@ -1376,16 +1549,29 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
         c->hpinv = nullptr;
         return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
     }
-    if (hipHostMalloc((void **)&c->hiter, sizeof(double) * 2 * S_NSLOTS, hipHostMallocDefault) !=
+    // coherent: the finalising kernel writes the iteration scalars here itself
+    if (hipHostMalloc((void **)&c->hiter, sizeof(double) * 2 * HSLOT, hipHostMallocCoherent) !=
         hipSuccess) {
         c->hiter = nullptr;
         return bail(fail(PP_ENOMEM, "hipHostMalloc failed"));
     }
+    // tickets start at 1 and only grow: no flag holds one before its kernel runs
+    std::fill(c->hscal, c->hscal + HSLOT, 0.0);
+    std::fill(c->hiter, c->hiter + 2 * HSLOT, 0.0);
+    c->ticket = 0.0;
     for (int i = 0; i < 2; ++i)
         if (hipEventCreateWithFlags(&c->iter_ev[i], hipEventDisableTiming) != hipSuccess) {
             c->iter_ev[i] = nullptr;
             return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
         }
+    if (hipEventCreateWithFlags(&c->scal_ev, hipEventDisableTiming) != hipSuccess) {
+        c->scal_ev = nullptr;
+        return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
+    }
+    if (hipEventCreateWithFlags(&c->coarse_ev, hipEventDisableTiming) != hipSuccess) {
+        c->coarse_ev = nullptr;
+        return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
+    }
     if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
         return bail(fail(PP_EHIP, "hipMemsetAsync failed"));
     rc = gen ? load_coeffs_general(c, bx, by, bz, sg) : load_coeffs(c, bx, by, bz);
@@ -1585,6 +1771,57 @@ int pp_project(pp_ctx *c, const double *usx, const double *usy, const double *us
     launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], op_rho(c), usx, usy,
                    usz, p, dt / c->grid.h, ux, uy, uz, c->stream);
     return check_launch("pp_project");
+}
+
+int pp_step(pp_ctx *c, const double *rho, const double *usx, const double *usy,
+            const double *usz, double dt, double tol, double *rhs, double *p, double *ux,
+            double *uy, double *uz, pp_stats *st)
+{
+    PP_TRY(check_ctx(c));
+    if (!rho || !usx || !usy || !usz || !rhs || !p || !ux || !uy || !uz)
+        return fail(PP_EINVAL, "pp_step: NULL array");
+    if (c->gen)
+        return fail(PP_EINVAL, "pp_step: a general context takes its coefficients from "
+                               "pp_update_general");
+    if (!(std::isfinite(dt) && dt != 0.0 && std::isfinite(1.0 / dt)))
+        return fail(PP_EINVAL, "pp_step: dt must be finite and nonzero");
+    if (!(tol > 0.0 && tol < 1.0))
+        return fail(PP_EINVAL, "pp_step: tol must be in (0, 1)");
+    const double *outs[5] = {rhs, p, ux, uy, uz};
+    const double *ins[4] = {rho, usx, usy, usz};
+    for (int a = 0; a < 5; ++a) {
+        for (int b = a + 1; b < 5; ++b)
+            if (outs[a] == outs[b])
+                return fail(PP_EINVAL, "pp_step: rhs, p and the u arrays must be distinct");
+        for (int b = 0; b < 4; ++b)
+            if (outs[a] == ins[b] && !(a >= 2 && b == a - 1))
+                return fail(PP_EINVAL, "pp_step: an output aliases an input (only u_m may "
+                                       "alias us_m)");
+    }
+    // the coefficient load leaves its validity counts to the solve's first
+    // wait, so the step waits on the host for the solve's results only
+    const double *src[3] = {nullptr, nullptr, nullptr};
+    PP_TRY(load_coeffs_impl(c, src, rho, true));
+    launch_divergence(c->d, c->bc, usx, usy, usz, (1.0 / dt) / c->grid.h, nullptr, nullptr, nullptr,
+                      rhs, c->stream);
+    PP_TRY(check_launch("pp_step divergence"));
+    const Tail project = [&]() {
+        launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], op_rho(c), usx,
+                       usy, usz, p, dt / c->grid.h, ux, uy, uz, c->stream);
+        return check_launch("pp_step projection");
+    };
+    // the projection is queued behind the confirmation of convergence, before
+    // the host waits for it; a projection in place (u over u*) waits instead,
+    // as it cannot be redone if the iterate goes on
+    const bool in_place = ux == usx || uy == usy || uz == usz;
+    bool queued = false;
+    const int rc = solve_impl(c, rhs, p, tol, st, c->opts.warm_start != 0,
+                              in_place ? nullptr : &project, &queued);
+    if (rc != PP_OK && rc != PP_ENOCONV)
+        return rc;
+    if (!queued)
+        PP_TRY(project());
+    return rc;
 }
 
 int pp_solve_adjoint(pp_ctx *c, const double *p, const double *gp, double tol, double *grhs,
@@ -1848,6 +2085,7 @@ int pp_vcycle(pp_ctx *c, const double *r, double *e)
     PP_TRY(check_ctx(c));
     if (!r || !e)
         return fail(PP_EINVAL, "pp_vcycle: NULL array");
+    PP_TRY(ensure_pinv(c));
     Hier &H = (c->opts.precision == PP_FP64) ? c->h64 : c->hmix;
     LevelBuf &v0 = H.lev[0];
     switch (H.st) {
@@ -1886,10 +2124,12 @@ int pp_timing_enable(pp_ctx *c, int32_t mask)
     if (mask < 0 || mask >= (1 << PP_KT_COUNT))
         return fail(PP_EINVAL, "pp_timing_enable: mask has bits beyond the kernel kinds");
     if (mask && c->ev.empty()) {
+        // timing only: no system-scope fence (cache writeback) when they
+        // complete, which would stall the kernels queued behind them
         c->ev.resize(8192);
         for (auto &e : c->ev) {
-            PP_HIP(hipEventCreate(&e.a));
-            PP_HIP(hipEventCreate(&e.b));
+            PP_HIP(hipEventCreateWithFlags(&e.a, hipEventDisableSystemFence));
+            PP_HIP(hipEventCreateWithFlags(&e.b, hipEventDisableSystemFence));
         }
     }
     if (!mask)

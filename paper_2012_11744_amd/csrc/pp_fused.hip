@@ -438,8 +438,8 @@ void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty, tz);   // distinct shapes per level in profiles
 #define PP_FUSED_LAUNCH(Z, S)                                                                  \
-    hipLaunchKernelGGL((k_rbgs_fused<T, Z, S>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz, r, \
-                       ein, eout, sg, (C)h2, first_colour, kz, tx, ty)
+    PP_LAUNCH((k_rbgs_fused<T, Z, S>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz, r, \
+              ein, eout, sg, (C)h2, first_colour, kz, tx, ty)
     if (sg) {
         if (zero)
             PP_FUSED_LAUNCH(true, true);
@@ -850,8 +850,8 @@ int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty, tz);
 #define PP_FUSED2_LAUNCH(Z, S, D)                                                                \
-    hipLaunchKernelGGL((k_rbgs_fused2<T, Z, S, D>), grid, dim3(GTHREADS), 0, s, d, bc, bx, by,   \
-                       bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty, part)
+    PP_LAUNCH((k_rbgs_fused2<T, Z, S, D>), grid, dim3(GTHREADS), 0, s, d, bc, bx, by,   \
+              bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty, part)
     if (dot) {
         if constexpr (std::is_same<T, float>::value)
             PP_FUSED2_LAUNCH(false, false, true);

@@ -2,12 +2,34 @@
 // pressure-projection library (kernels + host driver).  Not part of the ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
 
 namespace pp {
+
+// Kernel timing without markers: the host driver's timer scope leaves a pair
+// of events here, and the next launch made through PP_LAUNCH on the same
+// thread hands them to the dispatch itself (hipExtLaunchKernel), so they take
+// the kernel's own start and end and no event packet sits between kernels.
+struct LaunchTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchTimer g_launch_timer;
+
+#define PP_LAUNCH(kern, grid, block, shmem, stream, ...)                                       \
+    do {                                                                                       \
+        if (::pp::g_launch_timer.start) {                                                      \
+            const ::pp::LaunchTimer pp_lt_ = ::pp::g_launch_timer;                             \
+            ::pp::g_launch_timer = ::pp::LaunchTimer{};                                        \
+            hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, pp_lt_.start, pp_lt_.stop, \
+                                  0, __VA_ARGS__);                                             \
+        } else {                                                                               \
+            hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                 \
+        }                                                                                      \
+    } while (0)
 
 // Cell kernels run 64 x 4 thread blocks (four 64-wide waves, one x-row
 // segment per wave), with the z index taken from blockIdx.z.
@@ -215,8 +237,15 @@ void launch_fill(double *x, size_t n, double v, hipStream_t s);
 // block and quantity, quantity q at part[q * pstride + block]
 // act may be null (every cell); otherwise only active cells are summed
 void launch_sum(Dims d, const double *x, const unsigned char *act, double *part, hipStream_t s);
+// n doubles to pinned, coherent host memory, written by a kernel; a nonzero
+// ticket is then written to host[n] (which must exist), after the values
+void launch_publish(const double *src, double *host, int n, hipStream_t s, double ticket = 0.0);
+// host (optional): pinned, coherent host memory that receives a copy of all
+// S_NSLOTS scalars when the operation is done, then the ticket in
+// host[S_NSLOTS]
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
-                     double ncells, int first, double *scal, hipStream_t s);
+                     double ncells, int first, double *scal, hipStream_t s,
+                     double *host = nullptr, double ticket = 0.0);
 // returns the number of partial sums written (at most grid_blocks(red_grid(d)))
 int launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                     const double *b, const double *scal, double *x, bool zero_x, const double *sg,

@@ -24,6 +24,8 @@
 
 namespace pp {
 
+thread_local LaunchTimer g_launch_timer;
+
 template <typename T>
 __device__ __forceinline__ typename Acc<T>::type ld(const T *p, size_t i)
 {
@@ -127,8 +129,7 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double (*sm)[BLO
 }
 
 // Workgroups are dispatched to the 8 XCDs in turn and each XCD has its own L2.
-// The stencil kernels with 2 x 2 cells per thread (and the restriction, whose
-// threads own 2 x 2 x 2 fine cells) take their blocks in groups
+// The stencil kernels with 2 x 2 cells per thread take their blocks in groups
 // of all x-blocks of two block rows, one group per XCD in turn: the halo lines
 // and rows the blocks of a group share (and the periodic wrap in x) then sit
 // in one L2, while the XCDs still work through neighbouring groups, so their
@@ -148,6 +149,27 @@ __device__ __forceinline__ void xcd_groups(unsigned &bx, unsigned &by, unsigned 
     bz = group / (gy / 2);
     by = 2 * (group % (gy / 2)) + member / gx;
     bx = member % gx;
+}
+
+// The restriction takes its blocks in eighths of the whole grid instead, one
+// contiguous range of block planes per XCD (where the block count divides by
+// 8), so that each XCD's L2 holds a slab with halo planes at its two ends
+// only; for the restriction this is the faster order, for the direction and
+// residual passes the grouped one.  Identity otherwise.
+__device__ __forceinline__ void xcd_slabs(unsigned &bx, unsigned &by, unsigned &bz)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    bz = blockIdx.z;
+    const unsigned n = gx * gy * gz;
+    if (n % 8 != 0)
+        return;
+    const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned q = (p & 7u) * (n >> 3) + (p >> 3);
+    bx = q % gx;
+    by = (q / gx) % gy;
+    bz = q / (gx * gy);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,7 +230,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Dims fd, Bc bc, const 
     using T2 = typename Vec2<T>::type;
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
     unsigned gbx, gby, gbz;
-    xcd_groups(gbx, gby, gbz);
+    xcd_slabs(gbx, gby, gbz);
     const int I = (int)gbx * BX + threadIdx.x;
     const int J = (int)gby * BY + threadIdx.y;
     const int K0 = (int)gbz * kz;
@@ -1506,10 +1528,15 @@ __global__ __launch_bounds__(BLOCK) void k_sum(Dims d, const double *__restrict_
 // scalar update of `op`.  One barrier: the kernel is launched once or more
 // per outer iteration and sits on the iteration's critical path.
 constexpr int FIN_THREADS = 1024;
+// host (may be null): pinned host memory that also receives the whole scalar
+// array once the operation is done, written by the kernel itself so that the
+// outer loop reads an iteration's scalars without a separate copy; then
+// host[S_NSLOTS] = ticket, after the values (the host polls it)
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restrict__ part,
                                                           size_t pstride, int nparts, int op,
                                                           int slot, double ncells, int first,
-                                                          double *scal)
+                                                          double *scal, double *host,
+                                                          double ticket)
 {
     __shared__ double sm[2][FIN_THREADS / 64];
     const bool two = op == OP_INIT || op == OP_ALPHA;
@@ -1605,6 +1632,32 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restri
         break;
     default:
         break;
+    }
+    if (host) {
+        for (int q = 0; q < S_NSLOTS; ++q)
+            host[q] = scal[q];
+        __threadfence_system();   // the values before the ticket
+        *(volatile double *)(host + S_NSLOTS) = ticket;
+        __threadfence_system();   // visible to the host before the kernel completes
+    }
+}
+
+// n doubles from device memory to pinned, coherent host memory (one
+// workgroup): the scalars and small arrays the host reads back
+__global__ __launch_bounds__(256) void k_publish(const double *__restrict__ src, double *host, int n,
+                                                double ticket)
+{
+    for (int q = threadIdx.x; q < n; q += blockDim.x)
+        host[q] = src[q];
+    __threadfence_system();
+    if (ticket != 0.0) {
+        // host[n] = ticket once every thread's values are out (the host polls it)
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence_system();
+            *(volatile double *)(host + n) = ticket;
+            __threadfence_system();
+        }
     }
 }
 
@@ -2270,15 +2323,15 @@ void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz
     while (kz < 4 && (size_t)g.x * g.y * ((cd.nz + 2 * kz - 1) / (2 * kz)) >= 1024)
         kz *= 2;
     g.z = (cd.nz + kz - 1) / kz;
-    hipLaunchKernelGGL((k_resid_restrict<T>), g, kBlock, 0, s, fd, bc, bx, by, bz, e, r, sg, rH,
-                       (C)ih2, kz);
+    PP_LAUNCH((k_resid_restrict<T>), g, kBlock, 0, s, fd, bc, bx, by, bz, e, r, sg, rH,
+              (C)ih2, kz);
 }
 
 template <typename T>
 void launch_prolong(Dims fd, Bc bc, const T *eH, T *e, const unsigned *w, hipStream_t s)
 {
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    hipLaunchKernelGGL((k_prolong<T>), cell_grid(cd), kBlock, 0, s, fd, bc, eH, e, w);
+    PP_LAUNCH((k_prolong<T>), cell_grid(cd), kBlock, 0, s, fd, bc, eH, e, w);
 }
 
 void launch_prolong_weights(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
@@ -2487,11 +2540,17 @@ void launch_sum(Dims d, const double *x, const unsigned char *act, double *part,
     hipLaunchKernelGGL(k_sum, red_grid(d), kBlock, 0, s, d, x, act, part);
 }
 
+void launch_publish(const double *src, double *host, int n, hipStream_t s, double ticket)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, src, host, n, ticket);
+}
+
 void launch_finalize(const double *part, size_t pstride, int nparts, int op, int slot,
-                     double ncells, int first, double *scal, hipStream_t s)
+                     double ncells, int first, double *scal, hipStream_t s, double *host,
+                     double ticket)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, part, pstride, nparts, op, slot,
-                       ncells, first, scal);
+                       ncells, first, scal, host, ticket);
 }
 
 int launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
@@ -2521,8 +2580,8 @@ void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const 
                        const double *b, const double *scal, const double *x, const double *sg,
                        const unsigned char *act, T *rT, double ih2, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_residual_T<T>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal, x,
-                       sg, act, rT, ih2, part);
+    PP_LAUNCH((k_residual_T<T>), red_grid(d), kBlock, 0, s, d, bc, bx, by, bz, b, scal, x,
+              sg, act, rT, ih2, part);
 }
 
 template <typename T>
@@ -2558,8 +2617,8 @@ int launch_dir_apply(Dims d, Bc bc, const double *bx, const double *by, const do
                                (d.nz + RZ - 1) / RZ)
                         : red_grid(d);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, g, kBlock, 0, s, d, bc, bx, by, bz, rho, z, dold, dnew, q, x, sg,
-                           scal, ih2, part, pstride);
+        PP_LAUNCH(kern, g, kBlock, 0, s, d, bc, bx, by, bz, rho, z, dold, dnew, q, x, sg,
+                  scal, ih2, part, pstride);
     };
     auto by_mode = [&](auto r) {
         constexpr bool RH = decltype(r)::value;
@@ -2590,7 +2649,7 @@ template <typename T>
 void launch_pcg_update(Dims d, const double *q, double *r, T *rT, const double *scal, double *part,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pcg_update<T>), red_grid(d), kBlock, 0, s, d, q, r, rT, scal, part);
+    PP_LAUNCH((k_pcg_update<T>), red_grid(d), kBlock, 0, s, d, q, r, rT, scal, part);
 }
 
 template <typename D>

@@ -215,6 +215,30 @@ class Solver:
                                      *(self._field(v, "u") for v in out)), "pp_project")
         return out
 
+    def step(self, rho: torch.Tensor, us: Sequence[torch.Tensor], dt: float, tol: float = 1e-8,
+             p: Optional[torch.Tensor] = None, rhs: Optional[torch.Tensor] = None,
+             out: Optional[Sequence[torch.Tensor]] = None, check: bool = True):
+        """One projection step in one call (pp_step): coefficients from rho,
+        rhs = D us / dt, p from the solve, u projected; returns (p, u).  The
+        same results as update_density, divergence, solve and project."""
+        if self.general:
+            raise ValueError("a general context takes its coefficients from update_coeffs")
+        if p is None:
+            p = torch.empty_like(rho)
+        if rhs is None:
+            rhs = torch.empty_like(rho)
+        if out is None:
+            out = tuple(torch.empty_like(rho) for _ in range(3))
+        st = L.Stats()
+        rc = self._lib.pp_step(self._ctx, self._field(rho, "rho"),
+                               *(self._field(v, "us") for v in us), float(dt), float(tol),
+                               self._field(rhs, "rhs"), self._field(p, "p"),
+                               *(self._field(v, "u") for v in out), ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        if check or rc not in (L.PP_OK, L.PP_ENOCONV):
+            L.check(rc, "pp_step")
+        return p, out
+
     def adjoint(self, p: torch.Tensor, g_p: torch.Tensor, tol: float = 1e-8,
                 check: bool = True):
         """Returns (g_rhs, (g_beta_x, g_beta_y, g_beta_z)) for L with dL/dp = g_p."""

@@ -113,6 +113,8 @@ def test_calls_reject_null_context(lib):
     assert lib.pp_solve_adjoint(None, fake, fake, 1e-8, fake, fake, fake, fake, None) == L.PP_EINVAL
     assert lib.pp_divergence(None, fake, fake, fake, 1.0, fake) == L.PP_EINVAL
     assert lib.pp_update_density(None, fake) == L.PP_EINVAL
+    assert lib.pp_step(None, fake, fake, fake, fake, 1e-3, 1e-8, fake, fake, fake, fake, fake,
+                       None) == L.PP_EINVAL
     lib.pp_destroy(None)  # no-op
 
 

@@ -237,9 +237,10 @@ def _prolong_ref(eH, bc):
     return out
 
 
-# grids whose coarse level takes the restriction's grouped block order: two
-# x-blocks of 64 coarse columns with a partial last one, two block rows (the
-# second partial in the first case) and a multiple of 8 block planes
+# grids whose coarse level takes the restriction's slab block order (a block
+# count that divides by 8): two x-blocks of 64 coarse columns with a partial
+# last one, two block rows (the second partial in the first case) and a
+# multiple of 8 block planes
 XCD_GROUPED = [((144, 12, 16), (0, 1, 1)), ((144, 16, 32), (1, 0, 0))]
 
 
