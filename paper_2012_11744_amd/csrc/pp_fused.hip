@@ -143,7 +143,8 @@ __device__ __forceinline__ void xcd_tile(unsigned tx_tiles, unsigned ty_tiles, i
 // SIG: the general operator's diagonal term, stored as h^2 sigma, is read
 // with the other inputs and added to the diagonal.  In every variant a cell with a
 // zero diagonal (no open face, no diagonal term) is excluded and gets 0.
-template <typename T, bool ZERO, bool SIG>
+// WHOLE: the march runs whole blocks of its unroll length (see the loop).
+template <typename T, bool ZERO, bool SIG, bool WHOLE>
 __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T *__restrict__ bx,
                                                          const T *__restrict__ by,
                                                          const T *__restrict__ bz,
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
         // phase B: second colour of plane k-1 (at the column of this plane's
         // first colour); the store of a thread outside the tile is dropped
         const int kb = k - 1;
-        if (kb >= k0) {
+        if (kb >= k0 && kb < k1) {
             const int sb = slot3(kb);
             const C bzl = pick(o, pm.bz), bzh = pick(o, pc.bz);
             const C sbv = sxl * RED[sb][ly][ca - 1] + sxh * RED[sb][ly][ca + 1] +
@@ -355,7 +356,12 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
 
     // FNB input buffers rotate through the roles (k-1, k, k+1, and the planes
     // in flight); the loop is unrolled by FNB so no buffer with loads in
-    // flight is ever copied
+    // flight is ever copied.  WHOLE: it runs whole blocks of FNB steps, the
+    // last up to FNB - 1 steps past k1 (they store nothing), with one exit
+    // test per block, which keeps the loop-carried registers in place across
+    // the back edge; an exit after every step makes the compiler copy
+    // registers with loads in flight there (waiting for them), which costs
+    // less than the extra steps only on short chunks.
     PairIn<T> buf[FNB];
 #pragma unroll
     for (int u = 0; u < FNB - 1; ++u)
@@ -363,12 +369,22 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
     __syncthreads();                  // the zero fill is complete
     publish((k0 - 1) & 1, buf[1]);
     __syncthreads();
-    for (int k = k0 - 1;;) {
+    if constexpr (WHOLE) {
+        for (int k = k0 - 1; k <= k1; k += FNB) {
 #pragma unroll
-        for (int u = 0; u < FNB; ++u) {
-            step(k, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB], buf[(u + FNB - 1) % FNB]);
-            if (++k > k1)
-                return;
+            for (int u = 0; u < FNB; ++u)
+                step(k + u, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB],
+                     buf[(u + FNB - 1) % FNB]);
+        }
+    } else {
+        for (int k = k0 - 1;;) {
+#pragma unroll
+            for (int u = 0; u < FNB; ++u) {
+                step(k, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB],
+                     buf[(u + FNB - 1) % FNB]);
+                if (++k > k1)
+                    return;
+            }
         }
     }
 }
@@ -391,7 +407,7 @@ static long long fused_slots()
         dev = 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused<T, ZERO, SIG>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused<T, ZERO, SIG, false>,
                                                          FTHREADS, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
@@ -402,6 +418,11 @@ static long long fused_slots()
     }
     return cached[dev];
 }
+
+// Marches of at least this many plane steps run whole blocks of the unroll
+// length (the WHOLE variants): the few steps a block runs past the chunk cost
+// less there than the register copies at the back edge of the other form.
+constexpr int WHOLE_MIN_STEPS = 48;
 
 // Chunk length along z: the smallest chunk (fewest redundant halo planes)
 // whose workgroups all fit on the GPU at once, so a sweep runs as a single
@@ -437,9 +458,16 @@ void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
     const int kz = fused_kz(d, tx * ty, slots);
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty, tz);   // distinct shapes per level in profiles
+    const bool whole = kz + 2 >= WHOLE_MIN_STEPS;   // a chunk marches kz + 2 steps
 #define PP_FUSED_LAUNCH(Z, S)                                                                  \
-    PP_LAUNCH((k_rbgs_fused<T, Z, S>), grid, dim3(FTHREADS), 0, s, d, bc, bx, by, bz, r, \
-              ein, eout, sg, (C)h2, first_colour, kz, tx, ty)
+    do {                                                                                       \
+        if (whole)                                                                             \
+            PP_LAUNCH((k_rbgs_fused<T, Z, S, true>), grid, dim3(FTHREADS), 0, s, d, bc, bx,    \
+                      by, bz, r, ein, eout, sg, (C)h2, first_colour, kz, tx, ty);              \
+        else                                                                                   \
+            PP_LAUNCH((k_rbgs_fused<T, Z, S, false>), grid, dim3(FTHREADS), 0, s, d, bc, bx,   \
+                      by, bz, r, ein, eout, sg, (C)h2, first_colour, kz, tx, ty);              \
+    } while (0)
     if (sg) {
         if (zero)
             PP_FUSED_LAUNCH(true, true);
@@ -493,7 +521,7 @@ struct GsLag {
 // in FP64 (the outer iteration's residual against the preconditioned one,
 // both in units of the V-cycle's scale); part[workgroup].  The h^2 r values
 // that phases C and D already carry supply r, so nothing more is loaded.
-template <typename T, bool ZERO, bool SIG, bool DOT>
+template <typename T, bool ZERO, bool SIG, bool DOT, bool WHOLE>
 __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T *__restrict__ bx,
                                                           const T *__restrict__ by,
                                                           const T *__restrict__ bz,
@@ -728,7 +756,7 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
             const C blk2 = (b2.xl * dw + b2.xh * de + b2.yl * ds + b2.yh * dn + b2.zl * r2_km2 +
                             b2.zh * red2 - b2.hr) * b2.inv;
             const int kd = k - 3;
-            if (kd >= k0) {
+            if (kd >= k0 && kd < k1) {
                 T2 outv;
                 outv.x = static_cast<T>(o ? r2_km1 : blk2);
                 outv.y = static_cast<T>(o ? blk2 : r2_km1);
@@ -765,14 +793,27 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     __syncthreads();                  // the zero fill is complete
     publish(0, buf[1]);
     __syncthreads();
-    for (int k = kb, more = 1; more;) {
+    if constexpr (WHOLE) {
+        // whole blocks of FNB steps, the last up to FNB - 1 steps past k1 + 2
+        // (they store nothing), as in the single sweep.  FP16 does not take
+        // this form: its registers would then allow one workgroup per CU
+        // instead of two.
+        for (int k = kb; k <= k1 + 2; k += FNB) {
 #pragma unroll
-        for (int u = 0; u < FNB; ++u) {
-            step(k, u, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB],
-                 buf[(u + FNB - 1) % FNB]);
-            if (++k > k1 + 2) {
-                more = 0;
-                break;
+            for (int u = 0; u < FNB; ++u)
+                step(k + u, u, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB],
+                     buf[(u + FNB - 1) % FNB]);
+        }
+    } else {
+        for (int k = kb, more = 1; more;) {
+#pragma unroll
+            for (int u = 0; u < FNB; ++u) {
+                step(k, u, buf[u % FNB], buf[(u + 1) % FNB], buf[(u + 2) % FNB],
+                     buf[(u + FNB - 1) % FNB]);
+                if (++k > k1 + 2) {
+                    more = 0;
+                    break;
+                }
             }
         }
     }
@@ -804,7 +845,8 @@ static long long fused2_slots()
         dev = 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rbgs_fused2<T, ZERO, SIG, DOT>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                         k_rbgs_fused2<T, ZERO, SIG, DOT, false>,
                                                          GTHREADS, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
@@ -849,9 +891,19 @@ int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
         kz = (d.nz < 8) ? d.nz : 8;
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty, tz);
-#define PP_FUSED2_LAUNCH(Z, S, D)                                                                \
-    PP_LAUNCH((k_rbgs_fused2<T, Z, S, D>), grid, dim3(GTHREADS), 0, s, d, bc, bx, by,   \
-              bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty, part)
+    // a chunk marches kz + 6 steps; FP16 keeps the exit after every step
+    const bool whole = std::is_same<T, float>::value && kz + 6 >= WHOLE_MIN_STEPS;
+#define PP_FUSED2_LAUNCH(Z, S, D)                                                              \
+    do {                                                                                       \
+        if (whole)                                                                             \
+            PP_LAUNCH((k_rbgs_fused2<T, Z, S, D, std::is_same<T, float>::value>), grid,        \
+                      dim3(GTHREADS), 0, s, d, bc, bx, by, bz, r, ein, eout, sg, (float)h2,    \
+                      first_colour, kz, tx, ty, part);                                         \
+        else                                                                                   \
+            PP_LAUNCH((k_rbgs_fused2<T, Z, S, D, false>), grid, dim3(GTHREADS), 0, s, d, bc,   \
+                      bx, by, bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty,       \
+                      part);                                                                   \
+    } while (0)
     if (dot) {
         if constexpr (std::is_same<T, float>::value)
             PP_FUSED2_LAUNCH(false, false, true);

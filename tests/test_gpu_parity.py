@@ -111,7 +111,16 @@ def test_one_gauss_seidel_sweep_matches_paper_sor(S, n, bc):
     assert relmax(host(e), ref2) <= 1e-14
 
 
-@pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0))])
+# grids whose z chunks are long enough for the march in whole unrolled blocks
+# (the last block running past the chunk), with a ragged last chunk: FP64
+# single sweep (128 x 8 tiles, chunks of 47 planes) and FP32 two-sweep pass
+# (64 x 8 tiles, chunks of 48 planes)
+WHOLE_F64 = ((256, 128, 370), (1, 0, 0))
+WHOLE_F32 = ((256, 128, 190), (0, 0, 1))
+
+
+@pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0)),
+                                  WHOLE_F64])
 @pytest.mark.parametrize("first", [0, 1])
 def test_fused_sweep_matches_paper_sor(S, n, bc, first):
     """One fused out-of-place sweep (tiles of 128 x 8 cells, z chunks, ring
@@ -137,7 +146,7 @@ def test_fused_sweep_matches_paper_sor(S, n, bc, first):
 
 
 @pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0)),
-                                  ((200, 72, 40), (0, 0, 0))])
+                                  ((200, 72, 40), (0, 0, 0)), WHOLE_F32])
 @pytest.mark.parametrize("first", [0, 1])
 def test_two_sweep_fused_f32_matches_paper_sor(S, n, bc, first):
     """Two sweeps in one pass (FP32 storage and arithmetic; tiles of 64 x 8
@@ -171,7 +180,7 @@ def test_two_sweep_fused_f32_matches_paper_sor(S, n, bc, first):
 
 
 @pytest.mark.parametrize("n,bc", [((40, 20, 56), (1, 0, 1)), ((144, 80, 32), (0, 1, 1)),
-                                  ((200, 72, 40), (0, 0, 0))])
+                                  ((200, 72, 40), (0, 0, 0)), WHOLE_F32])
 def test_two_sweep_fused_dot_product(S, n, bc):
     """The FP32 V-cycle's last fine pass also forms r . e_out for the outer
     iteration, r its own right-hand side: e_out equals the plain pass bit for
