@@ -422,10 +422,9 @@ int enqueue_coarse_download(pp_ctx *c)
 {
     const int L = c->nlev - 1;
     const size_t n = cells(c->ld[L]);
-    for (int m = 0; m < 3; ++m)
-        launch_publish(c->chain[L][m], c->hcoarse + m * n, (int)n, c->stream);
-    if (c->sig_on)
-        launch_publish(c->sig[L], c->hcoarse + 3 * n, (int)n, c->stream);
+    const double *src[4] = {c->chain[L][0], c->chain[L][1], c->chain[L][2],
+                            c->sig_on ? c->sig[L] : nullptr};
+    launch_publish_arrays(src, c->sig_on ? 4 : 3, (int)n, c->hcoarse, c->stream);
     PP_TRY(check_launch("coarsest coefficients read-back"));
     PP_HIP(hipEventRecord(c->coarse_ev, c->stream));
     return PP_OK;
@@ -755,19 +754,24 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho, b
             double *lev[3] = {c->chain[l][0], c->chain[l][1], c->chain[l][2]};
             const double *src[3] = {lev[0], lev[1], lev[2]};
             double *crs[3] = {c->chain[l + 1][0], c->chain[l + 1][1], c->chain[l + 1][2]};
-            if (H.st == ST_F32) {
-                float *tt[3] = {(float *)H.lev[l].b[0], (float *)H.lev[l].b[1],
-                                (float *)H.lev[l].b[2]};
-                launch_load_coeffs<float>(c->ld[l], c->bc, src, lev, tt, crs, c->pw[l], c->part,
-                                          c->stream);
-            } else {
-                _Float16 *tt[3] = {(_Float16 *)H.lev[l].b[0], (_Float16 *)H.lev[l].b[1],
-                                   (_Float16 *)H.lev[l].b[2]};
-                launch_load_coeffs<_Float16>(c->ld[l], c->bc, src, lev, tt, crs, c->pw[l],
-                                             c->part, c->stream);
-            }
+            // the last of them also writes the coarsest level's storage copy
+            const bool last = l + 2 == c->nlev;
+            auto go = [&](auto *t) {
+                using TT = std::remove_pointer_t<decltype(t)>;
+                TT *tt[3] = {(TT *)H.lev[l].b[0], (TT *)H.lev[l].b[1], (TT *)H.lev[l].b[2]};
+                TT *ct[3] = {(TT *)H.lev[l + 1].b[0], (TT *)H.lev[l + 1].b[1],
+                             (TT *)H.lev[l + 1].b[2]};
+                launch_load_coeffs<TT>(c->ld[l], c->bc, src, lev, tt, crs, c->pw[l], nullptr,
+                                       c->stream, last ? ct : nullptr);
+            };
+            if (H.st == ST_F32)
+                go((float *)nullptr);
+            else
+                go((_Float16 *)nullptr);
         }
-        conv_from = std::max(1, c->nlev - 1);
+        // the coarsest level's storage copy is written above when there are
+        // levels between it and level 0; otherwise it is level 1, converted
+        conv_from = c->nlev > 2 ? c->nlev : 1;
     } else {
         for (int l = first_coarse; l + 1 < c->nlev; ++l)
             launch_coarsen_beta(c->ld[l], c->bc, c->chain[l][0], c->chain[l][1], c->chain[l][2],

@@ -188,11 +188,12 @@ void launch_coarsen_beta(Dims fd, Bc bc, const double *bx, const double *by, con
                          double *hx, double *hy, double *hz, hipStream_t s);
 // one pass: copy + wall zeroing + validity count (partials) + storage copy
 // (dstT[0] may be null) + first coarse level; the fine grid's n must all be
-// even; returns the number of partial sums written
+// even; returns the number of partial sums written (part null: no count, 0);
+// coarseT (may be null): the first coarse level's storage copy too
 template <typename T>
 int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
                        T *const dstT[3], double *const coarse[3], unsigned *w0, double *part,
-                       hipStream_t s);
+                       hipStream_t s, T *const coarseT[3] = nullptr);
 // as launch_load_coeffs with beta computed from the cell densities (the
 // arithmetic of launch_face_coeffs), also copying the densities to rcopy; the
 // partials also count cells whose density is not a finite positive number
@@ -237,6 +238,9 @@ void launch_fill(double *x, size_t n, double v, hipStream_t s);
 // block and quantity, quantity q at part[q * pstride + block]
 // act may be null (every cell); otherwise only active cells are summed
 void launch_sum(Dims d, const double *x, const unsigned char *act, double *part, hipStream_t s);
+// narr (at most 4) arrays of n doubles each, one after the other, to pinned,
+// coherent host memory, in one kernel
+void launch_publish_arrays(const double *const *src, int narr, int n, double *host, hipStream_t s);
 // n doubles to pinned, coherent host memory, written by a kernel; a nonzero
 // ticket is then written to host[n] (which must exist), after the values
 void launch_publish(const double *src, double *host, int n, hipStream_t s, double ticket = 0.0);

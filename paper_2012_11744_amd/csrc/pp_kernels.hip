@@ -947,7 +947,10 @@ __global__ __launch_bounds__(BLOCK) void k_zero_walls(Dims d, Bc bc, double *bx,
 // are not finite positive numbers, writes the storage-precision copy used by
 // the V-cycle (WT), and the first coarse level (mean of the 4 fine faces of
 // each coarse face).  One thread per coarse cell, i.e. per 2x2x2 fine block;
-// each block of threads covers RZ/2 coarse planes.
+// each block of threads covers kz coarse planes.  part null: no count (the
+// coarse levels, formed from valid coefficients, load one plane per block so
+// that their short grids do not walk planes in series).  htx (may be null):
+// the coarse level's storage copy too.
 template <typename T, bool WT>
 __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const double *__restrict__ sx,
                                                        const double *__restrict__ sy_,
@@ -956,8 +959,9 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
                                                        double *__restrict__ dz, T *__restrict__ tx,
                                                        T *__restrict__ ty, T *__restrict__ tz,
                                                        double *__restrict__ hx, double *__restrict__ hy,
-                                                       double *__restrict__ hz,
-                                                       unsigned *__restrict__ w0, double *part)
+                                                       double *__restrict__ hz, T *__restrict__ htx,
+                                                       T *__restrict__ hty, T *__restrict__ htz,
+                                                       unsigned *__restrict__ w0, double *part, int kz)
 {
     using D2 = double __attribute__((ext_vector_type(2)));
     using T2 = typename Vec2<T>::type;
@@ -978,8 +982,8 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
         // a face of wrapped index 0 in a wall direction is the wall (the
         // implicit upper one when reached from above): 0 whatever is stored
         const bool wxu = bc.x && xu == 0, wyu = bc.y && yu == 0;
-        const int Ke = min(cd.nz, ((int)blockIdx.z + 1) * (RZ / 2));
-        for (int K = blockIdx.z * (RZ / 2); K < Ke; ++K) {
+        const int Ke = min(cd.nz, ((int)blockIdx.z + 1) * kz);
+        for (int K = blockIdx.z * kz; K < Ke; ++K) {
             const int zl = (K == 0) ? fd.nz - 1 : 2 * K - 1;
             const int zu = (2 * K + 2 == fd.nz) ? 0 : 2 * K + 2, zu3 = (zu + 1 == fd.nz) ? 0 : zu + 1;
             const bool wzu = bc.z && zu == 0;
@@ -1059,15 +1063,24 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
                 }
             const size_t C = ((size_t)K * cd.ny + J) * cd.nx + I;
             // the same values in the same order as k_coarsen_beta
-            hx[C] = (bc.x && I == 0) ? 0.0 : coarse_face(xlo, xmid, xhi);
-            hy[C] = (bc.y && J == 0) ? 0.0 : coarse_face(ylo, ymid, yhi);
-            hz[C] = (bc.z && K == 0) ? 0.0 : coarse_face(zlo, zmid, zhi);
+            const double cx = (bc.x && I == 0) ? 0.0 : coarse_face(xlo, xmid, xhi);
+            const double cy = (bc.y && J == 0) ? 0.0 : coarse_face(ylo, ymid, yhi);
+            const double cz = (bc.z && K == 0) ? 0.0 : coarse_face(zlo, zmid, zhi);
+            hx[C] = cx;
+            hy[C] = cy;
+            hz[C] = cz;
+            if (htx) {
+                htx[C] = static_cast<T>(cx);
+                hty[C] = static_cast<T>(cy);
+                htz[C] = static_cast<T>(cz);
+            }
             // the level's prolongation weights, as k_prolong_weights forms them
             children_weights(xlo, xmid, xhi, x2, x3, ylo, ymid, yhi, y2, y3, zlo, zmid, zhi, z2, z3,
                              w0, (size_t)(2 * K) * fz + (size_t)y * fy + x, fy, fz);
         }
     }
-    block_partials<1>(v, sm, part, 0);
+    if (part)
+        block_partials<1>(v, sm, part, 0);
 }
 
 // k_load_coeffs with the face coefficients computed from the cell densities
@@ -2412,19 +2425,24 @@ void launch_zero_walls(Dims d, Bc bc, double *bx, double *by, double *bz, hipStr
 template <typename T>
 int launch_load_coeffs(Dims fd, Bc bc, const double *const src[3], double *const dst[3],
                        T *const dstT[3], double *const coarse[3], unsigned *w0, double *part,
-                       hipStream_t s)
+                       hipStream_t s, T *const coarseT[3])
 {
     const Dims cd{fd.nx / 2, fd.ny / 2, fd.nz / 2};
-    const dim3 g((cd.nx + BX - 1) / BX, (cd.ny + BY - 1) / BY, (cd.nz + RZ / 2 - 1) / (RZ / 2));
+    const int kz = part ? RZ / 2 : 1;
+    const dim3 g((cd.nx + BX - 1) / BX, (cd.ny + BY - 1) / BY, (cd.nz + kz - 1) / kz);
+    T *ct[3] = {nullptr, nullptr, nullptr};
+    if (coarseT)
+        for (int m = 0; m < 3; ++m)
+            ct[m] = coarseT[m];
     if (dstT[0])
         hipLaunchKernelGGL((k_load_coeffs<T, true>), g, kBlock, 0, s, fd, bc, src[0], src[1], src[2],
                            dst[0], dst[1], dst[2], dstT[0], dstT[1], dstT[2], coarse[0], coarse[1],
-                           coarse[2], w0, part);
+                           coarse[2], ct[0], ct[1], ct[2], w0, part, kz);
     else
         hipLaunchKernelGGL((k_load_coeffs<T, false>), g, kBlock, 0, s, fd, bc, src[0], src[1],
                            src[2], dst[0], dst[1], dst[2], dstT[0], dstT[1], dstT[2], coarse[0],
-                           coarse[1], coarse[2], w0, part);
-    return (int)grid_blocks(g);
+                           coarse[1], coarse[2], ct[0], ct[1], ct[2], w0, part, kz);
+    return part ? (int)grid_blocks(g) : 0;
 }
 
 template <typename T>
@@ -2538,6 +2556,28 @@ void launch_fill(double *x, size_t n, double v, hipStream_t s)
 void launch_sum(Dims d, const double *x, const unsigned char *act, double *part, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sum, red_grid(d), kBlock, 0, s, d, x, act, part);
+}
+
+// up to four arrays of n doubles, one after the other into host
+struct PublishSrc {
+    const double *p[4];
+};
+
+__global__ __launch_bounds__(256) void k_publish_arrays(PublishSrc src, int narr, int n, double *host)
+{
+    for (int a = 0; a < narr; ++a)
+        for (int q = threadIdx.x; q < n; q += blockDim.x)
+            host[(size_t)a * n + q] = src.p[a][q];
+    __threadfence_system();
+}
+
+void launch_publish_arrays(const double *const *src, int narr, int n, double *host, hipStream_t s)
+{
+    PublishSrc ps{{nullptr, nullptr, nullptr, nullptr}};
+    for (int a = 0; a < narr && a < 4; ++a)
+        ps.p[a] = src[a];
+    hipLaunchKernelGGL(k_publish_arrays, dim3(1), dim3(256), 0, s, ps, narr < 4 ? narr : 4, n,
+                       host);
 }
 
 void launch_publish(const double *src, double *host, int n, hipStream_t s, double ticket)
@@ -2678,7 +2718,7 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
     template void launch_prolong<T>(Dims, Bc, const T *, T *, const unsigned *, hipStream_t);    \
     template int launch_load_coeffs<T>(Dims, Bc, const double *const[3], double *const[3],      \
                                        T *const[3], double *const[3], unsigned *, double *,     \
-                                       hipStream_t);                                            \
+                                       hipStream_t, T *const[3]);                               \
     template int launch_load_density<T>(Dims, Bc, const double *, double *const[3], T *const[3], \
                                         double *const[3], double *, unsigned *, double *,       \
                                         hipStream_t);                                           \
