@@ -1038,7 +1038,7 @@ int check_progress(SolveState &S, int since_best_limit, int &since, double &best
 // operator kernels then read the coefficient arrays
 const double *op_rho(const pp_ctx *c) { return (c->rho_ok && !c->gen) ? c->rho : nullptr; }
 
-int gauge(pp_ctx *c, double *x);
+int gauge(pp_ctx *c, double *x, int xsum_parts = 0);
 
 // work a caller queues behind a solve's result (the projection of pp_step)
 using Tail = std::function<int()>;
@@ -1061,7 +1061,7 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
     launch_finalize(c->part, c->pstride, np, OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
     PP_TRY(check_launch("residual"));
     if (gauge_x)
-        PP_TRY(gauge(c, x));
+        PP_TRY(gauge(c, x, zero_x ? 0 : np));   // the residual kernel summed x too
     PP_TRY(post_scal(c));
     if (gauge_x && tail)
         PP_TRY((*tail)());
@@ -1270,13 +1270,20 @@ int run_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, Solve
 
 // Singular operator: remove the mean of x (over the active cells of the
 // general operator).  General operator: excluded cells are set to 0.
-int gauge(pp_ctx *c, double *x)
+// xsum_parts > 0: the partial sums of x are already in the third partials
+// row (the residual kernel formed them), that many of them.
+int gauge(pp_ctx *c, double *x, int xsum_parts)
 {
     const unsigned char *act = c->gen ? c->act : nullptr;
     if (!c->gen || c->singular) {
-        launch_sum(c->d, x, act, c->part, c->stream);
-        launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_XMEAN,
-                        c->gen ? c->nact : (double)c->N, 0, c->scal, c->stream);
+        if (xsum_parts > 0) {
+            launch_finalize(c->part + 2 * c->pstride, c->pstride, xsum_parts, OP_MEAN, S_XMEAN,
+                            c->gen ? c->nact : (double)c->N, 0, c->scal, c->stream);
+        } else {
+            launch_sum(c->d, x, act, c->part, c->stream);
+            launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_XMEAN,
+                            c->gen ? c->nact : (double)c->N, 0, c->scal, c->stream);
+        }
         launch_sub_mean(c->N, x, c->scal, S_XMEAN, act, c->stream);
     } else {
         launch_sub_mean(c->N, x, c->scal, -1, act, c->stream);
@@ -1286,8 +1293,10 @@ int gauge(pp_ctx *c, double *x)
 
 // tail (may be null): work to queue behind the result; *tail_queued tells
 // whether it was queued behind the final iterate (else the caller queues it)
+// mean_ready: scal[S_MEAN] already holds the mean of rhs (pp_step's
+// divergence formed it)
 int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st, bool warm,
-               const Tail *tail = nullptr, bool *tail_queued = nullptr)
+               const Tail *tail = nullptr, bool *tail_queued = nullptr, bool mean_ready = false)
 {
     if (tail_queued)
         *tail_queued = false;
@@ -1298,12 +1307,14 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
     SolveState S{0.0, 0.0, INFINITY, 0, st};
     // the mean of the right-hand side is removed when the operator is
     // singular (over the active cells for the general operator)
-    if (!c->gen || c->singular) {
-        launch_sum(c->d, rhs, c->gen ? c->act : nullptr, c->part, c->stream);
-        launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_MEAN,
-                        c->gen ? c->nact : (double)c->N, 0, c->scal, c->stream);
-    } else {
-        launch_fill(c->scal + S_MEAN, 1, 0.0, c->stream);
+    if (!mean_ready) {
+        if (!c->gen || c->singular) {
+            launch_sum(c->d, rhs, c->gen ? c->act : nullptr, c->part, c->stream);
+            launch_finalize(c->part, c->pstride, nparts(c), OP_MEAN, S_MEAN,
+                            c->gen ? c->nact : (double)c->N, 0, c->scal, c->stream);
+        } else {
+            launch_fill(c->scal + S_MEAN, 1, 0.0, c->stream);
+        }
     }
     if (c->gen && warm)
         launch_mask(c->N, x, c->act, c->stream);   // excluded cells of a warm start are not read
@@ -1533,7 +1544,7 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
         rc = dev_alloc_t(c, &c->q64, sizeof(double) * c->N);
     c->pstride = grid_blocks(red_grid(c->d));
     if (rc == PP_OK)
-        rc = dev_alloc_t(c, &c->part, sizeof(double) * 2 * c->pstride);
+        rc = dev_alloc_t(c, &c->part, sizeof(double) * 3 * c->pstride);
     if (rc == PP_OK)
         rc = dev_alloc_t(c, &c->scal, sizeof(double) * S_NSLOTS);
     if (rc != PP_OK)
@@ -1806,8 +1817,12 @@ int pp_step(pp_ctx *c, const double *rho, const double *usx, const double *usy,
     // wait, so the step waits on the host for the solve's results only
     const double *src[3] = {nullptr, nullptr, nullptr};
     PP_TRY(load_coeffs_impl(c, src, rho, true));
-    launch_divergence(c->d, c->bc, usx, usy, usz, (1.0 / dt) / c->grid.h, nullptr, nullptr, nullptr,
-                      rhs, c->stream);
+    // the divergence also sums what it writes, as the solve's pass over the
+    // right-hand side would (same blocks, same order, same bits)
+    const int np = launch_divergence_sum(c->d, c->bc, usx, usy, usz, (1.0 / dt) / c->grid.h, rhs,
+                                         c->part, c->stream);
+    launch_finalize(c->part, c->pstride, np, OP_MEAN, S_MEAN, (double)c->N, 0, c->scal,
+                    c->stream);
     PP_TRY(check_launch("pp_step divergence"));
     const Tail project = [&]() {
         launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], op_rho(c), usx,
@@ -1820,7 +1835,7 @@ int pp_step(pp_ctx *c, const double *rho, const double *usx, const double *usy,
     const bool in_place = ux == usx || uy == usy || uz == usz;
     bool queued = false;
     const int rc = solve_impl(c, rhs, p, tol, st, c->opts.warm_start != 0,
-                              in_place ? nullptr : &project, &queued);
+                              in_place ? nullptr : &project, &queued, true);
     if (rc != PP_OK && rc != PP_ENOCONV)
         return rc;
     if (!queued)

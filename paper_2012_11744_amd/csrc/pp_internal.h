@@ -218,6 +218,10 @@ void launch_mask(size_t n, double *x, const unsigned char *act, hipStream_t s);
 void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by, double *bz,
                         hipStream_t s);
 // bx/by/bz may be null; when given, closed links (beta = 0) carry no flux
+// the divergence of the pressure operator (no face coefficients) with the
+// partial sums of out in k_sum's blocks and order; returns their count
+int launch_divergence_sum(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
+                          double scale_over_h, double *out, double *part, hipStream_t s);
 void launch_divergence(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
                        double scale_over_h, const double *bx, const double *by, const double *bz,
                        double *out, hipStream_t s);

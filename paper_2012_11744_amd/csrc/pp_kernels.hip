@@ -1398,6 +1398,39 @@ __global__ __launch_bounds__(BLOCK) void k_divergence(Dims d, Bc bc, const doubl
     out[n.c] = s_h * ((xh - xl) + (yh - yl) + (zh - zl));
 }
 
+// k_divergence for the pressure operator (no face coefficients) walking RZ
+// planes per thread, which also sums the values it writes, in the blocks and
+// the order of k_sum: the partials are those k_sum would form from `out`,
+// bit for bit, so the right-hand side's mean needs no pass of its own
+__global__ __launch_bounds__(BLOCK) void k_divergence_sum(Dims d, Bc bc,
+                                                          const double *__restrict__ ux,
+                                                          const double *__restrict__ uy,
+                                                          const double *__restrict__ uz,
+                                                          double s_h, double *__restrict__ out,
+                                                          double *part)
+{
+    // the sum takes the rounded values, as k_sum reads them (no fused
+    // multiply-add of the product into the sum)
+#pragma clang fp contract(off)
+    __shared__ double sm[1][BLOCK / 64];
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    double v[1] = {0.0};
+    if (i < d.nx && j < d.ny) {
+        const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
+        for (int k = blockIdx.z * RZ; k < ke; ++k) {
+            const Nb n = neighbours(d, bc, i, j, k);
+            const double xl = n.wxl ? 0.0 : ux[n.c], xh = n.wxh ? 0.0 : ux[n.xp];
+            const double yl = n.wyl ? 0.0 : uy[n.c], yh = n.wyh ? 0.0 : uy[n.yp];
+            const double zl = n.wzl ? 0.0 : uz[n.c], zh = n.wzh ? 0.0 : uz[n.zp];
+            const double val = s_h * ((xh - xl) + (yh - yl) + (zh - zl));
+            out[n.c] = val;
+            v[0] += val;
+        }
+    }
+    block_partials<1>(v, sm, part, 0);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, Bc bc, const double *__restrict__ bx,
                                                  const double *__restrict__ by,
                                                  const double *__restrict__ bz,
@@ -1674,7 +1707,8 @@ __global__ __launch_bounds__(256) void k_publish(const double *__restrict__ src,
     }
 }
 
-// r = (b - mean b) - A x; partials ||r||^2 and ||b - mean b||^2.
+// r = (b - mean b) - A x; partials ||r||^2, ||b - mean b||^2 and the sum of
+// x over the active cells (the gauge's mean, at no extra pass).
 // ZEROX: x is set to zero (cold start) and A x is skipped.
 template <bool ZEROX>
 __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double *__restrict__ bx,
@@ -1687,17 +1721,18 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
                                                     double *__restrict__ r64, double ih2,
                                                     double *part, size_t pstride)
 {
-    __shared__ double sm[2][BLOCK / 64];
+    __shared__ double sm[3][BLOCK / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    double v[2] = {0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0};
     if (i < d.nx && j < d.ny) {
         const double mean = scal[S_MEAN];
         const int ke = min(d.nz, ((int)blockIdx.z + 1) * RZ);
         for (int k = blockIdx.z * RZ; k < ke; ++k) {
             const Nb n = neighbours(d, bc, i, j, k);
             // the right-hand side of an excluded cell is not part of the system
-            const double bm = (act && !act[n.c]) ? 0.0 : b[n.c] - mean;
+            const bool on = !act || act[n.c];
+            const double bm = on ? b[n.c] - mean : 0.0;
             double ax = 0.0;
             if (ZEROX) {
                 x[n.c] = 0.0;
@@ -1706,6 +1741,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
                 ax = ih2 * flux_sum(n, L, x);
                 if (sg)
                     ax -= sg[n.c] * x[n.c];
+                if (on)
+                    v[2] += x[n.c];
             }
             const double r = bm - ax;
             r64[n.c] = r;
@@ -1713,10 +1750,10 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Dims d, Bc bc, const double 
             v[1] += bm * bm;
         }
     }
-    block_partials<2>(v, sm, part, pstride);
+    block_partials<3>(v, sm, part, pstride);
 }
 
-// k_residual (x given) for grids with even nx and ny and 16-byte aligned
+// k_residual (x given, the same three partial sums) for grids with even nx and ny and 16-byte aligned
 // arrays: each thread owns a 2 x 2 block of cells and walks RZ planes with the
 // column's planes below and at the current one carried in registers, as in
 // k_dir_apply2; the same per-cell arithmetic as the one-cell kernel.
@@ -1732,12 +1769,12 @@ __global__ __launch_bounds__(BLOCK) void k_residual2(Dims d, Bc bc, const double
                                                      double *part, size_t pstride)
 {
     using F2 = double __attribute__((ext_vector_type(2)));
-    __shared__ double sm[2][BLOCK / 64];
+    __shared__ double sm[3][BLOCK / 64];
     unsigned gbx, gby, gbz;
     xcd_groups(gbx, gby, gbz);
     const int x0 = 2 * (int)(gbx * BX + threadIdx.x);
     const int j0 = 2 * (int)(gby * BY + threadIdx.y), j1 = j0 + 1;
-    double v[2] = {0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0};
     if (x0 < d.nx && j0 < d.ny) {
         const double mean = scal[S_MEAN];
         const size_t sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
@@ -1802,7 +1839,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual2(Dims d, Bc bc, const double
                 const double Lzh = wzh ? 0.0 : zh[c];
                 const double xc = Xc[c];
                 // the right-hand side of an excluded cell is not part of the system
-                const double bm = (act && !act[cell]) ? 0.0 : bb[c] - mean;
+                const bool on = !act || act[cell];
+                const double bm = on ? bb[c] - mean : 0.0;
                 const double f = Lxh * (nxp[c] - xc) - Lxl * (xc - nxm[c]) +
                                  Lyh * (nyp[c] - xc) - Lyl * (xc - nym[c]) +
                                  Lzh * (Xp[c] - xc) - Lzl * (xc - Xm[c]);
@@ -1812,6 +1850,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual2(Dims d, Bc bc, const double
                 rr[c] = bm - ax;
                 v[0] += rr[c] * rr[c];
                 v[1] += bm * bm;
+                if (on)
+                    v[2] += xc;
             }
             *reinterpret_cast<F2 *>(r64 + pl + o0) = F2{rr[0], rr[1]};
             *reinterpret_cast<F2 *>(r64 + pl + o1) = F2{rr[2], rr[3]};
@@ -1823,7 +1863,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual2(Dims d, Bc bc, const double
             }
         }
     }
-    block_partials<2>(v, sm, part, pstride);
+    block_partials<3>(v, sm, part, pstride);
 }
 
 // defect-correction residual: rT = ((b - mean b) - A x) / scal[S_NEXT]; partial ||r||^2
@@ -2501,6 +2541,14 @@ void launch_face_coeffs(Dims d, Bc bc, const double *rho, double *bx, double *by
                         hipStream_t s)
 {
     hipLaunchKernelGGL(k_face_coeffs, cell_grid(d), kBlock, 0, s, d, bc, rho, bx, by, bz);
+}
+
+int launch_divergence_sum(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
+                          double scale_over_h, double *out, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_divergence_sum, red_grid(d), kBlock, 0, s, d, bc, ux, uy, uz,
+                       scale_over_h, out, part);
+    return (int)grid_blocks(red_grid(d));
 }
 
 void launch_divergence(Dims d, Bc bc, const double *ux, const double *uy, const double *uz,
