@@ -85,7 +85,9 @@ typedef struct {
     int32_t warm_start;  /* 1: pp_solve starts from the p passed in; 0: from p = 0 */
     int32_t fallback;    /* 1: on stagnation of a mixed solve, continue with FP64 V-cycles */
     int32_t coarse_graph; /* 1: replay the coarse levels of each V-cycle from a HIP graph
-                            captured in pp_setup (same kernels, same order, same results) */
+                            captured in pp_setup (same kernels, same order, same results);
+                            0 (default): launch them one by one, which measured faster since
+                            the iterations are queued ahead of the GPU */
     int32_t nu_coarse;   /* red-black sweeps before and after the coarse correction on the
                             smallest levels (at most 4096 cells each), which run inside one
                             workgroup; they are cheap there and set the outer iteration
@@ -105,7 +107,7 @@ typedef struct {
 } pp_stats;
 
 /* Fill *o with the defaults: mixed FP32, PCG, nu_pre = nu_post = 2,
- * max_outer = 500, warm_start = 0, fallback = 1, coarse_graph = 1, nu_coarse = 4. */
+ * max_outer = 500, warm_start = 0, fallback = 1, coarse_graph = 0, nu_coarse = 4. */
 void pp_opts_default(pp_opts *o);
 
 /* Face coefficients from cell densities, beta_m[c] = 2 / (rho[c - e_m] + rho[c])

@@ -1406,7 +1406,7 @@ void pp_opts_default(pp_opts *o)
     o->max_outer = 500;
     o->warm_start = 0;
     o->fallback = 1;
-    o->coarse_graph = 1;
+    o->coarse_graph = 0;   // eager launches: the graph's exit costs more than its launches save
     o->nu_coarse = 4;
 }
 

@@ -77,7 +77,7 @@ class Solver:
     def __init__(self, beta: Sequence[torch.Tensor], h: float, bc: Sequence[int],
                  precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
                  max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
-                 coarse_graph: bool = True, nu_coarse: int = 4,
+                 coarse_graph: bool = False, nu_coarse: int = 4,
                  stream: Optional[torch.cuda.Stream] = None,
                  sigma: Optional[torch.Tensor] = None, general: bool = False):
         lib = L.load()

@@ -53,7 +53,7 @@ def test_opts_default(lib):
     o = L.Opts()
     lib.pp_opts_default(ctypes.byref(o))
     assert (o.precision, o.outer, o.nu_pre, o.nu_post, o.max_outer, o.warm_start, o.fallback,
-            o.coarse_graph, o.nu_coarse) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1, 1, 4)
+            o.coarse_graph, o.nu_coarse) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1, 0, 4)
 
 
 def _grid(n=(8, 8, 8), h=0.125, bc=(0, 0, 0)):
