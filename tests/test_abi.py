@@ -160,3 +160,16 @@ def test_kernel_entries_validate(lib):
     assert lib.pp_k_prolong_add(ctypes.byref(g), fake, ctypes.c_void_p(0x1008), None) == L.PP_EINVAL   # e misaligned
     assert lib.pp_k_copy(None, fake, 10, None) == L.PP_EINVAL
     assert lib.pp_k_copy(fake, fake, 0, None) == L.PP_OK   # nothing to do
+
+
+def test_entry_module_imports():
+    """The build and smoke entry points are importable Python (a syntax error there would
+    only show when the build is driven through them)."""
+    import importlib
+    import sys
+    sys.path.insert(0, ROOT)
+    try:
+        mod = importlib.import_module("__graft_entry__")
+    finally:
+        sys.path.remove(ROOT)
+    assert callable(mod.build) and callable(mod.smoke)
