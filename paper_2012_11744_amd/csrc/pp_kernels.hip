@@ -551,6 +551,7 @@ struct TailArgs {
 constexpr int TAIL_LDS = 4736;            // >= 4096 * (1 + 1/8 + 1/64 + ...)
 constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_PAIRS = 2;             // x-pairs per thread: 4096 cells / 2 / 1024
+constexpr int TAIL_PINV = 4096;           // coarsest pseudo-inverses of up to 64 cells are staged in LDS
 
 // One x-pair (cells i0, i0+1 of a row) of a smoothed tail level, as a thread
 // holds it during a visit of that level: LDS indices of the pair and of its
@@ -694,25 +695,109 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
 {
     using C = typename Acc<T>::type;
     constexpr bool BLDS = sizeof(C) == 4;   // FP32 arithmetic: face coefficients in LDS too
+    constexpr int SPW = (TAIL_LDS / 2 * (int)sizeof(C) + 7) / 8;
+    static_assert(SPW >= 1024, "the coarsest right-hand side reuses the pair sums' storage");
+    static_assert(TAIL_CELLS % TAIL_THREADS == 0 && TAIL_PINV % TAIL_THREADS == 0, "staging");
     __shared__ C E[TAIL_LDS];
     __shared__ C Rr[TAIL_LDS];
     __shared__ C Bs[BLDS ? 3 : 1][BLDS ? TAIL_LDS : 1];
-    __shared__ C Sp[TAIL_LDS / 2];          // per-pair residual sums
-    __shared__ double rs[1024];
+    __shared__ unsigned Wl[TAIL_LDS];      // prolongation weights of every level but the last
+    __shared__ double Pv[TAIL_PINV];       // the coarsest pseudo-inverse, when it fits
+    // per-pair residual sums during the restrictions, then the coarsest
+    // right-hand side (the last restriction has finished reading the sums)
+    __shared__ double SpRaw[SPW];
+    C *Sp = reinterpret_cast<C *>(SpRaw);
+    double *rs = SpRaw;
     const int L = a.n;
     const int tid = threadIdx.x;
     int off[TAIL_MAX + 1];                  // first cell of level q in the LDS arrays
     off[0] = 0;
     for (int l = 0; l < L; ++l)
         off[l + 1] = off[l] + (int)cells(a.d[l]);
-    // stage the input right-hand side and the coefficients
-    for (int c = tid; c < off[1]; c += TAIL_THREADS)
-        Rr[c] = ld(a.r[0], c);
-    if (BLDS)
-        for (int l = 0; l < L; ++l)
+    // Stage the input right-hand side, the coefficients, the weights and a
+    // small pseudo-inverse.  Every load is issued before the first LDS store,
+    // so the staging costs one memory round trip.  The first level has at
+    // most TAIL_CELLS cells (a fixed count per thread, indices clamped so that
+    // every load is in range); the levels below it together hold fewer than
+    // an eighth as many, at most one cell per thread.
+    constexpr int U0 = TAIL_CELLS / TAIL_THREADS;
+    constexpr int UP = TAIL_PINV / TAIL_THREADS;
+    const int n0 = off[1];
+    const int nrest = off[L] - n0;
+    const int nwt = off[L - 1];             // weights: every level but the last
+    const int nc = a.ncoarse;
+    const bool pvl = nc * nc <= TAIL_PINV;
+    const unsigned WDEF = 0x404040u;        // 64/256 = 1/4 on each axis: trilinear
+    C r0[U0], b0[3][U0], b1[3] = {C(0), C(0), C(0)};
+    unsigned w0[U0], w1 = WDEF;
+    double pv[UP];
+    const unsigned *wf = L > 1 ? a.w[0] : nullptr;
+#pragma unroll
+    for (int u = 0; u < U0; ++u) {
+        const int cc = min(tid + u * TAIL_THREADS, n0 - 1);
+        r0[u] = ld(a.r[0], cc);
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            b0[m][u] = BLDS ? ld(a.b[0][m], cc) : C(0);
+        w0[u] = wf ? wf[cc] : WDEF;
+    }
+    // this thread's cell of the levels below the first: its level's arrays
+    // are picked by selects over the (uniform) argument pointers, so that no
+    // load waits for another
+    const int g = n0 + tid;
+    const T *pb[3] = {nullptr, nullptr, nullptr};
+    const unsigned *pw = nullptr;
+    int ob = 0;
+#pragma unroll
+    for (int q = 1; q < TAIL_MAX; ++q)
+        if (q < L && g >= off[q]) {
+#pragma unroll
             for (int m = 0; m < 3; ++m)
-                for (int c = tid; c < off[l + 1] - off[l]; c += TAIL_THREADS)
-                    Bs[BLDS ? m : 0][BLDS ? off[l] + c : 0] = ld(a.b[l][m], c);
+                pb[m] = a.b[q][m];
+            pw = a.w[q];
+            ob = off[q];
+        }
+    const bool rin = tid < nrest;
+    const bool win = rin && g < nwt;
+    if (rin) {
+        if (BLDS)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                b1[m] = ld(pb[m], g - ob);
+        if (win && pw)
+            w1 = pw[g - ob];
+    }
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+        const int i = tid + u * TAIL_THREADS;
+        pv[u] = pvl ? a.pinv[min(i, nc * nc - 1)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U0; ++u) {
+        const int cc = tid + u * TAIL_THREADS;
+        if (cc < n0) {
+            Rr[cc] = r0[u];
+            if (BLDS)
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    Bs[BLDS ? m : 0][BLDS ? cc : 0] = b0[m][u];
+            if (L > 1)
+                Wl[cc] = w0[u];
+        }
+    }
+    if (rin) {
+        if (BLDS)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                Bs[BLDS ? m : 0][BLDS ? g : 0] = b1[m];
+        if (win)
+            Wl[g] = w1;
+    }
+    if (pvl)
+#pragma unroll
+        for (int u = 0; u < UP; ++u)
+            if (tid + u * TAIL_THREADS < nc * nc)
+                Pv[tid + u * TAIL_THREADS] = pv[u];
     __syncthreads();
     TPair<C> P[TAIL_PAIRS];
     auto visit = [&](int l) {
@@ -765,15 +850,20 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
         for (int t = tid; t < n; t += TAIL_THREADS)
             rs[t] = static_cast<double>(Rr[off[L - 1] + t]);
         __syncthreads();
-        int g = 1;
-        while (g < 64 && 2 * g * n <= TAIL_THREADS)
-            g *= 2;
-        const int outp = tid / g, lane = tid % g;
+        int gs = 1;
+        while (gs < 64 && 2 * gs * n <= TAIL_THREADS)
+            gs *= 2;
+        const int outp = tid / gs, lane = tid % gs;
         double s = 0.0;
-        if (outp < n)
-            for (int jj = lane; jj < n; jj += g)
-                s += a.pinv[(size_t)jj * n + outp] * rs[jj];
-        for (int o = g >> 1; o > 0; o >>= 1)
+        if (outp < n) {
+            if (pvl)
+                for (int jj = lane; jj < n; jj += gs)
+                    s += Pv[jj * n + outp] * rs[jj];
+            else
+                for (int jj = lane; jj < n; jj += gs)
+                    s += a.pinv[(size_t)jj * n + outp] * rs[jj];
+        }
+        for (int o = gs >> 1; o > 0; o >>= 1)
             s += __shfl_xor(s, o, 64);
         if (lane == 0 && outp < n)
             E[off[L - 1] + outp] = static_cast<C>(s);
@@ -785,7 +875,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
         visit(l);
 #pragma unroll
         for (int u = 0; u < TAIL_PAIRS; ++u)
-            tp_prolong(P[u], a.d[l], a.bc, E + off[l + 1], El, a.w[l]);
+            tp_prolong(P[u], a.d[l], a.bc, E + off[l + 1], El, Wl + off[l]);
         __syncthreads();
         for (int sw = 0; sw < a.nu_post; ++sw)
             for (int colour = 1; colour >= 0; --colour) {
