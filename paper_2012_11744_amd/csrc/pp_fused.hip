@@ -885,10 +885,20 @@ int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
                            : fused2_slots<T, false, true, false>())
                    : (zero ? fused2_slots<T, true, false, false>()
                            : fused2_slots<T, false, false, false>());
-    // the six planes a chunk marches beyond its own are recomputed: at least 8 per chunk
-    int kz = fused_kz(d, tx * ty, slots);
-    if (kz < 8)
-        kz = (d.nz < 8) ? d.nz : 8;
+    // Chunk length: the shortest that keeps every workgroup resident at once
+    // (a single round), but at least two planes.  A chunk marches six planes
+    // beyond its own, recomputed; on small levels, whose workgroups leave most
+    // CUs idle, short chunks cost no time and shorten the march, which sets
+    // the pass's duration there.  The pass that forms the dot product keeps
+    // chunks of at least 8 planes, so that its workgroup partials stay within
+    // the reduction buffer (sized for the grid of the reduction kernels).
+    long long kzl = ((long long)d.nz * tx * ty + slots - 1) / slots;
+    const int kmin = dot ? 8 : 2;
+    if (kzl < kmin)
+        kzl = kmin;
+    if (kzl > d.nz)
+        kzl = d.nz;
+    const int kz = (int)kzl;
     const unsigned tz = (d.nz + kz - 1) / kz;
     const dim3 grid(tx * ty, tz);
     // a chunk marches kz + 6 steps; FP16 keeps the exit after every step

@@ -52,8 +52,8 @@ __host__ __device__ inline size_t cells(Dims d) { return (size_t)d.nx * d.ny * d
 constexpr int TAIL_MAX = 8;
 constexpr size_t TAIL_CELLS = 4096;       // a level joins the tail at or below this size
 constexpr size_t FUSED_MIN_CELLS = (size_t)1 << 18;   // fused sweeps above 64^3 cells
-// FP32 / FP16 storage, whose fused pass does two sweeps per launch, from 64^3 cells
-constexpr size_t FUSED2_MIN_CELLS = (size_t)1 << 17;
+// FP32 / FP16 storage, whose fused pass does two sweeps per launch, from 32^3 cells
+constexpr size_t FUSED2_MIN_CELLS = (size_t)1 << 14;
 template <typename T>
 constexpr size_t fused_min_cells()
 {
