@@ -92,6 +92,10 @@ typedef struct {
                             smallest levels (at most 4096 cells each), which run inside one
                             workgroup; they are cheap there and set the outer iteration
                             count at high density ratios (1..16) */
+    double omega;        /* over-relaxation of the red-black smoother on every level
+                            (Sec. 3.7.1, eq. beta_pressure: p <- (1 - omega) p + omega p_GS),
+                            in (0, 2); the same factor before and after the coarse
+                            correction keeps the V-cycle symmetric */
 } pp_opts;
 
 #define PP_HIST 128
@@ -107,7 +111,8 @@ typedef struct {
 } pp_stats;
 
 /* Fill *o with the defaults: mixed FP32, PCG, nu_pre = nu_post = 2,
- * max_outer = 500, warm_start = 0, fallback = 1, coarse_graph = 0, nu_coarse = 4. */
+ * max_outer = 500, warm_start = 0, fallback = 1, coarse_graph = 0, nu_coarse = 4,
+ * omega = 1.2. */
 void pp_opts_default(pp_opts *o);
 
 /* Face coefficients from cell densities, beta_m[c] = 2 / (rho[c - e_m] + rho[c])

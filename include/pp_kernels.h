@@ -33,41 +33,47 @@
 extern "C" {
 #endif
 
-/* `sweeps` red-black Gauss-Seidel sweeps on A e = r (one sweep = all red
- * cells (i+j+k even), then all black cells), each cell update
- *   e_c <- (sum_nb beta_f e_nb - h^2 r_c) / sum_nb beta_f.
- * zero_init = 1 treats e as zero on entry (e need not be initialised).
- * beta_*: fine beta with wall faces already 0 or not (wall entries ignored).
- * Periodic directions need an even cell count (consistent colouring). */
+/* `sweeps` red-black Gauss-Seidel sweeps with over-relaxation on A e = r
+ * (Sec. 3.7.1, eq. beta_pressure; one sweep = all red cells (i+j+k even), then
+ * all black cells), each cell update
+ *   e_c <- (1 - omega) e_c + omega (sum_nb beta_f e_nb - h^2 r_c) / sum_nb beta_f,
+ * 0 < omega < 2 (1: plain Gauss-Seidel).  zero_init = 1 treats e as zero on
+ * entry (e need not be initialised).  beta_*: fine beta with wall faces
+ * already 0 or not (wall entries ignored).  Periodic directions need an even
+ * cell count (consistent colouring). */
 int pp_k_smooth(const pp_grid *grid, const double *beta_x, const double *beta_y,
                 const double *beta_z, const double *r, double *e, int32_t sweeps,
-                int32_t zero_init, void *hip_stream);
+                int32_t zero_init, double omega, void *hip_stream);
 
 /* One fused red-black sweep, out of place: e_out = sweep(e_in), the first
  * colour updated first (first_colour 0: red, (i+j+k) even; 1: black) and the
  * second colour from the new first-colour values.  The same cell update as
- * two colour passes of pp_k_smooth (results agree to rounding: the compiler
- * may contract the products into fused multiply-adds differently).  e_in and
+ * two colour passes of pp_k_smooth, relaxation omega included (results agree
+ * to rounding: the compiler may contract the products into fused
+ * multiply-adds differently).  e_in and
  * e_out must not alias; zero_init = 1 treats e_in as zero (it is not read).
  * nx must be even, and so must the cell count of every periodic direction;
  * an x-y plane must stay below 2^31 bytes; all arrays 16-byte aligned (the
  * kernel reads x-pairs of cells as vectors). */
 int pp_k_smooth_fused(const pp_grid *grid, const double *beta_x, const double *beta_y,
                       const double *beta_z, const double *r, const double *e_in, double *e_out,
-                      int32_t first_colour, int32_t zero_init, void *hip_stream);
+                      int32_t first_colour, int32_t zero_init, double omega, void *hip_stream);
 
 /* Two red-black sweeps in one pass on FP32 arrays (the kernel the FP32 V-cycle
  * uses on large levels): e_out = sweep(sweep(e_in)), each sweep the first
- * colour first as in pp_k_smooth_fused.  Arithmetic is FP32 with the
- * hardware reciprocal of the diagonal (within 1 ulp), so results agree with
- * the FP64 sweeps of the same FP32 inputs to FP32 rounding, not bit for bit.
+ * colour first as in pp_k_smooth_fused, with relaxation omega (folded into
+ * the reciprocal diagonal: e <- (1 - omega) e + (omega / diag) (sum - h^2 r)).
+ * Arithmetic is FP32 with the hardware reciprocal of the diagonal (within
+ * 1 ulp), so results agree with the FP64 sweeps of the same FP32 inputs to
+ * FP32 rounding, not bit for bit.
  * e_in and e_out must not alias; zero_init = 1 treats e_in as zero (it is not
  * read).  Every cell count must be >= 8; nx must be even, and so must the
  * cell count of every periodic direction; an x-y plane must stay below 2^31
  * bytes; all arrays 16-byte aligned. */
 int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *beta_x, const float *beta_y,
                            const float *beta_z, const float *r, const float *e_in, float *e_out,
-                           int32_t first_colour, int32_t zero_init, void *hip_stream);
+                           int32_t first_colour, int32_t zero_init, double omega,
+                           void *hip_stream);
 
 /* pp_k_smooth2_fused_f32 (regular pass: e_in is read) that also forms
  * *dot = sum over all cells of r[c] * e_out[c], with r the pass's own
@@ -80,7 +86,7 @@ int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *beta_x, const float
  * scratch and waits for the stream (a component-test entry). */
 int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *beta_x, const float *beta_y,
                                const float *beta_z, const float *r, const float *e_in,
-                               float *e_out, int32_t first_colour, double *dot,
+                               float *e_out, int32_t first_colour, double omega, double *dot,
                                void *hip_stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -100,7 +106,7 @@ int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *beta_x, const f
 int pp_k_smooth2_fused_dot_f32_noalloc(const pp_grid *grid, const float *beta_x,
                                        const float *beta_y, const float *beta_z, const float *r,
                                        const float *e_in, float *e_out, int32_t first_colour,
-                                       double *dot, void *hip_stream);
+                                       double omega, double *dot, void *hip_stream);
 
 /* rH[C] = (1/8) sum over the 8 fine cells c of C of (r - A e)[c].
  * grid: the fine grid (all n even); rH has n/2 cells per direction; beta,

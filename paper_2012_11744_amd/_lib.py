@@ -49,7 +49,7 @@ class Opts(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("fallback", ctypes.c_int32), ("coarse_graph", ctypes.c_int32),
-                ("nu_coarse", ctypes.c_int32)]
+                ("nu_coarse", ctypes.c_int32), ("omega", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -115,11 +115,11 @@ def load():
         "pp_destroy": (None, [P]),
         "pp_strerror": (ctypes.c_char_p, [I]),
         "pp_last_error": (ctypes.c_char_p, []),
-        "pp_k_smooth": (I, [GP, P, P, P, P, P, I32, I32, P]),
-        "pp_k_smooth_fused": (I, [GP, P, P, P, P, P, P, I32, I32, P]),
-        "pp_k_smooth2_fused_f32": (I, [GP, P, P, P, P, P, P, I32, I32, P]),
-        "pp_k_smooth2_fused_dot_f32": (I, [GP, P, P, P, P, P, P, I32, P, P]),
-        "pp_k_smooth2_fused_dot_f32_noalloc": (I, [GP, P, P, P, P, P, P, I32, P, P]),
+        "pp_k_smooth": (I, [GP, P, P, P, P, P, I32, I32, D, P]),
+        "pp_k_smooth_fused": (I, [GP, P, P, P, P, P, P, I32, I32, D, P]),
+        "pp_k_smooth2_fused_f32": (I, [GP, P, P, P, P, P, P, I32, I32, D, P]),
+        "pp_k_smooth2_fused_dot_f32": (I, [GP, P, P, P, P, P, P, I32, D, P, P]),
+        "pp_k_smooth2_fused_dot_f32_noalloc": (I, [GP, P, P, P, P, P, P, I32, D, P, P]),
         "pp_k_resid_restrict": (I, [GP, P, P, P, P, P, P, P]),
         "pp_k_prolong_add": (I, [GP, P, P, P]),
         "pp_k_prolong_weights": (I, [GP, P, P, P, P, P]),

@@ -243,6 +243,9 @@ int validate_grid(const pp_grid *g, int *nlev_out, Dims *ld, double *lh)
     return PP_OK;
 }
 
+// the smoother's over-relaxation: red-black SOR converges for 0 < omega < 2
+bool omega_ok(double omega) { return omega > 0.0 && omega < 2.0; }
+
 int validate_opts(const pp_opts *o)
 {
     if (o->precision < PP_FP64 || o->precision > PP_MIXED_FP16)
@@ -261,6 +264,8 @@ int validate_opts(const pp_opts *o)
         return fail(PP_EINVAL, "opts.coarse_graph must be 0 or 1");
     if (o->nu_coarse < 1 || o->nu_coarse > 16)
         return fail(PP_EINVAL, "opts.nu_coarse must be in 1..16");
+    if (!omega_ok(o->omega))
+        return fail(PP_EINVAL, "opts.omega must be in (0, 2)");
     return PP_OK;
 }
 
@@ -826,7 +831,8 @@ void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_c
                 const bool last = sw + 2 == nu;
                 const int np = launch_rbgs_fused2<T>(
                     v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
-                    (const T *)v.s, h2, first_colour, zero, s, (last && dot) ? c->part : nullptr);
+                    (const T *)v.s, h2, c->opts.omega, first_colour, zero, s,
+                    (last && dot) ? c->part : nullptr);
                 if (last && np > 0)
                     c->dot_np = np;
                 two = true;
@@ -834,7 +840,7 @@ void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_c
         }
         if (!two)
             launch_rbgs_fused<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (const T *)cur, (T *)out,
-                                 (const T *)v.s, h2, first_colour, zero, s);
+                                 (const T *)v.s, h2, c->opts.omega, first_colour, zero, s);
         sw += two ? 2 : 1;
         cur = out;
     }
@@ -856,10 +862,10 @@ void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s)
         v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_pre, v.e2, 0, true, s);
     } else {
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2, 0,
-                           sw == 0, s);
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2, 1,
-                           false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2,
+                           c->opts.omega, 0, sw == 0, false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2,
+                           c->opts.omega, 1, false, sw == 0, s);
         }
         v.cur = v.e;
     }
@@ -885,10 +891,10 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
                                 l == 0 && c->dot_on);
     } else {
         for (int sw = 0; sw < c->opts.nu_post; ++sw) {
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2, 1,
-                           false, s);
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2, 0,
-                           false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2,
+                           c->opts.omega, 1, false, false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.cur, (const T *)v.s, h2,
+                           c->opts.omega, 0, false, false, s);
         }
     }
 }
@@ -917,7 +923,8 @@ void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
         sg[q] = v.s;
         v.cur = v.e;
     }
-    launch_tail<T>(n, d, h2, b, e, r, sg, w, c->bc, c->opts.nu_coarse, c->opts.nu_coarse, c->pinv,
+    launch_tail<T>(n, d, h2, b, e, r, sg, w, c->bc, c->opts.nu_coarse, c->opts.nu_coarse,
+                   c->opts.omega, c->pinv,
                    c->ncoarse, s);
 }
 
@@ -1408,6 +1415,9 @@ void pp_opts_default(pp_opts *o)
     o->fallback = 1;
     o->coarse_graph = 0;   // eager launches: the graph's exit costs more than its launches save
     o->nu_coarse = 4;
+    // measured at 256^3 (layer and droplets): 1.1-1.4 all take 7 outer
+    // iterations where plain Gauss-Seidel (1.0) takes 8; 1.2 sits mid-plateau
+    o->omega = 1.2;
 }
 
 const char *pp_strerror(int status)
@@ -1603,9 +1613,11 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
 // *nparts_max bounds the number of workgroup partial sums the launch writes.
 int check_smooth2_dot(const char *who, const pp_grid *grid, const float *bx, const float *by,
                       const float *bz, const float *r, const float *e_in, const float *e_out,
-                      int32_t first_colour, const double *dot, size_t *nparts_max)
+                      int32_t first_colour, double omega, const double *dot, size_t *nparts_max)
 {
     const std::string w(who);
+    if (!omega_ok(omega))
+        return fail(PP_EINVAL, w + ": omega must be in (0, 2)");
     if (!dot)
         return fail(PP_EINVAL, w + ": NULL array");
     if ((uintptr_t)dot & 7)
@@ -1898,13 +1910,16 @@ int pp_memory(const pp_ctx *c, int64_t *bytes)
 // ---------------------------------------------------------------------------
 
 int pp_k_smooth(const pp_grid *grid, const double *bx, const double *by, const double *bz,
-                const double *r, double *e, int32_t sweeps, int32_t zero_init, void *hip_stream)
+                const double *r, double *e, int32_t sweeps, int32_t zero_init, double omega,
+                void *hip_stream)
 {
     PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
     if (!bx || !by || !bz || !r || !e)
         return fail(PP_EINVAL, "pp_k_smooth: NULL array");
     if (sweeps < 1)
         return fail(PP_EINVAL, "pp_k_smooth: sweeps must be >= 1");
+    if (!omega_ok(omega))
+        return fail(PP_EINVAL, "pp_k_smooth: omega must be in (0, 2)");
     for (int m = 0; m < 3; ++m)
         if (grid->bc[m] == PP_PERIODIC && grid->n[m] % 2)
             return fail(PP_EINVAL, "pp_k_smooth: periodic directions need an even cell count");
@@ -1913,19 +1928,22 @@ int pp_k_smooth(const pp_grid *grid, const double *bx, const double *by, const d
     const double h2 = grid->h * grid->h;
     hipStream_t s = (hipStream_t)hip_stream;
     for (int sw = 0; sw < sweeps; ++sw) {
-        launch_rbgs<double>(d, bc, bx, by, bz, r, e, nullptr, h2, 0, zero_init && sw == 0, s);
-        launch_rbgs<double>(d, bc, bx, by, bz, r, e, nullptr, h2, 1, false, s);
+        const bool z = zero_init && sw == 0;
+        launch_rbgs<double>(d, bc, bx, by, bz, r, e, nullptr, h2, omega, 0, z, false, s);
+        launch_rbgs<double>(d, bc, bx, by, bz, r, e, nullptr, h2, omega, 1, false, z, s);
     }
     return check_launch("pp_k_smooth");
 }
 
 int pp_k_smooth_fused(const pp_grid *grid, const double *bx, const double *by, const double *bz,
                       const double *r, const double *e_in, double *e_out, int32_t first_colour,
-                      int32_t zero_init, void *hip_stream)
+                      int32_t zero_init, double omega, void *hip_stream)
 {
     PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
     if (!bx || !by || !bz || !r || !e_in || !e_out)
         return fail(PP_EINVAL, "pp_k_smooth_fused: NULL array");
+    if (!omega_ok(omega))
+        return fail(PP_EINVAL, "pp_k_smooth_fused: omega must be in (0, 2)");
     if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)r | (uintptr_t)e_in |
          (uintptr_t)e_out) & 15)
         return fail(PP_EINVAL, "pp_k_smooth_fused: arrays must be 16-byte aligned");
@@ -1941,18 +1959,20 @@ int pp_k_smooth_fused(const pp_grid *grid, const double *bx, const double *by, c
     if (!fused_plane_fits(to_dims(grid), sizeof(double)))
         return fail(PP_EINVAL, "pp_k_smooth_fused: an x-y plane must stay below 2^31 bytes");
     launch_rbgs_fused<double>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in, e_out, nullptr,
-                              grid->h * grid->h, first_colour, zero_init != 0,
+                              grid->h * grid->h, omega, first_colour, zero_init != 0,
                               (hipStream_t)hip_stream);
     return check_launch("pp_k_smooth_fused");
 }
 
 int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *bx, const float *by, const float *bz,
                            const float *r, const float *e_in, float *e_out, int32_t first_colour,
-                           int32_t zero_init, void *hip_stream)
+                           int32_t zero_init, double omega, void *hip_stream)
 {
     PP_TRY(validate_grid(grid, nullptr, nullptr, nullptr));
     if (!bx || !by || !bz || !r || !e_in || !e_out)
         return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: NULL array");
+    if (!omega_ok(omega))
+        return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: omega must be in (0, 2)");
     if (((uintptr_t)bx | (uintptr_t)by | (uintptr_t)bz | (uintptr_t)r | (uintptr_t)e_in |
          (uintptr_t)e_out) & 15)
         return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: arrays must be 16-byte aligned");
@@ -1971,24 +1991,25 @@ int pp_k_smooth2_fused_f32(const pp_grid *grid, const float *bx, const float *by
     if (!fused_plane_fits(to_dims(grid), sizeof(float)))
         return fail(PP_EINVAL, "pp_k_smooth2_fused_f32: an x-y plane must stay below 2^31 bytes");
     launch_rbgs_fused2<float>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in, e_out, nullptr,
-                              grid->h * grid->h, first_colour, zero_init != 0,
+                              grid->h * grid->h, omega, first_colour, zero_init != 0,
                               (hipStream_t)hip_stream);
     return check_launch("pp_k_smooth2_fused_f32");
 }
 
 int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *bx, const float *by,
                                const float *bz, const float *r, const float *e_in, float *e_out,
-                               int32_t first_colour, double *dot, void *hip_stream)
+                               int32_t first_colour, double omega, double *dot, void *hip_stream)
 {
     size_t nparts_max = 0;
     PP_TRY(check_smooth2_dot("pp_k_smooth2_fused_dot_f32", grid, bx, by, bz, r, e_in, e_out,
-                             first_colour, dot, &nparts_max));
+                             first_colour, omega, dot, &nparts_max));
     const Dims d = to_dims(grid);
     double *part = nullptr;
     PP_HIP(hipMalloc((void **)&part, sizeof(double) * nparts_max));
     hipStream_t s = (hipStream_t)hip_stream;
     const int np = launch_rbgs_fused2<float>(d, to_bc(grid), bx, by, bz, r, e_in, e_out, nullptr,
-                                             grid->h * grid->h, first_colour, false, s, part);
+                                             grid->h * grid->h, omega, first_colour, false, s,
+                                             part);
     int rc = PP_OK;
     if (np <= 0 || (size_t)np > nparts_max)
         rc = fail(PP_EHIP, "pp_k_smooth2_fused_dot_f32: unexpected workgroup count");
@@ -2002,12 +2023,12 @@ int pp_k_smooth2_fused_dot_f32(const pp_grid *grid, const float *bx, const float
 
 int pp_k_smooth2_fused_dot_f32_noalloc(const pp_grid *grid, const float *bx, const float *by,
                                        const float *bz, const float *r, const float *e_in,
-                                       float *e_out, int32_t first_colour, double *dot,
-                                       void *hip_stream)
+                                       float *e_out, int32_t first_colour, double omega,
+                                       double *dot, void *hip_stream)
 {
     size_t nparts_max = 0;
     PP_TRY(check_smooth2_dot("pp_k_smooth2_fused_dot_f32_noalloc", grid, bx, by, bz, r, e_in,
-                             e_out, first_colour, dot, &nparts_max));
+                             e_out, first_colour, omega, dot, &nparts_max));
     if (nparts_max > NOALLOC_PARTS)
         return fail(PP_EINVAL, "pp_k_smooth2_fused_dot_f32_noalloc: the grid needs up to " +
                                    std::to_string(nparts_max) +
@@ -2020,8 +2041,8 @@ int pp_k_smooth2_fused_dot_f32_noalloc(const pp_grid *grid, const float *bx, con
     // the launch takes z chunks of at least 8 planes, so it never uses more
     // than nparts_max partial sums (checked above against the array size)
     const int np = launch_rbgs_fused2<float>(to_dims(grid), to_bc(grid), bx, by, bz, r, e_in,
-                                             e_out, nullptr, grid->h * grid->h, first_colour,
-                                             false, s, part);
+                                             e_out, nullptr, grid->h * grid->h, omega,
+                                             first_colour, false, s, part);
     PP_TRY(check_launch("pp_k_smooth2_fused_dot_f32_noalloc"));
     if (np <= 0 || (size_t)np > nparts_max)
         return fail(PP_EHIP, "pp_k_smooth2_fused_dot_f32_noalloc: unexpected workgroup count");

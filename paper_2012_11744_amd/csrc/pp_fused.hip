@@ -144,6 +144,8 @@ __device__ __forceinline__ void xcd_tile(unsigned tx_tiles, unsigned ty_tiles, i
 // with the other inputs and added to the diagonal.  In every variant a cell with a
 // zero diagonal (no open face, no diagonal term) is excluded and gets 0.
 // WHOLE: the march runs whole blocks of its unroll length (see the loop).
+// om: the over-relaxation of eq. beta_pressure, e <- (1 - om) e + om e_GS
+// (ZERO: the old value is 0).
 template <typename T, bool ZERO, bool SIG, bool WHOLE>
 __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T *__restrict__ bx,
                                                          const T *__restrict__ by,
@@ -152,11 +154,13 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
                                                          const T *__restrict__ ein,
                                                          T *__restrict__ eout,
                                                          const T *__restrict__ sg,
-                                                         typename Acc<T>::type h2, int c0, int kz,
+                                                         typename Acc<T>::type h2,
+                                                         typename Acc<T>::type om, int c0, int kz,
                                                          unsigned tx_tiles, unsigned ty_tiles)
 {
     using C = typename Acc<T>::type;
     using T2 = typename Vec2<T>::type;
+    const C om1 = C(1) - om;
     constexpr int FPD = FusedDepth<T>::value;   // planes of loads in flight beyond k+1
     constexpr int FNB = FPD + 3;                // input buffers: k-1, k, k+1 and those in flight
     // LDS: e_in, beta_x and beta_y of planes k and k+1 (two slots) for the
@@ -317,7 +321,8 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
                 yh * SE[si][ly + 1][ca] + zl * pick(o, pm.e) + zh * pick(o, pn.e);
         const C val = gs_quot(s - h2 * pick(o, pc.r), diag);
         // a missing plane (0/0) and an excluded cell (zero diagonal) get 0
-        const C red = (kin && diag > C(0)) ? val : C(0);
+        const C rel = ZERO ? om * val : om1 * pick(o, pc.e) + om * val;
+        const C red = (kin && diag > C(0)) ? rel : C(0);
         // in-plane faces of this plane's second-colour cell, for phase B at
         // the next step (the slot is overwritten before then)
         const int cb = lx + 1 - o;
@@ -339,7 +344,8 @@ __global__ __launch_bounds__(FTHREADS) void k_rbgs_fused(Dims d, Bc bc, const T 
             C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
             if (SIG)
                 dg += pick(o, pm.sg);
-            const C blk = dg > C(0) ? gs_quot(sbv - h2 * pick(o, pm.r), dg) : C(0);
+            const C q = gs_quot(sbv - h2 * pick(o, pm.r), dg);
+            const C blk = dg > C(0) ? (ZERO ? om * q : om1 * pick(o, pm.e) + om * q) : C(0);
             T2 outv;
             outv.x = static_cast<T>(o ? red_km1 : blk);
             outv.y = static_cast<T>(o ? blk : red_km1);
@@ -448,8 +454,8 @@ void prepare_fused()
 
 template <typename T>
 void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
-                       const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
-                       hipStream_t s)
+                       const T *ein, T *eout, const T *sg, double h2, double omega,
+                       int first_colour, bool zero, hipStream_t s)
 {
     using C = typename Acc<T>::type;
     const unsigned tx = (d.nx + FTX - 1) / FTX, ty = (d.ny + FTY - 1) / FTY;
@@ -463,10 +469,10 @@ void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
     do {                                                                                       \
         if (whole)                                                                             \
             PP_LAUNCH((k_rbgs_fused<T, Z, S, true>), grid, dim3(FTHREADS), 0, s, d, bc, bx,    \
-                      by, bz, r, ein, eout, sg, (C)h2, first_colour, kz, tx, ty);              \
+                      by, bz, r, ein, eout, sg, (C)h2, (C)omega, first_colour, kz, tx, ty);    \
         else                                                                                   \
             PP_LAUNCH((k_rbgs_fused<T, Z, S, false>), grid, dim3(FTHREADS), 0, s, d, bc, bx,   \
-                      by, bz, r, ein, eout, sg, (C)h2, first_colour, kz, tx, ty);              \
+                      by, bz, r, ein, eout, sg, (C)h2, (C)omega, first_colour, kz, tx, ty);    \
     } while (0)
     if (sg) {
         if (zero)
@@ -512,10 +518,14 @@ constexpr int GLR = GTY + 8;              // LDS rows: j0-4 .. j0+GTY+3
 // what phase A (B) computed for a cell, for phase C (D) two steps later
 struct GsLag {
     float xl, xh, yl, yh, zl, zh;   // link coefficients
-    float inv;                      // 1 / diagonal, or 0 for an excluded cell or missing plane
+    float inv;                      // om / diagonal, or 0 for an excluded cell or missing plane
     float hr;                       // h^2 r
 };
 
+// om: the over-relaxation of eq. beta_pressure, folded into the reciprocal
+// diagonal that the lag registers carry (inv = om / diag), so every phase
+// forms e <- (1 - om) e + inv (sum - h^2 r); the old value of phases A and B
+// is e_in (0 in the ZERO pass), that of C and D the sweep-1 value.
 // DOT (FP32, regular pass): also the partial sums of r . e_out over each
 // workgroup's output cells, r the pass's own right-hand side, products summed
 // in FP64 (the outer iteration's residual against the preconditioned one,
@@ -529,7 +539,7 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
                                                           const T *__restrict__ ein,
                                                           T *__restrict__ eout,
                                                           const T *__restrict__ sg, float h2,
-                                                          int c0, int kz, unsigned tx_tiles,
+                                                          float om, int c0, int kz, unsigned tx_tiles,
                                                           unsigned ty_tiles,
                                                           double *__restrict__ part)
 {
@@ -544,6 +554,7 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
     constexpr int FNB = FPD + 3;
     constexpr bool CT_SLOTS = FNB % 6 == 0;
     static_assert(!DOT || (!ZERO && !SIG), "the dot product rides on regular passes");
+    const C om1 = C(1) - om;
     __shared__ C SE[2][GLR][GLW];     // e_in of planes k, k+1
     __shared__ C SX[2][GLR][GLW];     // beta_x of planes k, k+1
     __shared__ C SY[2][GLR][GLW];     // beta_y of planes k, k+1
@@ -706,9 +717,14 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
         if (!ZERO)
             s = xl * SE[si][ly][ca - 1] + xh * SE[si][ly][ca + 1] + yl * SE[si][ly - 1][ca] +
                 yh * SE[si][ly + 1][ca] + zl * pick(o, pm.e) + zh * pick(o, pn.e);
-        const C inva = (kin && diag > C(0)) ? __builtin_amdgcn_rcpf(diag) : C(0);
+        const C inva = (kin && diag > C(0)) ? om * __builtin_amdgcn_rcpf(diag) : C(0);
         const C hra = h2 * pick(o, pc.r);
-        const C red = (s - hra) * inva;
+        C red = (s - hra) * inva;
+        if (!ZERO) {
+            red = om1 * pick(o, pc.e) + red;
+            if (SIG)
+                red = inva == C(0) ? C(0) : red;   // an excluded cell stays 0
+        }
         const int cb = lx + 1 - o;
         const C nxl = SX[si][ly][cb], nxh = SX[si][ly][cb + 1];
         const C nyl = SY[si][ly][cb], nyh = SY[si][ly + 1][cb];
@@ -739,22 +755,28 @@ __global__ __launch_bounds__(GTHREADS) void k_rbgs_fused2(Dims d, Bc bc, const T
         C dg = (sxl + sxh) + (syl + syh) + (bzl + bzh);
         if (SIG)
             dg += pick(o, pm.sg);
-        const C invb = dg > C(0) ? __builtin_amdgcn_rcpf(dg) : C(0);
+        const C invb = dg > C(0) ? om * __builtin_amdgcn_rcpf(dg) : C(0);
         const C hrb = h2 * pick(o, pm.r);
-        const C blk = (sxl * bw + sxh * be + syl * bs + syh * bn + bzl * red_km2 + bzh * red - hrb) *
-                      invb;
+        C blk = (sxl * bw + sxh * be + syl * bs + syh * bn + bzl * red_km2 + bzh * red - hrb) * invb;
+        if (!ZERO) {
+            blk = om1 * pick(o, pm.e) + blk;
+            if (SIG)
+                blk = invb == C(0) ? C(0) : blk;
+        }
         if (act)
             BLK1[si ^ 1][ly][ca] = blk;
         C red2 = C(0);
         if (cdw) {
             // phase C: first colour of plane k-2, sweep 2 (A's cell of step k-2)
-            red2 = (a2.xl * cw + a2.xh * ce + a2.yl * cs + a2.yh * cn + a2.zl * blk_km2 +
-                    a2.zh * blk - a2.hr) * a2.inv;
+            red2 = om1 * red_km2 + (a2.xl * cw + a2.xh * ce + a2.yl * cs + a2.yh * cn +
+                                    a2.zl * blk_km2 + a2.zh * blk - a2.hr) *
+                                       a2.inv;
             if (act)
                 RED2[si][ly][ca] = red2;
             // phase D: second colour of plane k-3, sweep 2 (B's cell of step k-2)
-            const C blk2 = (b2.xl * dw + b2.xh * de + b2.yl * ds + b2.yh * dn + b2.zl * r2_km2 +
-                            b2.zh * red2 - b2.hr) * b2.inv;
+            const C blk2 = om1 * blk_km2 + (b2.xl * dw + b2.xh * de + b2.yl * ds + b2.yh * dn +
+                                            b2.zl * r2_km2 + b2.zh * red2 - b2.hr) *
+                                               b2.inv;
             const int kd = k - 3;
             if (kd >= k0 && kd < k1) {
                 T2 outv;
@@ -871,8 +893,8 @@ void prepare_fused2()
 
 template <typename T>
 int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
-                       const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
-                       hipStream_t s, double *part)
+                       const T *ein, T *eout, const T *sg, double h2, double omega,
+                       int first_colour, bool zero, hipStream_t s, double *part)
 {
     const unsigned tx = (d.nx + GTX - 1) / GTX, ty = (d.ny + GTY - 1) / GTY;
     // the fused dot product: FP32 regular passes without a diagonal term
@@ -908,11 +930,11 @@ int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, con
         if (whole)                                                                             \
             PP_LAUNCH((k_rbgs_fused2<T, Z, S, D, std::is_same<T, float>::value>), grid,        \
                       dim3(GTHREADS), 0, s, d, bc, bx, by, bz, r, ein, eout, sg, (float)h2,    \
-                      first_colour, kz, tx, ty, part);                                         \
+                      (float)omega, first_colour, kz, tx, ty, part);                           \
         else                                                                                   \
             PP_LAUNCH((k_rbgs_fused2<T, Z, S, D, false>), grid, dim3(GTHREADS), 0, s, d, bc,   \
-                      bx, by, bz, r, ein, eout, sg, (float)h2, first_colour, kz, tx, ty,       \
-                      part);                                                                   \
+                      bx, by, bz, r, ein, eout, sg, (float)h2, (float)omega, first_colour, kz, \
+                      tx, ty, part);                                                           \
     } while (0)
     if (dot) {
         if constexpr (std::is_same<T, float>::value)
@@ -938,16 +960,17 @@ template void prepare_fused2<float>();
 template void prepare_fused2<_Float16>();
 template int launch_rbgs_fused2<float>(Dims, Bc, const float *, const float *, const float *,
                                        const float *, const float *, float *, const float *, double,
-                                       int, bool, hipStream_t, double *);
+                                       double, int, bool, hipStream_t, double *);
 template int launch_rbgs_fused2<_Float16>(Dims, Bc, const _Float16 *, const _Float16 *,
                                           const _Float16 *, const _Float16 *, const _Float16 *,
-                                          _Float16 *, const _Float16 *, double, int, bool,
+                                          _Float16 *, const _Float16 *, double, double, int, bool,
                                           hipStream_t, double *);
 
 #define PP_INSTANTIATE_FUSED(T)                                                                  \
     template void prepare_fused<T>();                                                           \
     template void launch_rbgs_fused<T>(Dims, Bc, const T *, const T *, const T *, const T *,    \
-                                       const T *, T *, const T *, double, int, bool, hipStream_t);
+                                       const T *, T *, const T *, double, double, int, bool,     \
+                                       hipStream_t);
 
 PP_INSTANTIATE_FUSED(double)
 PP_INSTANTIATE_FUSED(float)

@@ -128,11 +128,16 @@ enum FinalizeOp {
 // the diagonal term of the general operator A - diag(sigma) on that level,
 // stored as h^2 sigma (the unit of the face coefficients in the smoother), or
 // null for the pressure operator; cells with no open face and no diagonal
-// term are excluded (their correction stays 0).
+// term are excluded (their correction stays 0).  `omega` is the smoother's
+// over-relaxation (eq. beta_pressure): e <- (1 - omega) e + omega e_GS.
 // ---------------------------------------------------------------------------
+// one colour of a red-black sweep, in place; zero: e is 0 on entry (neither
+// the cell nor its neighbours are read); self_zero: the cell's own old value
+// is 0 (the second colour of a sweep from zero), its neighbours are read
 template <typename T>
 void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e,
-                 const T *sg, double h2, int colour, bool zero, hipStream_t s);
+                 const T *sg, double h2, double omega, int colour, bool zero, bool self_zero,
+                 hipStream_t s);
 // query (once) the occupancy figures the fused sweep's launch geometry uses;
 // called before stream capture so that capture records kernel launches only
 template <typename T>
@@ -141,8 +146,8 @@ void prepare_fused();
 // updates red ((i+j+k) even) first, 1 black first; zero: e_in treated as 0
 template <typename T>
 void launch_rbgs_fused(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
-                       const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
-                       hipStream_t s);
+                       const T *ein, T *eout, const T *sg, double h2, double omega,
+                       int first_colour, bool zero, hipStream_t s);
 // Two sweeps in one pass (FP32 and FP16 storage only), out of place, ein and
 // eout distinct; needs nz >= 8 (the chunks read four planes beyond their ends).
 template <typename T>
@@ -152,8 +157,8 @@ void prepare_fused2();
 // FP64), one per workgroup, and returns their number; otherwise returns 0.
 template <typename T>
 int launch_rbgs_fused2(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r,
-                       const T *ein, T *eout, const T *sg, double h2, int first_colour, bool zero,
-                       hipStream_t s, double *part = nullptr);
+                       const T *ein, T *eout, const T *sg, double h2, double omega,
+                       int first_colour, bool zero, hipStream_t s, double *part = nullptr);
 inline bool fused2_fits(Dims d) { return d.nz >= 8 && d.nx >= 8 && d.ny >= 8; }
 template <typename T>
 void launch_resid_restrict(Dims fd, Bc bc, const T *bx, const T *by, const T *bz, const T *e,
@@ -173,7 +178,8 @@ void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s)
 template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
                  void *const *r, const void *const *sg, const unsigned *const *w, Bc bc,
-                 int nu_pre, int nu_post, const double *pinv, int ncoarse, hipStream_t s);
+                 int nu_pre, int nu_post, double omega, const double *pinv, int ncoarse,
+                 hipStream_t s);
 template <typename T>
 void launch_convert(size_t n, const double *src, T *dst, hipStream_t s);
 template <typename T>

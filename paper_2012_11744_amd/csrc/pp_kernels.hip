@@ -184,7 +184,9 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restri
                                                 const T *__restrict__ bz,
                                                 const T *__restrict__ r, T *e,
                                                 const T *__restrict__ sg,
-                                                typename Acc<T>::type h2, int colour)
+                                                typename Acc<T>::type h2,
+                                                typename Acc<T>::type om, int colour,
+                                                int self_zero)
 {
     using C = typename Acc<T>::type;
     const int t = blockIdx.x * BX + threadIdx.x;
@@ -205,8 +207,11 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Dims d, Bc bc, const T *__restri
         s = L.xl * ld(e, n.xm) + L.xh * ld(e, n.xp) + L.yl * ld(e, n.ym) + L.yh * ld(e, n.yp) +
             L.zl * ld(e, n.zm) + L.zh * ld(e, n.zp);
     }
-    // a cell with no open face and no diagonal term is excluded: it stays 0
-    e[n.c] = static_cast<T>(diag > C(0) ? (s - h2 * ld(r, n.c)) / diag : C(0));
+    // over-relaxed (eq. beta_pressure); a cell with no open face and no
+    // diagonal term is excluded: it stays 0
+    const C g = (s - h2 * ld(r, n.c)) / diag;
+    const C v = (ZERO || self_zero) ? om * g : (C(1) - om) * ld(e, n.c) + om * g;
+    e[n.c] = static_cast<T>(diag > C(0) ? v : C(0));
 }
 
 // rH = mean over the 8 children of (r - A e).  One thread per coarse column
@@ -540,6 +545,7 @@ struct TailArgs {
     const unsigned *w[TAIL_MAX];   // prolongation weights of each level but the last, or null
     Bc bc;
     int nu_pre, nu_post;
+    double omega;              // the smoother's over-relaxation
     const double *pinv;        // pseudo-inverse of the coarsest operator
     int ncoarse;
 };
@@ -617,10 +623,13 @@ __device__ __forceinline__ void tp_load(TPair<C> &P, Dims d, Bc bc, int p, const
     }
 }
 
-// Gauss-Seidel update of the cell of colour `colour` in the pair (eq.
-// beta_pressure with relaxation 1); zero: e is zero on entry.
+// Over-relaxed Gauss-Seidel update of the cell of colour `colour` in the pair
+// (eq. beta_pressure, relaxation om); zero: e is zero on entry (neither the
+// cell nor its neighbours are read); self_zero: the cell's own old value is
+// zero (the second colour of the first sweep), its neighbours are read.
 template <typename C>
-__device__ __forceinline__ void tp_gs(const TPair<C> &P, C *E, C h2, int colour, bool zero)
+__device__ __forceinline__ void tp_gs(const TPair<C> &P, C *E, C h2, C om, int colour, bool zero,
+                                      bool self_zero)
 {
     if (!P.on)
         return;
@@ -631,8 +640,10 @@ __device__ __forceinline__ void tp_gs(const TPair<C> &P, C *E, C h2, int colour,
     if (!zero)
         s = xl * E[q == 0 ? P.xm : P.c] + xh * E[q == 0 ? P.c + 1 : P.xp] + P.fyl[q] * E[c + P.ym] +
             P.fyh[q] * E[c + P.yp] + P.fzl[q] * E[c + P.zm] + P.fzh[q] * E[c + P.zp];
+    const C g = (s - h2 * P.r[q]) / P.dg[q];
+    const C v = (zero || self_zero) ? om * g : (C(1) - om) * E[c] + om * g;
     // a cell with no open face and no diagonal term is excluded: it stays 0
-    E[c] = P.dg[q] > C(0) ? (s - h2 * P.r[q]) / P.dg[q] : C(0);
+    E[c] = P.dg[q] > C(0) ? v : C(0);
 }
 
 // r - A e at the two cells of the pair, summed (the restriction adds four pairs)
@@ -710,6 +721,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
     double *rs = SpRaw;
     const int L = a.n;
     const int tid = threadIdx.x;
+    const C om = static_cast<C>(a.omega);
     int off[TAIL_MAX + 1];                  // first cell of level q in the LDS arrays
     off[0] = 0;
     for (int l = 0; l < L; ++l)
@@ -821,7 +833,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
             for (int colour = 0; colour < 2; ++colour) {
 #pragma unroll
                 for (int u = 0; u < TAIL_PAIRS; ++u)
-                    tp_gs(P[u], El, h2, colour, sw == 0 && colour == 0);
+                    tp_gs(P[u], El, h2, om, colour, sw == 0 && colour == 0, sw == 0);
                 __syncthreads();
             }
         // restriction: residual sums per pair, then four pairs per coarse cell
@@ -881,7 +893,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
             for (int colour = 1; colour >= 0; --colour) {
 #pragma unroll
                 for (int u = 0; u < TAIL_PAIRS; ++u)
-                    tp_gs(P[u], El, h2, colour, false);
+                    tp_gs(P[u], El, h2, om, colour, false, false);
                 __syncthreads();
             }
     }
@@ -2442,15 +2454,16 @@ static const dim3 kBlock(BX, BY, 1);
 
 template <typename T>
 void launch_rbgs(Dims d, Bc bc, const T *bx, const T *by, const T *bz, const T *r, T *e,
-                 const T *sg, double h2, int colour, bool zero, hipStream_t s)
+                 const T *sg, double h2, double omega, int colour, bool zero, bool self_zero,
+                 hipStream_t s)
 {
     using C = typename Acc<T>::type;
     if (zero)
         hipLaunchKernelGGL((k_rbgs<T, true>), colour_grid(d), kBlock, 0, s, d, bc, bx, by, bz, r, e,
-                           sg, (C)h2, colour);
+                           sg, (C)h2, (C)omega, colour, 1);
     else
         hipLaunchKernelGGL((k_rbgs<T, false>), colour_grid(d), kBlock, 0, s, d, bc, bx, by, bz, r,
-                           e, sg, (C)h2, colour);
+                           e, sg, (C)h2, (C)omega, colour, self_zero ? 1 : 0);
 }
 
 template <typename T>
@@ -2486,7 +2499,8 @@ void launch_prolong_weights(Dims d, Bc bc, const double *bx, const double *by, c
 template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
                  void *const *r, const void *const *sg, const unsigned *const *w, Bc bc,
-                 int nu_pre, int nu_post, const double *pinv, int ncoarse, hipStream_t s)
+                 int nu_pre, int nu_post, double omega, const double *pinv, int ncoarse,
+                 hipStream_t s)
 {
     TailArgs<T> a;
     a.n = nlev;
@@ -2503,6 +2517,7 @@ void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*
     a.bc = bc;
     a.nu_pre = nu_pre;
     a.nu_post = nu_post;
+    a.omega = omega;
     a.pinv = pinv;
     a.ncoarse = ncoarse;
     hipLaunchKernelGGL((k_tail_cycle<T>), dim3(1), dim3(TAIL_THREADS), 0, s, a);
@@ -2850,7 +2865,7 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
 // explicit instantiations for the three storage types
 #define PP_INSTANTIATE(T)                                                                        \
     template void launch_rbgs<T>(Dims, Bc, const T *, const T *, const T *, const T *, T *,     \
-                                 const T *, double, int, bool, hipStream_t);                    \
+                                 const T *, double, double, int, bool, bool, hipStream_t);      \
     template void launch_resid_restrict<T>(Dims, Bc, const T *, const T *, const T *, const T *, \
                                            const T *, const T *, T *, double, hipStream_t);     \
     template void launch_prolong<T>(Dims, Bc, const T *, T *, const unsigned *, hipStream_t);    \
@@ -2863,8 +2878,8 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
     template void launch_coarsest<T>(int, const double *, const T *, T *, hipStream_t);         \
     template void launch_tail<T>(int, const Dims *, const double *, const void *const (*)[3],   \
                                  void *const *, void *const *, const void *const *,             \
-                                 const unsigned *const *, Bc, int, int, const double *, int,    \
-                                 hipStream_t);                                                  \
+                                 const unsigned *const *, Bc, int, int, double, const double *, \
+                                 int, hipStream_t);                                             \
     template void launch_convert<T>(size_t, const double *, T *, hipStream_t);                  \
     template int launch_convert_scaled<T>(size_t, const double *, double, double, T *, double *, \
                                           int, hipStream_t);                                    \

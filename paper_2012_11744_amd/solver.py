@@ -77,7 +77,7 @@ class Solver:
     def __init__(self, beta: Sequence[torch.Tensor], h: float, bc: Sequence[int],
                  precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
                  max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
-                 coarse_graph: bool = False, nu_coarse: int = 4,
+                 coarse_graph: bool = False, nu_coarse: int = 4, omega: Optional[float] = None,
                  stream: Optional[torch.cuda.Stream] = None,
                  sigma: Optional[torch.Tensor] = None, general: bool = False):
         lib = L.load()
@@ -99,6 +99,8 @@ class Solver:
         o.fallback = int(bool(fallback))
         o.coarse_graph = int(bool(coarse_graph))
         o.nu_coarse = nu_coarse
+        if omega is not None:       # None: the library's default
+            o.omega = float(omega)
         self.opts = o
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -313,24 +315,26 @@ def pressure_solve(rhs: torch.Tensor, beta: Sequence[torch.Tensor], solver: Solv
 
 # -- single-kernel entry points -----------------------------------------------
 
-def k_smooth(shape, h, bc, beta, r, e, sweeps=1, zero_init=False):
+def k_smooth(shape, h, bc, beta, r, e, sweeps=1, zero_init=False, omega=1.0):
     lib = L.load()
     g = make_grid(shape, h, bc)
     L.check(lib.pp_k_smooth(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r), _ptr(e), sweeps,
-                            int(zero_init), _stream_handle(None)), "pp_k_smooth")
+                            int(zero_init), float(omega), _stream_handle(None)), "pp_k_smooth")
     return e
 
 
-def k_smooth_fused(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero_init=False):
+def k_smooth_fused(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero_init=False,
+                   omega=1.0):
     lib = L.load()
     g = make_grid(shape, h, bc)
     L.check(lib.pp_k_smooth_fused(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r), _ptr(e_in),
-                                  _ptr(e_out), int(first_colour), int(zero_init),
+                                  _ptr(e_out), int(first_colour), int(zero_init), float(omega),
                                   _stream_handle(None)), "pp_k_smooth_fused")
     return e_out
 
 
-def k_smooth2_fused_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero_init=False):
+def k_smooth2_fused_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero_init=False,
+                        omega=1.0):
     """Two fused sweeps on float32 device tensors (the FP32 V-cycle's kernel)."""
     lib = L.load()
     g = make_grid(shape, h, bc)
@@ -339,11 +343,12 @@ def k_smooth2_fused_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0, zero
             raise TypeError("k_smooth2_fused_f32 takes float32 tensors")
     L.check(lib.pp_k_smooth2_fused_f32(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r),
                                        _ptr(e_in), _ptr(e_out), int(first_colour), int(zero_init),
-                                       _stream_handle(None)), "pp_k_smooth2_fused_f32")
+                                       float(omega), _stream_handle(None)),
+            "pp_k_smooth2_fused_f32")
     return e_out
 
 
-def k_smooth2_fused_dot_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0):
+def k_smooth2_fused_dot_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0, omega=1.0):
     """k_smooth2_fused_f32 that also returns sum(r * e_out), r the pass's own
     right-hand side (products and sum in FP64)."""
     lib = L.load()
@@ -353,13 +358,14 @@ def k_smooth2_fused_dot_f32(shape, h, bc, beta, r, e_in, e_out, first_colour=0):
             raise TypeError("k_smooth2_fused_dot_f32 takes float32 fields")
     dot = torch.empty(1, dtype=torch.float64, device=r.device)
     L.check(lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), *(_ptr(b) for b in beta), _ptr(r),
-                                           _ptr(e_in), _ptr(e_out), int(first_colour), _ptr(dot),
-                                           _stream_handle(None)),
+                                           _ptr(e_in), _ptr(e_out), int(first_colour),
+                                           float(omega), _ptr(dot), _stream_handle(None)),
             "pp_k_smooth2_fused_dot_f32")
     return float(dot[0].item())
 
 
-def k_smooth2_fused_dot_f32_noalloc(shape, h, bc, beta, r, e_in, e_out, dot, first_colour=0):
+def k_smooth2_fused_dot_f32_noalloc(shape, h, bc, beta, r, e_in, e_out, dot, first_colour=0,
+                                    omega=1.0):
     """The pass of k_smooth2_fused_dot_f32 through the entry point that
     allocates nothing: its partial sums use the library's static device
     array, and the result goes to `dot` (a float64 device tensor of at least
@@ -373,7 +379,7 @@ def k_smooth2_fused_dot_f32_noalloc(shape, h, bc, beta, r, e_in, e_out, dot, fir
         raise TypeError("dot must be a float64 tensor of at least one element")
     L.check(lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(g), *(_ptr(b) for b in beta),
                                                    _ptr(r), _ptr(e_in), _ptr(e_out),
-                                                   int(first_colour), _ptr(dot),
+                                                   int(first_colour), float(omega), _ptr(dot),
                                                    _stream_handle(None)),
             "pp_k_smooth2_fused_dot_f32_noalloc")
     return dot

@@ -53,7 +53,8 @@ def test_opts_default(lib):
     o = L.Opts()
     lib.pp_opts_default(ctypes.byref(o))
     assert (o.precision, o.outer, o.nu_pre, o.nu_post, o.max_outer, o.warm_start, o.fallback,
-            o.coarse_graph, o.nu_coarse) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1, 0, 4)
+            o.coarse_graph, o.nu_coarse, o.omega) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500,
+                                                      0, 1, 0, 4, 1.2)
 
 
 def _grid(n=(8, 8, 8), h=0.125, bc=(0, 0, 0)):
@@ -96,7 +97,8 @@ def test_setup_rejects_null_and_bad_options(lib):
     assert lib.pp_setup(ctypes.byref(g), fake, fake, fake, None, None, None) == L.PP_EINVAL
     for field, bad in (("precision", 7), ("outer", 3), ("nu_pre", 0), ("nu_post", 17),
                        ("max_outer", 0), ("warm_start", 2), ("coarse_graph", 5),
-                       ("nu_coarse", 0), ("nu_coarse", 17)):
+                       ("nu_coarse", 0), ("nu_coarse", 17), ("omega", 0.0), ("omega", 2.0),
+                       ("omega", float("nan"))):
         o = L.Opts()
         lib.pp_opts_default(ctypes.byref(o))
         setattr(o, field, bad)
@@ -123,36 +125,50 @@ def test_kernel_entries_validate(lib):
     fake = ctypes.c_void_p(0x1000)
     g = _grid((10, 8, 8), 0.1, (0, 0, 0))   # periodic x with an even count is fine,
     g2 = _grid((9, 8, 8), 0.1, (0, 0, 0))   # an odd periodic count is not
-    assert lib.pp_k_smooth(ctypes.byref(g2), fake, fake, fake, fake, fake, 1, 0, None) == L.PP_EINVAL
-    assert lib.pp_k_smooth(ctypes.byref(g), fake, fake, fake, fake, fake, 0, 0, None) == L.PP_EINVAL
+    assert lib.pp_k_smooth(ctypes.byref(g2), fake, fake, fake, fake, fake, 1, 0, 1.0,
+                           None) == L.PP_EINVAL
+    assert lib.pp_k_smooth(ctypes.byref(g), fake, fake, fake, fake, fake, 0, 0, 1.0,
+                           None) == L.PP_EINVAL
+    for om in (0.0, 2.0, -1.0, float("nan")):                # SOR needs 0 < omega < 2
+        assert lib.pp_k_smooth(ctypes.byref(g), fake, fake, fake, fake, fake, 1, 0, om,
+                               None) == L.PP_EINVAL
     g3 = _grid((9, 8, 8), 0.1, (1, 0, 0))   # the fused sweep needs even nx even with walls
     other = ctypes.c_void_p(0x2000)
     assert lib.pp_k_smooth_fused(ctypes.byref(g3), fake, fake, fake, fake, fake, other, 0, 0,
-                                 None) == L.PP_EINVAL
+                                 1.0, None) == L.PP_EINVAL
     assert lib.pp_k_smooth_fused(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0, 0,
-                                 None) == L.PP_EINVAL      # e_in aliases e_out
+                                 1.0, None) == L.PP_EINVAL      # e_in aliases e_out
     assert lib.pp_k_smooth_fused(ctypes.byref(g), fake, fake, fake, fake, fake, other, 2, 0,
-                                 None) == L.PP_EINVAL      # bad colour
+                                 1.0, None) == L.PP_EINVAL      # bad colour
+    assert lib.pp_k_smooth_fused(ctypes.byref(g), fake, fake, fake, fake, fake, other, 0, 0,
+                                 2.5, None) == L.PP_EINVAL      # bad omega
     for gg in (g3, _grid((10, 8, 6), 0.1, (1, 1, 1))):    # odd nx; a count below 8
         assert lib.pp_k_smooth2_fused_f32(ctypes.byref(gg), fake, fake, fake, fake, fake, other, 0,
-                                          0, None) == L.PP_EINVAL
+                                          0, 1.0, None) == L.PP_EINVAL
     assert lib.pp_k_smooth2_fused_f32(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0, 0,
-                                      None) == L.PP_EINVAL      # e_in aliases e_out
+                                      1.0, None) == L.PP_EINVAL      # e_in aliases e_out
+    assert lib.pp_k_smooth2_fused_f32(ctypes.byref(g), fake, fake, fake, fake, fake, other, 0, 0,
+                                      0.0, None) == L.PP_EINVAL      # bad omega
     assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, other, 0,
-                                          None, None) == L.PP_EINVAL      # no dot
+                                          1.0, None, None) == L.PP_EINVAL      # no dot
     assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, other, 0,
-                                          ctypes.c_void_p(0x1004), None) == L.PP_EINVAL   # dot misaligned
+                                          1.0, ctypes.c_void_p(0x1004), None) == L.PP_EINVAL   # dot misaligned
     assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, fake, 0,
-                                          other, None) == L.PP_EINVAL     # aliasing
+                                          1.0, other, None) == L.PP_EINVAL     # aliasing
+    assert lib.pp_k_smooth2_fused_dot_f32(ctypes.byref(g), fake, fake, fake, fake, fake, other, 0,
+                                          2.0, ctypes.c_void_p(0x3000), None) == L.PP_EINVAL   # bad omega
     # the entry point that allocates nothing checks the same arguments, and
     # rejects grids whose partial sums would not fit its static array
     assert lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(g), fake, fake, fake, fake, fake,
-                                                  other, 0, None, None) == L.PP_EINVAL
+                                                  other, 0, 1.0, None, None) == L.PP_EINVAL
     assert lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(g), fake, fake, fake, fake, fake,
-                                                  fake, 0, other, None) == L.PP_EINVAL
+                                                  fake, 0, 1.0, other, None) == L.PP_EINVAL
+    assert lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(g), fake, fake, fake, fake, fake,
+                                                  other, 0, -0.5, ctypes.c_void_p(0x3000),
+                                                  None) == L.PP_EINVAL
     big = _grid((1024, 1024, 1024), 1.0 / 1024, (0, 0, 0))   # 16 * 128 * 128 partial sums
     assert lib.pp_k_smooth2_fused_dot_f32_noalloc(ctypes.byref(big), fake, fake, fake, fake, fake,
-                                                  other, 0, ctypes.c_void_p(0x3000),
+                                                  other, 0, 1.0, ctypes.c_void_p(0x3000),
                                                   None) == L.PP_EINVAL
     assert b"65536" in lib.pp_last_error()
     assert lib.pp_k_resid_restrict(ctypes.byref(g2), fake, fake, fake, fake, fake, fake, None) == L.PP_EINVAL

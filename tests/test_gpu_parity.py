@@ -91,23 +91,26 @@ def test_divergence_apply_project(S, n, bc):
 
 
 @pytest.mark.parametrize("n,bc", RAGGED)
-def test_one_gauss_seidel_sweep_matches_paper_sor(S, n, bc):
-    """One red-black sweep (relaxation 1) equals the oracle's sweep of eq.
+@pytest.mark.parametrize("omega", [1.0, 1.3])
+def test_one_gauss_seidel_sweep_matches_paper_sor(S, n, bc, omega):
+    """One red-black sweep (relaxation omega) equals the oracle's sweep of eq.
     beta_pressure: same-colour updates are independent, so order-free."""
-    _say(f"rbgs sweep n={n} bc={bc}")
+    _say(f"rbgs sweep n={n} bc={bc} omega={omega}")
     w = W.random_case(n, bc, seed=103)
     beta = oracle.face_coeffs(w.rho, bc)
     rng = np.random.default_rng(2)
     r = rng.standard_normal(w.shape)
     e0 = rng.standard_normal(w.shape)
-    ref, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=e0, omega=1.0, sweeps=1)
+    ref, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=e0, omega=omega, sweeps=1)
     e = dev(e0)
-    S.k_smooth(w.shape, w.h, bc, [dev(b) for b in beta], dev(r), e, sweeps=1)
+    S.k_smooth(w.shape, w.h, bc, [dev(b) for b in beta], dev(r), e, sweeps=1, omega=omega)
     assert relmax(host(e), ref) <= 1e-14
-    # two sweeps from zero (zero_init skips reading e)
-    ref2, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=np.zeros(w.shape), omega=1.0, sweeps=2)
+    # two sweeps from zero (zero_init reads neither e nor, in the first sweep,
+    # the second colour's old values)
+    ref2, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=np.zeros(w.shape), omega=omega, sweeps=2)
     e = dev(np.full(w.shape, np.nan))
-    S.k_smooth(w.shape, w.h, bc, [dev(b) for b in beta], dev(r), e, sweeps=2, zero_init=True)
+    S.k_smooth(w.shape, w.h, bc, [dev(b) for b in beta], dev(r), e, sweeps=2, zero_init=True,
+               omega=omega)
     assert relmax(host(e), ref2) <= 1e-14
 
 
@@ -122,40 +125,43 @@ WHOLE_F32 = ((256, 128, 190), (0, 0, 1))
 @pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0)),
                                   WHOLE_F64])
 @pytest.mark.parametrize("first", [0, 1])
-def test_fused_sweep_matches_paper_sor(S, n, bc, first):
+@pytest.mark.parametrize("omega", [1.0, 1.3])
+def test_fused_sweep_matches_paper_sor(S, n, bc, first, omega):
     """One fused out-of-place sweep (tiles of 128 x 8 cells, z chunks, ring
     recomputation) equals the oracle's sweep of eq. beta_pressure with the
-    same colour order; also from a zero start (e_in not read)."""
-    _say(f"fused rbgs sweep n={n} bc={bc} first={first}")
+    same colour order and relaxation; also from a zero start (e_in not read)."""
+    _say(f"fused rbgs sweep n={n} bc={bc} first={first} omega={omega}")
     w = W.random_case(n, bc, seed=113)
     beta = oracle.face_coeffs(w.rho, bc)
     bt = [dev(b) for b in beta]
     rng = np.random.default_rng(4)
     r = rng.standard_normal(w.shape)
     e0 = rng.standard_normal(w.shape)
-    ref, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=e0, omega=1.0, sweeps=1, first_colour=first)
+    ref, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=e0, omega=omega, sweeps=1, first_colour=first)
     out = dev(np.full(w.shape, np.nan))
-    S.k_smooth_fused(w.shape, w.h, bc, bt, dev(r), dev(e0), out, first_colour=first)
+    S.k_smooth_fused(w.shape, w.h, bc, bt, dev(r), dev(e0), out, first_colour=first, omega=omega)
     assert relmax(host(out), ref) <= 1e-14
-    ref0, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=np.zeros(w.shape), omega=1.0, sweeps=1,
+    ref0, _, _ = oracle.rbsor(beta, bc, w.h, r, p0=np.zeros(w.shape), omega=omega, sweeps=1,
                               first_colour=first)
     out = dev(np.full(w.shape, np.nan))
     S.k_smooth_fused(w.shape, w.h, bc, bt, dev(r), dev(np.full(w.shape, np.nan)), out,
-                     first_colour=first, zero_init=True)
+                     first_colour=first, zero_init=True, omega=omega)
     assert relmax(host(out), ref0) <= 1e-14
 
 
 @pytest.mark.parametrize("n,bc", RAGGED + [((130, 12, 20), (0, 0, 1)), ((64, 16, 8), (1, 1, 0)),
                                   ((200, 72, 40), (0, 0, 0)), WHOLE_F32])
 @pytest.mark.parametrize("first", [0, 1])
-def test_two_sweep_fused_f32_matches_paper_sor(S, n, bc, first):
+@pytest.mark.parametrize("omega", [1.0, 1.3])
+def test_two_sweep_fused_f32_matches_paper_sor(S, n, bc, first, omega):
     """Two sweeps in one pass (FP32 storage and arithmetic; tiles of 64 x 8
     cells with a ring two pairs / three rows deep, z chunks marched three
     planes beyond their ends) against two of the oracle's sweeps of eq.
     beta_pressure on the same FP32-rounded inputs.  Tolerance: FP32 rounding
     of each update (a few ulps, the reciprocal within 1 ulp) carried through
-    four colour passes, relative to max|e|: 2e-6."""
-    _say(f"two-sweep fused f32 n={n} bc={bc} first={first}")
+    four colour passes, relative to max|e|: 2e-6 (with relaxation 1.3 each update
+    also rounds (1 - omega) e and omega / diag, a few more ulps)."""
+    _say(f"two-sweep fused f32 n={n} bc={bc} first={first} omega={omega}")
     w = W.random_case(n, bc, seed=117)
     beta = [b.astype(np.float32) for b in oracle.face_coeffs(w.rho, bc)]
     rng = np.random.default_rng(5)
@@ -166,12 +172,12 @@ def test_two_sweep_fused_f32_matches_paper_sor(S, n, bc, first):
     b64 = [b.astype(np.float64) for b in beta]
     for zero in (False, True):
         p0 = np.zeros(w.shape) if zero else e0.astype(np.float64)
-        ref, _, _ = oracle.rbsor(b64, bc, w.h, r.astype(np.float64), p0=p0, omega=1.0, sweeps=2,
-                                 first_colour=first)
+        ref, _, _ = oracle.rbsor(b64, bc, w.h, r.astype(np.float64), p0=p0, omega=omega,
+                                 sweeps=2, first_colour=first)
         out = f32(np.full(w.shape, np.nan))
         ein = f32(np.full(w.shape, np.nan)) if zero else f32(e0)
         S.k_smooth2_fused_f32(w.shape, w.h, bc, bt, f32(r), ein, out, first_colour=first,
-                              zero_init=zero)
+                              zero_init=zero, omega=omega)
         got = host(out).astype(np.float64)
         err = relmax(got, ref)
         _say(f"  zero={zero} err={err:.2e}")
@@ -198,12 +204,13 @@ def test_two_sweep_fused_dot_product(S, n, bc):
     hr = (h2f * r).astype(np.float64)            # FP32 product, as the sweep forms it
     f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     bt = [f32(b) for b in beta]
-    for first in (0, 1):
+    for first, omega in ((0, 1.0), (1, 1.0), (0, 1.3)):
         plain = f32(np.full(w.shape, np.nan))
-        S.k_smooth2_fused_f32(w.shape, w.h, bc, bt, f32(r), f32(e0), plain, first_colour=first)
+        S.k_smooth2_fused_f32(w.shape, w.h, bc, bt, f32(r), f32(e0), plain, first_colour=first,
+                              omega=omega)
         out = f32(np.full(w.shape, np.nan))
         dot = S.k_smooth2_fused_dot_f32(w.shape, w.h, bc, bt, f32(r), f32(e0), out,
-                                        first_colour=first)
+                                        first_colour=first, omega=omega)
         eo = host(out).astype(np.float64)
         assert np.array_equal(host(plain), host(out))
         ref = float(np.sum(hr * eo)) / float(h2f)

@@ -47,18 +47,18 @@ def test_noalloc_matches_allocating_entry_two_calls(S):
     # the first grid fills several tiles and z chunks with a ragged last tile;
     # the second is smaller, so the second call reads fewer partial sums than
     # the first left in the shared array
-    cases = [((200, 72, 40), (0, 1, 1), 0), ((40, 20, 56), (1, 0, 1), 1)]
+    cases = [((200, 72, 40), (0, 1, 1), 0, 1.0), ((40, 20, 56), (1, 0, 1), 1, 1.3)]
     dot = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
-    for n, bc, first in cases:
-        _say(f"no-alloc fused dot pass n={n} bc={bc} first_colour={first}")
+    for n, bc, first, omega in cases:
+        _say(f"no-alloc fused dot pass n={n} bc={bc} first_colour={first} omega={omega}")
         w, beta, r, e0 = _case(n, bc, seed=301 + n[0])
         bt = [_f32(b) for b in beta]
         ref_out = _f32(np.full(w.shape, np.nan))
         ref_dot = S.k_smooth2_fused_dot_f32(w.shape, w.h, bc, bt, _f32(r), _f32(e0), ref_out,
-                                            first_colour=first)
+                                            first_colour=first, omega=omega)
         out = _f32(np.full(w.shape, np.nan))
         S.k_smooth2_fused_dot_f32_noalloc(w.shape, w.h, bc, bt, _f32(r), _f32(e0), out, dot,
-                                          first_colour=first)
+                                          first_colour=first, omega=omega)
         torch.cuda.synchronize()
         got = float(dot[0].item())
         _say(f"  dot={got:.17e} allocating entry={ref_dot:.17e}")
