@@ -305,9 +305,9 @@ def _wall0(b, m, bc):
 
 
 def _coarse_beta_ref(beta, bc):
-    """Coarse face coefficient: the mean of (a) the mean of the 4 fine faces on
-    the coarse face and (b) the mean over the 4 rows of the series coefficient
-    2 / (1/(2 b[2I-1]) + 1/b[2I] + 1/(2 b[2I+1])) along the normal."""
+    """Coarse face coefficient: 1/4 of (a) the mean of the 4 fine faces on the
+    coarse face plus 3/4 of (b) the mean over the 4 rows of the series
+    coefficient 2 / (1/(2 b[2I-1]) + 1/b[2I] + 1/(2 b[2I+1])) along the normal."""
     out = []
     for m in range(3):
         ax = 2 - m
@@ -329,7 +329,7 @@ def _coarse_beta_ref(beta, bc):
             hi_[a] = slice(1, None, 2)
             par = 0.5 * (par[tuple(lo_)] + par[tuple(hi_)])
             srs = 0.5 * (srs[tuple(lo_)] + srs[tuple(hi_)])
-        f = 0.5 * (par + srs)
+        f = 0.25 * par + 0.75 * srs
         if bc[m] == 1:
             s0 = [slice(None)] * 3
             s0[ax] = 0
