@@ -89,13 +89,15 @@ def test_layer256_parity(S, layer256, precision):
     _say(f"  tol 1e-8: {it8} iterations, oracle residual {r8:.2e}, p error {err8:.2e}; "
          f"tol 1e-11: p error {err11:.2e}, div(u) error {err_div:.2e}, u error {err_u:.2e}")
     assert r8 <= 1.05e-8
-    # measured 1.4e-9 (FP32) and 5.5e-10; the residual tolerance does not
-    # bound the p error by itself (condition number ~1e8), so the bound
-    # leaves a margin of about 70 over the measured values
+    # measured 3.3e-8 (FP32 and FP64: 7 iterations, final residual 4.0e-9)
+    # and 3.7e-9 (FP16 storage, 8 iterations); the residual tolerance does
+    # not bound the p error by itself (condition number ~1e8), so the bound
+    # leaves a margin of 3 over the largest measured value
     assert err8 <= 1e-7
-    # iteration counts of the timed configuration (measured 8, 8 and 9): a
-    # mistake in a preconditioner kernel shows up here first
-    assert it8 <= (10 if precision == "fp16" else 9)
+    # iteration counts of the timed configuration (measured 7, 7 and 8 with
+    # the default over-relaxation): a mistake in a preconditioner kernel, or
+    # a smoother that lost its relaxation, shows up here first
+    assert it8 <= (9 if precision == "fp16" else 8)
     assert err11 <= 1e-8
     assert err_div <= 1e-8
     assert err_u <= 1e-8
