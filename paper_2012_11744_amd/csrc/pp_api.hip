@@ -151,10 +151,14 @@ struct pp_ctx {
     hipEvent_t scal_ev;          // the scalar block's read-back (hscal) done
     hipEvent_t coarse_ev;        // the coarsest coefficients' read-back (hcoarse) done
     double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
+    hipStream_t copy_stream;     // its upload, beside the stream's work ...
+    hipEvent_t pinv_ev;          // ... done
+    bool pinv_wait;              // the next V-cycle waits for the upload before its coarse levels
     bool pinv_dirty;             // the coefficients changed since pinv was built: the next
                                  // V-cycle's caller builds it first (from hcoarse)
     bool check_pending;          // a density load's validity counts still to be read back
                                  // (by the next solve's first wait): pp_step
+    bool scale_queued;           // the first V-cycle's scaled right-hand side is already queued
     bool check_rho_count;        // ... including the separate density count (S_SBAD)
     double *r64, *d64, *d64b, *q64;
     double *part;
@@ -401,21 +405,30 @@ int fill_hier(pp_ctx *c, Hier &H, int from)
     return check_launch("convert coefficients");
 }
 
+// In place, lower triangle (row-major), right-looking: after column j is
+// scaled, every entry of the trailing lower triangle takes its update
+// independently (row by row over contiguous memory), so the loops carry no
+// chain of dependent additions.  The pseudo-inverse is rebuilt on the host
+// at every coefficient update, overlapping the GPU's work before the first
+// V-cycle needs it.
 int cholesky(std::vector<double> &a, int n)
 {
+    std::vector<double> col((size_t)n);
     for (int j = 0; j < n; ++j) {
-        double dgl = a[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k)
-            dgl -= a[(size_t)j * n + k] * a[(size_t)j * n + k];
+        const double dgl = a[(size_t)j * n + j];
         if (!(dgl > 0.0))
             return -1;
-        dgl = std::sqrt(dgl);
-        a[(size_t)j * n + j] = dgl;
+        const double d = std::sqrt(dgl);
+        a[(size_t)j * n + j] = d;
         for (int i = j + 1; i < n; ++i) {
-            double s = a[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k)
-                s -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
-            a[(size_t)i * n + j] = s / dgl;
+            a[(size_t)i * n + j] /= d;
+            col[i] = a[(size_t)i * n + j];
+        }
+        for (int i = j + 1; i < n; ++i) {
+            const double lij = col[i];
+            double *ai = &a[(size_t)i * n];
+            for (int k = j + 1; k <= i; ++k)
+                ai[k] -= lij * col[k];
         }
     }
     return 0;
@@ -496,37 +509,58 @@ int build_pinv(pp_ctx *c)
     if (cholesky(K, na) != 0)
         return fail(PP_EINVAL, "coarsest operator is not definite on mean-zero fields "
                                "(disconnected domain?)");
-    // K^-1 = L^-T L^-1.  Row j of Mt holds column j of M = L^-1 (entries j..na-1),
-    // so both products below run over contiguous memory.
-    std::vector<double> Mt((size_t)na * na, 0.0);
-    for (int j = 0; j < na; ++j) {
-        double *mj = &Mt[(size_t)j * na];
-        mj[j] = 1.0 / K[(size_t)j * na + j];
-        for (int i = j + 1; i < na; ++i) {
-            const double *li = &K[(size_t)i * na];
-            double t = 0.0;
-            for (int kk = j; kk < i; ++kk)
-                t += li[kk] * mj[kk];
-            mj[i] = -t / li[i];
+    // K^-1 = L^-T L^-1 = M^T M with M = L^-1, lower triangular.  M comes from
+    // L M = I by forward substitution, all columns at once: row i of M is
+    // (e_i - sum_{k<i} L_ik M_k) / L_ii over rows k already formed, each step
+    // an update of a contiguous row.  M^T M is summed as outer products of
+    // the rows of M.  No loop carries a chain of dependent additions.
+    std::vector<double> M((size_t)na * na, 0.0);
+    for (int i = 0; i < na; ++i) {
+        double *mi = &M[(size_t)i * na];
+        const double *li = &K[(size_t)i * na];
+        mi[i] = 1.0;
+        for (int k = 0; k < i; ++k) {
+            const double lik = li[k];
+            const double *mk = &M[(size_t)k * na];
+            for (int q = 0; q <= k; ++q)
+                mi[q] -= lik * mk[q];
+        }
+        const double inv = 1.0 / li[i];
+        for (int q = 0; q <= i; ++q)
+            mi[q] *= inv;
+    }
+    std::vector<double> G((size_t)na * na, 0.0);   // M^T M, lower triangle
+    for (int k = 0; k < na; ++k) {
+        const double *mk = &M[(size_t)k * na];
+        for (int a = 0; a <= k; ++a) {
+            const double mka = mk[a];
+            double *ga = &G[(size_t)a * na];
+            for (int bb = 0; bb <= a; ++bb)
+                ga[bb] += mka * mk[bb];
         }
     }
+    // the previous upload has read hpinv (it completed before that solve's
+    // coarse levels ran, so this returns at once)
+    PP_HIP(hipEventSynchronize(c->pinv_ev));
     double *P = c->hpinv;
     std::fill(P, P + (size_t)n * n, 0.0);
     const double shift = singular ? 1.0 / (s * na) : 0.0;
-    for (int a = 0; a < na; ++a) {
-        const double *ma = &Mt[(size_t)a * na];
+    for (int a = 0; a < na; ++a)
         for (int bb = 0; bb <= a; ++bb) {
-            const double *mb = &Mt[(size_t)bb * na];
-            double t = 0.0;
-            for (int kk = a; kk < na; ++kk)
-                t += ma[kk] * mb[kk];
-            const double v = shift - t;
+            const double v = shift - G[(size_t)a * na + bb];
             P[(size_t)idx[a] * n + idx[bb]] = v;
             P[(size_t)idx[bb] * n + idx[a]] = v;
         }
-    }
-    // no wait: hpinv is next written after a later read_scal, which waits for this copy
-    PP_HIP(hipMemcpyAsync(c->pinv, P, sizeof(double) * n * n, hipMemcpyHostToDevice, c->stream));
+    // The upload goes on a stream of its own, behind everything queued so far
+    // (no earlier coarsest solve can still read pinv), so the work the host
+    // queues next, up to the first coarse level, does not wait for the copy;
+    // that V-cycle waits for it before its coarse levels (pinv_wait)
+    PP_HIP(hipEventRecord(c->pinv_ev, c->stream));
+    PP_HIP(hipStreamWaitEvent(c->copy_stream, c->pinv_ev, 0));
+    PP_HIP(hipMemcpyAsync(c->pinv, P, sizeof(double) * n * n, hipMemcpyHostToDevice,
+                          c->copy_stream));
+    PP_HIP(hipEventRecord(c->pinv_ev, c->copy_stream));
+    c->pinv_wait = true;
     return PP_OK;
 }
 
@@ -947,11 +981,20 @@ template <typename T>
 void vcycle_run(pp_ctx *c, Hier &H)
 {
     hipStream_t s = c->stream;
+    // a pseudo-inverse upload still on its way: the coarse levels wait for it
+    auto await_pinv = [c, s]() {
+        if (c->pinv_wait) {
+            (void)hipStreamWaitEvent(s, c->pinv_ev, 0);
+            c->pinv_wait = false;
+        }
+    };
     if (H.tail == 0) {
+        await_pinv();
         cycle_from<T>(c, H, 0, s);
         return;
     }
     level_down<T>(c, H, 0, s);
+    await_pinv();
     if (!H.coarse_exec || hipGraphLaunch(H.coarse_exec, s) != hipSuccess)
         cycle_from<T>(c, H, 1, s);    // no graph, or it could not be launched: run eagerly
     level_up<T>(c, H, 0, s);
@@ -1058,7 +1101,7 @@ using Tail = std::function<int()>;
 // behind the read-back, so the GPU has it to work on while the host waits; if
 // the iterate goes on, it is queued again at the next confirmation.
 int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveState &S,
-                  bool gauge_x = false, const Tail *tail = nullptr)
+                  bool gauge_x = false, const Tail *tail = nullptr, const Tail *pre = nullptr)
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
     const int np = launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs,
@@ -1072,6 +1115,8 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
     PP_TRY(post_scal(c));
     if (gauge_x && tail)
         PP_TRY((*tail)());
+    if (pre)
+        PP_TRY((*pre)());
     // a pseudo-inverse still to be built is built here, on the host, while
     // the GPU works through the residual and whatever was queued before it;
     // its upload follows the read-back in the queue, unwaited
@@ -1105,7 +1150,9 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
     const int np = nparts(c);
     LevelBuf &v0 = H.lev[0];
-    launch_scale_T<T>(c->N, c->r64, (T *)v0.r, c->scal, s);
+    if (!c->scale_queued)
+        launch_scale_T<T>(c->N, c->r64, (T *)v0.r, c->scal, s);
+    c->scale_queued = false;
     bool first = true;
     D *dold = (D *)c->d64, *dnew = (D *)c->d64b;
     int since = 0;
@@ -1325,7 +1372,25 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
     }
     if (c->gen && warm)
         launch_mask(c->N, x, c->act, c->stream);   // excluded cells of a warm start are not read
-    PP_TRY(true_residual(c, rhs, x, !warm, S));
+    // The outer loop's first step, the residual scaled by its RMS into the
+    // V-cycle's right-hand side, needs only values the device holds: it is
+    // queued before the host waits for the initial residual, so the GPU has it
+    // to work on meanwhile (if that residual is already small enough, nothing
+    // reads it)
+    Hier *H0 = (c->opts.precision == PP_FP64) ? &c->h64 : &c->hmix;
+    c->scale_queued = false;
+    const Tail pre = [c, H0]() -> int {
+        void *rT = H0->lev[0].r;
+        switch (H0->st) {
+        case ST_F64: launch_scale_T<double>(c->N, c->r64, (double *)rT, c->scal, c->stream); break;
+        case ST_F32: launch_scale_T<float>(c->N, c->r64, (float *)rT, c->scal, c->stream); break;
+        default: launch_scale_T<_Float16>(c->N, c->r64, (_Float16 *)rT, c->scal, c->stream); break;
+        }
+        c->scale_queued = true;
+        return check_launch("scale");
+    };
+    const bool pcg = c->opts.outer == PP_OUTER_PCG && H0->present;
+    PP_TRY(true_residual(c, rhs, x, !warm, S, false, nullptr, pcg ? &pre : nullptr));
     int rc = PP_OK;
     bool gauged = false;   // x is gauged and unchanged since
     if (!(S.nb > 0.0)) {
@@ -1474,6 +1539,10 @@ void pp_destroy(pp_ctx *c)
         (void)hipEventDestroy(c->scal_ev);
     if (c->coarse_ev)
         (void)hipEventDestroy(c->coarse_ev);
+    if (c->pinv_ev)
+        (void)hipEventDestroy(c->pinv_ev);
+    if (c->copy_stream)
+        (void)hipStreamDestroy(c->copy_stream);
     delete c;
 }
 
@@ -1596,6 +1665,15 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
     if (hipEventCreateWithFlags(&c->coarse_ev, hipEventDisableTiming) != hipSuccess) {
         c->coarse_ev = nullptr;
         return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
+    }
+    if (hipEventCreateWithFlags(&c->pinv_ev, hipEventDisableTiming) != hipSuccess) {
+        c->pinv_ev = nullptr;
+        return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
+    }
+    // default priority, like every stream here
+    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->copy_stream = nullptr;
+        return bail(fail(PP_EHIP, "hipStreamCreateWithFlags failed"));
     }
     if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
         return bail(fail(PP_EHIP, "hipMemsetAsync failed"));

@@ -2430,6 +2430,38 @@ __global__ void k_axpy_dir(size_t n, const D *__restrict__ dv, const D *__restri
     }
 }
 
+// k_axpy_dir on four cells per thread and step, as 16-byte vectors (n
+// divisible by 4 and aligned arrays): the same arithmetic per cell
+template <typename D>
+__global__ void k_axpy_dir4(size_t n4, const D *__restrict__ dv, const D *__restrict__ dv_prev,
+                            double *__restrict__ x, const double *__restrict__ scal)
+{
+    using F2 = double __attribute__((ext_vector_type(2)));
+    using D4 = D __attribute__((ext_vector_type(4)));
+    const double a = scal[S_ALPHA];
+    const double ap = dv_prev ? scal[S_APREV] : 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const F2 x0 = reinterpret_cast<const F2 *>(x)[2 * i];
+        const F2 x1 = reinterpret_cast<const F2 *>(x)[2 * i + 1];
+        const D4 d = reinterpret_cast<const D4 *>(dv)[i];
+        double v[4] = {x0.x, x0.y, x1.x, x1.y};
+        if (dv_prev) {
+            const D4 dp = reinterpret_cast<const D4 *>(dv_prev)[i];
+            v[0] += ap * static_cast<double>(dp.x);
+            v[1] += ap * static_cast<double>(dp.y);
+            v[2] += ap * static_cast<double>(dp.z);
+            v[3] += ap * static_cast<double>(dp.w);
+        }
+        v[0] = v[0] + a * static_cast<double>(d.x);
+        v[1] = v[1] + a * static_cast<double>(d.y);
+        v[2] = v[2] + a * static_cast<double>(d.z);
+        v[3] = v[3] + a * static_cast<double>(d.w);
+        reinterpret_cast<F2 *>(x)[2 * i] = F2{v[0], v[1]};
+        reinterpret_cast<F2 *>(x)[2 * i + 1] = F2{v[2], v[3]};
+    }
+}
+
 __global__ void k_sub_mean(size_t n, double *__restrict__ x, const double *__restrict__ scal, int slot,
                            const unsigned char *__restrict__ act)
 {
@@ -2852,7 +2884,12 @@ template <typename D>
 void launch_axpy_dir(size_t n, const D *dv, const D *dv_prev, double *x, const double *scal,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL((k_axpy_dir<D>), flat_grid(n), dim3(256), 0, s, n, dv, dv_prev, x, scal);
+    const uintptr_t al = (uintptr_t)dv | (uintptr_t)dv_prev | (uintptr_t)x;
+    if (n % 4 == 0 && (al & 15) == 0)
+        hipLaunchKernelGGL((k_axpy_dir4<D>), flat_grid(n / 4), dim3(256), 0, s, n / 4, dv, dv_prev, x,
+                           scal);
+    else
+        hipLaunchKernelGGL((k_axpy_dir<D>), flat_grid(n), dim3(256), 0, s, n, dv, dv_prev, x, scal);
 }
 template void launch_axpy_dir<double>(size_t, const double *, const double *, double *,
                                       const double *, hipStream_t);
