@@ -491,7 +491,8 @@ def oracle_errors(w, fields, ref, tol):
 def bench_bubbles128(args):
     """128^3, walls, 20 gas bubbles in liquid at density ratio 1000 (seed 1),
     gravity term in u*: FP64 and mixed FP32 projection steps to args.tol
-    (solves/s, iterations), with errors against the oracle."""
+    with the V-cycle and with the W-cycle (solves/s, iterations), with errors
+    against the oracle."""
     import numpy as np
     import torch
 
@@ -505,8 +506,10 @@ def bench_bubbles128(args):
     u = tuple(torch.empty_like(rho) for _ in range(3))
     out, fields = {}, {}
     steps = max(5, args.steps // 2)
-    for mode in ("fp64", "fp32"):
-        with S.Solver(beta, w.h, w.bc, precision=mode) as sol:
+    for mode, cycle in (("fp64", "v"), ("fp32", "v"), ("fp64", "w"), ("fp32", "w"), ("fp64", "f"),
+                        ("fp32", "f")):
+        key = mode if cycle == "v" else f"{mode}_{cycle}_cycle"
+        with S.Solver(beta, w.h, w.bc, precision=mode, cycle=cycle) as sol:
             step = _step_fn(sol, rho, us, b, p, u, w, args.tol)
             for _ in range(2):
                 step()
@@ -519,12 +522,12 @@ def bench_bubbles128(args):
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / steps
             st = sol.last_stats
-            out[mode] = {"solves_per_s": 1e3 / ms, "ms_per_step": ms,
-                         "outer_iters": int(np.median(iters)), "rel_res": st["rel_res"],
-                         "fell_back": st["fell_back"]}
-            fields[mode] = (p.cpu().numpy(), [c.cpu().numpy() for c in u])
-        log(f"[bench] bubbles 128^3 {mode}: {1e3 / ms:.1f} solves/s, {ms:.3f} ms/step, "
-            f"iters={out[mode]['outer_iters']}")
+            out[key] = {"solves_per_s": 1e3 / ms, "ms_per_step": ms,
+                        "outer_iters": int(np.median(iters)), "rel_res": st["rel_res"],
+                        "fell_back": st["fell_back"]}
+            fields[key] = (p.cpu().numpy(), [c.cpu().numpy() for c in u])
+        log(f"[bench] bubbles 128^3 {key}: {1e3 / ms:.1f} solves/s, {ms:.3f} ms/step, "
+            f"iters={out[key]['outer_iters']}")
     del rho, us, beta, b, p, u
     torch.cuda.empty_cache()
     if not args.no_errors:

@@ -69,6 +69,8 @@ enum { PP_FP64 = 0, PP_MIXED_FP32 = 1, PP_MIXED_FP16 = 2 };
 
 /* outer iteration around the V-cycle */
 enum { PP_OUTER_PCG = 0, PP_OUTER_DC = 1 };
+/* multigrid cycle: how often each level takes its coarse correction */
+enum { PP_CYCLE_V = 0, PP_CYCLE_W = 1, PP_CYCLE_F = 2 };
 
 typedef struct {
     int32_t n[3];        /* cells per direction {nx, ny, nz}; see pp_setup */
@@ -96,6 +98,16 @@ typedef struct {
                             (Sec. 3.7.1, eq. beta_pressure: p <- (1 - omega) p + omega p_GS),
                             in (0, 2); the same factor before and after the coarse
                             correction keeps the V-cycle symmetric */
+    int32_t cycle;       /* PP_CYCLE_V (default): each level's coarse correction once (the
+                            paper's V-cycle, Sec. 3.7.3).  PP_CYCLE_W: twice on every level
+                            above the single-workgroup tail, the second pass starting from
+                            the first one's correction (a W-cycle; symmetric like the V-cycle).
+                            PP_CYCLE_F: the first pass an F-cycle, the second a V-cycle (level
+                            k is visited k + 1 times, not 2^k; not symmetric, so meant for the
+                            flexible PCG).  W and F take fewer outer iterations where isolated
+                            gas bubbles defeat the coarse grids (20 bubbles at density ratio
+                            1000, 128^3: 23 -> 11 for W), at more coarse-level latency per
+                            iteration; other values: PP_EINVAL */
 } pp_opts;
 
 #define PP_HIST 128
@@ -112,7 +124,7 @@ typedef struct {
 
 /* Fill *o with the defaults: mixed FP32, PCG, nu_pre = nu_post = 2,
  * max_outer = 500, warm_start = 0, fallback = 1, coarse_graph = 0, nu_coarse = 4,
- * omega = 1.2. */
+ * omega = 1.2, cycle = PP_CYCLE_V. */
 void pp_opts_default(pp_opts *o);
 
 /* Face coefficients from cell densities, beta_m[c] = 2 / (rho[c - e_m] + rho[c])

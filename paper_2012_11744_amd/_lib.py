@@ -30,6 +30,10 @@ PP_MIXED_FP16 = 2
 PP_OUTER_PCG = 0
 PP_OUTER_DC = 1
 
+PP_CYCLE_V = 0
+PP_CYCLE_W = 1
+PP_CYCLE_F = 2
+
 PP_HIST = 128
 
 PP_KT_SMOOTH = 0
@@ -49,7 +53,8 @@ class Opts(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("fallback", ctypes.c_int32), ("coarse_graph", ctypes.c_int32),
-                ("nu_coarse", ctypes.c_int32), ("omega", ctypes.c_double)]
+                ("nu_coarse", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("cycle", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

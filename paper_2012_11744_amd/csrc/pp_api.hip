@@ -270,6 +270,8 @@ int validate_opts(const pp_opts *o)
         return fail(PP_EINVAL, "opts.nu_coarse must be in 1..16");
     if (!omega_ok(o->omega))
         return fail(PP_EINVAL, "opts.omega must be in (0, 2)");
+    if (o->cycle != PP_CYCLE_V && o->cycle != PP_CYCLE_W && o->cycle != PP_CYCLE_F)
+        return fail(PP_EINVAL, "opts.cycle must be PP_CYCLE_V, PP_CYCLE_W or PP_CYCLE_F");
     return PP_OK;
 }
 
@@ -885,23 +887,27 @@ void *fused_sweeps(pp_ctx *c, LevelBuf &v, int l, int nu, void *cur, int first_c
 // restriction into the right-hand side of level l + 1.  Large levels use the
 // fused out-of-place sweep (ping-pong between e and e2); smaller ones, where
 // the fused kernel's march along z is latency-bound, use one launch per
-// colour in place.
+// colour in place.  warm: the sweeps start from the level's current
+// correction (the second coarse correction of a W-cycle).
 template <typename T>
-void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s)
+void level_down(pp_ctx *c, Hier &H, int l, hipStream_t s, bool warm = false)
 {
     LevelBuf &v = H.lev[l];
     const double h2 = v.h * v.h;
     const T *b0 = (const T *)v.b[0], *b1 = (const T *)v.b[1], *b2 = (const T *)v.b[2];
     if (cells(v.d) > fused_min_cells<T>() && fused_plane_fits(v.d, sizeof(T))) {
-        v.cur = fused_sweeps<T>(c, v, l, c->opts.nu_pre, v.e2, 0, true, s);
+        v.cur = warm ? fused_sweeps<T>(c, v, l, c->opts.nu_pre, v.cur, 0, false, s)
+                     : fused_sweeps<T>(c, v, l, c->opts.nu_pre, v.e2, 0, true, s);
     } else {
+        T *e = warm ? (T *)v.cur : (T *)v.e;
         for (int sw = 0; sw < c->opts.nu_pre; ++sw) {
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2,
-                           c->opts.omega, 0, sw == 0, false, s);
-            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, (T *)v.e, (const T *)v.s, h2,
-                           c->opts.omega, 1, false, sw == 0, s);
+            const bool z = !warm && sw == 0;
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, e, (const T *)v.s, h2,
+                           c->opts.omega, 0, z, false, s);
+            launch_rbgs<T>(v.d, c->bc, b0, b1, b2, (const T *)v.r, e, (const T *)v.s, h2,
+                           c->opts.omega, 1, false, z, s);
         }
-        v.cur = v.e;
+        v.cur = e;
     }
     KT t(c, PP_KT_RESTRICT, l == 0);
     launch_resid_restrict<T>(v.d, c->bc, b0, b1, b2, (const T *)v.cur, (const T *)v.r,
@@ -935,7 +941,7 @@ void level_up(pp_ctx *c, Hier &H, int l, hipStream_t s)
 
 // levels t .. L-1 (the tail) in one single-workgroup kernel, in place on e
 template <typename T>
-void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
+void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s, bool warm = false)
 {
     const int n = H.nlev - t;
     Dims d[TAIL_MAX];
@@ -958,20 +964,37 @@ void run_tail(pp_ctx *c, Hier &H, int t, hipStream_t s)
         v.cur = v.e;
     }
     launch_tail<T>(n, d, h2, b, e, r, sg, w, c->bc, c->opts.nu_coarse, c->opts.nu_coarse,
-                   c->opts.omega, c->pinv,
-                   c->ncoarse, s);
+                   c->opts.omega, c->pinv, c->ncoarse, warm, s);
 }
 
-// the V-cycle restricted to levels from .. L-1 (input: lev[from].r)
+// The cycle on levels l .. L-1 for A e = r (input lev[l].r, output
+// lev[l].cur); warm: level l starts from its current correction.  Each level
+// above the tail takes its coarse correction once (V), or twice, the second
+// pass starting from the correction the first one left on the next level: by
+// the same cycle (W) or by a V-cycle (F).
+template <typename T>
+void cycle_level(pp_ctx *c, Hier &H, int l, bool warm, int kind, hipStream_t s)
+{
+    if (l >= H.tail) {
+        run_tail<T>(c, H, l, s, warm);
+        return;
+    }
+    level_down<T>(c, H, l, s, warm);
+    cycle_level<T>(c, H, l + 1, false, kind, s);
+    if (kind != PP_CYCLE_V)
+        cycle_level<T>(c, H, l + 1, true, kind == PP_CYCLE_W ? PP_CYCLE_W : PP_CYCLE_V, s);
+    level_up<T>(c, H, l, s);
+}
+
+// the coarse correction of level from - 1: the cycle on levels from .. L-1
+// (input: lev[from].r), once or, for W- and F-cycles, twice
 template <typename T>
 void cycle_from(pp_ctx *c, Hier &H, int from, hipStream_t s)
 {
-    const int t = std::max(H.tail, from);
-    for (int l = from; l < t; ++l)
-        level_down<T>(c, H, l, s);
-    run_tail<T>(c, H, t, s);
-    for (int l = t - 1; l >= from; --l)
-        level_up<T>(c, H, l, s);
+    const int kind = c->opts.cycle;
+    cycle_level<T>(c, H, from, false, kind, s);
+    if (kind != PP_CYCLE_V && from > 0)
+        cycle_level<T>(c, H, from, true, kind == PP_CYCLE_W ? PP_CYCLE_W : PP_CYCLE_V, s);
 }
 
 // One V-cycle for A e = r on level 0 (input lev[0].r, output lev[0].cur).
@@ -1483,6 +1506,7 @@ void pp_opts_default(pp_opts *o)
     // measured at 256^3 (layer and droplets): 1.1-1.4 all take 7 outer
     // iterations where plain Gauss-Seidel (1.0) takes 8; 1.2 sits mid-plateau
     o->omega = 1.2;
+    o->cycle = PP_CYCLE_V;
 }
 
 const char *pp_strerror(int status)

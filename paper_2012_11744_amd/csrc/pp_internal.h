@@ -174,12 +174,13 @@ void launch_prolong_weights(Dims d, Bc bc, const double *bx, const double *by, c
 template <typename T>
 void launch_coarsest(int n, const double *pinv, const T *r, T *e, hipStream_t s);
 // the V-cycle on nlev levels (the last one the coarsest) in one workgroup;
-// input r[0], output e[0] (in place; every level's e is overwritten)
+// input r[0], output e[0] (in place; every level's e is overwritten); warm:
+// e[0] holds a correction on entry, which the first level's sweeps start from
 template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
                  void *const *r, const void *const *sg, const unsigned *const *w, Bc bc,
                  int nu_pre, int nu_post, double omega, const double *pinv, int ncoarse,
-                 hipStream_t s);
+                 bool warm, hipStream_t s);
 template <typename T>
 void launch_convert(size_t n, const double *src, T *dst, hipStream_t s);
 template <typename T>

@@ -548,6 +548,7 @@ struct TailArgs {
     double omega;              // the smoother's over-relaxation
     const double *pinv;        // pseudo-inverse of the coarsest operator
     int ncoarse;
+    int warm;                  // e[0] holds a correction to start the first level from
 };
 
 // Tail levels live in LDS: corrections and right-hand sides always, face
@@ -740,7 +741,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
     const int nc = a.ncoarse;
     const bool pvl = nc * nc <= TAIL_PINV;
     const unsigned WDEF = 0x404040u;        // 64/256 = 1/4 on each axis: trilinear
-    C r0[U0], b0[3][U0], b1[3] = {C(0), C(0), C(0)};
+    C r0[U0], b0[3][U0], b1[3] = {C(0), C(0), C(0)}, e0[U0];
     unsigned w0[U0], w1 = WDEF;
     double pv[UP];
     const unsigned *wf = L > 1 ? a.w[0] : nullptr;
@@ -748,6 +749,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
     for (int u = 0; u < U0; ++u) {
         const int cc = min(tid + u * TAIL_THREADS, n0 - 1);
         r0[u] = ld(a.r[0], cc);
+        e0[u] = a.warm ? ld(a.e[0], cc) : C(0);
 #pragma unroll
         for (int m = 0; m < 3; ++m)
             b0[m][u] = BLDS ? ld(a.b[0][m], cc) : C(0);
@@ -789,6 +791,8 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
         const int cc = tid + u * TAIL_THREADS;
         if (cc < n0) {
             Rr[cc] = r0[u];
+            if (a.warm)
+                E[cc] = e0[u];
             if (BLDS)
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
@@ -833,7 +837,8 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_cycle(TailArgs<T> a)
             for (int colour = 0; colour < 2; ++colour) {
 #pragma unroll
                 for (int u = 0; u < TAIL_PAIRS; ++u)
-                    tp_gs(P[u], El, h2, om, colour, sw == 0 && colour == 0, sw == 0);
+                    tp_gs(P[u], El, h2, om, colour, sw == 0 && colour == 0 && !(a.warm && l == 0),
+                          sw == 0 && !(a.warm && l == 0));
                 __syncthreads();
             }
         // restriction: residual sums per pair, then four pairs per coarse cell
@@ -2535,7 +2540,7 @@ template <typename T>
 void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*b)[3], void *const *e,
                  void *const *r, const void *const *sg, const unsigned *const *w, Bc bc,
                  int nu_pre, int nu_post, double omega, const double *pinv, int ncoarse,
-                 hipStream_t s)
+                 bool warm, hipStream_t s)
 {
     TailArgs<T> a;
     a.n = nlev;
@@ -2553,6 +2558,7 @@ void launch_tail(int nlev, const Dims *d, const double *h2, const void *const (*
     a.nu_pre = nu_pre;
     a.nu_post = nu_post;
     a.omega = omega;
+    a.warm = warm ? 1 : 0;
     a.pinv = pinv;
     a.ncoarse = ncoarse;
     hipLaunchKernelGGL((k_tail_cycle<T>), dim3(1), dim3(TAIL_THREADS), 0, s, a);
@@ -2919,7 +2925,7 @@ void launch_sub_mean(size_t n, double *x, const double *scal, int slot, const un
     template void launch_tail<T>(int, const Dims *, const double *, const void *const (*)[3],   \
                                  void *const *, void *const *, const void *const *,             \
                                  const unsigned *const *, Bc, int, int, double, const double *, \
-                                 int, hipStream_t);                                             \
+                                 int, bool, hipStream_t);                                       \
     template void launch_convert<T>(size_t, const double *, T *, hipStream_t);                  \
     template int launch_convert_scaled<T>(size_t, const double *, double, double, T *, double *, \
                                           int, hipStream_t);                                    \

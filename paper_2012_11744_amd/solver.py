@@ -16,6 +16,7 @@ from . import _lib as L
 
 PRECISIONS = {"fp64": L.PP_FP64, "fp32": L.PP_MIXED_FP32, "fp16": L.PP_MIXED_FP16}
 OUTERS = {"pcg": L.PP_OUTER_PCG, "dc": L.PP_OUTER_DC}
+CYCLES = {"v": L.PP_CYCLE_V, "w": L.PP_CYCLE_W, "f": L.PP_CYCLE_F}
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
@@ -78,7 +79,7 @@ class Solver:
                  precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
                  max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
                  coarse_graph: bool = False, nu_coarse: int = 4, omega: Optional[float] = None,
-                 stream: Optional[torch.cuda.Stream] = None,
+                 cycle: str = "v", stream: Optional[torch.cuda.Stream] = None,
                  sigma: Optional[torch.Tensor] = None, general: bool = False):
         lib = L.load()
         self._lib = lib
@@ -101,6 +102,7 @@ class Solver:
         o.nu_coarse = nu_coarse
         if omega is not None:       # None: the library's default
             o.omega = float(omega)
+        o.cycle = CYCLES[cycle]
         self.opts = o
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()
