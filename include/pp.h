@@ -108,6 +108,10 @@ typedef struct {
                             gas bubbles defeat the coarse grids (20 bubbles at density ratio
                             1000, 128^3: 23 -> 11 for W), at more coarse-level latency per
                             iteration; other values: PP_EINVAL */
+    int32_t coarsest;    /* the hierarchy stops halving at a level of at most this many
+                            cells, 1..1024 (default 64: 4^3 for power-of-two grids); that
+                            level is solved with an FP64 pseudo-inverse (Sec. 3.7.3, the
+                            coarsest-grid solve), held in LDS up to 64 cells */
 } pp_opts;
 
 #define PP_HIST 128
@@ -124,7 +128,7 @@ typedef struct {
 
 /* Fill *o with the defaults: mixed FP32, PCG, nu_pre = nu_post = 2,
  * max_outer = 500, warm_start = 0, fallback = 1, coarse_graph = 0, nu_coarse = 4,
- * omega = 1.2, cycle = PP_CYCLE_V. */
+ * omega = 1.2, cycle = PP_CYCLE_V, coarsest = 64. */
 void pp_opts_default(pp_opts *o);
 
 /* Face coefficients from cell densities, beta_m[c] = 2 / (rho[c - e_m] + rho[c])
@@ -135,10 +139,12 @@ void pp_opts_default(pp_opts *o);
 int pp_face_coeffs(const pp_grid *grid, const double *rho, double *beta_x, double *beta_y,
                    double *beta_z, void *hip_stream);
 
-/* Build a solver context for one set of face coefficients beta = 1/rho_f.
+/* Build a solver context for one set of face coefficients beta = 1/rho_f
+ * (the pressure operator of eq. poisson and its multigrid hierarchy, Sec. 3.7.3).
  * Grid: every n[m] >= 4; the grid is halved in all directions while all
- * n[m] are even and >= 8; the coarsest level reached must have at most 1024
- * cells (every power-of-two grid qualifies).  h > 0.  beta_x/y/z: n cells
+ * n[m] are even and >= 8 and the level has more than opts.coarsest cells; the
+ * coarsest level reached must have at most 1024 cells (every power-of-two
+ * grid qualifies).  h > 0.  beta_x/y/z: n cells
  * each, finite; every non-wall face must have beta > 0 (a connected domain).
  * The context copies beta (caller may free it afterwards), builds the
  * multigrid hierarchy and the FP64 pseudo-inverse of the coarsest operator,
@@ -218,10 +224,13 @@ int pp_update_coeffs(pp_ctx *ctx, const double *beta_x, const double *beta_y,
 int pp_divergence(pp_ctx *ctx, const double *u_x, const double *u_y, const double *u_z,
                   double scale, double *out);
 
-/* out = A x, the FP64 pressure operator (x, out: n cells; must not alias). */
+/* out = A x, the FP64 pressure operator of eq. poisson, D(beta G x) (x, out: n
+ * cells; must not alias). */
 int pp_apply(pp_ctx *ctx, const double *x, double *out);
 
-/* Solve A p = rhs - mean(rhs) to ||b - A p||_2 <= tol ||b||_2 (b = rhs -
+/* The pressure solve of eq. poisson (Sec. 3.7: multigrid, Sec. 3.7.3, as the
+ * preconditioner of conjugate gradients or of defect correction).
+ * Solve A p = rhs - mean(rhs) to ||b - A p||_2 <= tol ||b||_2 (b = rhs -
  * mean(rhs)) and return the mean-zero p.  rhs, p: n cells; p is read as the
  * initial guess when opts.warm_start is set, and written.  tol in (0, 1).
  * stats may be NULL.  Returns PP_OK, PP_ENOCONV (p = best iterate, stats
@@ -257,7 +266,9 @@ int pp_step(pp_ctx *ctx, const double *rho, const double *us_x, const double *us
             const double *us_z, double dt, double tol, double *rhs, double *p, double *u_x,
             double *u_y, double *u_z, pp_stats *stats);
 
-/* Adjoint of p = pp_solve(rhs) for a loss L with dL/dp = g_p: solves
+/* Adjoint of the pressure solve of eq. poisson, derived from A's symmetry
+ * (the paper gives no adjoint): for p = pp_solve(rhs) and a loss L with
+ * dL/dp = g_p, solves
  * A lambda = g_p - mean(g_p) with the same hierarchy (A is symmetric) and
  * writes g_rhs = lambda (mean zero) and, on every non-wall face,
  * g_beta_m[c] = (lambda[c] - lambda[c - e_m]) (p[c] - p[c - e_m]) / h^2

@@ -54,7 +54,7 @@ class Opts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("fallback", ctypes.c_int32), ("coarse_graph", ctypes.c_int32),
                 ("nu_coarse", ctypes.c_int32), ("omega", ctypes.c_double),
-                ("cycle", ctypes.c_int32)]
+                ("cycle", ctypes.c_int32), ("coarsest", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

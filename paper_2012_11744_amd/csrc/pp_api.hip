@@ -207,7 +207,7 @@ int dev_alloc_t(pp_ctx *c, P **p, size_t bytes)
 Dims to_dims(const pp_grid *g) { return Dims{g->n[0], g->n[1], g->n[2]}; }
 Bc to_bc(const pp_grid *g) { return Bc{g->bc[0] == PP_WALL, g->bc[1] == PP_WALL, g->bc[2] == PP_WALL}; }
 
-int validate_grid(const pp_grid *g, int *nlev_out, Dims *ld, double *lh)
+int validate_grid(const pp_grid *g, int *nlev_out, Dims *ld, double *lh, int coarsest = 64)
 {
     if (!g)
         return fail(PP_EINVAL, "grid is NULL");
@@ -231,7 +231,7 @@ int validate_grid(const pp_grid *g, int *nlev_out, Dims *ld, double *lh)
         ld[0] = d;
         lh[0] = h;
         while (d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.nx >= 8 && d.ny >= 8 &&
-               d.nz >= 8 && l + 1 < MAXLEV) {
+               d.nz >= 8 && cells(d) > (size_t)coarsest && l + 1 < MAXLEV) {
             d = Dims{d.nx / 2, d.ny / 2, d.nz / 2};
             h *= 2.0;
             ++l;
@@ -272,6 +272,8 @@ int validate_opts(const pp_opts *o)
         return fail(PP_EINVAL, "opts.omega must be in (0, 2)");
     if (o->cycle != PP_CYCLE_V && o->cycle != PP_CYCLE_W && o->cycle != PP_CYCLE_F)
         return fail(PP_EINVAL, "opts.cycle must be PP_CYCLE_V, PP_CYCLE_W or PP_CYCLE_F");
+    if (o->coarsest < 1 || o->coarsest > COARSEST_MAX)
+        return fail(PP_EINVAL, "opts.coarsest must be in 1..1024");
     return PP_OK;
 }
 
@@ -1507,6 +1509,7 @@ void pp_opts_default(pp_opts *o)
     // iterations where plain Gauss-Seidel (1.0) takes 8; 1.2 sits mid-plateau
     o->omega = 1.2;
     o->cycle = PP_CYCLE_V;
+    o->coarsest = 64;
 }
 
 const char *pp_strerror(int status)
@@ -1583,15 +1586,15 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
     int nlev = 0;
     Dims ld[MAXLEV];
     double lh[MAXLEV];
-    PP_TRY(validate_grid(grid, &nlev, ld, lh));
-    if (!bx || !by || !bz)
-        return fail(PP_EINVAL, "pp_setup: NULL beta array");
     pp_opts o;
     if (opts)
         o = *opts;
     else
         pp_opts_default(&o);
     PP_TRY(validate_opts(&o));
+    PP_TRY(validate_grid(grid, &nlev, ld, lh, o.coarsest));
+    if (!bx || !by || !bz)
+        return fail(PP_EINVAL, "pp_setup: NULL beta array");
 
     pp_ctx *c = new pp_ctx();
     c->grid = *grid;

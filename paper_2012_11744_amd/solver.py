@@ -79,7 +79,7 @@ class Solver:
                  precision: str = "fp32", outer: str = "pcg", nu_pre: int = 2, nu_post: int = 2,
                  max_outer: int = 500, warm_start: bool = False, fallback: bool = True,
                  coarse_graph: bool = False, nu_coarse: int = 4, omega: Optional[float] = None,
-                 cycle: str = "v", stream: Optional[torch.cuda.Stream] = None,
+                 cycle: str = "v", coarsest: int = 64, stream: Optional[torch.cuda.Stream] = None,
                  sigma: Optional[torch.Tensor] = None, general: bool = False):
         lib = L.load()
         self._lib = lib
@@ -103,6 +103,7 @@ class Solver:
         if omega is not None:       # None: the library's default
             o.omega = float(omega)
         o.cycle = CYCLES[cycle]
+        o.coarsest = coarsest
         self.opts = o
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()

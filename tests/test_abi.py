@@ -53,8 +53,8 @@ def test_opts_default(lib):
     o = L.Opts()
     lib.pp_opts_default(ctypes.byref(o))
     assert (o.precision, o.outer, o.nu_pre, o.nu_post, o.max_outer, o.warm_start, o.fallback,
-            o.coarse_graph, o.nu_coarse, o.omega, o.cycle) == (L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2,
-                                                               500, 0, 1, 0, 4, 1.2, L.PP_CYCLE_V)
+            o.coarse_graph, o.nu_coarse, o.omega, o.cycle, o.coarsest) == (
+                L.PP_MIXED_FP32, L.PP_OUTER_PCG, 2, 2, 500, 0, 1, 0, 4, 1.2, L.PP_CYCLE_V, 64)
 
 
 def _grid(n=(8, 8, 8), h=0.125, bc=(0, 0, 0)):
@@ -98,7 +98,8 @@ def test_setup_rejects_null_and_bad_options(lib):
     for field, bad in (("precision", 7), ("outer", 3), ("nu_pre", 0), ("nu_post", 17),
                        ("max_outer", 0), ("warm_start", 2), ("coarse_graph", 5),
                        ("nu_coarse", 0), ("nu_coarse", 17), ("omega", 0.0), ("omega", 2.0),
-                       ("omega", float("nan")), ("cycle", 3), ("cycle", -1)):
+                       ("omega", float("nan")), ("cycle", 3), ("cycle", -1),
+                       ("coarsest", 0), ("coarsest", 1025)):
         o = L.Opts()
         lib.pp_opts_default(ctypes.byref(o))
         setattr(o, field, bad)

@@ -557,6 +557,30 @@ def test_w_cycle_layer_droplets_64(S, precision, outer, cycle):
     _parity_solve(S, w, precision, outer=outer, tol=1e-11, ptol=1e-8, cycle=cycle)
 
 
+@pytest.mark.parametrize("coarsest,dims", [(512, (8, 8, 8)), (1000, (8, 8, 8)), (200, (4, 4, 4)),
+                                            (1, (4, 4, 4))])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_coarsest_level_size(S, precision, coarsest, dims):
+    """opts.coarsest stops the halving at a level of at most that many cells:
+    on 64^3 a limit of 512 keeps 8^3 as the coarsest level (a 512 x 512
+    pseudo-inverse read from global memory by the tail), 64 or less ends at
+    4^3.  Parity with the oracle either way."""
+    _say(f"coarsest={coarsest} config3 64^3 {precision}")
+    w = W.config3(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    p_o = _oracle_p(w, beta, rhs, 1e-13)
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision=precision,
+                  coarsest=coarsest) as sol:
+        nl = sol.levels
+        assert sol.level_dims(nl - 1) == dims
+        p = sol.solve(dev(rhs), tol=1e-11)
+        it = sol.last_stats["outer_iters"]
+        p_h = host(p)
+    _say(f"  levels={nl} iters={it} err_p={relmax(p_h, p_o):.2e}")
+    assert relmax(p_h, p_o) <= 1e-8
+
+
 @pytest.mark.parametrize("cycle", ["w", "f"])
 @pytest.mark.parametrize("n,bc", RAGGED)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
