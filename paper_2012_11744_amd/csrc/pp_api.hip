@@ -1129,10 +1129,10 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
                   bool gauge_x = false, const Tail *tail = nullptr, const Tail *pre = nullptr)
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
-    const int np = launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs,
-                                   c->scal, x, zero_x, c->sig_on ? c->sig[0] : nullptr,
-                                   c->gen ? c->act : nullptr, c->r64, ih2, c->part, c->pstride,
-                                   c->stream);
+    const int np = launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                                   op_rho(c), rhs, c->scal, x, zero_x,
+                                   c->sig_on ? c->sig[0] : nullptr, c->gen ? c->act : nullptr,
+                                   c->r64, ih2, c->part, c->pstride, c->stream);
     launch_finalize(c->part, c->pstride, np, OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
     PP_TRY(check_launch("residual"));
     if (gauge_x)

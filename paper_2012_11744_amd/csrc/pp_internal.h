@@ -263,9 +263,9 @@ void launch_finalize(const double *part, size_t pstride, int nparts, int op, int
                      double *host = nullptr, double ticket = 0.0);
 // returns the number of partial sums written (at most grid_blocks(red_grid(d)))
 int launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
-                    const double *b, const double *scal, double *x, bool zero_x, const double *sg,
-                    const unsigned char *act, double *r64, double ih2, double *part,
-                    size_t pstride, hipStream_t s);
+                    const double *rho, const double *b, const double *scal, double *x, bool zero_x,
+                    const double *sg, const unsigned char *act, double *r64, double ih2,
+                    double *part, size_t pstride, hipStream_t s);
 template <typename T>
 void launch_residual_T(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                        const double *b, const double *scal, const double *x, const double *sg,
