@@ -116,6 +116,9 @@ struct pp_ctx {
     Dims ld[MAXLEV];
     double lh[MAXLEV];
     double *chain[MAXLEV][3];   // FP64 face coefficients per level; chain[0] = the fine copy
+    // chain[0] not written by the last density load (the mixed modes' solve
+    // forms the fine coefficients from rho); ensure_b64 forms it on demand
+    bool b64_stale = false;
     // prolongation weights (one packed word per cell) of every level but the
     // coarsest, formed from the chain: shared by both hierarchies
     unsigned *pw[MAXLEV];
@@ -725,6 +728,7 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho, b
 {
     c->rho_ok = false;
     c->check_pending = false;
+    c->b64_stale = false;
     if (rho && !c->rho)
         PP_TRY(dev_alloc_t(c, &c->rho, sizeof(double) * c->N));
     int first_coarse = 0;   // first level whose coefficients are still to be coarsened from
@@ -734,11 +738,17 @@ int load_coeffs_impl(pp_ctx *c, const double *const src[3], const double *rho, b
     bool rho_checked = false;
     if (c->nlev > 1 && !(align & 15)) {
         // one pass: copy (or beta from rho), walls, validity, storage copy of
-        // level 0, level 1
+        // level 0, level 1.  From densities in a mixed mode the FP64 fine
+        // coefficients are left unwritten: the outer kernels form them from
+        // the copy of rho, and ensure_b64 writes them for anything else.
+        const Hier &H = c->hmix;
+        const bool skip64 = rho && H.present && (H.st == ST_F32 || H.st == ST_F16);
         double *dst[3] = {c->chain[0][0], c->chain[0][1], c->chain[0][2]};
+        if (skip64)
+            dst[0] = dst[1] = dst[2] = nullptr;
+        c->b64_stale = skip64;
         double *crs[3] = {c->chain[1][0], c->chain[1][1], c->chain[1][2]};
         int np = 0;
-        const Hier &H = c->hmix;
         auto one_pass = [&](auto *t) {
             using TT = std::remove_pointer_t<decltype(t)>;
             TT *tt[3] = {t, t ? (TT *)H.lev[0].b[1] : nullptr, t ? (TT *)H.lev[0].b[2] : nullptr};
@@ -1113,6 +1123,20 @@ int check_progress(SolveState &S, int since_best_limit, int &since, double &best
 // operator kernels then read the coefficient arrays
 const double *op_rho(const pp_ctx *c) { return (c->rho_ok && !c->gen) ? c->rho : nullptr; }
 
+// the FP64 fine-level coefficients for a reader that takes them from chain[0]
+// (pp_apply, defect correction, the FP64 fallback, and the outer kernels
+// before a density load is confirmed): formed from the context's copy of rho
+// by the expression the density load uses, so with the same bits
+int ensure_b64(pp_ctx *c)
+{
+    if (!c->b64_stale)
+        return PP_OK;
+    launch_face_coeffs(c->d, c->bc, c->rho, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                       c->stream);
+    c->b64_stale = false;
+    return check_launch("fine-level coefficients from rho");
+}
+
 int gauge(pp_ctx *c, double *x, int xsum_parts = 0);
 
 // work a caller queues behind a solve's result (the projection of pp_step)
@@ -1129,6 +1153,8 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
                   bool gauge_x = false, const Tail *tail = nullptr, const Tail *pre = nullptr)
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
+    if (!zero_x && !residual_from_rho(c->d, op_rho(c), rhs, x, c->r64))
+        PP_TRY(ensure_b64(c));
     const int np = launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
                                    op_rho(c), rhs, c->scal, x, zero_x,
                                    c->sig_on ? c->sig[0] : nullptr, c->gen ? c->act : nullptr,
@@ -1211,6 +1237,8 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
             // passes of odd iterations hold theirs, those of even ones apply
             // the last two
             const int mode = first ? DIR_FIRST : ((launched & 1) ? DIR_HOLD : DIR_TWO);
+            if (!op_rho(c))
+                PP_TRY(ensure_b64(c));
             npd = launch_dir_apply<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
                                       op_rho(c), (const T *)v0.cur, dold, dnew, c->q64, x,
                                       c->sig_on ? c->sig[0] : nullptr, c->scal, mode, ih2, c->part,
@@ -1311,6 +1339,7 @@ int dc_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, SolveS
         if (S.st)
             S.st->vcycles++;
         launch_axpy_T<T>(c->N, (const T *)v0.cur, x, c->scal, s);
+        PP_TRY(ensure_b64(c));
         {
             KT t(c, PP_KT_OUTER_APPLY, true);
             launch_residual_T<T>(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], rhs,
@@ -1446,6 +1475,7 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
             }
             if (rc == STAGNATED) {
                 if (H != &c->h64 && c->opts.fallback && c->h64.present) {
+                    PP_TRY(ensure_b64(c));     // the FP64 hierarchy's fine level
                     H = &c->h64;
                     if (st)
                         st->fell_back = 1;
@@ -1873,6 +1903,7 @@ int pp_apply(pp_ctx *c, const double *x, double *y)
         return fail(PP_EINVAL, "pp_apply: NULL array");
     if (x == y)
         return fail(PP_EINVAL, "pp_apply: x and out must not alias");
+    PP_TRY(ensure_b64(c));
     launch_apply(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], x,
                  c->sig_on ? c->sig[0] : nullptr, y, 1.0 / (c->grid.h * c->grid.h), c->stream);
     return check_launch("pp_apply");
@@ -1900,6 +1931,8 @@ int pp_project(pp_ctx *c, const double *usx, const double *usy, const double *us
         return fail(PP_EINVAL, "pp_project: p must not alias the output");
     if (!std::isfinite(dt))
         return fail(PP_EINVAL, "pp_project: dt must be finite");
+    if (!op_rho(c))
+        PP_TRY(ensure_b64(c));
     launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], op_rho(c), usx, usy,
                    usz, p, dt / c->grid.h, ux, uy, uz, c->stream);
     return check_launch("pp_project");
@@ -1942,6 +1975,8 @@ int pp_step(pp_ctx *c, const double *rho, const double *usx, const double *usy,
                     c->stream);
     PP_TRY(check_launch("pp_step divergence"));
     const Tail project = [&]() {
+        if (!op_rho(c))
+            PP_TRY(ensure_b64(c));
         launch_project(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2], op_rho(c), usx,
                        usy, usz, p, dt / c->grid.h, ux, uy, uz, c->stream);
         return check_launch("pp_step projection");

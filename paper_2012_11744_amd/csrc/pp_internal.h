@@ -262,6 +262,15 @@ void launch_finalize(const double *part, size_t pstride, int nparts, int op, int
                      double ncells, int first, double *scal, hipStream_t s,
                      double *host = nullptr, double ticket = 0.0);
 // returns the number of partial sums written (at most grid_blocks(red_grid(d)))
+// whether launch_residual (x given) forms the link coefficients from rho
+// rather than reading bx, by, bz: the 2 x 2 kernel on even grids with 16-byte
+// aligned arrays
+inline bool residual_from_rho(Dims d, const double *rho, const double *b, const double *x,
+                              const double *r64)
+{
+    return rho && d.nx % 2 == 0 && d.ny % 2 == 0 &&
+           (((uintptr_t)x | (uintptr_t)b | (uintptr_t)r64 | (uintptr_t)rho) & 15) == 0;
+}
 int launch_residual(Dims d, Bc bc, const double *bx, const double *by, const double *bz,
                     const double *rho, const double *b, const double *scal, double *x, bool zero_x,
                     const double *sg, const unsigned char *act, double *r64, double ih2,

@@ -1198,6 +1198,8 @@ __global__ __launch_bounds__(BLOCK) void k_load_coeffs(Dims fd, Bc bc, const dou
 // the bits are the same): each coarse cell's 8 children read rho at the
 // children and at their low x, y, z neighbours, and copy it to rcopy, which
 // the outer operator kernels read in place of the three coefficient arrays.
+// dx == nullptr: the FP64 fine-level coefficients are not written (the
+// caller forms them from rcopy when something needs them).
 // Partial: non-wall faces whose beta is not a finite positive number plus
 // cells whose rho is not.
 template <typename T, bool WT>
@@ -1270,9 +1272,11 @@ __global__ __launch_bounds__(BLOCK) void k_load_density(Dims fd, Bc bc, const do
                         v[0] += 1.0;
                     if (!(rc.y > 0.0 && rc.y < INFINITY))
                         v[0] += 1.0;
-                    *reinterpret_cast<D2 *>(dx + c) = bxv;
-                    *reinterpret_cast<D2 *>(dy + c) = byv;
-                    *reinterpret_cast<D2 *>(dz + c) = bzv;
+                    if (dx) {
+                        *reinterpret_cast<D2 *>(dx + c) = bxv;
+                        *reinterpret_cast<D2 *>(dy + c) = byv;
+                        *reinterpret_cast<D2 *>(dz + c) = bzv;
+                    }
                     *reinterpret_cast<D2 *>(rcopy + c) = rc;
                     if (WT) {
                         *reinterpret_cast<T2 *>(tx + c) = T2{static_cast<T>(bxv.x), static_cast<T>(bxv.y)};
@@ -2845,7 +2849,7 @@ int launch_residual(Dims d, Bc bc, const double *bx, const double *by, const dou
                       (((uintptr_t)x | (uintptr_t)b | (uintptr_t)r64) & 15) == 0;
     if (quad) {
         const dim3 g((d.nx / 2 + BX - 1) / BX, (d.ny / 2 + BY - 1) / BY, (d.nz + RZ - 1) / RZ);
-        if (rho && !((uintptr_t)rho & 15))
+        if (residual_from_rho(d, rho, b, x, r64))
             hipLaunchKernelGGL(k_residual2<true>, g, kBlock, 0, s, d, bc, bx, by, bz, rho, b, scal,
                                x, sg, act, r64, ih2, part, pstride);
         else
