@@ -511,6 +511,34 @@ def test_unaligned_iterate_one_cell_direction_pass(S, precision, load):
     assert abs(it_u - it_a) <= 1
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_density_load_then_fp64_coefficient_readers(S, precision):
+    """After a density load in a mixed mode the FP64 fine-level coefficients
+    are formed from rho only when something reads them: pp_apply gives the
+    same bits as a context loaded with the coefficients themselves, and
+    defect correction (whose residual reads them every iteration) and a
+    second PCG solve reach parity with the oracle."""
+    _say(f"density load then FP64 readers, config3 64^3 {precision}")
+    w = W.config3(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    p_o = _oracle_p(w, beta, rhs, 1e-13)
+    x = dev(np.random.default_rng(5).standard_normal(w.shape))
+    with S.Solver([dev(b) for b in beta], w.h, w.bc, precision=precision) as ref:
+        y_ref = host(ref.apply(x)).copy()
+    flat = [dev(np.ones(w.shape)) for _ in range(3)]
+    for outer in ("dc", "pcg"):
+        with S.Solver(flat, w.h, w.bc, precision=precision, outer=outer) as sol:
+            sol.update_density(dev(w.rho))
+            p = sol.solve(dev(rhs), tol=1e-11)
+            it = sol.last_stats["outer_iters"]
+            p_h = host(p)
+            if outer == "dc":
+                assert np.array_equal(host(sol.apply(x)), y_ref)
+        _say(f"  {outer}: iters={it} err_p={relmax(p_h, p_o):.2e}")
+        assert relmax(p_h, p_o) <= 1e-8
+
+
 @pytest.mark.parametrize("outer", ["pcg", "dc"])
 def test_config3_layer_droplets_64(S, outer):
     _say(f"config3 geometry at 64^3, fp32, {outer}")
