@@ -585,6 +585,34 @@ def test_w_cycle_layer_droplets_64(S, precision, outer, cycle):
     _parity_solve(S, w, precision, outer=outer, tol=1e-11, ptol=1e-8, cycle=cycle)
 
 
+@pytest.mark.parametrize("cycle", ["w", "f"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cycles_from_the_coarse_graph(S, precision, cycle):
+    """W- and F-cycles with the coarse levels replayed from a HIP graph (the
+    whole recursion below the fine level, warm-started tails included, is
+    captured once): the same iterations and the same bits as the eager
+    launches, on three solves in a row, and parity with the oracle."""
+    _say(f"{cycle.upper()}-cycle coarse graph config3 64^3 {precision}")
+    w = W.config3(64)
+    beta = oracle.face_coeffs(w.rho, w.bc)
+    rhs = oracle.divergence(w.us, w.bc, w.h, 1.0 / w.dt)
+    p_o = _oracle_p(w, beta, rhs, 1e-13)
+    out = {}
+    for graph in (False, True):
+        with S.Solver([dev(b) for b in beta], w.h, w.bc, precision=precision, cycle=cycle,
+                      coarse_graph=graph) as sol:
+            runs = []
+            for _ in range(3):
+                p = sol.solve(dev(rhs), tol=1e-11)
+                runs.append((sol.last_stats["outer_iters"], host(p).copy()))
+        out[graph] = runs
+    for (ie, pe), (ig, pg) in zip(out[False], out[True]):
+        assert ie == ig
+        assert np.array_equal(pe, pg)
+    _say(f"  iters={out[True][0][0]} err_p={relmax(out[True][0][1], p_o):.2e}")
+    assert relmax(out[True][-1][1], p_o) <= 1e-8
+
+
 @pytest.mark.parametrize("coarsest,dims", [(512, (8, 8, 8)), (1000, (8, 8, 8)), (200, (4, 4, 4)),
                                             (1, (4, 4, 4))])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
