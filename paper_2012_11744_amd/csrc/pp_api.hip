@@ -156,6 +156,9 @@ struct pp_ctx {
     double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
     hipStream_t copy_stream;     // its upload, beside the stream's work ...
     hipEvent_t pinv_ev;          // ... done
+    hipStream_t aux_stream;      // pp_step's divergence, beside the coefficient load:
+    hipEvent_t aux_start;        // the stream's earlier work done (u* written) ...
+    hipEvent_t aux_done;         // ... and the divergence with its sum done
     bool pinv_wait;              // the next V-cycle waits for the upload before its coarse levels
     bool pinv_dirty;             // the coefficients changed since pinv was built: the next
                                  // V-cycle's caller builds it first (from hcoarse)
@@ -1600,6 +1603,12 @@ void pp_destroy(pp_ctx *c)
         (void)hipEventDestroy(c->pinv_ev);
     if (c->copy_stream)
         (void)hipStreamDestroy(c->copy_stream);
+    if (c->aux_start)
+        (void)hipEventDestroy(c->aux_start);
+    if (c->aux_done)
+        (void)hipEventDestroy(c->aux_done);
+    if (c->aux_stream)
+        (void)hipStreamDestroy(c->aux_stream);
     delete c;
 }
 
@@ -1731,6 +1740,16 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
     if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
         c->copy_stream = nullptr;
         return bail(fail(PP_EHIP, "hipStreamCreateWithFlags failed"));
+    }
+    if (hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->aux_stream = nullptr;
+        return bail(fail(PP_EHIP, "hipStreamCreateWithFlags failed"));
+    }
+    for (hipEvent_t *ev : {&c->aux_start, &c->aux_done}) {
+        if (hipEventCreateWithFlags(ev, hipEventDisableTiming) != hipSuccess) {
+            *ev = nullptr;
+            return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
+        }
     }
     if (hipMemsetAsync(c->scal, 0, sizeof(double) * S_NSLOTS, c->stream) != hipSuccess)
         return bail(fail(PP_EHIP, "hipMemsetAsync failed"));
@@ -1963,17 +1982,28 @@ int pp_step(pp_ctx *c, const double *rho, const double *usx, const double *usy,
                 return fail(PP_EINVAL, "pp_step: an output aliases an input (only u_m may "
                                        "alias us_m)");
     }
+    // The divergence needs only u*: it runs on a side stream beside the
+    // coefficient load (both stream memory below the HBM rate, and the load's
+    // coarse levels are short latency-bound launches), with its partial sums
+    // in a row of their own and its mean in a scalar slot the load does not
+    // write.  It also sums what it writes, as the solve's pass over the
+    // right-hand side would (same blocks, same order, same bits).
+    PP_HIP(hipEventRecord(c->aux_start, c->stream));
+    PP_HIP(hipStreamWaitEvent(c->aux_stream, c->aux_start, 0));
+    double *dpart = c->part + c->pstride;
+    const int np = launch_divergence_sum(c->d, c->bc, usx, usy, usz, (1.0 / dt) / c->grid.h, rhs,
+                                         dpart, c->aux_stream);
+    launch_finalize(dpart, c->pstride, np, OP_MEAN, S_MEAN, (double)c->N, 0, c->scal,
+                    c->aux_stream);
+    PP_HIP(hipEventRecord(c->aux_done, c->aux_stream));
+    PP_TRY(check_launch("pp_step divergence"));
     // the coefficient load leaves its validity counts to the solve's first
     // wait, so the step waits on the host for the solve's results only
     const double *src[3] = {nullptr, nullptr, nullptr};
-    PP_TRY(load_coeffs_impl(c, src, rho, true));
-    // the divergence also sums what it writes, as the solve's pass over the
-    // right-hand side would (same blocks, same order, same bits)
-    const int np = launch_divergence_sum(c->d, c->bc, usx, usy, usz, (1.0 / dt) / c->grid.h, rhs,
-                                         c->part, c->stream);
-    launch_finalize(c->part, c->pstride, np, OP_MEAN, S_MEAN, (double)c->N, 0, c->scal,
-                    c->stream);
-    PP_TRY(check_launch("pp_step divergence"));
+    const int lrc = load_coeffs_impl(c, src, rho, true);
+    // the solve (and any later work on the stream) follows the divergence
+    PP_HIP(hipStreamWaitEvent(c->stream, c->aux_done, 0));
+    PP_TRY(lrc);
     const Tail project = [&]() {
         if (!op_rho(c))
             PP_TRY(ensure_b64(c));
