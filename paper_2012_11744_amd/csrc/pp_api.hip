@@ -165,6 +165,8 @@ struct pp_ctx {
     bool check_pending;          // a density load's validity counts still to be read back
                                  // (by the next solve's first wait): pp_step
     bool scale_queued;           // the first V-cycle's scaled right-hand side is already queued
+    bool init_queued;            // pp_step queued the cold start's initial residual (rows 3..5
+    bool init_scaled;            // of part) and, for PCG, its scaling, on aux_stream
     bool check_rho_count;        // ... including the separate density count (S_SBAD)
     double *r64, *d64, *d64b, *q64;
     double *part;
@@ -1016,26 +1018,31 @@ void cycle_from(pp_ctx *c, Hier &H, int from, hipStream_t s)
 // Levels 1 .. L-1 are short kernels whose cost is launch latency; they are
 // replayed from a HIP graph captured at setup when one is available.
 template <typename T>
-void vcycle_run(pp_ctx *c, Hier &H)
+int vcycle_run(pp_ctx *c, Hier &H)
 {
     hipStream_t s = c->stream;
-    // a pseudo-inverse upload still on its way: the coarse levels wait for it
-    auto await_pinv = [c, s]() {
+    // a pseudo-inverse still to be built (pp_step leaves it to the first
+    // V-cycle, whose fine-level pass the GPU works on meanwhile) or an upload
+    // still on its way: the coarse levels wait for it
+    auto await_pinv = [c, s]() -> int {
+        PP_TRY(ensure_pinv(c));
         if (c->pinv_wait) {
             (void)hipStreamWaitEvent(s, c->pinv_ev, 0);
             c->pinv_wait = false;
         }
+        return PP_OK;
     };
     if (H.tail == 0) {
-        await_pinv();
+        PP_TRY(await_pinv());
         cycle_from<T>(c, H, 0, s);
-        return;
+        return PP_OK;
     }
     level_down<T>(c, H, 0, s);
-    await_pinv();
+    PP_TRY(await_pinv());
     if (!H.coarse_exec || hipGraphLaunch(H.coarse_exec, s) != hipSuccess)
         cycle_from<T>(c, H, 1, s);    // no graph, or it could not be launched: run eagerly
     level_up<T>(c, H, 0, s);
+    return PP_OK;
 }
 
 // Record levels 1 .. L-1 of the cycle into a graph on a private stream.  The
@@ -1156,25 +1163,37 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
                   bool gauge_x = false, const Tail *tail = nullptr, const Tail *pre = nullptr)
 {
     const double ih2 = 1.0 / (c->grid.h * c->grid.h);
-    if (!zero_x && !residual_from_rho(c->d, op_rho(c), rhs, x, c->r64))
-        PP_TRY(ensure_b64(c));
-    const int np = launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
-                                   op_rho(c), rhs, c->scal, x, zero_x,
-                                   c->sig_on ? c->sig[0] : nullptr, c->gen ? c->act : nullptr,
-                                   c->r64, ih2, c->part, c->pstride, c->stream);
-    launch_finalize(c->part, c->pstride, np, OP_INIT, 0, (double)c->N, 0, c->scal, c->stream);
-    PP_TRY(check_launch("residual"));
+    // a cold start's residual that pp_step queued already (b - mean b)
+    const bool init_queued = zero_x && c->init_queued;
+    c->init_queued = false;
+    int np = 0;
+    if (!init_queued) {
+        if (!zero_x && !residual_from_rho(c->d, op_rho(c), rhs, x, c->r64))
+            PP_TRY(ensure_b64(c));
+        np = launch_residual(c->d, c->bc, c->chain[0][0], c->chain[0][1], c->chain[0][2],
+                             op_rho(c), rhs, c->scal, x, zero_x, c->sig_on ? c->sig[0] : nullptr,
+                             c->gen ? c->act : nullptr, c->r64, ih2, c->part, c->pstride,
+                             c->stream);
+        launch_finalize(c->part, c->pstride, np, OP_INIT, 0, (double)c->N, 0, c->scal,
+                        c->stream);
+        PP_TRY(check_launch("residual"));
+    }
     if (gauge_x)
         PP_TRY(gauge(c, x, zero_x ? 0 : np));   // the residual kernel summed x too
     PP_TRY(post_scal(c));
     if (gauge_x && tail)
         PP_TRY((*tail)());
-    if (pre)
+    if (init_queued && c->init_scaled)
+        c->scale_queued = true;      // queued with the residual
+    else if (pre)
         PP_TRY((*pre)());
+    c->init_scaled = false;
     // a pseudo-inverse still to be built is built here, on the host, while
     // the GPU works through the residual and whatever was queued before it;
-    // its upload follows the read-back in the queue, unwaited
-    const int prc = ensure_pinv(c);
+    // its upload follows the read-back in the queue, unwaited.  After pp_step
+    // queued the residual early, the GPU has little left before it: the first
+    // V-cycle builds it instead, behind its first fine-level pass.
+    const int prc = init_queued ? PP_OK : ensure_pinv(c);
     PP_TRY(wait_scal(c));
     if (c->check_pending) {
         // a deferred density check: its rejection takes precedence over a
@@ -1222,8 +1241,9 @@ int pcg_loop(pp_ctx *c, Hier &H, double *x, double tol, SolveState &S)
         // can form it, else from its own kernel
         c->dot_on = true;
         c->dot_np = 0;
-        vcycle_run<T>(c, H);
+        const int vrc = vcycle_run<T>(c, H);
         c->dot_on = false;
+        PP_TRY(vrc);
         if (S.st)
             S.st->vcycles++;
         int nrz = c->dot_np, op = OP_RZ_T;
@@ -1338,7 +1358,7 @@ int dc_loop(pp_ctx *c, Hier &H, const double *rhs, double *x, double tol, SolveS
     for (;;) {
         if (S.it >= c->opts.max_outer)
             return fail(PP_ENOCONV, "no convergence within max_outer iterations");
-        vcycle_run<T>(c, H);
+        PP_TRY(vcycle_run<T>(c, H));
         if (S.st)
             S.st->vcycles++;
         launch_axpy_T<T>(c->N, (const T *)v0.cur, x, c->scal, s);
@@ -1406,6 +1426,20 @@ int gauge(pp_ctx *c, double *x, int xsum_parts)
 // whether it was queued behind the final iterate (else the caller queues it)
 // mean_ready: scal[S_MEAN] already holds the mean of rhs (pp_step's
 // divergence formed it)
+// the hierarchy a solve starts with, and the outer loop's first step on it:
+// the residual divided by its RMS into level 0's right-hand side
+Hier *first_hier(pp_ctx *c) { return (c->opts.precision == PP_FP64) ? &c->h64 : &c->hmix; }
+
+void queue_scale_T(pp_ctx *c, Hier &H0, hipStream_t s)
+{
+    void *rT = H0.lev[0].r;
+    switch (H0.st) {
+    case ST_F64: launch_scale_T<double>(c->N, c->r64, (double *)rT, c->scal, s); break;
+    case ST_F32: launch_scale_T<float>(c->N, c->r64, (float *)rT, c->scal, s); break;
+    default: launch_scale_T<_Float16>(c->N, c->r64, (_Float16 *)rT, c->scal, s); break;
+    }
+}
+
 int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st, bool warm,
                const Tail *tail = nullptr, bool *tail_queued = nullptr, bool mean_ready = false)
 {
@@ -1434,15 +1468,10 @@ int solve_impl(pp_ctx *c, const double *rhs, double *x, double tol, pp_stats *st
     // queued before the host waits for the initial residual, so the GPU has it
     // to work on meanwhile (if that residual is already small enough, nothing
     // reads it)
-    Hier *H0 = (c->opts.precision == PP_FP64) ? &c->h64 : &c->hmix;
+    Hier *H0 = first_hier(c);
     c->scale_queued = false;
     const Tail pre = [c, H0]() -> int {
-        void *rT = H0->lev[0].r;
-        switch (H0->st) {
-        case ST_F64: launch_scale_T<double>(c->N, c->r64, (double *)rT, c->scal, c->stream); break;
-        case ST_F32: launch_scale_T<float>(c->N, c->r64, (float *)rT, c->scal, c->stream); break;
-        default: launch_scale_T<_Float16>(c->N, c->r64, (_Float16 *)rT, c->scal, c->stream); break;
-        }
+        queue_scale_T(c, *H0, c->stream);
         c->scale_queued = true;
         return check_launch("scale");
     };
@@ -1689,7 +1718,7 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
         rc = dev_alloc_t(c, &c->q64, sizeof(double) * c->N);
     c->pstride = grid_blocks(red_grid(c->d));
     if (rc == PP_OK)
-        rc = dev_alloc_t(c, &c->part, sizeof(double) * 3 * c->pstride);
+        rc = dev_alloc_t(c, &c->part, sizeof(double) * 6 * c->pstride);   // rows 3..5: pp_step's side stream
     if (rc == PP_OK)
         rc = dev_alloc_t(c, &c->scal, sizeof(double) * S_NSLOTS);
     if (rc != PP_OK)
@@ -1988,21 +2017,41 @@ int pp_step(pp_ctx *c, const double *rho, const double *usx, const double *usy,
     // in a row of their own and its mean in a scalar slot the load does not
     // write.  It also sums what it writes, as the solve's pass over the
     // right-hand side would (same blocks, same order, same bits).
+    // A cold start's initial residual, b - mean b with p = 0, needs no
+    // coefficients either: it follows on the side stream, with (for PCG) the
+    // outer loop's first step, and the solve takes them from there.
     PP_HIP(hipEventRecord(c->aux_start, c->stream));
     PP_HIP(hipStreamWaitEvent(c->aux_stream, c->aux_start, 0));
-    double *dpart = c->part + c->pstride;
+    double *apart = c->part + 3 * c->pstride;
     const int np = launch_divergence_sum(c->d, c->bc, usx, usy, usz, (1.0 / dt) / c->grid.h, rhs,
-                                         dpart, c->aux_stream);
-    launch_finalize(dpart, c->pstride, np, OP_MEAN, S_MEAN, (double)c->N, 0, c->scal,
+                                         apart, c->aux_stream);
+    launch_finalize(apart, c->pstride, np, OP_MEAN, S_MEAN, (double)c->N, 0, c->scal,
                     c->aux_stream);
+    c->init_queued = c->init_scaled = false;
+    if (c->opts.warm_start == 0) {
+        Hier *H0 = first_hier(c);
+        const int npr = launch_residual(c->d, c->bc, nullptr, nullptr, nullptr, nullptr, rhs,
+                                        c->scal, p, true, nullptr, nullptr, c->r64,
+                                        1.0 / (c->grid.h * c->grid.h), apart, c->pstride,
+                                        c->aux_stream);
+        launch_finalize(apart, c->pstride, npr, OP_INIT, 0, (double)c->N, 0, c->scal,
+                        c->aux_stream);
+        c->init_queued = true;
+        if (c->opts.outer == PP_OUTER_PCG && H0->present) {
+            queue_scale_T(c, *H0, c->aux_stream);
+            c->init_scaled = true;
+        }
+    }
     PP_HIP(hipEventRecord(c->aux_done, c->aux_stream));
     PP_TRY(check_launch("pp_step divergence"));
     // the coefficient load leaves its validity counts to the solve's first
     // wait, so the step waits on the host for the solve's results only
     const double *src[3] = {nullptr, nullptr, nullptr};
     const int lrc = load_coeffs_impl(c, src, rho, true);
-    // the solve (and any later work on the stream) follows the divergence
+    // the solve (and any later work on the stream) follows the side stream
     PP_HIP(hipStreamWaitEvent(c->stream, c->aux_done, 0));
+    if (lrc != PP_OK)
+        c->init_queued = c->init_scaled = false;
     PP_TRY(lrc);
     const Tail project = [&]() {
         if (!op_rho(c))
@@ -2301,17 +2350,17 @@ int pp_vcycle(pp_ctx *c, const double *r, double *e)
     switch (H.st) {
     case ST_F64:
         launch_copy(r, (double *)v0.r, c->N, c->stream);
-        vcycle_run<double>(c, H);
+        PP_TRY(vcycle_run<double>(c, H));
         launch_copy((const double *)v0.cur, e, c->N, c->stream);
         break;
     case ST_F32:
         launch_convert<float>(c->N, r, (float *)v0.r, c->stream);
-        vcycle_run<float>(c, H);
+        PP_TRY(vcycle_run<float>(c, H));
         launch_to_double<float>(c->N, (const float *)v0.cur, e, c->stream);
         break;
     default:
         launch_convert<_Float16>(c->N, r, (_Float16 *)v0.r, c->stream);
-        vcycle_run<_Float16>(c, H);
+        PP_TRY(vcycle_run<_Float16>(c, H));
         launch_to_double<_Float16>(c->N, (const _Float16 *)v0.cur, e, c->stream);
         break;
     }
