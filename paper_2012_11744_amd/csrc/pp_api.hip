@@ -156,6 +156,8 @@ struct pp_ctx {
     double *hpinv;               // pinned: the pseudo-inverse on its way to pinv
     hipStream_t copy_stream;     // its upload, beside the stream's work ...
     hipEvent_t pinv_ev;          // ... done
+    hipEvent_t pinv_free;        // recorded where no V-cycle that reads pinv is still
+    bool pinv_free_set;          // queued after it: the upload need wait for nothing later
     hipStream_t aux_stream;      // pp_step's divergence, beside the coefficient load:
     hipEvent_t aux_start;        // the stream's earlier work done (u* written) ...
     hipEvent_t aux_done;         // ... and the divergence with its sum done
@@ -564,11 +566,17 @@ int build_pinv(pp_ctx *c)
             P[(size_t)idx[bb] * n + idx[a]] = v;
         }
     // The upload goes on a stream of its own, behind everything queued so far
-    // (no earlier coarsest solve can still read pinv), so the work the host
-    // queues next, up to the first coarse level, does not wait for the copy;
-    // that V-cycle waits for it before its coarse levels (pinv_wait)
-    PP_HIP(hipEventRecord(c->pinv_ev, c->stream));
-    PP_HIP(hipStreamWaitEvent(c->copy_stream, c->pinv_ev, 0));
+    // (no earlier coarsest solve can still read pinv), or only behind
+    // pinv_free where that was recorded, so the work the host queues next, up
+    // to the first coarse level, does not wait for the copy; that V-cycle
+    // waits for it before its coarse levels (pinv_wait)
+    if (c->pinv_free_set) {
+        PP_HIP(hipStreamWaitEvent(c->copy_stream, c->pinv_free, 0));
+        c->pinv_free_set = false;
+    } else {
+        PP_HIP(hipEventRecord(c->pinv_ev, c->stream));
+        PP_HIP(hipStreamWaitEvent(c->copy_stream, c->pinv_ev, 0));
+    }
     PP_HIP(hipMemcpyAsync(c->pinv, P, sizeof(double) * n * n, hipMemcpyHostToDevice,
                           c->copy_stream));
     PP_HIP(hipEventRecord(c->pinv_ev, c->copy_stream));
@@ -1193,6 +1201,12 @@ int true_residual(pp_ctx *c, const double *rhs, double *x, bool zero_x, SolveSta
     // its upload follows the read-back in the queue, unwaited.  After pp_step
     // queued the residual early, the GPU has little left before it: the first
     // V-cycle builds it instead, behind its first fine-level pass.
+    if (init_queued && c->pinv_dirty) {
+        // no V-cycle of this solve is queued yet, and every later one builds
+        // the pseudo-inverse before reading it: its upload may start from here
+        PP_HIP(hipEventRecord(c->pinv_free, c->stream));
+        c->pinv_free_set = true;
+    }
     const int prc = init_queued ? PP_OK : ensure_pinv(c);
     PP_TRY(wait_scal(c));
     if (c->check_pending) {
@@ -1638,6 +1652,8 @@ void pp_destroy(pp_ctx *c)
         (void)hipEventDestroy(c->aux_done);
     if (c->aux_stream)
         (void)hipStreamDestroy(c->aux_stream);
+    if (c->pinv_free)
+        (void)hipEventDestroy(c->pinv_free);
     delete c;
 }
 
@@ -1774,7 +1790,7 @@ int setup_impl(const pp_grid *grid, const double *bx, const double *by, const do
         c->aux_stream = nullptr;
         return bail(fail(PP_EHIP, "hipStreamCreateWithFlags failed"));
     }
-    for (hipEvent_t *ev : {&c->aux_start, &c->aux_done}) {
+    for (hipEvent_t *ev : {&c->aux_start, &c->aux_done, &c->pinv_free}) {
         if (hipEventCreateWithFlags(ev, hipEventDisableTiming) != hipSuccess) {
             *ev = nullptr;
             return bail(fail(PP_EHIP, "hipEventCreateWithFlags failed"));
