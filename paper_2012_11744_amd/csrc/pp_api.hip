@@ -158,9 +158,9 @@ struct pp_ctx {
     hipEvent_t pinv_ev;          // ... done
     hipEvent_t pinv_free;        // recorded where no V-cycle that reads pinv is still
     bool pinv_free_set;          // queued after it: the upload need wait for nothing later
-    hipStream_t aux_stream;      // pp_step's divergence, beside the coefficient load:
-    hipEvent_t aux_start;        // the stream's earlier work done (u* written) ...
-    hipEvent_t aux_done;         // ... and the divergence with its sum done
+    hipStream_t aux_stream;      // pp_step's divergence and cold-start residual, beside the
+    hipEvent_t aux_start;        // coefficient load: the stream's earlier work done (u*
+    hipEvent_t aux_done;         // written) ... and that side-stream work done
     bool pinv_wait;              // the next V-cycle waits for the upload before its coarse levels
     bool pinv_dirty;             // the coefficients changed since pinv was built: the next
                                  // V-cycle's caller builds it first (from hcoarse)
@@ -2030,8 +2030,8 @@ int pp_step(pp_ctx *c, const double *rho, const double *usx, const double *usy,
     // The divergence needs only u*: it runs on a side stream beside the
     // coefficient load (both stream memory below the HBM rate, and the load's
     // coarse levels are short latency-bound launches), with its partial sums
-    // in a row of their own and its mean in a scalar slot the load does not
-    // write.  It also sums what it writes, as the solve's pass over the
+    // in rows 3..5 of the reduction buffer, which the load does not use, and
+    // its mean in a scalar slot the load does not write.  It also sums what it writes, as the solve's pass over the
     // right-hand side would (same blocks, same order, same bits).
     // A cold start's initial residual, b - mean b with p = 0, needs no
     // coefficients either: it follows on the side stream, with (for PCG) the
